@@ -1,0 +1,252 @@
+"""Pins of the oracle to things other than itself: published known-answer
+vectors, closed-form counts, adjacency-matrix identities, brute force over all
+injective maps, and group-theoretic identities of symmetry breaking."""
+import itertools
+import json
+import os
+
+import numpy as np
+import pytest
+
+import graphgen as gg
+import oracle
+from graphgen import patterns as P
+from tests import closed_forms as cf
+from tests.named_graphs import by_name
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+M64 = (1 << 64) - 1
+
+
+def _golden(name):
+    with open(os.path.join(GOLDEN, name)) as f:
+        return json.load(f)
+
+
+def test_splitmix64_known_answers():
+    kat = _golden("kat.json")["splitmix64"]
+    for x, y in zip(kat["inputs_hex"], kat["outputs_hex"]):
+        assert oracle.mix64(int(x, 16)) == int(y, 16)
+    # the inputs are the published generator's successive states
+    g = 0x9E3779B97F4A7C15
+    assert [int(x, 16) for x in kat["inputs_hex"]] == [(g * i) & M64 for i in range(1, 5)]
+
+
+def test_philox_known_answers():
+    for c in _golden("kat.json")["philox4x32_10"]["cases"]:
+        out = gg.philox4x32_10([int(x, 16) for x in c["ctr"]], [int(x, 16) for x in c["key"]])
+        assert out == [int(x, 16) for x in c["out"]]
+
+
+@pytest.mark.parametrize("case", _golden("closed_forms.json")["cases"], ids=lambda c: c["graph"] + ":" + c["pattern"])
+def test_closed_form_counts(case):
+    g = by_name(case["graph"])
+    k, e = P.NAMED[case["pattern"]]
+    r = oracle.enumerate_query(g.row_ptr, g.col, k, e)
+    assert r["count"] == case["count"], case["why"]
+    rc = oracle.enumerate_query(g.row_ptr, g.col, k, e, mode=oracle.MODE_CANON)
+    assert (rc["count"], rc["hash_sum"], rc["hash_xor"]) == (r["count"], r["hash_sum"], r["hash_xor"])
+
+
+def test_automorphism_orders():
+    aut = _golden("closed_forms.json")["automorphisms"]
+    for name, order in aut.items():
+        if name.startswith("_"):
+            continue
+        k, e = P.NAMED[name]
+        A = oracle.automorphisms(k, e)
+        assert A.shape[0] == order
+        # every listed map is a permutation preserving the edge set
+        es = {frozenset(x) for x in e}
+        for p in A:
+            assert sorted(p.tolist()) == list(range(k))
+            assert {frozenset((int(p[a]), int(p[b]))) for a, b in e} == es
+
+
+def test_grochow_kellis_pairs_of_named_patterns():
+    expect = {
+        "triangle": [(0, 1), (0, 2), (1, 2)],
+        "4-cycle": [(0, 1), (0, 2), (0, 3), (1, 3)],
+        "diamond": [(0, 3), (1, 2)],
+        "4-clique": [(0, 1), (0, 2), (0, 3), (1, 2), (1, 3), (2, 3)],
+        "house": [(0, 1)],
+        "5-clique": [(a, b) for a in range(5) for b in range(a + 1, 5)],
+    }
+    for name, pairs in expect.items():
+        k, e = P.NAMED[name]
+        assert sorted(oracle.sb_pairs(k, e)) == sorted(pairs), name
+
+
+def test_sb_identities_on_random_graph():
+    """count_SB * |Aut| = number of injective maps, the hash sum over maps is
+    |Aut| times the set-hash sum, and SB agrees with the canonical mode."""
+    g = gg.gnp(40, 0.3, seed=11)
+    for name in ["triangle", "4-cycle", "diamond", "4-clique", "house", "tailed-triangle", "3-star", "5-cycle"]:
+        k, e = P.NAMED[name]
+        naut = oracle.automorphisms(k, e).shape[0]
+        sb = oracle.enumerate_query(g.row_ptr, g.col, k, e)
+        al = oracle.enumerate_query(g.row_ptr, g.col, k, e, mode=oracle.MODE_ALL)
+        cn = oracle.enumerate_query(g.row_ptr, g.col, k, e, mode=oracle.MODE_CANON)
+        assert sb["count"] > 0, name
+        assert sb["count"] * naut == al["count"], name
+        assert (sb["hash_sum"] * naut) & M64 == al["hash_sum"], name
+        assert (cn["count"], cn["hash_sum"], cn["hash_xor"]) == (sb["count"], sb["hash_sum"], sb["hash_xor"]), name
+
+
+@pytest.mark.parametrize("n,p,seed", [(8, 0.55, 1), (9, 0.45, 2)])
+def test_brute_force_all_small_patterns(n, p, seed):
+    g = gg.gnp(n, p, seed=seed)
+    pats = [(k, e) for k in (2, 3, 4) for e in P.all_connected(k)]
+    pats += [(5, e) for e in P.all_connected(5)[::3]]
+    for k, e in pats:
+        bf = oracle.brute_force(g.row_ptr, g.col, k, e)
+        sb = oracle.enumerate_query(g.row_ptr, g.col, k, e)
+        al = oracle.enumerate_query(g.row_ptr, g.col, k, e, mode=oracle.MODE_ALL)
+        assert (sb["count"], sb["hash_sum"], sb["hash_xor"]) == (bf["count"], bf["hash_sum"], bf["hash_xor"]), (k, e)
+        assert al["count"] == bf["maps"], (k, e)
+
+
+def test_brute_force_six_vertex_patterns():
+    g = gg.gnp(8, 0.7, seed=5)
+    for name in ["6-cycle", "6-clique"]:
+        k, e = P.NAMED[name]
+        bf = oracle.brute_force(g.row_ptr, g.col, k, e)
+        sb = oracle.enumerate_query(g.row_ptr, g.col, k, e)
+        assert (sb["count"], sb["hash_sum"], sb["hash_xor"]) == (bf["count"], bf["hash_sum"], bf["hash_xor"])
+    for pat in P.random_patterns(3, seed=9, kmin=6, kmax=6):
+        bf = oracle.brute_force(g.row_ptr, g.col, pat["k"], pat["edges"])
+        sb = oracle.enumerate_query(g.row_ptr, g.col, pat["k"], pat["edges"])
+        assert (sb["count"], sb["hash_sum"], sb["hash_xor"]) == (bf["count"], bf["hash_sum"], bf["hash_xor"])
+
+
+@pytest.fixture(scope="module")
+def chung_lu_16k():
+    return gg.chung_lu(16384, 16, 2.5, seed=1, exact=True)
+
+
+def test_trace_identities_chung_lu(chung_lu_16k):
+    g = chung_lu_16k
+    assert oracle.enumerate_query(g.row_ptr, g.col, *P.NAMED["triangle"])["count"] == cf.triangles(g)
+    assert oracle.enumerate_query(g.row_ptr, g.col, *P.NAMED["4-cycle"])["count"] == cf.four_cycles(g)
+    assert oracle.enumerate_query(g.row_ptr, g.col, *P.NAMED["diamond"])["count"] == cf.diamonds(g)
+
+
+def test_trace_identities_rmat():
+    g = gg.rmat(11, 8, seed=3)
+    for name, fn in [("triangle", cf.triangles), ("4-cycle", cf.four_cycles), ("diamond", cf.diamonds)]:
+        assert oracle.enumerate_query(g.row_ptr, g.col, *P.NAMED[name])["count"] == fn(g), name
+
+
+def test_root_slices_partition():
+    g = gg.chung_lu(4096, 12, 2.5, seed=7)
+    for name in ["triangle", "4-cycle", "house"]:
+        k, e = P.NAMED[name]
+        full = oracle.enumerate_query(g.row_ptr, g.col, k, e)
+        S = 8
+        cs, hs, hx = 0, 0, 0
+        for s in range(S):
+            r = oracle.enumerate_query(g.row_ptr, g.col, k, e, slice_count=S, slice_id=s)
+            cs += r["count"]
+            hs = (hs + r["hash_sum"]) & M64
+            hx ^= r["hash_xor"]
+        assert (cs, hs, hx) == (full["count"], full["hash_sum"], full["hash_xor"]), name
+
+
+def test_results_independent_of_order():
+    g = gg.gnp(30, 0.35, seed=4)
+    k, e = P.NAMED["house"]
+    ref = oracle.enumerate_query(g.row_ptr, g.col, k, e)
+    adj = {frozenset(x) for x in e}
+    n_orders = 0
+    for order in itertools.permutations(range(k)):
+        if any(not any(frozenset((order[p], order[i])) in adj for p in range(i)) for i in range(1, k)):
+            with pytest.raises(ValueError):
+                oracle.enumerate_query(g.row_ptr, g.col, k, e, order=order)
+            continue
+        r = oracle.enumerate_query(g.row_ptr, g.col, k, e, order=order)
+        assert (r["count"], r["hash_sum"], r["hash_xor"]) == (ref["count"], ref["hash_sum"], ref["hash_xor"])
+        n_orders += 1
+    assert n_orders > 10
+
+
+def _brute_level_counts(g, k, e, order, pairs):
+    """Partial maps of each prefix of ``order``: injective, keeping the induced
+    prefix edges, and satisfying constraints with both ends in the prefix."""
+    n = g.n
+    rank = oracle.ranks(g.row_ptr)
+    adj = set()
+    for u in range(n):
+        for x in range(int(g.row_ptr[u]), int(g.row_ptr[u + 1])):
+            adj.add((u, int(g.col[x])))
+    out = []
+    for d in range(1, k + 1):
+        pre = list(order[:d])
+        pe = [(a, b) for a, b in e if a in pre and b in pre]
+        pp = [(a, b) for a, b in pairs if a in pre and b in pre]
+        c = 0
+        for img in itertools.permutations(range(n), d):
+            f = dict(zip(pre, img))
+            if all((f[a], f[b]) in adj for a, b in pe) and all(rank[f[a]] < rank[f[b]] for a, b in pp):
+                c += 1
+        out.append(c)
+    return out
+
+
+def test_level_counts_match_brute_force():
+    g = gg.gnp(9, 0.5, seed=8)
+    for name, order in [("house", (4, 0, 1, 2, 3)), ("diamond", (1, 2, 0, 3)), ("4-cycle", (0, 1, 2, 3))]:
+        k, e = P.NAMED[name]
+        pairs = oracle.sb_pairs(k, e)
+        r = oracle.enumerate_query(g.row_ptr, g.col, k, e, order=order)
+        assert r["level_counts"][:k] == _brute_level_counts(g, k, e, order, pairs), name
+
+
+def test_explicit_sb_pairs_give_same_result():
+    """Any valid constraint set gives the same subgraphs: here the constraints
+    of an isomorphic relabelling of the 4-cycle, mapped back."""
+    g = gg.gnp(25, 0.4, seed=6)
+    k, e = P.NAMED["4-cycle"]
+    ref = oracle.enumerate_query(g.row_ptr, g.col, k, e)
+    # rotate the query labels by one: constraints of the rotated query, mapped back
+    rot = [(a + 1) % 4 for a in range(4)]
+    inv = {rot[a]: a for a in range(4)}
+    re_ = [(rot[a], rot[b]) for a, b in e]
+    pairs = [(inv[a], inv[b]) for a, b in oracle.sb_pairs(k, re_)]
+    alt = oracle.enumerate_query(g.row_ptr, g.col, k, e, sb_pairs=pairs)
+    assert (alt["count"], alt["hash_sum"], alt["hash_xor"]) == (ref["count"], ref["hash_sum"], ref["hash_xor"])
+    # no constraints: every map
+    none = oracle.enumerate_query(g.row_ptr, g.col, k, e, sb_pairs=[])
+    assert none["count"] == 8 * ref["count"]
+
+
+def test_csr_hygiene_checks():
+    g = gg.gnp(12, 0.5, seed=3)
+    assert oracle.check_csr(g.row_ptr, g.col) == 0
+    rp, col = g.row_ptr.copy(), g.col.copy()
+    u = int(np.argmax(np.diff(rp)))
+    a, b = int(rp[u]), int(rp[u + 1])
+    c = col.copy()
+    c[a], c[a + 1] = c[a + 1], c[a]
+    assert oracle.check_csr(rp, c) == 1
+    c = col.copy()
+    c[a + 1] = c[a]
+    assert oracle.check_csr(rp, c) in (1, 4)
+    c = col.copy()
+    c[a] = u if u < c[a + 1] else c[a]
+    if c[a] == u:
+        assert oracle.check_csr(rp, c) in (2, 4)
+    c = col.copy()
+    c[b - 1] = 12
+    assert oracle.check_csr(rp, c) == 3
+    # drop one direction of an edge: asymmetric
+    e = gg.from_edges(4, [(0, 1), (1, 2), (2, 3)])
+    rp2 = e.row_ptr.copy()
+    col2 = e.col.copy()
+    col2[0] = 2  # row 0 says 0-2, row 2 has no 0
+    assert oracle.check_csr(rp2, col2) == 4
+
+
+def test_mix_is_a_bijection_on_samples():
+    xs = [0, 1, 2, 3, 1 << 32, (1 << 64) - 1, 0x123456789ABCDEF0]
+    ys = [oracle.mix64(x) for x in xs]
+    assert len(set(ys)) == len(xs)
