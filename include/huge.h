@@ -1,0 +1,205 @@
+/*
+ * huge.h -- C ABI of a single-GPU (MI355X, gfx950) subgraph enumeration
+ * library built around the PULL-EXTEND operator of HUGE (Yang, Lai, Lin, Hao,
+ * Zhang, "HUGE: An Efficient and Scalable Subgraph Enumeration System").
+ *
+ * Problem (Section 2, "Subgraph Enumeration"): given an unlabelled, undirected,
+ * connected query q and an unlabelled undirected data graph G, find every
+ * subgraph g of G isomorphic to q.  Subgraphs are non-induced: only q's edges
+ * must be present.  Symmetry breaking (Section 2) reports each g exactly once.
+ *
+ * The computation is the left-deep chain of complete star joins on induced
+ * prefixes (Section 3.1, Definition 3.1 and the BiGJoin discussion): a SCAN of
+ * the first query edge followed by one PULL-EXTEND per further query vertex
+ * (Section 4.2), whose candidate set is the intersection of the neighbour
+ * lists of the already-matched neighbours (Eq. 2), filtered by injectivity
+ * (Algorithm 4, intersect stage) and by the symmetry-breaking order, and a
+ * counting SINK (Section 4.2).  Execution follows the DFS/BFS-adaptive
+ * scheduler (Section 5.2, Algorithm 5) with a bounded device frontier, and
+ * work stealing (Section 5.3) inside the GPU.
+ *
+ * Conventions for every function:
+ *   - returns huge_status; no exception crosses the ABI;
+ *   - out-parameters are written only on HUGE_OK (or HUGE_STOPPED where
+ *     stated);
+ *   - huge_last_error() gives a thread-local message for the last failure
+ *     on the calling thread, valid until the next call on that thread;
+ *   - handles are immutable after creation and may be shared between threads;
+ *     two concurrent exec calls need two workspaces (or NULL workspaces).
+ *
+ * IDs: vertex IDs in and out of the library are the caller's original IDs.
+ * Internally the graph is relabelled by degree rank (ascending degree, ties by
+ * original ID), the data-vertex total order of Section 2's symmetry breaking.
+ */
+#ifndef HUGE_H
+#define HUGE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define HUGE_KMAX 8 /* largest query: 8 vertices */
+
+typedef enum {
+    HUGE_OK = 0,
+    HUGE_STOPPED = 1,    /* huge_enumerate: the callback asked to stop */
+    HUGE_EINVAL = -1,    /* NULL pointer, bad size, bad option */
+    HUGE_ENOMEM = -2,    /* device or host allocation failed, or workspace too small */
+    HUGE_EDEVICE = -3,   /* a HIP runtime call or kernel failed */
+    HUGE_EGRAPH = -4,    /* CSR not sorted, duplicate, self-loop, asymmetric, ID out of range */
+    HUGE_EQUERY = -5,    /* k < 2, k > 8, bad/duplicate/self edge, or disconnected query */
+    HUGE_EORDER = -6,    /* order is not a permutation, or a prefix is disconnected */
+    HUGE_EOVERFLOW = -7  /* a 64-bit count overflowed */
+} huge_status;
+
+typedef struct huge_graph huge_graph;
+typedef struct huge_plan huge_plan;
+
+/* huge_load_csr flags */
+#define HUGE_HOST_PTRS 0x1u   /* row_ptr / col are host memory (copied) */
+#define HUGE_DEVICE_PTRS 0x2u /* row_ptr / col are device memory (read, not kept) */
+#define HUGE_NO_VALIDATE 0x4u /* skip the hygiene checks (caller guarantees a clean CSR) */
+
+/* huge_plan flags */
+#define HUGE_PLAN_COST_MODEL 0x0u /* order from the cost model (Algorithm 1, wco plans) */
+#define HUGE_PLAN_LEARNED 0x1u    /* order from the learned cardinality model (see huge_mlp_*) */
+
+/* huge_exec_opts.engine */
+#define HUGE_ENGINE_AUTO 0
+#define HUGE_ENGINE_LEVELS 1     /* host-driven Algorithm 5, one grid-wide launch per chunk */
+#define HUGE_ENGINE_PERSISTENT 2 /* one persistent launch: per-workgroup Algorithm 5 + stealing */
+
+typedef struct {
+    uint64_t count;                    /* subgraphs found (in the selected slice) */
+    uint64_t hash_sum;                 /* sum of h(g) mod 2^64, see below */
+    uint64_t hash_xor;                 /* xor of h(g) */
+    uint64_t level_counts[HUGE_KMAX];  /* [i]: partial matches of the first i+1 order vertices */
+    double query_ms;                   /* wall time of the call (planning excluded, D2H included) */
+    uint64_t peak_frontier_bytes;      /* largest device bytes held by intermediate partial matches */
+    uint64_t launches;                 /* kernel launches issued */
+    uint64_t steals;                   /* successful steals (persistent engine) */
+} huge_result;
+/*
+ * h(g) = mix( sum over query edges (a,b) of mix(edge(f(a), f(b))) ) with
+ * edge(x, y) = (min(rx, ry) << 32) | max(rx, ry), rx the degree rank of x,
+ * mix the SplitMix64 finalizer; all arithmetic mod 2^64.  h depends only on
+ * the image edge set of g, so hash_sum / hash_xor do not depend on the plan,
+ * the schedule or the symmetry-breaking scheme.
+ */
+
+typedef struct {
+    uint64_t frontier_cap_bytes; /* device bytes for intermediate partial matches;
+                                    0 = smallest workable (DFS-like), UINT64_MAX = as large as fits */
+    int64_t chunk_rows;          /* rows per scheduling segment; 0 = autotuned / default */
+    int32_t strategy;            /* intersection strategy; -1 = autotuned */
+    int32_t engine;              /* HUGE_ENGINE_* */
+    int32_t work_stealing;       /* persistent engine: 1 = steal, 0 = static root split only */
+    int32_t deterministic;       /* reserved: results are exact and order-free either way */
+    uint32_t slice_count;        /* root slice: keep matches with mix(rank(f(0))) % slice_count == slice_id */
+    uint32_t slice_id;           /* (query vertex 0's image); slice_count 0 or 1 = everything */
+    void *stream;                /* hipStream_t; NULL = the null stream */
+    void *workspace;             /* caller-owned device memory, or NULL = library allocates */
+    uint64_t workspace_bytes;
+} huge_exec_opts;
+
+/* Default options: frontier cap 4 GiB, autotuned chunk and strategy, AUTO engine, no slice. */
+huge_status huge_exec_opts_default(huge_exec_opts *opts);
+
+/*
+ * huge_load_csr -- load an undirected simple graph (Section 2, "Graph
+ * Storage": each vertex with its adjacency list; here all on one device).
+ *   n, nnz   : vertices, directed adjacency entries (= 2|E|); n < 2^31, nnz < 2^32
+ *   row_ptr  : int64[n+1], row_ptr[0] = 0, nondecreasing, row_ptr[n] = nnz
+ *   col      : int32[nnz], each list strictly ascending, symmetric, no self-loops
+ *   flags    : HUGE_HOST_PTRS or HUGE_DEVICE_PTRS, optionally | HUGE_NO_VALIDATE
+ *   stream   : hipStream_t for the load kernels (NULL = null stream)
+ * The library relabels by degree rank on the GPU, re-sorts every list and
+ * builds a degree sketch; the inputs are not retained.  Errors: HUGE_EGRAPH
+ * (hygiene), HUGE_ENOMEM, HUGE_EDEVICE, HUGE_EINVAL.
+ */
+huge_status huge_load_csr(int64_t n, int64_t nnz, const int64_t *row_ptr, const int32_t *col, uint32_t flags,
+                          void *stream, huge_graph **out);
+void huge_graph_free(huge_graph *g);
+
+typedef struct {
+    int64_t n, nnz;
+    int64_t max_degree;
+    uint64_t degree_hist[32];   /* [0]: degree 0; [b>0]: 2^(b-1) <= degree < 2^b */
+    double degree_moments[8];   /* sum_u d_u^p, p = 0..7 */
+    double load_ms;
+    uint64_t device_bytes;      /* device memory held by the graph */
+} huge_graph_info;
+huge_status huge_graph_get_info(const huge_graph *g, huge_graph_info *out);
+
+/*
+ * Copy the relabelled device graph back to the host (for inspection / tests).
+ * row_ptr int64[n+1], col int32[nnz], inv_rank int32[n] (rank -> original ID);
+ * any pointer may be NULL to skip it.
+ */
+huge_status huge_graph_export(const huge_graph *g, int64_t *row_ptr, int32_t *col, int32_t *inv_rank);
+
+/*
+ * huge_plan -- build the execution plan of one query (host only).
+ *   g        : the graph whose degree sketch drives the cost model; NULL plans
+ *              without statistics (the lexicographically first connected
+ *              order unless one is given)
+ *   k        : query vertices 0..k-1, 2 <= k <= 8
+ *   qedges   : 2*n_qedges ints, undirected, no self/duplicate edges; q connected
+ *   order    : k entries, a matching order whose every prefix is connected
+ *              (user-supplied logical plan, Remark 3.2), or NULL: the planner
+ *              picks one (cost model of Algorithm 1 restricted to left-deep
+ *              worst-case-optimal plans, or the learned model per flags)
+ * Symmetry-breaking constraints come from q alone (Grochow-Kellis with a
+ * lowest-ID tie-break), never from the order, so every order gives the same
+ * matches.  Errors: HUGE_EQUERY, HUGE_EORDER, HUGE_EINVAL.
+ */
+huge_status huge_plan_create(const huge_graph *g, int32_t k, int32_t n_qedges, const int32_t *qedges,
+                             const int32_t *order, uint32_t flags, huge_plan **out);
+void huge_plan_free(huge_plan *p);
+
+/*
+ * Plan details: order_out int32[k]; n_sb number of constraints; sb_pairs
+ * int32[2*28] as (a, b) meaning rank(f(a)) < rank(f(b)); est_cost: the
+ * model's estimated total partial matches (sum over prefixes).  NULL skips.
+ */
+huge_status huge_plan_info(const huge_plan *p, int32_t *k, int32_t *order_out, int32_t *n_sb, int32_t *sb_pairs,
+                           double *est_cost);
+
+/* Device workspace needed by huge_count / huge_enumerate for these options. */
+huge_status huge_workspace_size(const huge_graph *g, const huge_plan *p, const huge_exec_opts *opts,
+                                uint64_t *bytes);
+
+/*
+ * huge_count -- enumerate and count (SINK by counting, Section 4.2).  Fills
+ * count, hash_sum, hash_xor, level_counts, timing and frontier statistics.
+ * opts NULL = huge_exec_opts_default.  Blocks until the result is on the host.
+ */
+huge_status huge_count(const huge_graph *g, const huge_plan *p, const huge_exec_opts *opts, huge_result *out);
+
+/*
+ * huge_enumerate -- enumerate and deliver every match.  Matches are written to
+ * host_buf (buf_rows rows of k int32, row = f(0), ..., f(k-1) indexed by query
+ * vertex, original IDs) and cb(user, host_buf, nrows, k) is called on the
+ * calling thread each time the buffer is full and once at the end.  A nonzero
+ * return from cb stops the run with HUGE_STOPPED; out->count is then the
+ * number of rows delivered.  Row order is unspecified.
+ */
+typedef int (*huge_emit_fn)(void *user, const int32_t *rows, int64_t nrows, int32_t k);
+huge_status huge_enumerate(const huge_graph *g, const huge_plan *p, const huge_exec_opts *opts, int32_t *host_buf,
+                           int64_t buf_rows, huge_emit_fn cb, void *user, huge_result *out);
+
+/*
+ * huge_count_batch -- count np queries in one persistent launch (plans share
+ * the frontier budget and the stealing pool); outs[np].
+ */
+huge_status huge_count_batch(const huge_graph *g, const huge_plan *const *plans, int32_t np,
+                             const huge_exec_opts *opts, huge_result *outs);
+
+const char *huge_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* HUGE_H */

@@ -1,0 +1,333 @@
+"""Python binding of libhuge.so (include/huge.h): argument marshalling only.
+
+Every step of the enumeration runs in the library's HIP kernels; this module
+only converts arguments, hands device memory and streams from PyTorch to the
+library, and turns status codes into exceptions.  It refuses to run without
+the built library: there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import threading
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libhuge.so")
+KMAX = 8
+
+HUGE_OK, HUGE_STOPPED = 0, 1
+STATUS = {0: "HUGE_OK", 1: "HUGE_STOPPED", -1: "HUGE_EINVAL", -2: "HUGE_ENOMEM", -3: "HUGE_EDEVICE",
+          -4: "HUGE_EGRAPH", -5: "HUGE_EQUERY", -6: "HUGE_EORDER", -7: "HUGE_EOVERFLOW"}
+HOST_PTRS, DEVICE_PTRS, NO_VALIDATE = 0x1, 0x2, 0x4
+PLAN_COST_MODEL, PLAN_LEARNED = 0x0, 0x1
+ENGINE_AUTO, ENGINE_LEVELS, ENGINE_PERSISTENT = 0, 1, 2
+
+EXPORTED = [
+    "huge_exec_opts_default", "huge_load_csr", "huge_graph_free", "huge_graph_get_info", "huge_graph_export",
+    "huge_plan_create", "huge_plan_free", "huge_plan_info", "huge_workspace_size", "huge_count",
+    "huge_enumerate", "huge_count_batch", "huge_last_error",
+]
+
+
+class HugeError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__("%s: %s" % (STATUS.get(status, status), msg))
+        self.status = status
+        self.name = STATUS.get(status, str(status))
+
+
+class Result(ctypes.Structure):
+    _fields_ = [("count", ctypes.c_uint64), ("hash_sum", ctypes.c_uint64), ("hash_xor", ctypes.c_uint64),
+                ("level_counts", ctypes.c_uint64 * KMAX), ("query_ms", ctypes.c_double),
+                ("peak_frontier_bytes", ctypes.c_uint64), ("launches", ctypes.c_uint64),
+                ("steals", ctypes.c_uint64)]
+
+    def to_dict(self):
+        return {"count": int(self.count), "hash_sum": int(self.hash_sum), "hash_xor": int(self.hash_xor),
+                "level_counts": [int(x) for x in self.level_counts], "query_ms": float(self.query_ms),
+                "peak_frontier_bytes": int(self.peak_frontier_bytes), "launches": int(self.launches),
+                "steals": int(self.steals)}
+
+
+class ExecOpts(ctypes.Structure):
+    _fields_ = [("frontier_cap_bytes", ctypes.c_uint64), ("chunk_rows", ctypes.c_int64),
+                ("strategy", ctypes.c_int32), ("engine", ctypes.c_int32), ("work_stealing", ctypes.c_int32),
+                ("deterministic", ctypes.c_int32), ("slice_count", ctypes.c_uint32), ("slice_id", ctypes.c_uint32),
+                ("stream", ctypes.c_void_p), ("workspace", ctypes.c_void_p), ("workspace_bytes", ctypes.c_uint64)]
+
+
+class GraphInfo(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("nnz", ctypes.c_int64), ("max_degree", ctypes.c_int64),
+                ("degree_hist", ctypes.c_uint64 * 32), ("degree_moments", ctypes.c_double * 8),
+                ("load_ms", ctypes.c_double), ("device_bytes", ctypes.c_uint64)]
+
+
+EMIT_FN = ctypes.CFUNCTYPE(ctypes.c_int, ctypes.c_void_p, ctypes.POINTER(ctypes.c_int32), ctypes.c_int64,
+                           ctypes.c_int32)
+
+_lib = None
+_lock = threading.Lock()
+
+
+def load_library(path: str = LIB_PATH):
+    """Load libhuge.so and declare its signatures.  Raises if it is missing."""
+    global _lib
+    with _lock:
+        if _lib is not None:
+            return _lib
+        if not os.path.exists(path):
+            raise RuntimeError("libhuge.so is not built (run __graft_entry__.build() or "
+                               "python paper_2103_14294_amd/build.py); there is no fallback path")
+        lib = ctypes.CDLL(path)
+        vp, i32, i64, u32 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32
+        st = ctypes.c_int
+        lib.huge_exec_opts_default.restype = st
+        lib.huge_exec_opts_default.argtypes = [ctypes.POINTER(ExecOpts)]
+        lib.huge_load_csr.restype = st
+        lib.huge_load_csr.argtypes = [i64, i64, vp, vp, u32, vp, ctypes.POINTER(vp)]
+        lib.huge_graph_free.restype = None
+        lib.huge_graph_free.argtypes = [vp]
+        lib.huge_graph_get_info.restype = st
+        lib.huge_graph_get_info.argtypes = [vp, ctypes.POINTER(GraphInfo)]
+        lib.huge_graph_export.restype = st
+        lib.huge_graph_export.argtypes = [vp, vp, vp, vp]
+        lib.huge_plan_create.restype = st
+        lib.huge_plan_create.argtypes = [vp, i32, i32, vp, vp, u32, ctypes.POINTER(vp)]
+        lib.huge_plan_free.restype = None
+        lib.huge_plan_free.argtypes = [vp]
+        lib.huge_plan_info.restype = st
+        lib.huge_plan_info.argtypes = [vp, vp, vp, vp, vp, vp]
+        lib.huge_workspace_size.restype = st
+        lib.huge_workspace_size.argtypes = [vp, vp, ctypes.POINTER(ExecOpts), ctypes.POINTER(ctypes.c_uint64)]
+        lib.huge_count.restype = st
+        lib.huge_count.argtypes = [vp, vp, ctypes.POINTER(ExecOpts), ctypes.POINTER(Result)]
+        lib.huge_enumerate.restype = st
+        lib.huge_enumerate.argtypes = [vp, vp, ctypes.POINTER(ExecOpts), vp, i64, EMIT_FN, vp, ctypes.POINTER(Result)]
+        lib.huge_count_batch.restype = st
+        lib.huge_count_batch.argtypes = [vp, ctypes.POINTER(vp), i32, ctypes.POINTER(ExecOpts), ctypes.POINTER(Result)]
+        lib.huge_last_error.restype = ctypes.c_char_p
+        lib.huge_last_error.argtypes = []
+        _lib = lib
+        return lib
+
+
+def _check(status):
+    if status not in (HUGE_OK, HUGE_STOPPED):
+        msg = _lib.huge_last_error()
+        raise HugeError(status, msg.decode() if msg else "")
+    return status
+
+
+def _torch():
+    import torch  # deferred: only needed for device memory and streams
+    return torch
+
+
+def _current_stream():
+    torch = _torch()
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+class Graph:
+    """A graph loaded on the current device (relabelled by degree rank)."""
+
+    def __init__(self, handle, n, nnz):
+        self._h = ctypes.c_void_p(handle)
+        self.n = n
+        self.nnz = nnz
+
+    @property
+    def handle(self):
+        return self._h
+
+    def info(self):
+        gi = GraphInfo()
+        _check(_lib.huge_graph_get_info(self._h, ctypes.byref(gi)))
+        return {"n": gi.n, "nnz": gi.nnz, "max_degree": gi.max_degree,
+                "degree_hist": [int(x) for x in gi.degree_hist],
+                "degree_moments": [float(x) for x in gi.degree_moments], "load_ms": gi.load_ms,
+                "device_bytes": int(gi.device_bytes)}
+
+    def export(self):
+        rp = np.empty(self.n + 1, dtype=np.int64)
+        col = np.empty(max(self.nnz, 1), dtype=np.int32)
+        inv = np.empty(self.n, dtype=np.int32)
+        _check(_lib.huge_graph_export(self._h, rp.ctypes.data, col.ctypes.data, inv.ctypes.data))
+        return rp, col[: self.nnz], inv
+
+    def free(self):
+        if self._h and self._h.value and _lib is not None:
+            _lib.huge_graph_free(self._h)
+            self._h = ctypes.c_void_p(None)
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+class Plan:
+    def __init__(self, handle, k):
+        self._h = ctypes.c_void_p(handle)
+        self.k = k
+
+    @property
+    def handle(self):
+        return self._h
+
+    def info(self):
+        k = ctypes.c_int32()
+        order = np.zeros(KMAX, dtype=np.int32)
+        nsb = ctypes.c_int32()
+        pairs = np.zeros(56, dtype=np.int32)
+        est = ctypes.c_double()
+        _check(_lib.huge_plan_info(self._h, ctypes.byref(k), order.ctypes.data, ctypes.byref(nsb),
+                                   pairs.ctypes.data, ctypes.byref(est)))
+        return {"k": k.value, "order": order[: k.value].tolist(),
+                "sb_pairs": [tuple(pairs[2 * i:2 * i + 2].tolist()) for i in range(nsb.value)],
+                "est_cost": est.value}
+
+    def free(self):
+        if self._h and self._h.value and _lib is not None:
+            _lib.huge_plan_free(self._h)
+            self._h = ctypes.c_void_p(None)
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+def load(row_ptr, col, validate=True, stream=None) -> Graph:
+    """huge_load_csr.  row_ptr/col: numpy arrays (host) or torch tensors on the GPU."""
+    lib = load_library()
+    flags = 0 if validate else NO_VALIDATE
+    keep = []
+    if hasattr(row_ptr, "is_cuda") and row_ptr.is_cuda:
+        torch = _torch()
+        rp = row_ptr.to(torch.int64).contiguous()
+        cl = col.to(torch.int32).contiguous()
+        keep += [rp, cl]
+        n, nnz = rp.numel() - 1, cl.numel()
+        flags |= DEVICE_PTRS
+        prp, pcl = rp.data_ptr(), (cl.data_ptr() if nnz else None)
+        s = stream if stream is not None else _current_stream()
+    else:
+        rp = np.ascontiguousarray(row_ptr, dtype=np.int64)
+        cl = np.ascontiguousarray(col, dtype=np.int32)
+        keep += [rp, cl]
+        n, nnz = rp.shape[0] - 1, cl.shape[0]
+        flags |= HOST_PTRS
+        prp, pcl = rp.ctypes.data, (cl.ctypes.data if nnz else None)
+        s = stream if stream is not None else _current_stream()
+    h = ctypes.c_void_p()
+    _check(lib.huge_load_csr(int(n), int(nnz), prp, pcl, flags, s, ctypes.byref(h)))
+    return Graph(h.value, int(n), int(nnz))
+
+
+def plan(g: Graph, k, edges, order=None, learned=False) -> Plan:
+    """huge_plan_create for query edges over vertices 0..k-1."""
+    lib = load_library()
+    e = np.ascontiguousarray(np.asarray(edges, dtype=np.int32).reshape(-1, 2))
+    o = None if order is None else np.ascontiguousarray(np.asarray(order, dtype=np.int32))
+    h = ctypes.c_void_p()
+    _check(lib.huge_plan_create(None if g is None else g.handle, int(k), int(e.shape[0]), e.ctypes.data,
+                                None if o is None else o.ctypes.data, PLAN_LEARNED if learned else PLAN_COST_MODEL,
+                                ctypes.byref(h)))
+    return Plan(h.value, int(k))
+
+
+def exec_opts(cap=None, chunk_rows=0, strategy=-1, engine=ENGINE_AUTO, work_stealing=1, slice_count=1, slice_id=0,
+              stream=None, workspace=None) -> ExecOpts:
+    lib = load_library()
+    o = ExecOpts()
+    lib.huge_exec_opts_default(ctypes.byref(o))
+    if cap is not None:
+        o.frontier_cap_bytes = (1 << 64) - 1 if cap == float("inf") else int(cap)
+    o.chunk_rows = int(chunk_rows)
+    o.strategy = int(strategy)
+    o.engine = int(engine)
+    o.work_stealing = int(work_stealing)
+    o.slice_count = int(slice_count)
+    o.slice_id = int(slice_id)
+    o.stream = (stream if stream is not None else _current_stream()).value \
+        if not isinstance(stream, int) else stream
+    if workspace is not None:
+        o.workspace = workspace.data_ptr()
+        o.workspace_bytes = workspace.numel() * workspace.element_size()
+    return o
+
+
+class Workspace:
+    """A grow-only device buffer (torch-owned) reused across exec calls."""
+
+    def __init__(self):
+        self.buf = None
+
+    def get(self, nbytes):
+        torch = _torch()
+        if self.buf is None or self.buf.numel() < nbytes:
+            self.buf = None
+            self.buf = torch.empty(int(nbytes), dtype=torch.uint8, device="cuda")
+        return self.buf
+
+
+_default_ws = Workspace()
+
+
+def workspace_size(g: Graph, p: Plan, opts: ExecOpts) -> int:
+    b = ctypes.c_uint64()
+    _check(_lib.huge_workspace_size(g.handle, p.handle, ctypes.byref(opts), ctypes.byref(b)))
+    return int(b.value)
+
+
+def count(g: Graph, p: Plan, workspace: Workspace | None = _default_ws, **kw) -> dict:
+    """huge_count: count matches; returns count, hash_sum, hash_xor, level_counts, query_ms, ..."""
+    lib = load_library()
+    opts = exec_opts(**kw)
+    if workspace is not None:
+        ws = workspace.get(workspace_size(g, p, opts))
+        opts.workspace = ws.data_ptr()
+        opts.workspace_bytes = ws.numel()
+    r = Result()
+    _check(lib.huge_count(g.handle, p.handle, ctypes.byref(opts), ctypes.byref(r)))
+    return r.to_dict()
+
+
+def count_batch(g: Graph, plans, **kw):
+    lib = load_library()
+    opts = exec_opts(**kw)
+    arr = (ctypes.c_void_p * len(plans))(*[p.handle.value for p in plans])
+    res = (Result * len(plans))()
+    _check(lib.huge_count_batch(g.handle, arr, len(plans), ctypes.byref(opts), res))
+    return [r.to_dict() for r in res]
+
+
+def enumerate_matches(g: Graph, p: Plan, buf_rows=1 << 16, callback=None, **kw):
+    """huge_enumerate.  With callback None, returns all rows as an (N, k) array
+    (query-vertex order, original IDs).  Otherwise callback(rows) -> bool stop."""
+    lib = load_library()
+    opts = exec_opts(**kw)
+    buf = np.empty((int(buf_rows), p.k), dtype=np.int32)
+    chunks = []
+
+    def _cb(user, rows, nrows, k):
+        a = np.ctypeslib.as_array(rows, shape=(int(nrows) * int(k),)).reshape(int(nrows), int(k)).copy()
+        if callback is None:
+            chunks.append(a)
+            return 0
+        return 1 if callback(a) else 0
+
+    fn = EMIT_FN(_cb)
+    r = Result()
+    st = _check(lib.huge_enumerate(g.handle, p.handle, ctypes.byref(opts), buf.ctypes.data, int(buf_rows), fn, None,
+                                   ctypes.byref(r)))
+    d = r.to_dict()
+    d["stopped"] = st == HUGE_STOPPED
+    if callback is None:
+        d["rows"] = np.concatenate(chunks) if chunks else np.zeros((0, p.k), dtype=np.int32)
+    return d

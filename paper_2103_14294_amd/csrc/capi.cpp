@@ -1,0 +1,188 @@
+// The C ABI (include/huge.h): argument checks, error capture, dispatch.
+#include <chrono>
+#include <cstdarg>
+#include <cstring>
+
+#include "internal.h"
+
+namespace huge {
+
+static thread_local std::string g_last_error;
+
+void set_error(const char *fmt, ...) {
+    char buf[1024];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+}
+
+template <typename F>
+static huge_status guard(F &&f) {
+    try {
+        g_last_error.clear();
+        return f();
+    } catch (const Error &e) {
+        return e.st;
+    } catch (const std::bad_alloc &) {
+        set_error("host allocation failed");
+        return HUGE_ENOMEM;
+    } catch (...) {
+        set_error("unexpected internal error");
+        return HUGE_EDEVICE;
+    }
+}
+
+static huge_exec_opts resolve_opts(const huge_exec_opts *o) {
+    huge_exec_opts r;
+    huge_exec_opts_default(&r);
+    if (o) r = *o;
+    return r;
+}
+
+}  // namespace huge
+
+using namespace huge;
+
+extern "C" {
+
+huge_status huge_exec_opts_default(huge_exec_opts *o) {
+    if (!o) return HUGE_EINVAL;
+    memset(o, 0, sizeof(*o));
+    o->frontier_cap_bytes = 4ull << 30;
+    o->chunk_rows = 0;
+    o->strategy = -1;
+    o->engine = HUGE_ENGINE_AUTO;
+    o->work_stealing = 1;
+    o->slice_count = 1;
+    return HUGE_OK;
+}
+
+huge_status huge_load_csr(int64_t n, int64_t nnz, const int64_t *row_ptr, const int32_t *col, uint32_t flags,
+                          void *stream, huge_graph **out) {
+    return guard([&] {
+        if (!out) HUGE_FAIL(HUGE_EINVAL, "out is NULL");
+        huge_graph *g = graph_load(n, nnz, row_ptr, col, flags, (hipStream_t)stream);
+        *out = g;
+        return HUGE_OK;
+    });
+}
+
+void huge_graph_free(huge_graph *g) { graph_free(g); }
+
+huge_status huge_graph_get_info(const huge_graph *g, huge_graph_info *out) {
+    return guard([&] {
+        if (!g || !out) HUGE_FAIL(HUGE_EINVAL, "NULL argument");
+        *out = g->info;
+        return HUGE_OK;
+    });
+}
+
+huge_status huge_graph_export(const huge_graph *g, int64_t *row_ptr, int32_t *col, int32_t *inv_rank) {
+    return guard([&] {
+        if (!g) HUGE_FAIL(HUGE_EINVAL, "NULL graph");
+        if (row_ptr) HUGE_HIP(hipMemcpy(row_ptr, g->rp, sizeof(int64_t) * (g->dev.n + 1), hipMemcpyDeviceToHost));
+        if (col && g->dev.nnz)
+            HUGE_HIP(hipMemcpy(col, g->col, sizeof(int32_t) * g->dev.nnz, hipMemcpyDeviceToHost));
+        if (inv_rank) HUGE_HIP(hipMemcpy(inv_rank, g->inv_rank, sizeof(int32_t) * g->dev.n, hipMemcpyDeviceToHost));
+        return HUGE_OK;
+    });
+}
+
+huge_status huge_plan_create(const huge_graph *g, int32_t k, int32_t n_qedges, const int32_t *qedges,
+                             const int32_t *order, uint32_t flags, huge_plan **out) {
+    return guard([&] {
+        if (!out) HUGE_FAIL(HUGE_EINVAL, "NULL argument");
+        huge_plan *p = new huge_plan();
+        try {
+            plan_build(g, k, n_qedges, qedges, order, flags, p);
+        } catch (...) {
+            delete p;
+            throw;
+        }
+        *out = p;
+        return HUGE_OK;
+    });
+}
+
+void huge_plan_free(huge_plan *p) { delete p; }
+
+huge_status huge_plan_info(const huge_plan *p, int32_t *k, int32_t *order_out, int32_t *n_sb, int32_t *sb_pairs,
+                           double *est_cost) {
+    return guard([&] {
+        if (!p) HUGE_FAIL(HUGE_EINVAL, "NULL plan");
+        if (k) *k = p->k;
+        if (order_out)
+            for (int i = 0; i < p->k; ++i) order_out[i] = p->order[i];
+        if (n_sb) *n_sb = (int32_t)p->sb.size();
+        if (sb_pairs)
+            for (size_t i = 0; i < p->sb.size(); ++i) {
+                sb_pairs[2 * i] = p->sb[i].first;
+                sb_pairs[2 * i + 1] = p->sb[i].second;
+            }
+        if (est_cost) *est_cost = p->est_cost;
+        return HUGE_OK;
+    });
+}
+
+huge_status huge_workspace_size(const huge_graph *g, const huge_plan *p, const huge_exec_opts *opts,
+                                uint64_t *bytes) {
+    return guard([&] {
+        if (!g || !p || !bytes) HUGE_FAIL(HUGE_EINVAL, "NULL argument");
+        huge_exec_opts o = resolve_opts(opts);
+        *bytes = workspace_bytes(g, p, o);
+        return HUGE_OK;
+    });
+}
+
+huge_status huge_count(const huge_graph *g, const huge_plan *p, const huge_exec_opts *opts, huge_result *out) {
+    return guard([&] {
+        if (!g || !p || !out) HUGE_FAIL(HUGE_EINVAL, "NULL argument");
+        huge_exec_opts o = resolve_opts(opts);
+        huge_result r;
+        if (o.engine == HUGE_ENGINE_PERSISTENT) {
+            const huge_plan *pl[1] = {p};
+            run_persistent(g, pl, 1, o, &r);
+        } else {
+            run_levels(g, p, o, &r, nullptr);
+        }
+        *out = r;
+        return HUGE_OK;
+    });
+}
+
+huge_status huge_enumerate(const huge_graph *g, const huge_plan *p, const huge_exec_opts *opts, int32_t *host_buf,
+                           int64_t buf_rows, huge_emit_fn cb, void *user, huge_result *out) {
+    return guard([&] {
+        if (!g || !p || !out) HUGE_FAIL(HUGE_EINVAL, "NULL argument");
+        huge_exec_opts o = resolve_opts(opts);
+        EmitSink sink;
+        sink.host_buf = host_buf;
+        sink.buf_rows = buf_rows;
+        sink.cb = cb;
+        sink.user = user;
+        huge_result r;
+        run_levels(g, p, o, &r, &sink);
+        *out = r;
+        return sink.stopped ? HUGE_STOPPED : HUGE_OK;
+    });
+}
+
+huge_status huge_count_batch(const huge_graph *g, const huge_plan *const *plans, int32_t np,
+                             const huge_exec_opts *opts, huge_result *outs) {
+    return guard([&] {
+        if (!g || !plans || np <= 0 || !outs) HUGE_FAIL(HUGE_EINVAL, "bad arguments");
+        for (int i = 0; i < np; ++i)
+            if (!plans[i]) HUGE_FAIL(HUGE_EINVAL, "plan %d is NULL", i);
+        huge_exec_opts o = resolve_opts(opts);
+        std::vector<huge_result> r(np);
+        run_persistent(g, plans, np, o, r.data());
+        for (int i = 0; i < np; ++i) outs[i] = r[i];
+        return HUGE_OK;
+    });
+}
+
+const char *huge_last_error(void) { return huge::g_last_error.c_str(); }
+
+}  // extern "C"

@@ -1,0 +1,285 @@
+// The level engine: Algorithm 5 (DFS/BFS-adaptive scheduling, Section 5.2)
+// driven from the host, one grid-wide launch per chunk.
+//
+// Operators form a line: SCAN (level-2 rows, read straight from the CSR edge
+// array, never materialised) -> EXTEND at widths 2..k-2 -> EXTEND+SINK at
+// width k-1 (counting fused in, never materialised).  Every materialised
+// level W (3..k-1) owns a fixed-capacity queue.  The scheduler keeps running
+// the current operator until its output queue is full or its input is empty,
+// then moves to the successor; an operator with no input hands control back
+// to its precursor, and the fused SINK always does.
+//
+// Bounded memory, stricter than Lemma 5.1: a chunk never produces more rows
+// than the free space of the output queue, because each launch covers at
+// most `free` work items and a work item (one probe element) emits at most
+// one row.  A single hub row larger than the queue is simply split across
+// launches.  So the frontier never exceeds the configured capacity.
+#include <algorithm>
+#include <chrono>
+#include <cstring>
+
+#include "internal.h"
+#include "prims.h"
+
+namespace huge {
+
+namespace {
+
+constexpr int64_t kDefaultSeg = 1 << 22;
+constexpr int64_t kMinQueueRows = 1 << 12;
+constexpr int64_t kMaxItems = 1ll << 30;
+constexpr uint64_t kDefaultCap = 4ull << 30;
+
+struct Layout {
+    int64_t seg_cap[HUGE_KMAX] = {};
+    int64_t q_cap[HUGE_KMAX + 1] = {};
+    int64_t stage_rows = 0;
+    int64_t scan_tmp = 0;
+    uint64_t total = 0;
+};
+
+inline uint64_t align_up(uint64_t x) { return (x + 255) & ~uint64_t(255); }
+
+Layout make_layout(const huge_graph *g, const huge_plan *p, const huge_exec_opts &o, int64_t stage_rows) {
+    Layout L;
+    const int k = p->k;
+    int64_t seg = o.chunk_rows > 0 ? o.chunk_rows : kDefaultSeg;
+    const int nq = std::max(0, k - 3);
+    uint64_t cap = o.frontier_cap_bytes;
+    if (cap == UINT64_MAX) {
+        size_t fr = 0, tot = 0;
+        HUGE_HIP(hipMemGetInfo(&fr, &tot));
+        cap = (uint64_t)(fr * 0.6);
+    }
+    for (int w = 3; w <= k - 1; ++w) {
+        uint64_t share = nq ? cap / nq : 0;
+        L.q_cap[w] = std::max<int64_t>(kMinQueueRows, (int64_t)(share / (4ull * w)));
+    }
+    L.seg_cap[2] = std::min<int64_t>(seg, std::max<int64_t>(1, g->dev.nnz));
+    for (int w = 3; w <= k - 1; ++w) L.seg_cap[w] = std::min<int64_t>(seg, L.q_cap[w]);
+    L.stage_rows = stage_rows;
+    int64_t maxseg = 1;
+    for (int w = 2; w <= k - 1; ++w) maxseg = std::max(maxseg, L.seg_cap[w]);
+    L.scan_tmp = scan_tmp_elems(maxseg + 1);
+    uint64_t t = align_up(sizeof(Ctrl));
+    if (k >= 3)
+        for (int w = 2; w <= k - 1; ++w) {
+            int64_t c = L.seg_cap[w];
+            t += align_up(8ull * (c + 1)) + align_up(8ull * c) * 2 + align_up(4ull * c);
+        }
+    for (int w = 3; w <= k - 1; ++w) t += align_up(4ull * w * L.q_cap[w]);
+    t += align_up(4ull * k * std::max<int64_t>(1, stage_rows));
+    t += align_up(8ull * L.scan_tmp);
+    L.total = t;
+    return L;
+}
+
+struct Carver {
+    char *base;
+    uint64_t off = 0;
+    template <typename T>
+    T *take(uint64_t count) {
+        T *p = (T *)(base + off);
+        off += align_up(sizeof(T) * count);
+        return p;
+    }
+};
+
+struct DevMem {
+    void *p = nullptr;
+    ~DevMem() {
+        if (p) (void)hipFree(p);
+    }
+};
+
+int64_t read_i64(const void *dev, hipStream_t st) {
+    int64_t v = 0;
+    HUGE_HIP(hipMemcpyAsync(&v, dev, 8, hipMemcpyDeviceToHost, st));
+    HUGE_HIP(hipStreamSynchronize(st));
+    return v;
+}
+
+}  // namespace
+
+uint64_t workspace_bytes(const huge_graph *g, const huge_plan *p, const huge_exec_opts &o) {
+    return make_layout(g, p, o, 1 << 16).total;
+}
+
+void run_levels(const huge_graph *g, const huge_plan *p, const huge_exec_opts &o, huge_result *out, EmitSink *emit) {
+    auto t0 = std::chrono::steady_clock::now();
+    hipStream_t st = (hipStream_t)o.stream;
+    const int k = p->k;
+    DevPlan P = p->dev;
+    P.slice_count = o.slice_count > 1 ? o.slice_count : 1;
+    P.slice_id = o.slice_count > 1 ? o.slice_id : 0;
+    if (P.slice_count > 1 && P.slice_id >= P.slice_count) HUGE_FAIL(HUGE_EINVAL, "slice_id >= slice_count");
+
+    int64_t stage_rows = 0;
+    if (emit) {
+        if (!emit->host_buf || emit->buf_rows <= 0 || !emit->cb)
+            HUGE_FAIL(HUGE_EINVAL, "huge_enumerate: host_buf, buf_rows and cb are required");
+        stage_rows = std::min<int64_t>(emit->buf_rows, 1 << 22);
+    }
+    Layout L = make_layout(g, p, o, stage_rows);
+    DevMem own;
+    char *ws = (char *)o.workspace;
+    if (ws) {
+        if (o.workspace_bytes < L.total)
+            HUGE_FAIL(HUGE_ENOMEM, "workspace too small: %llu bytes given, %llu needed",
+                      (unsigned long long)o.workspace_bytes, (unsigned long long)L.total);
+    } else {
+        HUGE_HIP(hipMalloc(&own.p, L.total));
+        ws = (char *)own.p;
+    }
+    Carver cv{ws};
+    Ctrl *ctrl = cv.take<Ctrl>(1);
+    struct Lv {
+        int64_t nrows = 0, next = 0;
+        int64_t seg_row0 = 0, seg_n = 0, seg_total = 0, seg_done = 0;
+        SegBufs s{};
+        int32_t *q = nullptr;
+        int64_t qcap = 0;
+    } lv[HUGE_KMAX + 1];
+    if (k >= 3)
+        for (int w = 2; w <= k - 1; ++w) {
+            int64_t c = L.seg_cap[w];
+            lv[w].s.off = cv.take<int64_t>(c + 1);
+            lv[w].s.pinfo = cv.take<uint64_t>(c);
+            lv[w].s.hpre = cv.take<uint64_t>(c);
+            lv[w].s.bound = cv.take<int32_t>(c);
+            lv[w].s.cap = c;
+        }
+    for (int w = 3; w <= k - 1; ++w) {
+        lv[w].q = cv.take<int32_t>((uint64_t)w * L.q_cap[w]);
+        lv[w].qcap = L.q_cap[w];
+    }
+    int32_t *stage = cv.take<int32_t>((uint64_t)k * std::max<int64_t>(1, stage_rows));
+    int64_t *scan_tmp = cv.take<int64_t>(L.scan_tmp);
+
+    HUGE_HIP(hipMemsetAsync(ctrl, 0, sizeof(Ctrl), st));
+    ExecStats stats;
+    const GraphDev &G = g->dev;
+    const bool root_slice = P.slice_count > 1 && P.st[0].slice;
+    if (root_slice) {
+        launch_root_count(G, P, ctrl, st);
+        stats.launches++;
+    }
+
+    auto deliver = [&](int64_t nout) {
+        if (nout <= 0) return;
+        HUGE_HIP(hipMemcpyAsync(emit->host_buf, stage, sizeof(int32_t) * k * nout, hipMemcpyDeviceToHost, st));
+        HUGE_HIP(hipStreamSynchronize(st));
+        emit->delivered += (uint64_t)nout;
+        if (emit->cb(emit->user, emit->host_buf, nout, k) != 0) emit->stopped = true;
+    };
+
+    if (k == 2) {
+        const int64_t nnz = G.nnz;
+        if (!emit) {
+            for (int64_t e = 0; e < nnz; e += kMaxItems) {
+                launch_edge_sink(G, P, e, std::min(nnz, e + kMaxItems), MODE_COUNT, nullptr, g->inv_rank, ctrl, st);
+                stats.launches++;
+            }
+        } else {
+            for (int64_t e = 0; e < nnz && !emit->stopped; e += stage_rows) {
+                launch_edge_sink(G, P, e, std::min(nnz, e + stage_rows), MODE_OUTPUT, stage, g->inv_rank, ctrl, st);
+                stats.launches++;
+                int64_t nout = read_i64(&ctrl->qcount[HUGE_KMAX], st);
+                deliver(nout);
+                HUGE_HIP(hipMemsetAsync(&ctrl->qcount[HUGE_KMAX], 0, 8, st));
+            }
+        }
+    } else {
+        const int lastW = k - 1;
+        lv[2].nrows = G.nnz;
+        int W = 2;
+        uint64_t cur_bytes = 0;
+        auto has_input = [](const Lv &l) { return l.seg_done < l.seg_total || l.next < l.nrows; };
+        bool stop = false;
+        while (!stop) {
+            Lv &l = lv[W];
+            if (!has_input(l)) {
+                if (W == 2) break;
+                cur_bytes -= (uint64_t)l.nrows * 4ull * W;
+                l.nrows = l.next = 0;
+                l.seg_total = l.seg_done = 0;
+                HUGE_HIP(hipMemsetAsync(&ctrl->qcount[W], 0, 8, st));
+                --W;
+                continue;
+            }
+            // Schedule(O): run until the output queue is full or the input is empty
+            for (;;) {
+                if (l.seg_done == l.seg_total) {
+                    if (l.next == l.nrows) break;
+                    int64_t cnt = std::min(l.s.cap, l.nrows - l.next);
+                    launch_prepare(W, W == lastW, G, P, lv[W].q, l.next, cnt, l.s, ctrl, st);
+                    launch_scan_bounds(l.s, cnt, scan_tmp, st);
+                    stats.launches += 2;
+                    l.seg_row0 = l.next;
+                    l.seg_n = cnt;
+                    l.seg_total = read_i64(l.s.off + cnt, st);
+                    l.seg_done = 0;
+                    l.next += cnt;
+                    if (l.seg_total == 0) continue;
+                }
+                const int64_t remaining = l.seg_total - l.seg_done;
+                if (W == lastW) {
+                    if (!emit) {
+                        int64_t chunk = std::min(remaining, kMaxItems);
+                        launch_extend(W, MODE_COUNT, G, P, l.q, l.seg_row0, l.s, l.seg_n, l.seg_done,
+                                      l.seg_done + chunk, nullptr, ctrl, g->inv_rank, st);
+                        stats.launches++;
+                        l.seg_done += chunk;
+                    } else {
+                        int64_t chunk = std::min(remaining, stage_rows);
+                        launch_extend(W, MODE_OUTPUT, G, P, l.q, l.seg_row0, l.s, l.seg_n, l.seg_done,
+                                      l.seg_done + chunk, stage, ctrl, g->inv_rank, st);
+                        stats.launches++;
+                        l.seg_done += chunk;
+                        int64_t nout = read_i64(&ctrl->qcount[HUGE_KMAX], st);
+                        deliver(nout);
+                        HUGE_HIP(hipMemsetAsync(&ctrl->qcount[HUGE_KMAX], 0, 8, st));
+                        if (emit->stopped) {
+                            stop = true;
+                            break;
+                        }
+                    }
+                } else {
+                    Lv &q = lv[W + 1];
+                    const int64_t free = q.qcap - q.nrows;
+                    if (free <= 0 || (free < remaining && free < q.qcap / 8)) break;  // Q_O full: yield
+                    const int64_t chunk = std::min(std::min(free, remaining), kMaxItems);
+                    launch_extend(W, MODE_EMIT, G, P, l.q, l.seg_row0, l.s, l.seg_n, l.seg_done, l.seg_done + chunk,
+                                  q.q, ctrl, g->inv_rank, st);
+                    stats.launches++;
+                    l.seg_done += chunk;
+                    int64_t nr = read_i64(&ctrl->qcount[W + 1], st);
+                    cur_bytes += (uint64_t)(nr - q.nrows) * 4ull * (W + 1);
+                    q.nrows = nr;
+                    stats.peak_frontier_bytes = std::max(stats.peak_frontier_bytes, cur_bytes);
+                }
+            }
+            if (W == lastW) {
+                if (W > 2) --W;
+            } else {
+                ++W;
+            }
+        }
+    }
+
+    Ctrl h;
+    HUGE_HIP(hipMemcpyAsync(&h, ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, st));
+    HUGE_HIP(hipStreamSynchronize(st));
+    memset(out, 0, sizeof(*out));
+    out->count = emit ? emit->delivered : h.acc[0];
+    out->hash_sum = h.acc[1];
+    out->hash_xor = h.acc[2];
+    for (int i = 0; i < HUGE_KMAX; ++i) out->level_counts[i] = h.level[i];
+    if (!root_slice) out->level_counts[0] = (uint64_t)G.n;
+    out->peak_frontier_bytes = stats.peak_frontier_bytes;
+    out->launches = stats.launches;
+    auto t1 = std::chrono::steady_clock::now();
+    out->query_ms = std::chrono::duration<double, std::milli>(t1 - t0).count();
+}
+
+}  // namespace huge

@@ -1,0 +1,523 @@
+// PULL-EXTEND on gfx950 (Section 4.2 semantics, Algorithm 4's intersect
+// stage): for every partial match f of the induced prefix pi_0..pi_{W-1},
+// the candidates for the next query vertex pi_W are
+//     C = intersection over p in Ext of N(f[p])              (Eq. 2)
+// kept when v differs from every f[p] outside Ext (injectivity), and when v
+// respects the symmetry-breaking constraints between pi_W and the prefix.
+//
+// One segment of input rows is handled in two launches:
+//   k_prepare : per row, the constraints become one window [lo, hi) on v
+//               (lo = 1 + max f[p] over "f[p] < v", hi = min f[p] over
+//               "v < f[p]"); each list N(f[p]), p in Ext, is trimmed to the
+//               window by binary search and the shortest trimmed list is the
+//               probe.  Its length bounds the row's output (used for
+//               bounded-memory chunking) and is the row's work.
+//   k_extend  : a flat, load-balanced pass over the segment's work items
+//               (one probe element each): locate the row (binary search in
+//               the exclusive scan of the bounds), test the probe element
+//               against the other Ext lists (binary search), apply the
+//               injectivity and slice filters, then either append the
+//               extended row to the next level's queue (wave ballot +
+//               one atomic per workgroup) or, at the last level, fold it into
+//               the counting SINK (count, set-hash sum and xor).
+#include "internal.h"
+#include "prims.h"
+
+namespace huge {
+namespace {
+
+constexpr int kT = 256;
+constexpr int kIPT = 4;
+constexpr int kTile = kT * kIPT;
+constexpr uint64_t kPbMask = (1ull << 56) - 1;
+
+__device__ __forceinline__ uint64_t mix64(uint64_t x) {
+    x ^= x >> 30;
+    x *= 0xbf58476d1ce4e5b9ull;
+    x ^= x >> 27;
+    x *= 0x94d049bb133111ebull;
+    x ^= x >> 31;
+    return x;
+}
+
+__device__ __forceinline__ uint64_t edge_key(int32_t a, int32_t b) {
+    uint32_t lo = (uint32_t)(a < b ? a : b), hi = (uint32_t)(a < b ? b : a);
+    return ((uint64_t)lo << 32) | hi;
+}
+
+// first index in [lo, hi) with col[i] >= key
+__device__ __forceinline__ int64_t lower_bound(const int32_t *__restrict__ col, int64_t lo, int64_t hi, int32_t key) {
+    while (lo < hi) {
+        int64_t mid = lo + ((hi - lo) >> 1);
+        if (col[mid] < key) lo = mid + 1; else hi = mid;
+    }
+    return lo;
+}
+
+__device__ __forceinline__ bool contains(const int32_t *__restrict__ col, int64_t lo, int64_t hi, int32_t key) {
+    while (lo < hi) {
+        int64_t mid = lo + ((hi - lo) >> 1);
+        int32_t x = col[mid];
+        if (x == key) return true;
+        if (x < key) lo = mid + 1; else hi = mid;
+    }
+    return false;
+}
+
+template <int W>
+__device__ __forceinline__ void load_row(const int32_t *__restrict__ rows, const GraphDev &g, int64_t r,
+                                         int32_t (&f)[W]) {
+    if constexpr (W == 2) {
+        f[0] = g.src[r];
+        f[1] = g.col[r];
+    } else {
+#pragma unroll
+        for (int p = 0; p < W; ++p) f[p] = rows[r * W + p];
+    }
+}
+
+__device__ __forceinline__ bool in_slice(int32_t v, const DevPlan &P) {
+    return (uint32_t)(mix64((uint64_t)(uint32_t)v) % P.slice_count) == P.slice_id;
+}
+
+// Validity of a level-2 row (the SCAN of the first query edge): the
+// constraint between positions 0 and 1 and the root slice.
+__device__ __forceinline__ bool level2_ok(const int32_t (&f)[2], const DevPlan &P) {
+    const DevStep &s1 = P.st[1];
+    if ((s1.lo & 1u) && !(f[0] < f[1])) return false;
+    if ((s1.hi & 1u) && !(f[1] < f[0])) return false;
+    if (P.slice_count > 1) {
+        if (P.st[0].slice && !in_slice(f[0], P)) return false;
+        if (s1.slice && !in_slice(f[1], P)) return false;
+    }
+    return true;
+}
+
+__device__ __forceinline__ unsigned long long wave_sum_u64(unsigned long long x) {
+#pragma unroll
+    for (int d = 32; d > 0; d >>= 1) x += __shfl_xor(x, d, 64);
+    return x;
+}
+__device__ __forceinline__ unsigned long long wave_xor_u64(unsigned long long x) {
+#pragma unroll
+    for (int d = 32; d > 0; d >>= 1) x ^= __shfl_xor(x, d, 64);
+    return x;
+}
+
+// ---------------------------------------------------------------------------
+// prepare
+// ---------------------------------------------------------------------------
+template <int W, bool LAST>
+__global__ __launch_bounds__(kT) void k_prepare(const int32_t *__restrict__ rows, int64_t row0, int64_t nrows,
+                                                GraphDev g, DevPlan P, SegBufs s, Ctrl *ctrl) {
+    __shared__ unsigned long long s_valid[kT / 64];
+    const int64_t i = (int64_t)blockIdx.x * kT + threadIdx.x;
+    bool valid = false;
+    if (i < nrows) {
+        int32_t f[W];
+        load_row<W>(rows, g, row0 + i, f);
+        valid = true;
+        if constexpr (W == 2) valid = level2_ok(f, P);
+        int32_t bound = 0;
+        uint64_t pinfo = 0;
+        if (valid) {
+            const DevStep &st = P.st[W];
+            int32_t lo = 0, hi = 0x7FFFFFFF;
+#pragma unroll
+            for (int p = 0; p < W; ++p) {
+                if ((st.lo >> p) & 1u) lo = max(lo, f[p] + 1);
+                if ((st.hi >> p) & 1u) hi = min(hi, f[p]);
+            }
+            if (lo < hi) {
+                int64_t best = -1, bb = 0;
+                int bp = 0;
+#pragma unroll
+                for (int p = 0; p < W; ++p) {
+                    if ((st.ext >> p) & 1u) {
+                        int32_t x = f[p];
+                        int64_t b = g.rp[x], e = g.rp[x + 1];
+                        int64_t a = lo > 0 ? lower_bound(g.col, b, e, lo) : b;
+                        int64_t z = hi < 0x7FFFFFFF ? lower_bound(g.col, a, e, hi) : e;
+                        if (best < 0 || z - a < best) {
+                            best = z - a;
+                            bb = a;
+                            bp = p;
+                        }
+                    }
+                }
+                bound = (int32_t)best;
+                pinfo = (uint64_t)bb | ((uint64_t)bp << 56);
+            }
+        }
+        s.bound[i] = bound;
+        s.pinfo[i] = pinfo;
+        if constexpr (LAST) {
+            uint64_t h = 0;
+            for (int e = 0; e < P.ne; ++e) {
+                int b = P.eb[e];
+                if (b < W) {
+                    int a = P.ea[e];
+                    int32_t fa = 0, fb = 0;
+#pragma unroll
+                    for (int p = 0; p < W; ++p) {
+                        if (p == a) fa = f[p];
+                        if (p == b) fb = f[p];
+                    }
+                    h += mix64(edge_key(fa, fb));
+                }
+            }
+            s.hpre[i] = h;
+        }
+    }
+    if constexpr (W == 2) {
+        unsigned long long c = wave_sum_u64(valid ? 1ull : 0ull);
+        if (__lane_id() == 0) s_valid[threadIdx.x >> 6] = c;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            unsigned long long t = 0;
+            for (int q = 0; q < kT / 64; ++q) t += s_valid[q];
+            if (t) atomicAdd(&ctrl->level[1], t);
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// extend
+// ---------------------------------------------------------------------------
+struct ExtArgs {
+    const int32_t *rows;
+    int64_t row0;
+    const int64_t *off;
+    const uint64_t *pinfo;
+    const uint64_t *hpre;
+    int64_t nrows;
+    int64_t w0, w1;
+    int32_t *out;
+    Ctrl *ctrl;
+    const int32_t *inv_rank;
+    GraphDev g;
+    DevPlan P;
+};
+
+// largest r in [lo, hi] with off[r] <= w
+__device__ __forceinline__ int64_t find_row(const int64_t *__restrict__ off, int64_t lo, int64_t hi, int64_t w) {
+    while (lo < hi) {
+        int64_t mid = (lo + hi + 1) >> 1;
+        if (off[mid] <= w) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+template <int W, int MODE>
+__global__ __launch_bounds__(kT) void k_extend(ExtArgs a) {
+    __shared__ int64_t s_rng[2];
+    __shared__ unsigned long long s_red[3][kT / 64];
+    __shared__ int32_t s_cnt[kT / 64];
+    __shared__ unsigned long long s_base;
+
+    const int64_t tile0 = a.w0 + (int64_t)blockIdx.x * kTile;
+    const int64_t tile1 = min(tile0 + (int64_t)kTile, a.w1);
+    if (threadIdx.x == 0) {
+        s_rng[0] = find_row(a.off, 0, a.nrows - 1, tile0);
+        s_rng[1] = find_row(a.off, s_rng[0], a.nrows - 1, tile1 - 1);
+    }
+    __syncthreads();
+    const int64_t rlo = s_rng[0], rhi = s_rng[1];
+    const DevStep st = a.P.st[W];
+    const GraphDev &g = a.g;
+
+    unsigned long long cnt = 0, hs = 0, hx = 0;
+    uint32_t okmask = 0;
+    int32_t vv[kIPT];
+    int32_t rr[kIPT];
+#pragma unroll
+    for (int j = 0; j < kIPT; ++j) {
+        vv[j] = 0;
+        rr[j] = 0;
+        const int64_t w = tile0 + j * kT + threadIdx.x;
+        if (w >= tile1) continue;
+        const int64_t r = find_row(a.off, rlo, rhi, w);
+        const uint64_t pi = a.pinfo[r];
+        const int pp = (int)(pi >> 56);
+        const int32_t v = g.col[(int64_t)(pi & kPbMask) + (w - a.off[r])];
+        int32_t f[W];
+        load_row<W>(a.rows, g, a.row0 + r, f);
+        bool ok = true;
+#pragma unroll
+        for (int p = 0; p < W; ++p)
+            if ((st.neq >> p) & 1u) ok &= (v != f[p]);
+        if (st.slice && a.P.slice_count > 1) ok &= in_slice(v, a.P);
+#pragma unroll
+        for (int p = 0; p < W; ++p) {
+            if (ok && ((st.ext >> p) & 1u) && p != pp) {
+                const int32_t x = f[p];
+                ok = contains(g.col, g.rp[x], g.rp[x + 1], v);
+            }
+        }
+        if (!ok) continue;
+        if constexpr (MODE == MODE_COUNT) {
+            uint64_t h = a.hpre[r];
+#pragma unroll
+            for (int p = 0; p < W; ++p)
+                if ((st.ext >> p) & 1u) h += mix64(edge_key(f[p], v));
+            h = mix64(h);
+            cnt += 1;
+            hs += h;
+            hx ^= h;
+        } else {
+            okmask |= 1u << j;
+            vv[j] = v;
+            rr[j] = (int32_t)r;
+        }
+    }
+
+    const int wv = threadIdx.x >> 6;
+    if constexpr (MODE == MODE_COUNT) {
+        cnt = wave_sum_u64(cnt);
+        hs = wave_sum_u64(hs);
+        hx = wave_xor_u64(hx);
+        if (__lane_id() == 0) {
+            s_red[0][wv] = cnt;
+            s_red[1][wv] = hs;
+            s_red[2][wv] = hx;
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            unsigned long long c = 0, s = 0, x = 0;
+            for (int q = 0; q < kT / 64; ++q) {
+                c += s_red[0][q];
+                s += s_red[1][q];
+                x ^= s_red[2][q];
+            }
+            if (c) {
+                atomicAdd(&a.ctrl->acc[0], c);
+                atomicAdd(&a.ctrl->acc[1], s);
+                atomicXor(&a.ctrl->acc[2], x);
+                atomicAdd(&a.ctrl->level[W], c);
+            }
+        }
+        return;
+    } else {
+        // workgroup-wide exclusive scan of per-thread output counts
+        int c = __popc(okmask);
+        int inc = c;
+        const int lane = __lane_id();
+#pragma unroll
+        for (int d = 1; d < 64; d <<= 1) {
+            int y = __shfl_up(inc, d, 64);
+            if (lane >= d) inc += y;
+        }
+        if (lane == 63) s_cnt[wv] = inc;
+        __syncthreads();
+        int wbase = 0, tot = 0;
+#pragma unroll
+        for (int q = 0; q < kT / 64; ++q) {
+            if (q < wv) wbase += s_cnt[q];
+            tot += s_cnt[q];
+        }
+        if (threadIdx.x == 0) {
+            unsigned long long b = 0;
+            if (tot) {
+                const int qi = (MODE == MODE_EMIT) ? (W + 1) : HUGE_KMAX;
+                b = atomicAdd(&a.ctrl->qcount[qi], (unsigned long long)tot);
+                atomicAdd(&a.ctrl->level[W], (unsigned long long)tot);
+            }
+            s_base = b;
+        }
+        __syncthreads();
+        if (!okmask) return;
+        int64_t o = (int64_t)s_base + wbase + (inc - c);
+#pragma unroll
+        for (int j = 0; j < kIPT; ++j) {
+            if (!((okmask >> j) & 1u)) continue;
+            int32_t f[W];
+            load_row<W>(a.rows, g, a.row0 + rr[j], f);
+            if constexpr (MODE == MODE_EMIT) {
+                int32_t *dst = a.out + o * (W + 1);
+#pragma unroll
+                for (int p = 0; p < W; ++p) dst[p] = f[p];
+                dst[W] = vv[j];
+            } else {
+                // final match, indexed by query vertex, original IDs
+                int32_t *dst = a.out + o * (W + 1);
+#pragma unroll
+                for (int q = 0; q < W + 1; ++q) {
+                    const int p = a.P.pos[q];
+                    int32_t x = vv[j];
+#pragma unroll
+                    for (int t = 0; t < W; ++t)
+                        if (t == p) x = f[t];
+                    dst[q] = a.inv_rank[x];
+                }
+            }
+            ++o;
+        }
+    }
+}
+
+// k == 2: every valid level-2 row is a match.
+__global__ __launch_bounds__(kT) void k_edge_sink(GraphDev g, DevPlan P, int64_t e0, int64_t e1, int mode,
+                                                  int32_t *out, const int32_t *inv_rank, Ctrl *ctrl) {
+    __shared__ unsigned long long s_red[3][kT / 64];
+    __shared__ int32_t s_cnt[kT / 64];
+    __shared__ unsigned long long s_base;
+    const int64_t e = e0 + (int64_t)blockIdx.x * kT + threadIdx.x;
+    bool ok = false;
+    int32_t f[2] = {0, 0};
+    if (e < e1) {
+        f[0] = g.src[e];
+        f[1] = g.col[e];
+        ok = level2_ok(f, P);
+    }
+    const int wv = threadIdx.x >> 6;
+    if (mode == MODE_COUNT) {
+        unsigned long long c = ok ? 1 : 0, h = ok ? mix64(mix64(edge_key(f[0], f[1]))) : 0;
+        unsigned long long cs = wave_sum_u64(c), hs = wave_sum_u64(h), hx = wave_xor_u64(h);
+        if (__lane_id() == 0) {
+            s_red[0][wv] = cs;
+            s_red[1][wv] = hs;
+            s_red[2][wv] = hx;
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            unsigned long long a = 0, s = 0, x = 0;
+            for (int q = 0; q < kT / 64; ++q) {
+                a += s_red[0][q];
+                s += s_red[1][q];
+                x ^= s_red[2][q];
+            }
+            if (a) {
+                atomicAdd(&ctrl->acc[0], a);
+                atomicAdd(&ctrl->acc[1], s);
+                atomicXor(&ctrl->acc[2], x);
+                atomicAdd(&ctrl->level[1], a);
+            }
+        }
+    } else {
+        uint64_t m = __ballot(ok);
+        const int lane = __lane_id();
+        if (lane == 0) s_cnt[wv] = __popcll(m);
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            int t = 0;
+            for (int q = 0; q < kT / 64; ++q) t += s_cnt[q];
+            s_base = t ? atomicAdd(&ctrl->qcount[HUGE_KMAX], (unsigned long long)t) : 0;
+            if (t) atomicAdd(&ctrl->level[1], (unsigned long long)t);
+        }
+        __syncthreads();
+        if (ok) {
+            int wb = 0;
+            for (int q = 0; q < wv; ++q) wb += s_cnt[q];
+            int64_t o = (int64_t)s_base + wb + __popcll(m & ((lane == 0) ? 0ull : (~0ull >> (64 - lane))));
+            // row indexed by query vertex: vertex q sits at position pos[q]
+            const int32_t a0 = P.pos[0] == 0 ? f[0] : f[1];
+            const int32_t a1 = P.pos[1] == 0 ? f[0] : f[1];
+            out[o * 2 + 0] = inv_rank[a0];
+            out[o * 2 + 1] = inv_rank[a1];
+        }
+    }
+}
+
+__global__ __launch_bounds__(kT) void k_root_count(int64_t n, DevPlan P, Ctrl *ctrl) {
+    __shared__ unsigned long long s[kT / 64];
+    const int64_t v = (int64_t)blockIdx.x * kT + threadIdx.x;
+    unsigned long long c = (v < n && in_slice((int32_t)v, P)) ? 1 : 0;
+    c = wave_sum_u64(c);
+    if (__lane_id() == 0) s[threadIdx.x >> 6] = c;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned long long t = 0;
+        for (int q = 0; q < kT / 64; ++q) t += s[q];
+        if (t) atomicAdd(&ctrl->level[0], t);
+    }
+}
+
+template <int W>
+void prepare_w(bool last, const GraphDev &g, const DevPlan &P, const int32_t *rows, int64_t row0, int64_t nrows,
+               const SegBufs &s, Ctrl *ctrl, hipStream_t st) {
+    dim3 grid((unsigned)((nrows + kT - 1) / kT));
+    if (last)
+        hipLaunchKernelGGL((k_prepare<W, true>), grid, dim3(kT), 0, st, rows, row0, nrows, g, P, s, ctrl);
+    else
+        hipLaunchKernelGGL((k_prepare<W, false>), grid, dim3(kT), 0, st, rows, row0, nrows, g, P, s, ctrl);
+}
+
+template <int W>
+void extend_w(int mode, const ExtArgs &a, hipStream_t st) {
+    const int64_t items = a.w1 - a.w0;
+    dim3 grid((unsigned)((items + kTile - 1) / kTile));
+    if (mode == MODE_COUNT)
+        hipLaunchKernelGGL((k_extend<W, MODE_COUNT>), grid, dim3(kT), 0, st, a);
+    else if (mode == MODE_EMIT)
+        hipLaunchKernelGGL((k_extend<W, MODE_EMIT>), grid, dim3(kT), 0, st, a);
+    else
+        hipLaunchKernelGGL((k_extend<W, MODE_OUTPUT>), grid, dim3(kT), 0, st, a);
+}
+
+}  // namespace
+
+void launch_prepare(int width, bool last, const GraphDev &g, const DevPlan &P, const int32_t *rows, int64_t row0,
+                    int64_t nrows, const SegBufs &s, Ctrl *ctrl, hipStream_t st) {
+    if (nrows <= 0) return;
+    switch (width) {
+        case 2: prepare_w<2>(last, g, P, rows, row0, nrows, s, ctrl, st); break;
+        case 3: prepare_w<3>(last, g, P, rows, row0, nrows, s, ctrl, st); break;
+        case 4: prepare_w<4>(last, g, P, rows, row0, nrows, s, ctrl, st); break;
+        case 5: prepare_w<5>(last, g, P, rows, row0, nrows, s, ctrl, st); break;
+        case 6: prepare_w<6>(last, g, P, rows, row0, nrows, s, ctrl, st); break;
+        case 7: prepare_w<7>(last, g, P, rows, row0, nrows, s, ctrl, st); break;
+        default: HUGE_FAIL(HUGE_EINVAL, "bad width %d", width);
+    }
+    HUGE_HIP(hipGetLastError());
+}
+
+void launch_scan_bounds(const SegBufs &s, int64_t nrows, int64_t *tmp, hipStream_t st) {
+    scan_excl(s.bound, s.off, nrows, s.off + nrows, tmp, st);
+    HUGE_HIP(hipGetLastError());
+}
+
+void launch_extend(int width, int mode, const GraphDev &g, const DevPlan &P, const int32_t *rows, int64_t row0,
+                   const SegBufs &s, int64_t nrows, int64_t w0, int64_t w1, int32_t *out_rows, Ctrl *ctrl,
+                   const int32_t *inv_rank, hipStream_t st) {
+    if (w1 <= w0) return;
+    ExtArgs a;
+    a.rows = rows;
+    a.row0 = row0;
+    a.off = s.off;
+    a.pinfo = s.pinfo;
+    a.hpre = s.hpre;
+    a.nrows = nrows;
+    a.w0 = w0;
+    a.w1 = w1;
+    a.out = out_rows;
+    a.ctrl = ctrl;
+    a.inv_rank = inv_rank;
+    a.g = g;
+    a.P = P;
+    switch (width) {
+        case 2: extend_w<2>(mode, a, st); break;
+        case 3: extend_w<3>(mode, a, st); break;
+        case 4: extend_w<4>(mode, a, st); break;
+        case 5: extend_w<5>(mode, a, st); break;
+        case 6: extend_w<6>(mode, a, st); break;
+        case 7: extend_w<7>(mode, a, st); break;
+        default: HUGE_FAIL(HUGE_EINVAL, "bad width %d", width);
+    }
+    HUGE_HIP(hipGetLastError());
+}
+
+void launch_edge_sink(const GraphDev &g, const DevPlan &P, int64_t e0, int64_t e1, int mode, int32_t *out,
+                      const int32_t *inv_rank, Ctrl *ctrl, hipStream_t st) {
+    if (e1 <= e0) return;
+    dim3 grid((unsigned)((e1 - e0 + kT - 1) / kT));
+    hipLaunchKernelGGL(k_edge_sink, grid, dim3(kT), 0, st, g, P, e0, e1, mode, out, inv_rank, ctrl);
+    HUGE_HIP(hipGetLastError());
+}
+
+void launch_root_count(const GraphDev &g, const DevPlan &P, Ctrl *ctrl, hipStream_t st) {
+    dim3 grid((unsigned)((g.n + kT - 1) / kT));
+    hipLaunchKernelGGL(k_root_count, grid, dim3(kT), 0, st, g.n, P, ctrl);
+    HUGE_HIP(hipGetLastError());
+}
+
+}  // namespace huge

@@ -1,0 +1,167 @@
+// Internal declarations shared by the library's translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstdio>
+#include <string>
+#include <vector>
+
+#include "../../include/huge.h"
+
+namespace huge {
+
+// ---------------------------------------------------------------------------
+// errors
+// ---------------------------------------------------------------------------
+void set_error(const char *fmt, ...);
+
+struct Error {
+    huge_status st;
+};
+
+#define HUGE_HIP(call)                                                                              \
+    do {                                                                                            \
+        hipError_t e_ = (call);                                                                     \
+        if (e_ != hipSuccess) {                                                                     \
+            ::huge::set_error("%s failed: %s (%s:%d)", #call, hipGetErrorString(e_), __FILE__, __LINE__); \
+            throw ::huge::Error{e_ == hipErrorOutOfMemory ? HUGE_ENOMEM : HUGE_EDEVICE};              \
+        }                                                                                           \
+    } while (0)
+
+#define HUGE_FAIL(status, ...)                 \
+    do {                                       \
+        ::huge::set_error(__VA_ARGS__);        \
+        throw ::huge::Error{status};           \
+    } while (0)
+
+// ---------------------------------------------------------------------------
+// device graph (relabelled by degree rank: vertex IDs are ranks)
+// ---------------------------------------------------------------------------
+struct GraphDev {
+    int64_t n;
+    int64_t nnz;
+    const int64_t *rp;   // [n+1]
+    const int32_t *col;  // [nnz], each list strictly ascending
+    const int32_t *src;  // [nnz], src[e] = the row that holds entry e
+};
+
+}  // namespace huge
+
+struct huge_graph {
+    huge::GraphDev dev;
+    int64_t *rp = nullptr;
+    int32_t *col = nullptr;
+    int32_t *src = nullptr;
+    int32_t *inv_rank = nullptr;  // rank -> original ID
+    huge_graph_info info{};
+    int device = 0;
+    std::string sha;  // content digest of the relabelled CSR (autotune cache key)
+};
+
+namespace huge {
+
+// ---------------------------------------------------------------------------
+// plan: one PULL-EXTEND step per new query-vertex position i = 1..k-1
+// ---------------------------------------------------------------------------
+struct DevStep {
+    uint32_t ext;   // positions p < i adjacent to position i in q (lists to intersect)
+    uint32_t lo;    // positions p with constraint f[p] < v
+    uint32_t hi;    // positions p with constraint v < f[p]
+    uint32_t neq;   // positions p < i not in ext (injectivity checks)
+    int32_t slice;  // 1 if position i holds query vertex 0 (root-slice filter)
+    int32_t pad;
+};
+
+struct DevPlan {
+    int32_t k;
+    int32_t ne;                 // query edges, as position pairs ea < eb
+    uint8_t ea[32], eb[32];
+    uint8_t pos[HUGE_KMAX];     // pos[v] = position of query vertex v
+    DevStep st[HUGE_KMAX];      // st[i], i = 1..k-1
+    uint32_t slice_count, slice_id;
+};
+
+}  // namespace huge
+
+struct huge_plan {
+    int32_t k = 0;
+    std::vector<std::pair<int, int>> edges;  // query edges (a < b)
+    int adj[HUGE_KMAX][HUGE_KMAX] = {};
+    std::vector<std::pair<int, int>> sb;     // a < b constraints (query vertex IDs)
+    int32_t naut = 0;
+    int32_t order[HUGE_KMAX] = {};
+    double est_cost = 0;                     // sum over prefixes of estimated partial matches
+    double est_prefix[HUGE_KMAX] = {};       // estimated partial matches per prefix size
+    uint32_t flags = 0;
+    huge::DevPlan dev{};
+};
+
+namespace huge {
+
+// plan.cpp
+void plan_build(const huge_graph *g, int k, int ne, const int32_t *qe, const int32_t *order, uint32_t flags,
+                huge_plan *out);
+bool order_connected(const huge_plan &p, const int32_t *order);
+void plan_set_order(huge_plan &p, const int32_t *order);
+double estimate_prefix(const huge_graph_info &gi, const huge_plan &p, const int32_t *order, int size);
+void all_connected_orders(const huge_plan &p, std::vector<std::vector<int32_t>> &out);
+
+// graph.hip
+huge_graph *graph_load(int64_t n, int64_t nnz, const int64_t *rp, const int32_t *col, uint32_t flags,
+                       hipStream_t stream);
+void graph_free(huge_graph *g);
+
+// engine.cpp
+struct ExecStats {
+    uint64_t launches = 0;
+    uint64_t steals = 0;
+    uint64_t peak_frontier_bytes = 0;
+};
+struct EmitSink {
+    int32_t *host_buf = nullptr;
+    int64_t buf_rows = 0;
+    huge_emit_fn cb = nullptr;
+    void *user = nullptr;
+    bool stopped = false;
+    uint64_t delivered = 0;
+};
+uint64_t workspace_bytes(const huge_graph *g, const huge_plan *p, const huge_exec_opts &o);
+void run_levels(const huge_graph *g, const huge_plan *p, const huge_exec_opts &o, huge_result *out, EmitSink *emit);
+void run_persistent(const huge_graph *g, const huge_plan *const *plans, int np, const huge_exec_opts &o,
+                    huge_result *outs);
+
+// ---------------------------------------------------------------------------
+// kernel launchers (extend.hip)
+// ---------------------------------------------------------------------------
+struct SegBufs {
+    int64_t *off;       // [cap+1] exclusive scan of bounds, then total
+    uint64_t *pinfo;    // [cap] probe begin (low 56 bits) | probe position << 56
+    uint64_t *hpre;     // [cap] prefix hash (last level only)
+    int32_t *bound;     // [cap]
+    int64_t cap;
+};
+
+struct Ctrl {                      // device-resident counters
+    unsigned long long qcount[HUGE_KMAX + 1];   // rows in the queue of level i
+    unsigned long long level[HUGE_KMAX];        // level_counts
+    unsigned long long acc[4];                  // count, hash_sum, hash_xor, overflow flag
+    long long scratch[8];
+};
+
+void launch_prepare(int width, bool last, const GraphDev &g, const DevPlan &P, const int32_t *rows, int64_t row0,
+                    int64_t nrows, const SegBufs &s, Ctrl *ctrl, hipStream_t st);
+void launch_scan_bounds(const SegBufs &s, int64_t nrows, int64_t *tmp, hipStream_t st);
+void launch_extend(int width, int mode, const GraphDev &g, const DevPlan &P, const int32_t *rows, int64_t row0,
+                   const SegBufs &s, int64_t nrows, int64_t w0, int64_t w1, int32_t *out_rows, Ctrl *ctrl,
+                   const int32_t *inv_rank, hipStream_t st);
+void launch_edge_sink(const GraphDev &g, const DevPlan &P, int64_t e0, int64_t e1, int mode, int32_t *out,
+                      const int32_t *inv_rank, Ctrl *ctrl, hipStream_t st);
+void launch_root_count(const GraphDev &g, const DevPlan &P, Ctrl *ctrl, hipStream_t st);
+int64_t scan_tmp_elems(int64_t n);
+
+// extend modes
+enum { MODE_EMIT = 0, MODE_COUNT = 1, MODE_OUTPUT = 2 };
+
+}  // namespace huge

@@ -1,0 +1,256 @@
+// Query planning (host): validation, automorphisms, symmetry-breaking
+// constraints, matching orders, the PULL-EXTEND step table and the plain
+// cost-model plan.
+//
+// The execution plan is the worst-case-optimal left-deep chain of Section 3.1
+// (BiGJoin as complete star joins on induced prefixes, Definition 3.1): for a
+// matching order pi, step i extends partial matches of the induced prefix
+// {pi_0..pi_{i-1}} by pi_i, intersecting the neighbour lists of the matched
+// vertices adjacent to pi_i (Eq. 2, PULL-EXTEND's extend index in Section 4.2).
+// Every step is a complete star join, which Eq. 3 sets to (wco join, pull).
+//
+// Cost model: Algorithm 1's cost of a plan is the sum of the result sizes of
+// its joins plus communication; for left-deep wco plans on one device the
+// communication term is the same for every order and drops out, leaving
+// cost(pi) = sum over prefixes of |R(prefix)|.  The paper leaves the
+// cardinality estimator open; this one uses the Chung-Lu expected-degree
+// model: the expected number of injective maps of a pattern H is
+// prod_v M_{deg_H(v)} / (2m)^{|E_H|} with M_p = sum_u d_u^p, scaled by the
+// fraction of vertex orderings of H that satisfy the symmetry-breaking
+// constraints inside H.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+
+#include "internal.h"
+
+namespace huge {
+
+namespace {
+
+void check_query(int k, int ne, const int32_t *qe, huge_plan *p) {
+    if (k < 2 || k > HUGE_KMAX) HUGE_FAIL(HUGE_EQUERY, "query must have 2..8 vertices (k=%d)", k);
+    if (ne < 1 || ne > k * (k - 1) / 2 || !qe) HUGE_FAIL(HUGE_EQUERY, "bad number of query edges (%d)", ne);
+    memset(p->adj, 0, sizeof(p->adj));
+    p->edges.clear();
+    for (int i = 0; i < ne; ++i) {
+        int a = qe[2 * i], b = qe[2 * i + 1];
+        if (a < 0 || b < 0 || a >= k || b >= k) HUGE_FAIL(HUGE_EQUERY, "query edge %d has a vertex out of range", i);
+        if (a == b) HUGE_FAIL(HUGE_EQUERY, "query edge %d is a self-loop", i);
+        if (p->adj[a][b]) HUGE_FAIL(HUGE_EQUERY, "query edge %d is a duplicate", i);
+        p->adj[a][b] = p->adj[b][a] = 1;
+        p->edges.push_back({std::min(a, b), std::max(a, b)});
+    }
+    // connected?
+    int seen = 1, stack[HUGE_KMAX], sp = 0;
+    stack[sp++] = 0;
+    int mark[HUGE_KMAX] = {1};
+    while (sp) {
+        int a = stack[--sp];
+        for (int b = 0; b < k; ++b)
+            if (p->adj[a][b] && !mark[b]) {
+                mark[b] = 1;
+                ++seen;
+                stack[sp++] = b;
+            }
+    }
+    if (seen != k) HUGE_FAIL(HUGE_EQUERY, "query is not connected");
+    p->k = k;
+}
+
+// Automorphism group by testing every permutation (k <= 8).
+std::vector<std::vector<int8_t>> automorphisms(const huge_plan &p) {
+    std::vector<std::vector<int8_t>> out;
+    std::vector<int8_t> perm(p.k);
+    for (int i = 0; i < p.k; ++i) perm[i] = (int8_t)i;
+    do {
+        bool ok = true;
+        for (auto &e : p.edges)
+            if (!p.adj[perm[e.first]][perm[e.second]]) {
+                ok = false;
+                break;
+            }
+        if (ok) out.push_back(perm);
+    } while (std::next_permutation(perm.begin(), perm.end()));
+    return out;
+}
+
+// Grochow-Kellis symmetry breaking (RECOMB 2007): repeatedly pick, among the
+// vertices with the largest orbit under the remaining group, the one with the
+// smallest ID; constrain it below the rest of its orbit; keep its stabiliser.
+void grochow_kellis(huge_plan &p) {
+    auto group = automorphisms(p);
+    p.naut = (int32_t)group.size();
+    p.sb.clear();
+    while (group.size() > 1) {
+        int best = -1;
+        size_t best_sz = 0;
+        std::vector<int> best_orbit;
+        for (int v = 0; v < p.k; ++v) {
+            bool in[HUGE_KMAX] = {};
+            for (auto &s : group) in[(int)s[v]] = true;
+            std::vector<int> orb;
+            for (int w = 0; w < p.k; ++w)
+                if (in[w]) orb.push_back(w);
+            if (orb.size() > best_sz) {
+                best_sz = orb.size();
+                best = v;
+                best_orbit = orb;
+            }
+        }
+        for (int w : best_orbit)
+            if (w != best) p.sb.push_back({best, w});
+        std::vector<std::vector<int8_t>> stab;
+        for (auto &s : group)
+            if (s[best] == best) stab.push_back(s);
+        group.swap(stab);
+    }
+}
+
+// Fraction of the |S|! orderings of the vertex set S that satisfy every
+// constraint with both ends in S.
+double sb_fraction(const huge_plan &p, const int32_t *verts, int m) {
+    std::vector<std::pair<int, int>> cons;
+    for (auto &c : p.sb) {
+        int ia = -1, ib = -1;
+        for (int i = 0; i < m; ++i) {
+            if (verts[i] == c.first) ia = i;
+            if (verts[i] == c.second) ib = i;
+        }
+        if (ia >= 0 && ib >= 0) cons.push_back({ia, ib});
+    }
+    if (cons.empty()) return 1.0;
+    std::vector<int> perm(m);  // perm[i] = rank position of local vertex i
+    for (int i = 0; i < m; ++i) perm[i] = i;
+    long long good = 0, tot = 0;
+    do {
+        ++tot;
+        bool ok = true;
+        for (auto &c : cons)
+            if (perm[c.first] > perm[c.second]) {
+                ok = false;
+                break;
+            }
+        if (ok) ++good;
+    } while (std::next_permutation(perm.begin(), perm.end()));
+    return (double)good / (double)tot;
+}
+
+}  // namespace
+
+bool order_connected(const huge_plan &p, const int32_t *order) {
+    bool used[HUGE_KMAX] = {};
+    for (int i = 0; i < p.k; ++i) {
+        if (order[i] < 0 || order[i] >= p.k || used[order[i]]) return false;
+        used[order[i]] = true;
+    }
+    for (int i = 1; i < p.k; ++i) {
+        bool adj = false;
+        for (int j = 0; j < i; ++j) adj |= p.adj[order[j]][order[i]] != 0;
+        if (!adj) return false;
+    }
+    return true;
+}
+
+void all_connected_orders(const huge_plan &p, std::vector<std::vector<int32_t>> &out) {
+    out.clear();
+    std::vector<int32_t> perm(p.k);
+    for (int i = 0; i < p.k; ++i) perm[i] = i;
+    do {
+        if (order_connected(p, perm.data())) out.push_back(perm);
+    } while (std::next_permutation(perm.begin(), perm.end()));
+}
+
+// Estimated partial matches of the induced prefix order[0..size-1].
+double estimate_prefix(const huge_graph_info &gi, const huge_plan &p, const int32_t *order, int size) {
+    double two_m = (double)gi.nnz;
+    if (gi.n <= 0) return 0;  // no graph statistics (host-only planning)
+    if (two_m <= 0) return 0;
+    double logv = 0;
+    int ne = 0;
+    for (int i = 0; i < size; ++i) {
+        int dv = 0;
+        for (int j = 0; j < size; ++j) dv += p.adj[order[i]][order[j]];
+        double M = gi.degree_moments[dv < 8 ? dv : 7];
+        if (M <= 0) return 0;
+        logv += std::log(M);
+    }
+    for (int i = 0; i < size; ++i)
+        for (int j = i + 1; j < size; ++j) ne += p.adj[order[i]][order[j]];
+    logv -= ne * std::log(two_m);
+    double f = sb_fraction(p, order, size);
+    return std::exp(logv) * f;
+}
+
+void plan_set_order(huge_plan &p, const int32_t *order) {
+    const int k = p.k;
+    for (int i = 0; i < k; ++i) p.order[i] = order[i];
+    DevPlan &d = p.dev;
+    memset(&d, 0, sizeof(d));
+    d.k = k;
+    int pos[HUGE_KMAX];
+    for (int i = 0; i < k; ++i) pos[order[i]] = i;
+    for (int v = 0; v < k; ++v) d.pos[v] = (uint8_t)pos[v];
+    d.ne = (int32_t)p.edges.size();
+    for (size_t e = 0; e < p.edges.size(); ++e) {
+        int a = pos[p.edges[e].first], b = pos[p.edges[e].second];
+        d.ea[e] = (uint8_t)std::min(a, b);
+        d.eb[e] = (uint8_t)std::max(a, b);
+    }
+    for (int i = 1; i < k; ++i) {
+        DevStep &s = d.st[i];
+        for (int j = 0; j < i; ++j) {
+            if (p.adj[order[j]][order[i]]) s.ext |= 1u << j;
+        }
+        s.neq = ((1u << i) - 1) & ~s.ext;
+        s.slice = order[i] == 0 ? 1 : 0;
+        for (auto &c : p.sb) {
+            int pa = pos[c.first], pb = pos[c.second];
+            // constraint f(first) < f(second), checked when the later one is placed
+            if (pb == i && pa < i) s.lo |= 1u << pa;
+            if (pa == i && pb < i) s.hi |= 1u << pb;
+        }
+    }
+    // position 0's slice flag lives in st[0]
+    d.st[0].slice = order[0] == 0 ? 1 : 0;
+    p.est_cost = 0;
+    for (int s = 1; s <= k; ++s) p.est_prefix[s - 1] = 0;
+    return;
+}
+
+void plan_build(const huge_graph *g, int k, int ne, const int32_t *qe, const int32_t *order, uint32_t flags,
+                huge_plan *p) {
+    static const huge_graph_info no_stats{};
+    const huge_graph_info &gi = g ? g->info : no_stats;
+    check_query(k, ne, qe, p);
+    grochow_kellis(*p);
+    p->flags = flags;
+    std::vector<int32_t> chosen(k);
+    if (order) {
+        if (!order_connected(*p, order))
+            HUGE_FAIL(HUGE_EORDER, "order is not a permutation of 0..k-1 with connected prefixes");
+        for (int i = 0; i < k; ++i) chosen[i] = order[i];
+    } else {
+        // plain cost-model plan: minimum estimated total partial matches,
+        // ties to the lexicographically smallest order
+        std::vector<std::vector<int32_t>> orders;
+        all_connected_orders(*p, orders);
+        double best = INFINITY;
+        for (auto &o : orders) {
+            double c = 0;
+            for (int s = 2; s <= k; ++s) c += estimate_prefix(gi, *p, o.data(), s);
+            if (c < best * (1 - 1e-12)) {
+                best = c;
+                chosen = o;
+            }
+        }
+    }
+    plan_set_order(*p, chosen.data());
+    p->est_cost = 0;
+    for (int s = 1; s <= k; ++s) {
+        p->est_prefix[s - 1] = estimate_prefix(gi, *p, chosen.data(), s);
+        if (s >= 2) p->est_cost += p->est_prefix[s - 1];
+    }
+}
+
+}  // namespace huge
