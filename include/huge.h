@@ -61,6 +61,7 @@ typedef struct huge_plan huge_plan;
 #define HUGE_HOST_PTRS 0x1u   /* row_ptr / col are host memory (copied) */
 #define HUGE_DEVICE_PTRS 0x2u /* row_ptr / col are device memory (read, not kept) */
 #define HUGE_NO_VALIDATE 0x4u /* skip the hygiene checks (caller guarantees a clean CSR) */
+#define HUGE_NO_HUB_BITMAP 0x8u /* do not build adjacency bitmaps for the highest-degree vertices */
 
 /* huge_plan flags */
 #define HUGE_PLAN_COST_MODEL 0x0u /* order from the cost model (Algorithm 1, wco plans) */
@@ -80,7 +81,20 @@ typedef struct {
     uint64_t peak_frontier_bytes;      /* largest device bytes held by intermediate partial matches */
     uint64_t launches;                 /* kernel launches issued */
     uint64_t steals;                   /* successful steals (persistent engine) */
+    /* filled when huge_exec_opts.profile != 0 (HIP events on the exec stream),
+       per kernel class HUGE_KC_*: summed device time, launches, and the
+       algorithmic bytes of the work those launches did: a merge intersection
+       over symmetry-breaking-trimmed lists moves 4i + 16j + 4 * (sum of the
+       trimmed list lengths) bytes per input row of width i with j
+       intersected lists, plus 4(i+1) bytes per emitted row */
+    double kernel_ms[4];
+    uint64_t kernel_launches[4];
+    double alg_bytes[4];
 } huge_result;
+#define HUGE_KC_PREPARE 0 /* SB window trim + probe choice */
+#define HUGE_KC_SCAN 1    /* exclusive scan of per-row bounds */
+#define HUGE_KC_EXTEND 2  /* intersection + filters + compaction into the next level */
+#define HUGE_KC_SINK 3    /* last-level intersection + filters + counting SINK (or output) */
 /*
  * h(g) = mix( sum over query edges (a,b) of mix(edge(f(a), f(b))) ) with
  * edge(x, y) = (min(rx, ry) << 32) | max(rx, ry), rx the degree rank of x,
@@ -97,12 +111,18 @@ typedef struct {
     int32_t engine;              /* HUGE_ENGINE_* */
     int32_t work_stealing;       /* persistent engine: 1 = steal, 0 = static root split only */
     int32_t deterministic;       /* reserved: results are exact and order-free either way */
-    uint32_t slice_count;        /* root slice: keep matches with mix(rank(f(0))) % slice_count == slice_id */
-    uint32_t slice_id;           /* (query vertex 0's image); slice_count 0 or 1 = everything */
+    uint32_t slice_count;        /* root slice: keep matches with mix(rank(f(s))) % slice_count == slice_id, */
+    uint32_t slice_id;           /* s = slice_vertex; slice_count 0 or 1 = everything */
     void *stream;                /* hipStream_t; NULL = the null stream */
     void *workspace;             /* caller-owned device memory, or NULL = library allocates */
     uint64_t workspace_bytes;
+    int32_t profile;             /* 1 = time every launch with HIP events (kernel_ms etc.) */
+    int32_t slice_vertex;        /* query vertex whose image is sliced (default 0); slices of any fixed
+                                    vertex partition the matches, so counts add and hashes add / xor */
+    uint32_t exec_flags;         /* HUGE_EXEC_* bits */
+    uint32_t reserved;
 } huge_exec_opts;
+#define HUGE_EXEC_NO_HASH 0x1u /* count only: hash_sum / hash_xor are left 0 */
 
 /* Default options: frontier cap 4 GiB, autotuned chunk and strategy, AUTO engine, no slice. */
 huge_status huge_exec_opts_default(huge_exec_opts *opts);
@@ -116,7 +136,11 @@ huge_status huge_exec_opts_default(huge_exec_opts *opts);
  *   flags    : HUGE_HOST_PTRS or HUGE_DEVICE_PTRS, optionally | HUGE_NO_VALIDATE
  *   stream   : hipStream_t for the load kernels (NULL = null stream)
  * The library relabels by degree rank on the GPU, re-sorts every list and
- * builds a degree sketch; the inputs are not retained.  Errors: HUGE_EGRAPH
+ * builds a degree sketch; the inputs are not retained.  Unless
+ * HUGE_NO_HUB_BITMAP is given it also keeps an n-bit adjacency bitmap for each
+ * of the highest-degree vertices (degree >= 256, at most HUGE_HUB_BYTES bytes
+ * in total, environment variable, default 4 GiB), so that a membership test
+ * against a hub's list is one load.  Errors: HUGE_EGRAPH
  * (hygiene), HUGE_ENOMEM, HUGE_EDEVICE, HUGE_EINVAL.
  */
 huge_status huge_load_csr(int64_t n, int64_t nnz, const int64_t *row_ptr, const int32_t *col, uint32_t flags,
@@ -130,6 +154,8 @@ typedef struct {
     double degree_moments[8];   /* sum_u d_u^p, p = 0..7 */
     double load_ms;
     uint64_t device_bytes;      /* device memory held by the graph */
+    int64_t hub_count;          /* vertices with an adjacency bitmap (the highest degree ranks) */
+    int64_t hub_min_degree;     /* smallest degree among them */
 } huge_graph_info;
 huge_status huge_graph_get_info(const huge_graph *g, huge_graph_info *out);
 

@@ -48,8 +48,9 @@
  * prefix, satisfying the constraints (mode SB) whose two ends are both in the
  * prefix, and the root slice when query vertex 0 is in the prefix.
  *
- * Root slice (slice_count S, slice_id s): only maps with
- * mix(r(f(0))) mod S == s are kept.  The slices partition the results, so
+ * Root slice (slice_count S, slice_id s, slice_vertex a): only maps with
+ * mix(r(f(a))) mod S == s are kept (a = query vertex 0 by default).  The
+ * slices of any fixed query vertex partition the results, so
  * counts and sums add and xors combine over s.
  */
 #include <pthread.h>
@@ -267,11 +268,11 @@ typedef struct {
     int lt[ORC_KMAX][28];       /* positions p: need r(f[p]) < r(new) */
     int gt[ORC_KMAX][28];       /* positions p: need r(new) < r(f[p]) */
     uint32_t slice_count, slice_id;
-    int slice_pos;              /* position of query vertex 0 */
+    int slice_pos;              /* position of the sliced query vertex */
 } orc_plan;
 
 static int orc_plan_init(orc_plan *P, const orc_query *q, const orc_graph *g, int mode,
-                         const int32_t *order, uint32_t sc, uint32_t sid) {
+                         const int32_t *order, uint32_t sc, uint32_t sid, int slice_vertex) {
     memset(P, 0, sizeof(*P));
     P->q = q;
     P->g = g;
@@ -320,7 +321,8 @@ static int orc_plan_init(orc_plan *P, const orc_query *q, const orc_graph *g, in
     }
     P->slice_count = sc ? sc : 1;
     P->slice_id = sid;
-    P->slice_pos = P->pos[0];
+    if (slice_vertex < 0 || slice_vertex >= k) return -1;
+    P->slice_pos = P->pos[slice_vertex];
     return 0;
 }
 
@@ -435,7 +437,7 @@ static void *orc_thread(void *arg) {
  */
 int orc_enumerate(int64_t n, const int64_t *rp, const int32_t *col, int k, int nqe,
                   const int32_t *qedges, int mode, const int32_t *order, int nsb,
-                  const int32_t *sb_pairs, uint32_t slice_count, uint32_t slice_id, int nthreads,
+                  const int32_t *sb_pairs, uint32_t slice_count, uint32_t slice_id, int slice_vertex, int nthreads,
                   orc_result *out) {
     orc_query q;
     if (orc_query_init(&q, k, nqe, qedges) != 0) return -1;
@@ -464,7 +466,7 @@ int orc_enumerate(int64_t n, const int64_t *rp, const int32_t *col, int k, int n
     g.rank = (int32_t *)malloc(sizeof(int32_t) * (size_t)(n > 0 ? n : 1));
     orc_ranks(n, rp, g.rank);
     orc_plan P;
-    if (orc_plan_init(&P, &q, &g, mode, order, slice_count, slice_id) != 0) {
+    if (orc_plan_init(&P, &q, &g, mode, order, slice_count, slice_id, slice_vertex) != 0) {
         free(g.rank);
         free(q.aut);
         return -1;

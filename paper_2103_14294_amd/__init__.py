@@ -20,9 +20,11 @@ KMAX = 8
 HUGE_OK, HUGE_STOPPED = 0, 1
 STATUS = {0: "HUGE_OK", 1: "HUGE_STOPPED", -1: "HUGE_EINVAL", -2: "HUGE_ENOMEM", -3: "HUGE_EDEVICE",
           -4: "HUGE_EGRAPH", -5: "HUGE_EQUERY", -6: "HUGE_EORDER", -7: "HUGE_EOVERFLOW"}
-HOST_PTRS, DEVICE_PTRS, NO_VALIDATE = 0x1, 0x2, 0x4
+HOST_PTRS, DEVICE_PTRS, NO_VALIDATE, NO_HUB_BITMAP = 0x1, 0x2, 0x4, 0x8
 PLAN_COST_MODEL, PLAN_LEARNED = 0x0, 0x1
 ENGINE_AUTO, ENGINE_LEVELS, ENGINE_PERSISTENT = 0, 1, 2
+EXEC_NO_HASH = 0x1
+STRAT_BSEARCH, STRAT_WAVE_STAGED, STRAT_LANE_MERGE = 0, 1, 2
 
 EXPORTED = [
     "huge_exec_opts_default", "huge_load_csr", "huge_graph_free", "huge_graph_get_info", "huge_graph_export",
@@ -42,26 +44,32 @@ class Result(ctypes.Structure):
     _fields_ = [("count", ctypes.c_uint64), ("hash_sum", ctypes.c_uint64), ("hash_xor", ctypes.c_uint64),
                 ("level_counts", ctypes.c_uint64 * KMAX), ("query_ms", ctypes.c_double),
                 ("peak_frontier_bytes", ctypes.c_uint64), ("launches", ctypes.c_uint64),
-                ("steals", ctypes.c_uint64)]
+                ("steals", ctypes.c_uint64), ("kernel_ms", ctypes.c_double * 4),
+                ("kernel_launches", ctypes.c_uint64 * 4), ("alg_bytes", ctypes.c_double * 4)]
 
     def to_dict(self):
         return {"count": int(self.count), "hash_sum": int(self.hash_sum), "hash_xor": int(self.hash_xor),
                 "level_counts": [int(x) for x in self.level_counts], "query_ms": float(self.query_ms),
                 "peak_frontier_bytes": int(self.peak_frontier_bytes), "launches": int(self.launches),
-                "steals": int(self.steals)}
+                "steals": int(self.steals), "kernel_ms": [float(x) for x in self.kernel_ms],
+                "kernel_launches": [int(x) for x in self.kernel_launches],
+                "alg_bytes": [float(x) for x in self.alg_bytes]}
 
 
 class ExecOpts(ctypes.Structure):
     _fields_ = [("frontier_cap_bytes", ctypes.c_uint64), ("chunk_rows", ctypes.c_int64),
                 ("strategy", ctypes.c_int32), ("engine", ctypes.c_int32), ("work_stealing", ctypes.c_int32),
                 ("deterministic", ctypes.c_int32), ("slice_count", ctypes.c_uint32), ("slice_id", ctypes.c_uint32),
-                ("stream", ctypes.c_void_p), ("workspace", ctypes.c_void_p), ("workspace_bytes", ctypes.c_uint64)]
+                ("stream", ctypes.c_void_p), ("workspace", ctypes.c_void_p), ("workspace_bytes", ctypes.c_uint64),
+                ("profile", ctypes.c_int32), ("slice_vertex", ctypes.c_int32), ("exec_flags", ctypes.c_uint32),
+                ("reserved", ctypes.c_uint32)]
 
 
 class GraphInfo(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int64), ("nnz", ctypes.c_int64), ("max_degree", ctypes.c_int64),
                 ("degree_hist", ctypes.c_uint64 * 32), ("degree_moments", ctypes.c_double * 8),
-                ("load_ms", ctypes.c_double), ("device_bytes", ctypes.c_uint64)]
+                ("load_ms", ctypes.c_double), ("device_bytes", ctypes.c_uint64), ("hub_count", ctypes.c_int64),
+                ("hub_min_degree", ctypes.c_int64)]
 
 
 EMIT_FN = ctypes.CFUNCTYPE(ctypes.c_int, ctypes.c_void_p, ctypes.POINTER(ctypes.c_int32), ctypes.c_int64,
@@ -148,7 +156,8 @@ class Graph:
         return {"n": gi.n, "nnz": gi.nnz, "max_degree": gi.max_degree,
                 "degree_hist": [int(x) for x in gi.degree_hist],
                 "degree_moments": [float(x) for x in gi.degree_moments], "load_ms": gi.load_ms,
-                "device_bytes": int(gi.device_bytes)}
+                "device_bytes": int(gi.device_bytes), "hub_count": int(gi.hub_count),
+                "hub_min_degree": int(gi.hub_min_degree)}
 
     def export(self):
         rp = np.empty(self.n + 1, dtype=np.int64)
@@ -202,10 +211,10 @@ class Plan:
             pass
 
 
-def load(row_ptr, col, validate=True, stream=None) -> Graph:
+def load(row_ptr, col, validate=True, stream=None, hub_bitmaps=True) -> Graph:
     """huge_load_csr.  row_ptr/col: numpy arrays (host) or torch tensors on the GPU."""
     lib = load_library()
-    flags = 0 if validate else NO_VALIDATE
+    flags = (0 if validate else NO_VALIDATE) | (0 if hub_bitmaps else NO_HUB_BITMAP)
     keep = []
     if hasattr(row_ptr, "is_cuda") and row_ptr.is_cuda:
         torch = _torch()
@@ -242,7 +251,7 @@ def plan(g: Graph, k, edges, order=None, learned=False) -> Plan:
 
 
 def exec_opts(cap=None, chunk_rows=0, strategy=-1, engine=ENGINE_AUTO, work_stealing=1, slice_count=1, slice_id=0,
-              stream=None, workspace=None) -> ExecOpts:
+              stream=None, workspace=None, profile=False, slice_vertex=0, hash=True) -> ExecOpts:
     lib = load_library()
     o = ExecOpts()
     lib.huge_exec_opts_default(ctypes.byref(o))
@@ -254,6 +263,9 @@ def exec_opts(cap=None, chunk_rows=0, strategy=-1, engine=ENGINE_AUTO, work_stea
     o.work_stealing = int(work_stealing)
     o.slice_count = int(slice_count)
     o.slice_id = int(slice_id)
+    o.profile = 1 if profile else 0
+    o.slice_vertex = int(slice_vertex)
+    o.exec_flags = 0 if hash else EXEC_NO_HASH
     o.stream = (stream if stream is not None else _current_stream()).value \
         if not isinstance(stream, int) else stream
     if workspace is not None:

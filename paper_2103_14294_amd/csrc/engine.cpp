@@ -101,6 +101,53 @@ int64_t read_i64(const void *dev, hipStream_t st) {
 
 }  // namespace
 
+// Per-kernel-class device timing with HIP events recorded on the exec stream
+// around each launch (only when profiling is requested).
+struct Profiler {
+    bool on = false;
+    hipStream_t st = nullptr;
+    std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> ev;
+    uint64_t launches[4] = {0, 0, 0, 0};
+    double bytes[4] = {0, 0, 0, 0};
+    template <typename F>
+    void run(int cls, F &&launch) {
+        launches[cls]++;
+        if (!on) {
+            launch();
+            return;
+        }
+        hipEvent_t a, b;
+        HUGE_HIP(hipEventCreate(&a));
+        HUGE_HIP(hipEventCreate(&b));
+        ev.push_back({cls, {a, b}});
+        HUGE_HIP(hipEventRecord(a, st));
+        launch();
+        HUGE_HIP(hipEventRecord(b, st));
+    }
+    void finish(huge_result *out) {
+        for (int c = 0; c < 4; ++c) {
+            out->kernel_ms[c] = 0;
+            out->kernel_launches[c] = launches[c];
+            out->alg_bytes[c] = bytes[c];
+        }
+        if (on) HUGE_HIP(hipStreamSynchronize(st));
+        for (auto &e : ev) {
+            float ms = 0;
+            if (on) HUGE_HIP(hipEventElapsedTime(&ms, e.second.first, e.second.second));
+            out->kernel_ms[e.first] += ms;
+            (void)hipEventDestroy(e.second.first);
+            (void)hipEventDestroy(e.second.second);
+        }
+        ev.clear();
+    }
+    ~Profiler() {
+        for (auto &e : ev) {
+            (void)hipEventDestroy(e.second.first);
+            (void)hipEventDestroy(e.second.second);
+        }
+    }
+};
+
 uint64_t workspace_bytes(const huge_graph *g, const huge_plan *p, const huge_exec_opts &o) {
     return make_layout(g, p, o, 1 << 16).total;
 }
@@ -113,6 +160,8 @@ void run_levels(const huge_graph *g, const huge_plan *p, const huge_exec_opts &o
     P.slice_count = o.slice_count > 1 ? o.slice_count : 1;
     P.slice_id = o.slice_count > 1 ? o.slice_id : 0;
     if (P.slice_count > 1 && P.slice_id >= P.slice_count) HUGE_FAIL(HUGE_EINVAL, "slice_id >= slice_count");
+    if (o.slice_vertex < 0 || o.slice_vertex >= k) HUGE_FAIL(HUGE_EINVAL, "slice_vertex out of range");
+    for (int i = 0; i < k; ++i) P.st[i].slice = p->order[i] == o.slice_vertex ? 1 : 0;
 
     int64_t stage_rows = 0;
     if (emit) {
@@ -136,6 +185,7 @@ void run_levels(const huge_graph *g, const huge_plan *p, const huge_exec_opts &o
     struct Lv {
         int64_t nrows = 0, next = 0;
         int64_t seg_row0 = 0, seg_n = 0, seg_total = 0, seg_done = 0;
+        double seg_bytes = 0;
         SegBufs s{};
         int32_t *q = nullptr;
         int64_t qcap = 0;
@@ -158,7 +208,12 @@ void run_levels(const huge_graph *g, const huge_plan *p, const huge_exec_opts &o
 
     HUGE_HIP(hipMemsetAsync(ctrl, 0, sizeof(Ctrl), st));
     ExecStats stats;
+    Profiler prof;
+    prof.on = o.profile != 0;
+    prof.st = st;
     const GraphDev &G = g->dev;
+    const int strat = (o.strategy >= 0 && o.strategy < STRAT_COUNT) ? o.strategy : STRAT_LANE_MERGE;
+    const int count_mode = (o.exec_flags & HUGE_EXEC_NO_HASH) ? MODE_COUNT_NOHASH : MODE_COUNT;
     const bool root_slice = P.slice_count > 1 && P.st[0].slice;
     if (root_slice) {
         launch_root_count(G, P, ctrl, st);
@@ -212,12 +267,19 @@ void run_levels(const huge_graph *g, const huge_plan *p, const huge_exec_opts &o
                 if (l.seg_done == l.seg_total) {
                     if (l.next == l.nrows) break;
                     int64_t cnt = std::min(l.s.cap, l.nrows - l.next);
-                    launch_prepare(W, W == lastW, G, P, lv[W].q, l.next, cnt, l.s, ctrl, st);
-                    launch_scan_bounds(l.s, cnt, scan_tmp, st);
+                    HUGE_HIP(hipMemsetAsync(&ctrl->segbytes[W], 0, 8, st));
+                    prof.run(HUGE_KC_PREPARE,
+                             [&] { launch_prepare(W, W == lastW, G, P, lv[W].q, l.next, cnt, l.s, ctrl, st); });
+                    prof.run(HUGE_KC_SCAN, [&] { launch_scan_bounds(l.s, cnt, scan_tmp, st); });
                     stats.launches += 2;
                     l.seg_row0 = l.next;
                     l.seg_n = cnt;
-                    l.seg_total = read_i64(l.s.off + cnt, st);
+                    int64_t hv[2] = {0, 0};
+                    HUGE_HIP(hipMemcpyAsync(&hv[0], l.s.off + cnt, 8, hipMemcpyDeviceToHost, st));
+                    HUGE_HIP(hipMemcpyAsync(&hv[1], &ctrl->segbytes[W], 8, hipMemcpyDeviceToHost, st));
+                    HUGE_HIP(hipStreamSynchronize(st));
+                    l.seg_total = hv[0];
+                    l.seg_bytes = (double)(uint64_t)hv[1];
                     l.seg_done = 0;
                     l.next += cnt;
                     if (l.seg_total == 0) continue;
@@ -226,14 +288,19 @@ void run_levels(const huge_graph *g, const huge_plan *p, const huge_exec_opts &o
                 if (W == lastW) {
                     if (!emit) {
                         int64_t chunk = std::min(remaining, kMaxItems);
-                        launch_extend(W, MODE_COUNT, G, P, l.q, l.seg_row0, l.s, l.seg_n, l.seg_done,
-                                      l.seg_done + chunk, nullptr, ctrl, g->inv_rank, st);
+                        prof.run(HUGE_KC_SINK, [&] {
+                            launch_extend(W, count_mode, strat, G, P, l.q, l.seg_row0, l.s, l.seg_n, l.seg_done,
+                                          l.seg_done + chunk, nullptr, ctrl, g->inv_rank, st);
+                        });
+                        prof.bytes[HUGE_KC_SINK] += l.seg_bytes * (double)chunk / (double)l.seg_total;
                         stats.launches++;
                         l.seg_done += chunk;
                     } else {
                         int64_t chunk = std::min(remaining, stage_rows);
-                        launch_extend(W, MODE_OUTPUT, G, P, l.q, l.seg_row0, l.s, l.seg_n, l.seg_done,
-                                      l.seg_done + chunk, stage, ctrl, g->inv_rank, st);
+                        prof.run(HUGE_KC_SINK, [&] {
+                            launch_extend(W, MODE_OUTPUT, strat, G, P, l.q, l.seg_row0, l.s, l.seg_n, l.seg_done,
+                                          l.seg_done + chunk, stage, ctrl, g->inv_rank, st);
+                        });
                         stats.launches++;
                         l.seg_done += chunk;
                         int64_t nout = read_i64(&ctrl->qcount[HUGE_KMAX], st);
@@ -249,11 +316,15 @@ void run_levels(const huge_graph *g, const huge_plan *p, const huge_exec_opts &o
                     const int64_t free = q.qcap - q.nrows;
                     if (free <= 0 || (free < remaining && free < q.qcap / 8)) break;  // Q_O full: yield
                     const int64_t chunk = std::min(std::min(free, remaining), kMaxItems);
-                    launch_extend(W, MODE_EMIT, G, P, l.q, l.seg_row0, l.s, l.seg_n, l.seg_done, l.seg_done + chunk,
-                                  q.q, ctrl, g->inv_rank, st);
+                    prof.run(HUGE_KC_EXTEND, [&] {
+                        launch_extend(W, MODE_EMIT, strat, G, P, l.q, l.seg_row0, l.s, l.seg_n, l.seg_done,
+                                      l.seg_done + chunk, q.q, ctrl, g->inv_rank, st);
+                    });
                     stats.launches++;
                     l.seg_done += chunk;
                     int64_t nr = read_i64(&ctrl->qcount[W + 1], st);
+                    prof.bytes[HUGE_KC_EXTEND] +=
+                        l.seg_bytes * (double)chunk / (double)l.seg_total + 4.0 * (W + 1) * (double)(nr - q.nrows);
                     cur_bytes += (uint64_t)(nr - q.nrows) * 4ull * (W + 1);
                     q.nrows = nr;
                     stats.peak_frontier_bytes = std::max(stats.peak_frontier_bytes, cur_bytes);
@@ -278,6 +349,7 @@ void run_levels(const huge_graph *g, const huge_plan *p, const huge_exec_opts &o
     if (!root_slice) out->level_counts[0] = (uint64_t)G.n;
     out->peak_frontier_bytes = stats.peak_frontier_bytes;
     out->launches = stats.launches;
+    prof.finish(out);
     auto t1 = std::chrono::steady_clock::now();
     out->query_ms = std::chrono::duration<double, std::milli>(t1 - t0).count();
 }

@@ -64,6 +64,15 @@ __device__ __forceinline__ bool contains(const int32_t *__restrict__ col, int64_
     return false;
 }
 
+// v in N(x): one bitmap load for a hub, a binary search otherwise
+__device__ __forceinline__ bool adj_has(const GraphDev &g, int32_t x, int32_t v) {
+    if (x >= g.hub_base) {
+        const uint32_t word = g.hub_bm[(int64_t)(x - g.hub_base) * g.hub_words + (v >> 5)];
+        return (word >> (v & 31)) & 1u;
+    }
+    return contains(g.col, g.rp[x], g.rp[x + 1], v);
+}
+
 template <int W>
 __device__ __forceinline__ void load_row(const int32_t *__restrict__ rows, const GraphDev &g, int64_t r,
                                          int32_t (&f)[W]) {
@@ -111,9 +120,12 @@ template <int W, bool LAST>
 __global__ __launch_bounds__(kT) void k_prepare(const int32_t *__restrict__ rows, int64_t row0, int64_t nrows,
                                                 GraphDev g, DevPlan P, SegBufs s, Ctrl *ctrl) {
     __shared__ unsigned long long s_valid[kT / 64];
+    __shared__ unsigned long long s_bytes[kT / 64];
     const int64_t i = (int64_t)blockIdx.x * kT + threadIdx.x;
     bool valid = false;
+    unsigned long long abytes = 0;  // algorithmic bytes of a merge intersection for this row
     if (i < nrows) {
+        abytes = 4ull * W;
         int32_t f[W];
         load_row<W>(rows, g, row0 + i, f);
         valid = true;
@@ -138,6 +150,7 @@ __global__ __launch_bounds__(kT) void k_prepare(const int32_t *__restrict__ rows
                         int64_t b = g.rp[x], e = g.rp[x + 1];
                         int64_t a = lo > 0 ? lower_bound(g.col, b, e, lo) : b;
                         int64_t z = hi < 0x7FFFFFFF ? lower_bound(g.col, a, e, hi) : e;
+                        abytes += 16ull + 4ull * (unsigned long long)(z - a);
                         if (best < 0 || z - a < best) {
                             best = z - a;
                             bb = a;
@@ -169,14 +182,22 @@ __global__ __launch_bounds__(kT) void k_prepare(const int32_t *__restrict__ rows
             s.hpre[i] = h;
         }
     }
-    if constexpr (W == 2) {
+    {
         unsigned long long c = wave_sum_u64(valid ? 1ull : 0ull);
-        if (__lane_id() == 0) s_valid[threadIdx.x >> 6] = c;
+        unsigned long long b = wave_sum_u64(abytes);
+        if (__lane_id() == 0) {
+            s_valid[threadIdx.x >> 6] = c;
+            s_bytes[threadIdx.x >> 6] = b;
+        }
         __syncthreads();
         if (threadIdx.x == 0) {
-            unsigned long long t = 0;
-            for (int q = 0; q < kT / 64; ++q) t += s_valid[q];
-            if (t) atomicAdd(&ctrl->level[1], t);
+            unsigned long long t = 0, tb = 0;
+            for (int q = 0; q < kT / 64; ++q) {
+                t += s_valid[q];
+                tb += s_bytes[q];
+            }
+            if (W == 2 && t) atomicAdd(&ctrl->level[1], t);
+            if (tb) atomicAdd(&ctrl->segbytes[W], tb);
         }
     }
 }
@@ -208,12 +229,112 @@ __device__ __forceinline__ int64_t find_row(const int64_t *__restrict__ off, int
     return lo;
 }
 
-template <int W, int MODE>
+// first index in [lo, hi) with col[i] > key
+__device__ __forceinline__ int64_t upper_bound(const int32_t *__restrict__ col, int64_t lo, int64_t hi, int32_t key) {
+    while (lo < hi) {
+        int64_t mid = lo + ((hi - lo) >> 1);
+        if (col[mid] <= key) lo = mid + 1; else hi = mid;
+    }
+    return lo;
+}
+
+__device__ __forceinline__ bool lds_contains(const int32_t *s, int32_t n, int32_t key) {
+    int32_t lo = 0, hi = n;
+    while (lo < hi) {
+        int32_t mid = (lo + hi) >> 1;
+        int32_t x = s[mid];
+        if (x == key) return true;
+        if (x < key) lo = mid + 1; else hi = mid;
+    }
+    return false;
+}
+
+// Orders this wave's LDS writes before its later LDS reads (all lanes).
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+constexpr int kStage = 512;  // staged list entries per wave
+
+struct WaveSeg {
+    int head, tail;  // first and last lane of this lane's row segment
+    int ord, nseg;   // segment ordinal within the wave, number of segments
+    bool big;        // segment long enough to share one window search
+};
+
+// Wave-cooperative membership test of each lane's candidate v in the list of
+// vertex x (one list per row segment).  The 64 lanes hold consecutive work
+// items, so a row's candidates occupy a run of lanes in increasing order.  For
+// a run of >= 3 lanes, its first lane finds the first list entry >= its
+// candidate and its last lane the first entry > its candidate: the run's
+// candidates can only match inside that window.  The windows of all runs are
+// copied into LDS with coalesced loads when they fit, and each lane then
+// binary-searches LDS; otherwise each lane searches its run's window in
+// global memory.  Short runs search the whole list directly.
+__device__ __forceinline__ bool wave_member(const GraphDev &g, bool need_any, int32_t x, int32_t v, int lane,
+                                            const WaveSeg &sg, int32_t *stage, int32_t *spref, int64_t *slb) {
+    // hub lists are answered by their bitmap; only the others take part below
+    const bool hub = need_any && x >= g.hub_base;
+    const bool need = need_any && !hub;
+    int64_t lo = 0, hi = 0;
+    if (need) {
+        lo = g.rp[x];
+        hi = g.rp[x + 1];
+    }
+    const bool nb = need && sg.big;
+    int64_t lbv = 0, ubv = 0;
+    if (nb && lane == sg.head) lbv = lower_bound(g.col, lo, hi, v);
+    if (nb && lane == sg.tail) ubv = upper_bound(g.col, lo, hi, v);
+    const int64_t lb = __shfl(lbv, sg.head, 64);
+    const int64_t ub = __shfl(ubv, sg.tail, 64);
+    const int32_t wlen = nb ? (int32_t)(ub - lb) : 0;
+    const int32_t contrib = (lane == sg.head) ? wlen : 0;
+    int32_t incl = contrib;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        int32_t y = __shfl_up(incl, d, 64);
+        if (lane >= d) incl += y;
+    }
+    const int32_t total = __shfl(incl, 63, 64);
+    const int32_t myoff = __shfl(incl - contrib, sg.head, 64);
+    bool found = false;
+    if (total > 0 && total <= kStage) {
+        if (lane == sg.head) {
+            spref[sg.ord] = incl - contrib;
+            slb[sg.ord] = lb;
+        }
+        if (lane == 0) spref[sg.nseg] = total;
+        wave_sync();
+        for (int idx = lane; idx < total; idx += 64) {
+            int s0 = 0, s1 = sg.nseg - 1;
+            while (s0 < s1) {
+                int m = (s0 + s1 + 1) >> 1;
+                if (spref[m] <= idx) s0 = m; else s1 = m - 1;
+            }
+            stage[idx] = g.col[slb[s0] + (idx - spref[s0])];
+        }
+        wave_sync();
+        if (nb) found = lds_contains(stage + myoff, wlen, v);
+        wave_sync();
+    } else if (nb) {
+        found = contains(g.col, lb, ub, v);
+    }
+    if (need && !sg.big) found = contains(g.col, lo, hi, v);
+    if (hub) found = adj_has(g, x, v);
+    return found;
+}
+
+template <int W, int MODE, int STRAT>
 __global__ __launch_bounds__(kT) void k_extend(ExtArgs a) {
     __shared__ int64_t s_rng[2];
     __shared__ unsigned long long s_red[3][kT / 64];
     __shared__ int32_t s_cnt[kT / 64];
     __shared__ unsigned long long s_base;
+    __shared__ int32_t s_stage[STRAT == 1 ? kT / 64 : 1][STRAT == 1 ? kStage : 1];
+    __shared__ int32_t s_pref[STRAT == 1 ? kT / 64 : 1][65];
+    __shared__ int64_t s_lb[STRAT == 1 ? kT / 64 : 1][64];
 
     const int64_t tile0 = a.w0 + (int64_t)blockIdx.x * kTile;
     const int64_t tile1 = min(tile0 + (int64_t)kTile, a.w1);
@@ -225,6 +346,8 @@ __global__ __launch_bounds__(kT) void k_extend(ExtArgs a) {
     const int64_t rlo = s_rng[0], rhi = s_rng[1];
     const DevStep st = a.P.st[W];
     const GraphDev &g = a.g;
+    const int lane = __lane_id();
+    const int wvi = threadIdx.x >> 6;
 
     unsigned long long cnt = 0, hs = 0, hx = 0;
     uint32_t okmask = 0;
@@ -235,23 +358,54 @@ __global__ __launch_bounds__(kT) void k_extend(ExtArgs a) {
         vv[j] = 0;
         rr[j] = 0;
         const int64_t w = tile0 + j * kT + threadIdx.x;
-        if (w >= tile1) continue;
-        const int64_t r = find_row(a.off, rlo, rhi, w);
-        const uint64_t pi = a.pinfo[r];
-        const int pp = (int)(pi >> 56);
-        const int32_t v = g.col[(int64_t)(pi & kPbMask) + (w - a.off[r])];
+        const bool active = w < tile1;
+        if (STRAT == 0 && !active) continue;
+        int64_t r = rlo;
+        int32_t v = 0;
+        int pp = 0;
         int32_t f[W];
-        load_row<W>(a.rows, g, a.row0 + r, f);
-        bool ok = true;
+#pragma unroll
+        for (int p = 0; p < W; ++p) f[p] = 0;
+        if (active) {
+            r = find_row(a.off, rlo, rhi, w);
+            const uint64_t pi = a.pinfo[r];
+            pp = (int)(pi >> 56);
+            v = g.col[(int64_t)(pi & kPbMask) + (w - a.off[r])];
+            load_row<W>(a.rows, g, a.row0 + r, f);
+        }
+        bool ok = active;
 #pragma unroll
         for (int p = 0; p < W; ++p)
             if ((st.neq >> p) & 1u) ok &= (v != f[p]);
         if (st.slice && a.P.slice_count > 1) ok &= in_slice(v, a.P);
+        if constexpr (STRAT == 0) {
 #pragma unroll
-        for (int p = 0; p < W; ++p) {
-            if (ok && ((st.ext >> p) & 1u) && p != pp) {
-                const int32_t x = f[p];
-                ok = contains(g.col, g.rp[x], g.rp[x + 1], v);
+            for (int p = 0; p < W; ++p) {
+                if (ok && ((st.ext >> p) & 1u) && p != pp) ok = adj_has(g, f[p], v);
+            }
+        } else {
+            // row segments of this wave
+            const int64_t rprev = __shfl_up(r, 1, 64);
+            const bool head = active && (lane == 0 || rprev != r);
+            const uint64_t hmask = __ballot(head);
+            const uint64_t amask = __ballot(active);
+            const uint64_t le = (lane == 63) ? ~0ull : ((2ull << lane) - 1);
+            WaveSeg sg;
+            const uint64_t hle = hmask & le;
+            sg.head = hle ? 63 - __clzll(hle) : 0;
+            const uint64_t after = hmask & ~le;
+            const int last_active = amask ? 63 - __clzll(amask) : 0;
+            sg.tail = after ? __ffsll((long long)after) - 2 : last_active;
+            sg.ord = __popcll(hle) - 1;
+            sg.nseg = __popcll(hmask);
+            sg.big = (sg.tail - sg.head) >= 2;
+#pragma unroll
+            for (int p = 0; p < W; ++p) {
+                if ((st.ext >> p) & 1u) {
+                    const bool need = active && p != pp;
+                    const bool in = wave_member(g, need, f[p], v, lane, sg, s_stage[wvi], s_pref[wvi], s_lb[wvi]);
+                    if (need) ok &= in;
+                }
             }
         }
         if (!ok) continue;
@@ -264,6 +418,8 @@ __global__ __launch_bounds__(kT) void k_extend(ExtArgs a) {
             cnt += 1;
             hs += h;
             hx ^= h;
+        } else if constexpr (MODE == MODE_COUNT_NOHASH) {
+            cnt += 1;
         } else {
             okmask |= 1u << j;
             vv[j] = v;
@@ -271,8 +427,8 @@ __global__ __launch_bounds__(kT) void k_extend(ExtArgs a) {
         }
     }
 
-    const int wv = threadIdx.x >> 6;
-    if constexpr (MODE == MODE_COUNT) {
+    const int wv = wvi;
+    if constexpr (MODE == MODE_COUNT || MODE == MODE_COUNT_NOHASH) {
         cnt = wave_sum_u64(cnt);
         hs = wave_sum_u64(hs);
         hx = wave_xor_u64(hx);
@@ -301,7 +457,6 @@ __global__ __launch_bounds__(kT) void k_extend(ExtArgs a) {
         // workgroup-wide exclusive scan of per-thread output counts
         int c = __popc(okmask);
         int inc = c;
-        const int lane = __lane_id();
 #pragma unroll
         for (int d = 1; d < 64; d <<= 1) {
             int y = __shfl_up(inc, d, 64);
@@ -442,16 +597,281 @@ void prepare_w(bool last, const GraphDev &g, const DevPlan &P, const int32_t *ro
         hipLaunchKernelGGL((k_prepare<W, false>), grid, dim3(kT), 0, st, rows, row0, nrows, g, P, s, ctrl);
 }
 
-template <int W>
-void extend_w(int mode, const ExtArgs &a, hipStream_t st) {
+// ---------------------------------------------------------------------------
+// lane merge: every lane owns a run of kRun consecutive work items (probe
+// elements, usually of one row).  For each other Ext list it finds the first
+// entry >= its first candidate once, then advances that cursor by galloping
+// (exponential then binary search, Bentley-Yao) as the sorted candidates
+// increase, so a membership test costs O(log gap) instead of O(log degree).
+// Hub lists are answered by their bitmap.
+// ---------------------------------------------------------------------------
+constexpr int kRun = 16;
+constexpr int kMTile = kT * kRun;
+
+// first index in [pos, end) with col[i] >= key; every index before pos holds a smaller value
+__device__ __forceinline__ int64_t gallop(const int32_t *__restrict__ col, int64_t pos, int64_t end, int32_t key) {
+    if (pos >= end || col[pos] >= key) return pos;
+    int64_t lo = pos, step = 1;  // col[lo] < key
+    while (lo + step < end && col[lo + step] < key) {
+        lo += step;
+        step <<= 1;
+    }
+    int64_t hi = min(lo + step, end);
+    lo += 1;
+    while (lo < hi) {
+        int64_t mid = (lo + hi) >> 1;
+        if (col[mid] < key) lo = mid + 1; else hi = mid;
+    }
+    return lo;
+}
+
+template <int W, int MODE>
+__global__ __launch_bounds__(kT) void k_extend_merge(ExtArgs a) {
+    constexpr bool kEmit = MODE == MODE_EMIT || MODE == MODE_OUTPUT;
+    constexpr bool kHash = MODE == MODE_COUNT;
+    __shared__ int64_t s_rng[2];
+    __shared__ unsigned long long s_red[3][kT / 64];
+    __shared__ int32_t s_cnt[kT / 64];
+    __shared__ unsigned long long s_base;
+    __shared__ int32_t s_ov[kEmit ? kT * kRun : 1];
+    __shared__ int32_t s_or[kEmit ? kT * kRun : 1];
+    // hits waiting to be hashed, per wave (hashing them 64 at a time keeps
+    // every lane busy even when hits are sparse across lanes)
+    __shared__ int32_t s_pv[kHash ? kT / 64 : 1][128];
+    __shared__ int32_t s_pr[kHash ? kT / 64 : 1][128];
+
+    const int64_t tile0 = a.w0 + (int64_t)blockIdx.x * kMTile;
+    const int64_t tile1 = min(tile0 + (int64_t)kMTile, a.w1);
+    if (threadIdx.x == 0) {
+        s_rng[0] = find_row(a.off, 0, a.nrows - 1, tile0);
+        s_rng[1] = find_row(a.off, s_rng[0], a.nrows - 1, tile1 - 1);
+    }
+    __syncthreads();
+    const int64_t rlo = s_rng[0], rhi = s_rng[1];
+    const DevStep st = a.P.st[W];
+    const GraphDev &g = a.g;
+    const int wv = threadIdx.x >> 6;
+    const int lane = __lane_id();
+    const uint64_t lt = (lane == 0) ? 0ull : ((~0ull) >> (64 - lane));
+
+    unsigned long long cnt = 0, hs = 0, hx = 0;
+    int nout = 0;
+    int npend = 0;  // wave-uniform
+    auto hash_hit = [&](int32_t v, int32_t rr) {
+        int32_t ff[W];
+        load_row<W>(a.rows, g, a.row0 + rr, ff);
+        uint64_t h = a.hpre[rr];
+#pragma unroll
+        for (int p = 0; p < W; ++p)
+            if ((st.ext >> p) & 1u) h += mix64(edge_key(ff[p], v));
+        h = mix64(h);
+        cnt += 1;
+        hs += h;
+        hx ^= h;
+    };
+
+    const int64_t wb = tile0 + (int64_t)threadIdx.x * kRun;
+    const int64_t we = min(wb + (int64_t)kRun, tile1);
+    int64_t r = rlo, rend = -1, pshift = 0;
+    int pp = 0;
+    int32_t f[W];
+    int64_t cur[W], end[W];
+#pragma unroll
+    for (int p = 0; p < W; ++p) {
+        f[p] = 0;
+        cur[p] = 0;
+        end[p] = 0;
+    }
+    for (int it = 0; it < kRun; ++it) {
+        const int64_t w = wb + it;
+        bool ok = false;
+        int32_t v = 0;
+        if (w < we) {
+            if (w >= rend) {
+                // enter the row that holds item w
+                r = (rend < 0) ? find_row(a.off, rlo, rhi, w) : find_row(a.off, r + 1, rhi, w);
+                rend = a.off[r + 1];
+                const uint64_t pi = a.pinfo[r];
+                pp = (int)(pi >> 56);
+                pshift = (int64_t)(pi & kPbMask) - a.off[r];
+                load_row<W>(a.rows, g, a.row0 + r, f);
+                const int32_t v0 = g.col[pshift + w];
+#pragma unroll
+                for (int p = 0; p < W; ++p) {
+                    if (((st.ext >> p) & 1u) && p != pp && f[p] < g.hub_base) {
+                        end[p] = g.rp[f[p] + 1];
+                        cur[p] = lower_bound(g.col, g.rp[f[p]], end[p], v0);
+                    }
+                }
+            }
+            v = g.col[pshift + w];
+            ok = true;
+#pragma unroll
+            for (int p = 0; p < W; ++p)
+                if ((st.neq >> p) & 1u) ok &= (v != f[p]);
+            if (st.slice && a.P.slice_count > 1) ok &= in_slice(v, a.P);
+#pragma unroll
+            for (int p = 0; p < W; ++p) {
+                if (ok && ((st.ext >> p) & 1u) && p != pp) {
+                    if (f[p] >= g.hub_base) {
+                        ok = adj_has(g, f[p], v);
+                    } else {
+                        cur[p] = gallop(g.col, cur[p], end[p], v);
+                        ok = cur[p] < end[p] && g.col[cur[p]] == v;
+                    }
+                }
+            }
+        }
+        if constexpr (kHash) {
+            const uint64_t m = __ballot(ok);
+            if (ok) {
+                const int q = npend + (int)__popcll(m & lt);
+                s_pv[wv][q] = v;
+                s_pr[wv][q] = (int32_t)r;
+            }
+            npend += (int)__popcll(m);
+            if (npend >= 64) {
+                wave_sync();
+                hash_hit(s_pv[wv][lane], s_pr[wv][lane]);
+                const int rest = npend - 64;
+                int32_t tv = 0, tr = 0;
+                if (lane < rest) {
+                    tv = s_pv[wv][64 + lane];
+                    tr = s_pr[wv][64 + lane];
+                }
+                wave_sync();
+                if (lane < rest) {
+                    s_pv[wv][lane] = tv;
+                    s_pr[wv][lane] = tr;
+                }
+                wave_sync();
+                npend = rest;
+            }
+        } else if constexpr (MODE == MODE_COUNT_NOHASH) {
+            cnt += ok ? 1 : 0;
+        } else {
+            if (ok) {
+                s_ov[threadIdx.x * kRun + nout] = v;
+                s_or[threadIdx.x * kRun + nout] = (int32_t)r;
+                ++nout;
+            }
+        }
+    }
+    if constexpr (kHash) {
+        wave_sync();
+        if (lane < npend) hash_hit(s_pv[wv][lane], s_pr[wv][lane]);
+    }
+
+    if constexpr (!kEmit) {
+        cnt = wave_sum_u64(cnt);
+        hs = wave_sum_u64(hs);
+        hx = wave_xor_u64(hx);
+        if (lane == 0) {
+            s_red[0][wv] = cnt;
+            s_red[1][wv] = hs;
+            s_red[2][wv] = hx;
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            unsigned long long c = 0, s = 0, x = 0;
+            for (int q = 0; q < kT / 64; ++q) {
+                c += s_red[0][q];
+                s += s_red[1][q];
+                x ^= s_red[2][q];
+            }
+            if (c) {
+                atomicAdd(&a.ctrl->acc[0], c);
+                if (kHash) {
+                    atomicAdd(&a.ctrl->acc[1], s);
+                    atomicXor(&a.ctrl->acc[2], x);
+                }
+                atomicAdd(&a.ctrl->level[W], c);
+            }
+        }
+    } else {
+        int inc = nout;
+#pragma unroll
+        for (int d = 1; d < 64; d <<= 1) {
+            int y = __shfl_up(inc, d, 64);
+            if (lane >= d) inc += y;
+        }
+        if (lane == 63) s_cnt[wv] = inc;
+        __syncthreads();
+        int wbase = 0, tot = 0;
+#pragma unroll
+        for (int q = 0; q < kT / 64; ++q) {
+            if (q < wv) wbase += s_cnt[q];
+            tot += s_cnt[q];
+        }
+        if (threadIdx.x == 0) {
+            unsigned long long b = 0;
+            if (tot) {
+                const int qi = (MODE == MODE_EMIT) ? (W + 1) : HUGE_KMAX;
+                b = atomicAdd(&a.ctrl->qcount[qi], (unsigned long long)tot);
+                atomicAdd(&a.ctrl->level[W], (unsigned long long)tot);
+            }
+            s_base = b;
+        }
+        __syncthreads();
+        int64_t o = (int64_t)s_base + wbase + (inc - nout);
+        for (int q = 0; q < nout; ++q, ++o) {
+            const int32_t v = s_ov[threadIdx.x * kRun + q];
+            int32_t ff[W];
+            load_row<W>(a.rows, g, a.row0 + s_or[threadIdx.x * kRun + q], ff);
+            int32_t *dst = a.out + o * (W + 1);
+            if constexpr (MODE == MODE_EMIT) {
+#pragma unroll
+                for (int p = 0; p < W; ++p) dst[p] = ff[p];
+                dst[W] = v;
+            } else {
+#pragma unroll
+                for (int qq = 0; qq < W + 1; ++qq) {
+                    const int p = a.P.pos[qq];
+                    int32_t x = v;
+#pragma unroll
+                    for (int t = 0; t < W; ++t)
+                        if (t == p) x = ff[t];
+                    dst[qq] = a.inv_rank[x];
+                }
+            }
+        }
+    }
+}
+
+template <int W, int STRAT>
+void extend_ws(int mode, const ExtArgs &a, hipStream_t st) {
     const int64_t items = a.w1 - a.w0;
-    dim3 grid((unsigned)((items + kTile - 1) / kTile));
-    if (mode == MODE_COUNT)
-        hipLaunchKernelGGL((k_extend<W, MODE_COUNT>), grid, dim3(kT), 0, st, a);
-    else if (mode == MODE_EMIT)
-        hipLaunchKernelGGL((k_extend<W, MODE_EMIT>), grid, dim3(kT), 0, st, a);
+    if constexpr (STRAT == STRAT_LANE_MERGE) {
+        dim3 grid((unsigned)((items + kMTile - 1) / kMTile));
+        if (mode == MODE_COUNT)
+            hipLaunchKernelGGL((k_extend_merge<W, MODE_COUNT>), grid, dim3(kT), 0, st, a);
+        else if (mode == MODE_COUNT_NOHASH)
+            hipLaunchKernelGGL((k_extend_merge<W, MODE_COUNT_NOHASH>), grid, dim3(kT), 0, st, a);
+        else if (mode == MODE_EMIT)
+            hipLaunchKernelGGL((k_extend_merge<W, MODE_EMIT>), grid, dim3(kT), 0, st, a);
+        else
+            hipLaunchKernelGGL((k_extend_merge<W, MODE_OUTPUT>), grid, dim3(kT), 0, st, a);
+    } else {
+        dim3 grid((unsigned)((items + kTile - 1) / kTile));
+        if (mode == MODE_COUNT)
+            hipLaunchKernelGGL((k_extend<W, MODE_COUNT, STRAT>), grid, dim3(kT), 0, st, a);
+        else if (mode == MODE_COUNT_NOHASH)
+            hipLaunchKernelGGL((k_extend<W, MODE_COUNT_NOHASH, STRAT>), grid, dim3(kT), 0, st, a);
+        else if (mode == MODE_EMIT)
+            hipLaunchKernelGGL((k_extend<W, MODE_EMIT, STRAT>), grid, dim3(kT), 0, st, a);
+        else
+            hipLaunchKernelGGL((k_extend<W, MODE_OUTPUT, STRAT>), grid, dim3(kT), 0, st, a);
+    }
+}
+
+template <int W>
+void extend_w(int mode, int strategy, const ExtArgs &a, hipStream_t st) {
+    if (strategy == STRAT_BSEARCH)
+        extend_ws<W, STRAT_BSEARCH>(mode, a, st);
+    else if (strategy == STRAT_WAVE_STAGED)
+        extend_ws<W, STRAT_WAVE_STAGED>(mode, a, st);
     else
-        hipLaunchKernelGGL((k_extend<W, MODE_OUTPUT>), grid, dim3(kT), 0, st, a);
+        extend_ws<W, STRAT_LANE_MERGE>(mode, a, st);
 }
 
 }  // namespace
@@ -476,9 +896,9 @@ void launch_scan_bounds(const SegBufs &s, int64_t nrows, int64_t *tmp, hipStream
     HUGE_HIP(hipGetLastError());
 }
 
-void launch_extend(int width, int mode, const GraphDev &g, const DevPlan &P, const int32_t *rows, int64_t row0,
-                   const SegBufs &s, int64_t nrows, int64_t w0, int64_t w1, int32_t *out_rows, Ctrl *ctrl,
-                   const int32_t *inv_rank, hipStream_t st) {
+void launch_extend(int width, int mode, int strategy, const GraphDev &g, const DevPlan &P, const int32_t *rows,
+                   int64_t row0, const SegBufs &s, int64_t nrows, int64_t w0, int64_t w1, int32_t *out_rows,
+                   Ctrl *ctrl, const int32_t *inv_rank, hipStream_t st) {
     if (w1 <= w0) return;
     ExtArgs a;
     a.rows = rows;
@@ -495,12 +915,12 @@ void launch_extend(int width, int mode, const GraphDev &g, const DevPlan &P, con
     a.g = g;
     a.P = P;
     switch (width) {
-        case 2: extend_w<2>(mode, a, st); break;
-        case 3: extend_w<3>(mode, a, st); break;
-        case 4: extend_w<4>(mode, a, st); break;
-        case 5: extend_w<5>(mode, a, st); break;
-        case 6: extend_w<6>(mode, a, st); break;
-        case 7: extend_w<7>(mode, a, st); break;
+        case 2: extend_w<2>(mode, strategy, a, st); break;
+        case 3: extend_w<3>(mode, strategy, a, st); break;
+        case 4: extend_w<4>(mode, strategy, a, st); break;
+        case 5: extend_w<5>(mode, strategy, a, st); break;
+        case 6: extend_w<6>(mode, strategy, a, st); break;
+        case 7: extend_w<7>(mode, strategy, a, st); break;
         default: HUGE_FAIL(HUGE_EINVAL, "bad width %d", width);
     }
     HUGE_HIP(hipGetLastError());

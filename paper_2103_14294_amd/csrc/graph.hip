@@ -12,7 +12,9 @@
 // of these pairs by s groups them by s and keeps t ascending inside each
 // group, which is exactly the relabelled CSR with sorted lists: the sorted
 // keys are the row of each entry and the sorted values are the column IDs.
+#include <algorithm>
 #include <chrono>
+#include <cstdlib>
 #include <cstring>
 
 #include "internal.h"
@@ -91,14 +93,29 @@ __global__ __launch_bounds__(kT) void k_check_edges(const int64_t *__restrict__ 
     if (f) atomicOr(flags, f);
 }
 
+constexpr uint32_t kHubMinDegree = 256;
+
 __global__ void k_degree_keys(const int64_t *__restrict__ rp, int64_t n, uint32_t *__restrict__ key,
-                              uint32_t *__restrict__ val, uint32_t *dmax) {
+                              uint32_t *__restrict__ val, uint32_t *dmax, unsigned long long *nhub) {
     int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (u >= n) return;
     uint32_t d = (uint32_t)(rp[u + 1] - rp[u]);
     key[u] = d;
     val[u] = (uint32_t)u;
     atomicMax(dmax, d);
+    if (d >= kHubMinDegree) atomicAdd(nhub, 1ull);
+}
+
+// One n-bit adjacency bitmap per hub (ranks base..n-1): bit w of hub x is
+// set iff w is a neighbour of x.
+__global__ __launch_bounds__(kT) void k_hub_bitmap(const int64_t *__restrict__ rp, const int32_t *__restrict__ col,
+                                                   int64_t base, int64_t words, uint32_t *__restrict__ bm) {
+    const int64_t x = base + blockIdx.x;
+    uint32_t *row = bm + (int64_t)blockIdx.x * words;
+    for (int64_t e = rp[x] + threadIdx.x; e < rp[x + 1]; e += kT) {
+        const int32_t w = col[e];
+        atomicOr(&row[w >> 5], 1u << (w & 31));
+    }
 }
 
 // inv = vertices sorted by (degree, id); rank[inv[i]] = i; newdeg[i] = deg(inv[i]).
@@ -254,6 +271,7 @@ huge_graph *graph_load(int64_t n, int64_t nnz, const int64_t *rp_in, const int32
     unsigned long long *d_hist = (unsigned long long *)(small + 64);
     double *d_mom = (double *)(small + 64 + 32 * 8);
     unsigned long long *d_digest = (unsigned long long *)(small + 64 + 32 * 8 + 8 * 8);
+    unsigned long long *d_nhub = d_digest + 1;
     HUGE_HIP(hipMemsetAsync(small, 0, 1024, st));
 
     // ---- hygiene checks
@@ -289,9 +307,11 @@ huge_graph *graph_load(int64_t n, int64_t nnz, const int64_t *rp_in, const int32
     DevBuf b_k0, b_v0, b_k1, b_v1;
     uint32_t *vk0 = b_k0.alloc<uint32_t>(vn), *vv0 = b_v0.alloc<uint32_t>(vn);
     uint32_t *vk1 = b_k1.alloc<uint32_t>(vn), *vv1 = b_v1.alloc<uint32_t>(vn);
-    hipLaunchKernelGGL(k_degree_keys, dim3(grid_for(vn, kT)), dim3(kT), 0, st, rp0, vn, vk0, vv0, d_dmax);
+    hipLaunchKernelGGL(k_degree_keys, dim3(grid_for(vn, kT)), dim3(kT), 0, st, rp0, vn, vk0, vv0, d_dmax, d_nhub);
     uint32_t dmax = 0;
+    unsigned long long nhub = 0;
     HUGE_HIP(hipMemcpyAsync(&dmax, d_dmax, 4, hipMemcpyDeviceToHost, st));
+    HUGE_HIP(hipMemcpyAsync(&nhub, d_nhub, 8, hipMemcpyDeviceToHost, st));
     HUGE_HIP(hipStreamSynchronize(st));
     int dbits = 0;
     while (dbits < 32 && (dmax >> dbits)) ++dbits;
@@ -355,13 +375,43 @@ huge_graph *graph_load(int64_t n, int64_t nnz, const int64_t *rp_in, const int32
     g->dev.rp = g->rp;
     g->dev.col = g->col;
     g->dev.src = g->src;
+
+    // ---- hub bitmaps for the highest-degree ranks
+    int64_t words = (n + 31) / 32;
+    int64_t H = 0;
+    if (!(flags & HUGE_NO_HUB_BITMAP) && nnz) {
+        uint64_t budget = 4ull << 30;
+        if (const char *e = getenv("HUGE_HUB_BYTES")) budget = strtoull(e, nullptr, 10);
+        size_t fr = 0, tot = 0;
+        HUGE_HIP(hipMemGetInfo(&fr, &tot));
+        budget = std::min<uint64_t>(budget, fr / 4);
+        H = std::min<int64_t>((int64_t)nhub, (int64_t)(budget / (4ull * words)));
+    }
+    g->dev.hub_words = words;
+    g->dev.hub_base = (int32_t)(n - H);
+    g->dev.hub_bm = nullptr;
+    if (H > 0) {
+        HUGE_HIP(hipMalloc(&g->hub_bm, 4ull * words * H));
+        HUGE_HIP(hipMemsetAsync(g->hub_bm, 0, 4ull * words * H, st));
+        hipLaunchKernelGGL(k_hub_bitmap, dim3((unsigned)H), dim3(kT), 0, st, (const int64_t *)g->rp,
+                           (const int32_t *)g->col, (int64_t)(n - H), words, g->hub_bm);
+        HUGE_HIP(hipGetLastError());
+        int64_t dmin = 0;
+        int64_t rp2[2];
+        HUGE_HIP(hipMemcpyAsync(rp2, g->rp + (n - H), 16, hipMemcpyDeviceToHost, st));
+        HUGE_HIP(hipStreamSynchronize(st));
+        dmin = rp2[1] - rp2[0];
+        g->dev.hub_bm = g->hub_bm;
+        g->info.hub_min_degree = dmin;
+    }
+    g->info.hub_count = H;
     HUGE_HIP(hipGetDevice(&g->device));
     g->info.n = n;
     g->info.nnz = nnz;
     g->info.max_degree = dmax;
     for (int i = 0; i < 32; ++i) g->info.degree_hist[i] = hh[i];
     for (int i = 0; i < 8; ++i) g->info.degree_moments[i] = mom[i];
-    g->info.device_bytes = (uint64_t)(n + 1) * 8 + (uint64_t)en * 8 + (uint64_t)n * 4;
+    g->info.device_bytes = (uint64_t)(n + 1) * 8 + (uint64_t)en * 8 + (uint64_t)n * 4 + 4ull * words * H;
     char buf[64];
     snprintf(buf, sizeof(buf), "%016llx-%lld-%lld", dig, (long long)n, (long long)nnz);
     g->sha = buf;
@@ -376,6 +426,7 @@ void graph_free(huge_graph *g) {
     if (g->col) (void)hipFree(g->col);
     if (g->src) (void)hipFree(g->src);
     if (g->inv_rank) (void)hipFree(g->inv_rank);
+    if (g->hub_bm) (void)hipFree(g->hub_bm);
     delete g;
 }
 

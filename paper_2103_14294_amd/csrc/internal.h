@@ -45,6 +45,10 @@ struct GraphDev {
     const int64_t *rp;   // [n+1]
     const int32_t *col;  // [nnz], each list strictly ascending
     const int32_t *src;  // [nnz], src[e] = the row that holds entry e
+    const uint32_t *hub_bm;  // adjacency bitmaps of vertices hub_base..n-1, hub_words words each
+    int64_t hub_words;
+    int32_t hub_base;        // first vertex (rank) with a bitmap; n when there is none
+    int32_t pad;
 };
 
 }  // namespace huge
@@ -55,6 +59,7 @@ struct huge_graph {
     int32_t *col = nullptr;
     int32_t *src = nullptr;
     int32_t *inv_rank = nullptr;  // rank -> original ID
+    uint32_t *hub_bm = nullptr;
     huge_graph_info info{};
     int device = 0;
     std::string sha;  // content digest of the relabelled CSR (autotune cache key)
@@ -79,7 +84,7 @@ struct DevPlan {
     int32_t ne;                 // query edges, as position pairs ea < eb
     uint8_t ea[32], eb[32];
     uint8_t pos[HUGE_KMAX];     // pos[v] = position of query vertex v
-    DevStep st[HUGE_KMAX];      // st[i], i = 1..k-1
+    DevStep st[HUGE_KMAX];      // st[i], i = 1..k-1; st[i].slice marks the sliced vertex's position
     uint32_t slice_count, slice_id;
 };
 
@@ -147,21 +152,24 @@ struct Ctrl {                      // device-resident counters
     unsigned long long qcount[HUGE_KMAX + 1];   // rows in the queue of level i
     unsigned long long level[HUGE_KMAX];        // level_counts
     unsigned long long acc[4];                  // count, hash_sum, hash_xor, overflow flag
+    unsigned long long segbytes[HUGE_KMAX];     // algorithmic bytes of the current segment, per width
     long long scratch[8];
 };
 
 void launch_prepare(int width, bool last, const GraphDev &g, const DevPlan &P, const int32_t *rows, int64_t row0,
                     int64_t nrows, const SegBufs &s, Ctrl *ctrl, hipStream_t st);
 void launch_scan_bounds(const SegBufs &s, int64_t nrows, int64_t *tmp, hipStream_t st);
-void launch_extend(int width, int mode, const GraphDev &g, const DevPlan &P, const int32_t *rows, int64_t row0,
-                   const SegBufs &s, int64_t nrows, int64_t w0, int64_t w1, int32_t *out_rows, Ctrl *ctrl,
-                   const int32_t *inv_rank, hipStream_t st);
+void launch_extend(int width, int mode, int strategy, const GraphDev &g, const DevPlan &P, const int32_t *rows,
+                   int64_t row0, const SegBufs &s, int64_t nrows, int64_t w0, int64_t w1, int32_t *out_rows,
+                   Ctrl *ctrl, const int32_t *inv_rank, hipStream_t st);
 void launch_edge_sink(const GraphDev &g, const DevPlan &P, int64_t e0, int64_t e1, int mode, int32_t *out,
                       const int32_t *inv_rank, Ctrl *ctrl, hipStream_t st);
 void launch_root_count(const GraphDev &g, const DevPlan &P, Ctrl *ctrl, hipStream_t st);
 int64_t scan_tmp_elems(int64_t n);
 
 // extend modes
-enum { MODE_EMIT = 0, MODE_COUNT = 1, MODE_OUTPUT = 2 };
+enum { MODE_EMIT = 0, MODE_COUNT = 1, MODE_OUTPUT = 2, MODE_COUNT_NOHASH = 3 };
+// intersection strategies (huge_exec_opts.strategy)
+enum { STRAT_BSEARCH = 0, STRAT_WAVE_STAGED = 1, STRAT_LANE_MERGE = 2, STRAT_COUNT = 3 };
 
 }  // namespace huge

@@ -31,7 +31,8 @@ def assert_parity(H, G, g, k, e, order=None, levels=True, **kw):
     r = H.count(G, p, **kw)
     okw = {}
     if kw.get("slice_count", 1) > 1:
-        okw = {"slice_count": kw["slice_count"], "slice_id": kw.get("slice_id", 0)}
+        okw = {"slice_count": kw["slice_count"], "slice_id": kw.get("slice_id", 0),
+               "slice_vertex": kw.get("slice_vertex", 0)}
     ref = oracle_run(g, k, e, order=used, **okw)
     assert cmp_key(r, k) == cmp_key(ref, k), (k, e, used, r, ref)
     if levels:

@@ -161,9 +161,15 @@ def test_edge_query(H, small):
     assert got == want
 
 
+@pytest.fixture(scope="module")
+def tiny(H):
+    g = gg.chung_lu(700, 6, 2.5, seed=5)
+    return g, H.load(g.row_ptr, g.col)
+
+
 @pytest.mark.parametrize("name", ["triangle", "4-cycle", "house", "tailed-triangle"])
-def test_enumerate_rows(H, small, name):
-    g, G = small
+def test_enumerate_rows(H, tiny, name):
+    g, G = tiny
     k, e = P.NAMED[name]
     p = H.plan(G, k, e)
     out = H.enumerate_matches(G, p, buf_rows=4096)
@@ -188,8 +194,8 @@ def test_enumerate_rows(H, small, name):
     assert len({tuple(sorted(map(int, r))) + tuple(sorted(tuple(sorted((int(r[a]), int(r[b])))) for a, b in e)) for r in rows}) == rows.shape[0]
 
 
-def test_enumerate_stop(H, small):
-    g, G = small
+def test_enumerate_stop(H, tiny):
+    g, G = tiny
     k, e = P.NAMED["triangle"]
     calls = []
 
@@ -225,3 +231,63 @@ def test_bad_graphs_rejected(H, defect):
     with pytest.raises(H.HugeError) as ei:
         H.load(rp, col)
     assert ei.value.name == "HUGE_EGRAPH", str(ei.value)
+
+
+@pytest.mark.parametrize("strategy", [0, 1, 2])
+def test_strategies_agree(H, small, strategy):
+    g, G = small
+    for name in ["4-clique", "diamond", "4-cycle", "house", "5-clique"]:
+        k, e = P.NAMED[name]
+        assert_parity(H, G, g, k, e, strategy=strategy)
+    g2 = gg.chung_lu(2000, 8, 2.5, seed=33)
+    G2 = H.load(g2.row_ptr, g2.col)
+    for pat in P.random_patterns(6, seed=strategy + 40, kmin=4, kmax=5):
+        assert_parity(H, G2, g2, pat["k"], pat["edges"], strategy=strategy, chunk_rows=5000)
+    g3 = gg.rmat(10, 8, seed=17)
+    G3 = H.load(g3.row_ptr, g3.col)
+    for name in ["4-clique", "diamond", "4-cycle"]:
+        k, e = P.NAMED[name]
+        assert_parity(H, G3, g3, k, e, strategy=strategy)
+
+
+@pytest.mark.parametrize("sv", [1, 3, 4])
+def test_slice_on_other_vertex(H, small, sv):
+    g, G = small
+    k, e = P.NAMED["house"]
+    full = H.count(G, H.plan(G, k, e))
+    cs = 0
+    for s in range(4):
+        r, _ = assert_parity(H, G, g, k, e, slice_count=4, slice_id=s, slice_vertex=sv)
+        cs += r["count"]
+    assert cs == full["count"]
+
+
+def test_hub_bitmaps_do_not_change_results(H, monkeypatch):
+    g = gg.rmat(13, 16, seed=9)
+    base = H.load(g.row_ptr, g.col, hub_bitmaps=False)
+    assert base.info()["hub_count"] == 0
+    full = H.load(g.row_ptr, g.col)
+    assert full.info()["hub_count"] > 0 and full.info()["hub_min_degree"] >= 256
+    words = (g.n + 31) // 32
+    monkeypatch.setenv("HUGE_HUB_BYTES", str(3 * 4 * words))
+    part = H.load(g.row_ptr, g.col)
+    assert part.info()["hub_count"] == 3
+    for name in ["4-clique", "diamond", "4-cycle", "triangle"]:
+        k, e = P.NAMED[name]
+        ref = H.count(base, H.plan(base, k, e))
+        for G in (full, part):
+            for strategy in (0, 1, 2):
+                r = H.count(G, H.plan(G, k, e), strategy=strategy)
+                assert cmp_key(r, k) == cmp_key(ref, k), (name, strategy)
+
+
+def test_count_without_hash(H, small):
+    g, G = small
+    for name in ["triangle", "4-cycle", "house"]:
+        k, e = P.NAMED[name]
+        p = H.plan(G, k, e)
+        ref = oracle_run(g, k, e, order=p.info()["order"])
+        for strategy in (0, 1, 2):
+            r = H.count(G, p, hash=False, strategy=strategy)
+            assert r["count"] == ref["count"] and r["hash_sum"] == 0 and r["hash_xor"] == 0
+            assert r["level_counts"][:k] == ref["level_counts"][:k]

@@ -250,3 +250,17 @@ def test_mix_is_a_bijection_on_samples():
     xs = [0, 1, 2, 3, 1 << 32, (1 << 64) - 1, 0x123456789ABCDEF0]
     ys = [oracle.mix64(x) for x in xs]
     assert len(set(ys)) == len(xs)
+
+
+def test_slices_of_any_query_vertex_partition():
+    g = gg.chung_lu(2048, 10, 2.5, seed=12)
+    k, e = P.NAMED["house"]
+    full = oracle.enumerate_query(g.row_ptr, g.col, k, e)
+    for sv in range(k):
+        cs, hs, hx = 0, 0, 0
+        for s in range(5):
+            r = oracle.enumerate_query(g.row_ptr, g.col, k, e, slice_count=5, slice_id=s, slice_vertex=sv)
+            cs += r["count"]
+            hs = (hs + r["hash_sum"]) & M64
+            hx ^= r["hash_xor"]
+        assert (cs, hs, hx) == (full["count"], full["hash_sum"], full["hash_xor"]), sv
