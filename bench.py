@@ -3,9 +3,12 @@
 Default workload (the plain PULL-EXTEND configuration): 4-clique, diamond and
 4-cycle counted on an R-MAT graph of scale 22, edge factor 16,
 (a, b, c, d) = (0.57, 0.19, 0.19, 0.05), symmetrised and deduplicated, seed 2.
-One step = one huge_count of each of the three queries with the graph already
-resident in HBM (planning excluded; every kernel and the result read-back
-included).  value = total embeddings / total timed seconds.
+The whole-graph counts are of order 10^11 to 10^12, so the input is processed
+in 64 root batches: batch s holds the matches whose first matched vertex u
+has mix(rank(u)) mod 64 == s (the batches partition the matches).  One step =
+one batch of all three queries, each a huge_count call with the graph already
+resident in HBM (planning excluded; every kernel, the count, the set-hash and
+the result read-back included).  value = embeddings / timed seconds.
 
 Prints one JSON line.  Also reports, for the kernel class with the most device
 time, the algorithmic bytes it moved per second against the 8 TB/s HBM peak
@@ -26,7 +29,8 @@ if ROOT not in sys.path:
 
 HBM_PEAK_GBS = 8000.0
 KC_NAMES = ["prepare", "scan", "extend", "extend_sink"]
-KC_KERNELS = ["k_prepare", "k_tile_scan/k_tile_reduce", "k_extend<W,EMIT>", "k_extend<W,COUNT>"]
+KC_KERNELS = ["k_prepare", "k_tile_scan/k_tile_reduce", "k_extend*<W,EMIT>", "k_extend*<W,COUNT>"]
+STRAT_KERNEL = {0: "k_extend", 1: "k_extend", 2: "k_extend_merge", -1: "k_extend_merge"}
 
 WORKLOADS = {
     "c2": {
@@ -34,18 +38,21 @@ WORKLOADS = {
         "graph": ("rmat", dict(scale=22, edge_factor=16, seed=2)),
         "queries": ["4-clique", "diamond", "4-cycle"],
         "cap": 4 << 30,
+        "batches": 64,
     },
     "c1": {
         "desc": "Chung-Lu n=16384, mean degree 16, gamma 2.5, exact, seed 1: triangle, 4-cycle",
         "graph": ("chung_lu", dict(n=16384, dbar=16, gamma=2.5, seed=1, exact=True)),
         "queries": ["triangle", "4-cycle"],
         "cap": 4 << 30,
+        "batches": 1,
     },
     "c3": {
         "desc": "Chung-Lu n=3072441, mean degree 76, gamma 2.2, seed 3: 5-clique, house, frontier cap 32 GiB",
         "graph": ("chung_lu", dict(n=3072441, dbar=76, gamma=2.2, seed=3)),
         "queries": ["5-clique", "house"],
         "cap": 32 << 30,
+        "batches": 16,
     },
 }
 
@@ -68,7 +75,7 @@ def cpu_baseline(g, queries, budget_s, threads):
     import oracle
     from graphgen import patterns as P
 
-    S = 4096
+    S = 1 << 20
     per_q = budget_s / len(queries)
     tot_cnt, tot_t, slices = 0, 0.0, {}
     for name in queries:
@@ -102,6 +109,8 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=20.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--learned", action="store_true", help="plan with the learned cardinality model")
+    ap.add_argument("--strategy", type=int, default=-1, help="intersection strategy (-1 = library default)")
+    ap.add_argument("--no-hash", action="store_true", help="count only (no set-hash)")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -132,33 +141,41 @@ def main():
         plans.append((name, p))
         log("plan %s: order %s est_cost %.3g" % (name, p.info()["order"], p.info()["est_cost"]))
     ws = huge.Workspace()
-    kw = dict(cap=W["cap"], workspace=ws)
+    nb = W["batches"]
+    kw = dict(cap=W["cap"], workspace=ws, strategy=args.strategy, hash=not args.no_hash)
 
+    def batch_kw(name, p, b):
+        if nb <= 1:
+            return {}
+        return dict(slice_count=nb, slice_id=b % nb, slice_vertex=p.info()["order"][0])
+
+    # warmup on the last batches, time the first ones: no batch is seen twice
     for i in range(args.warmup):
+        b = nb - 1 - i
         for name, p in plans:
-            r = huge.count(G, p, **kw)
-            log("warmup %d %s: count=%d %.1f ms launches=%d peak_frontier=%.2f GB" % (
-                i, name, r["count"], r["query_ms"], r["launches"], r["peak_frontier_bytes"] / 1e9))
+            r = huge.count(G, p, **kw, **batch_kw(name, p, b))
+            log("warmup batch %d %s: count=%d %.1f ms launches=%d peak_frontier=%.2f GB" % (
+                b, name, r["count"], r["query_ms"], r["launches"], r["peak_frontier_bytes"] / 1e9))
 
     kms = [0.0] * 4
     kl = [0] * 4
     kb = [0.0] * 4
     total = 0
     per_q = {name: [] for name, _ in plans}
-    counts = {}
+    counts = {name: [] for name, _ in plans}
     torch.cuda.synchronize()
     t_start = time.perf_counter()
     for s in range(args.steps):
         for name, p in plans:
-            r = huge.count(G, p, profile=True, **kw)
+            r = huge.count(G, p, profile=True, **kw, **batch_kw(name, p, s))
             total += r["count"]
-            counts[name] = r["count"]
+            counts[name].append(r["count"])
             per_q[name].append(r["query_ms"])
             for c in range(4):
                 kms[c] += r["kernel_ms"][c]
                 kl[c] += r["kernel_launches"][c]
                 kb[c] += r["alg_bytes"][c]
-        log("step %d done" % s)
+        log("step %d (batch %d) done" % (s, s % max(1, nb)))
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t_start
 
@@ -168,7 +185,8 @@ def main():
     achieved = (bytes_per_launch / (avg_ms * 1e-3)) / 1e9 if avg_ms > 0 else 0.0
     roof = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-            "kernel": KC_KERNELS[dom], "avg_launch_ms": round(avg_ms, 4),
+            "kernel": KC_KERNELS[dom].replace("k_extend*", STRAT_KERNEL.get(args.strategy, "k_extend")),
+            "avg_launch_ms": round(avg_ms, 4),
             "alg_bytes_per_launch": bytes_per_launch, "launches": kl[dom],
             "kernel_ms_by_class": {KC_NAMES[c]: round(kms[c], 3) for c in range(4)}}
 
@@ -186,7 +204,10 @@ def main():
         "dtype": "int32",
         "data": "synthetic",
         "config": {"workload": W["desc"], "plan": "learned" if args.learned else "cost-model",
-                   "engine": "levels", "frontier_cap_bytes": W["cap"],
+                   "batches": "%d root batches (first matched vertex), batch i timed at step i" % nb
+                   if nb > 1 else "whole graph per step",
+                   "engine": "levels", "strategy": args.strategy, "hash": not args.no_hash,
+                   "frontier_cap_bytes": W["cap"],
                    "counts": counts,
                    "query_ms_median": {k: sorted(v)[len(v) // 2] for k, v in per_q.items()},
                    "graph_load_ms": info["load_ms"], "n": g.n, "m": g.m},
