@@ -20,98 +20,19 @@
 //               extended row to the next level's queue (wave ballot +
 //               one atomic per workgroup) or, at the last level, fold it into
 //               the counting SINK (count, set-hash sum and xor).
+#include "devfuncs.h"
 #include "internal.h"
 #include "prims.h"
 
 namespace huge {
 namespace {
 
+using namespace dev;
+
 constexpr int kT = 256;
 constexpr int kIPT = 4;
 constexpr int kTile = kT * kIPT;
-constexpr uint64_t kPbMask = (1ull << 56) - 1;
 
-__device__ __forceinline__ uint64_t mix64(uint64_t x) {
-    x ^= x >> 30;
-    x *= 0xbf58476d1ce4e5b9ull;
-    x ^= x >> 27;
-    x *= 0x94d049bb133111ebull;
-    x ^= x >> 31;
-    return x;
-}
-
-__device__ __forceinline__ uint64_t edge_key(int32_t a, int32_t b) {
-    uint32_t lo = (uint32_t)(a < b ? a : b), hi = (uint32_t)(a < b ? b : a);
-    return ((uint64_t)lo << 32) | hi;
-}
-
-// first index in [lo, hi) with col[i] >= key
-__device__ __forceinline__ int64_t lower_bound(const int32_t *__restrict__ col, int64_t lo, int64_t hi, int32_t key) {
-    while (lo < hi) {
-        int64_t mid = lo + ((hi - lo) >> 1);
-        if (col[mid] < key) lo = mid + 1; else hi = mid;
-    }
-    return lo;
-}
-
-__device__ __forceinline__ bool contains(const int32_t *__restrict__ col, int64_t lo, int64_t hi, int32_t key) {
-    while (lo < hi) {
-        int64_t mid = lo + ((hi - lo) >> 1);
-        int32_t x = col[mid];
-        if (x == key) return true;
-        if (x < key) lo = mid + 1; else hi = mid;
-    }
-    return false;
-}
-
-// v in N(x): one bitmap load for a hub, a binary search otherwise
-__device__ __forceinline__ bool adj_has(const GraphDev &g, int32_t x, int32_t v) {
-    if (x >= g.hub_base) {
-        const uint32_t word = g.hub_bm[(int64_t)(x - g.hub_base) * g.hub_words + (v >> 5)];
-        return (word >> (v & 31)) & 1u;
-    }
-    return contains(g.col, g.rp[x], g.rp[x + 1], v);
-}
-
-template <int W>
-__device__ __forceinline__ void load_row(const int32_t *__restrict__ rows, const GraphDev &g, int64_t r,
-                                         int32_t (&f)[W]) {
-    if constexpr (W == 2) {
-        f[0] = g.src[r];
-        f[1] = g.col[r];
-    } else {
-#pragma unroll
-        for (int p = 0; p < W; ++p) f[p] = rows[r * W + p];
-    }
-}
-
-__device__ __forceinline__ bool in_slice(int32_t v, const DevPlan &P) {
-    return (uint32_t)(mix64((uint64_t)(uint32_t)v) % P.slice_count) == P.slice_id;
-}
-
-// Validity of a level-2 row (the SCAN of the first query edge): the
-// constraint between positions 0 and 1 and the root slice.
-__device__ __forceinline__ bool level2_ok(const int32_t (&f)[2], const DevPlan &P) {
-    const DevStep &s1 = P.st[1];
-    if ((s1.lo & 1u) && !(f[0] < f[1])) return false;
-    if ((s1.hi & 1u) && !(f[1] < f[0])) return false;
-    if (P.slice_count > 1) {
-        if (P.st[0].slice && !in_slice(f[0], P)) return false;
-        if (s1.slice && !in_slice(f[1], P)) return false;
-    }
-    return true;
-}
-
-__device__ __forceinline__ unsigned long long wave_sum_u64(unsigned long long x) {
-#pragma unroll
-    for (int d = 32; d > 0; d >>= 1) x += __shfl_xor(x, d, 64);
-    return x;
-}
-__device__ __forceinline__ unsigned long long wave_xor_u64(unsigned long long x) {
-#pragma unroll
-    for (int d = 32; d > 0; d >>= 1) x ^= __shfl_xor(x, d, 64);
-    return x;
-}
 
 // ---------------------------------------------------------------------------
 // prepare
@@ -220,23 +141,6 @@ struct ExtArgs {
     DevPlan P;
 };
 
-// largest r in [lo, hi] with off[r] <= w
-__device__ __forceinline__ int64_t find_row(const int64_t *__restrict__ off, int64_t lo, int64_t hi, int64_t w) {
-    while (lo < hi) {
-        int64_t mid = (lo + hi + 1) >> 1;
-        if (off[mid] <= w) lo = mid; else hi = mid - 1;
-    }
-    return lo;
-}
-
-// first index in [lo, hi) with col[i] > key
-__device__ __forceinline__ int64_t upper_bound(const int32_t *__restrict__ col, int64_t lo, int64_t hi, int32_t key) {
-    while (lo < hi) {
-        int64_t mid = lo + ((hi - lo) >> 1);
-        if (col[mid] <= key) lo = mid + 1; else hi = mid;
-    }
-    return lo;
-}
 
 __device__ __forceinline__ bool lds_contains(const int32_t *s, int32_t n, int32_t key) {
     int32_t lo = 0, hi = n;
@@ -608,22 +512,6 @@ void prepare_w(bool last, const GraphDev &g, const DevPlan &P, const int32_t *ro
 constexpr int kRun = 16;
 constexpr int kMTile = kT * kRun;
 
-// first index in [pos, end) with col[i] >= key; every index before pos holds a smaller value
-__device__ __forceinline__ int64_t gallop(const int32_t *__restrict__ col, int64_t pos, int64_t end, int32_t key) {
-    if (pos >= end || col[pos] >= key) return pos;
-    int64_t lo = pos, step = 1;  // col[lo] < key
-    while (lo + step < end && col[lo + step] < key) {
-        lo += step;
-        step <<= 1;
-    }
-    int64_t hi = min(lo + step, end);
-    lo += 1;
-    while (lo < hi) {
-        int64_t mid = (lo + hi) >> 1;
-        if (col[mid] < key) lo = mid + 1; else hi = mid;
-    }
-    return lo;
-}
 
 template <int W, int MODE>
 __global__ __launch_bounds__(kT) void k_extend_merge(ExtArgs a) {
