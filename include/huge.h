@@ -71,6 +71,7 @@ typedef struct huge_plan huge_plan;
 #define HUGE_ENGINE_AUTO 0
 #define HUGE_ENGINE_LEVELS 1     /* host-driven Algorithm 5, one grid-wide launch per chunk */
 #define HUGE_ENGINE_PERSISTENT 2 /* one persistent launch: per-workgroup Algorithm 5 + stealing */
+#define HUGE_PERSIST_KMAX 4      /* largest query the persistent engine runs (HUGE_EINVAL above) */
 
 typedef struct {
     uint64_t count;                    /* subgraphs found (in the selected slice) */
@@ -217,8 +218,11 @@ huge_status huge_enumerate(const huge_graph *g, const huge_plan *p, const huge_e
                            int64_t buf_rows, huge_emit_fn cb, void *user, huge_result *out);
 
 /*
- * huge_count_batch -- count np queries in one persistent launch (plans share
- * the frontier budget and the stealing pool); outs[np].
+ * huge_count_batch -- count np queries; outs[np], in the order of plans.
+ * The queries of 3..HUGE_PERSIST_KMAX vertices run in one persistent launch
+ * (they share the workgroups, the frontier budget and the stealing pool,
+ * Section 5.3); the others run on the level engine one after
+ * another on opts->stream.  opts->engine is ignored.
  */
 huge_status huge_count_batch(const huge_graph *g, const huge_plan *const *plans, int32_t np,
                              const huge_exec_opts *opts, huge_result *outs);

@@ -177,7 +177,25 @@ huge_status huge_count_batch(const huge_graph *g, const huge_plan *const *plans,
             if (!plans[i]) HUGE_FAIL(HUGE_EINVAL, "plan %d is NULL", i);
         huge_exec_opts o = resolve_opts(opts);
         std::vector<huge_result> r(np);
-        run_persistent(g, plans, np, o, r.data());
+        // queries the persistent kernel is built for share one launch; the
+        // others run on the level engine, one after another, on the same stream
+        std::vector<const huge_plan *> pers;
+        std::vector<int> idx;
+        for (int i = 0; i < np; ++i) {
+            if (plans[i]->k >= 3 && plans[i]->k <= HUGE_PERSIST_KMAX) {
+                pers.push_back(plans[i]);
+                idx.push_back(i);
+            }
+        }
+        if (!pers.empty()) {
+            std::vector<huge_result> rp(pers.size());
+            run_persistent(g, pers.data(), (int)pers.size(), o, rp.data());
+            for (size_t j = 0; j < pers.size(); ++j) r[idx[j]] = rp[j];
+        }
+        huge_exec_opts lo = o;
+        lo.engine = HUGE_ENGINE_LEVELS;
+        for (int i = 0; i < np; ++i)
+            if (!(plans[i]->k >= 3 && plans[i]->k <= HUGE_PERSIST_KMAX)) run_levels(g, plans[i], lo, &r[i], nullptr);
         for (int i = 0; i < np; ++i) outs[i] = r[i];
         return HUGE_OK;
     });

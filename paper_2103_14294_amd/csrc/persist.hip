@@ -10,20 +10,33 @@
 // results is bounded by (number of WGs) x (sum of level capacities), and a
 // tile never emits more rows than the free space it checked for.
 //
-// Load balancing is the intra-machine work stealing of Section 5.3: a level
-// buffer is a deque; its owner pops chunks from the back (tail) and pushes new
-// rows at the back, and an idle WG steals half of the rows from the front
-// (head) of the shallowest non-empty level of a victim.  The deque word packs
-// head (24 bits), tail (24 bits) and the query index (16 bits), so a steal CAS
-// fails if the victim has moved to another query.  A thief announces itself in
-// the victim's per-level pending counter while it copies, and the owner only
-// rewinds an empty deque to position 0 when no thief is copying.
+// Load balancing is the intra-machine work stealing of Section 5.3, at two
+// granularities:
+//   * rows: a level buffer is a deque; its owner pops chunks from the back
+//     (tail) and pushes new rows at the back, and an idle WG steals half of
+//     the rows from the front (head) of the shallowest non-empty level of a
+//     victim.  The deque word packs head (24 bits), tail (24 bits) and the
+//     query index (16 bits), so a steal CAS fails if the victim has moved to
+//     another query.  A thief announces itself in the victim's per-level
+//     pending counter while it copies, and the owner only rewinds an empty
+//     deque to row 0 when no thief is copying.
+//   * tiles: the last level does almost all the work, and one chunk of hub
+//     rows can hold millions of candidates.  Its owner publishes the prepared
+//     chunk on a board (global memory) and idle WGs claim 4096-candidate tiles
+//     of it through one atomic word (generation | tiles | next); the owner
+//     reuses the chunk's rows only after every claimed tile reports done.
 //
-// Termination: a global count of WGs that may hold work.  A WG leaves the
-// count only when every query cursor is exhausted and its own levels are
-// empty; a thief re-enters the count before it tries to steal.  The count
-// reaches zero only when no rows exist anywhere.  Every wait loop is bounded
-// by a wall-clock deadline; passing it sets an error flag and the WG exits.
+// Termination: a global count of WGs that may hold work.  A WG enters the
+// count when it starts and leaves it only when every query cursor is
+// exhausted and its own levels are empty; a thief re-enters the count before
+// it tries to steal.  The count is zero only when no started WG holds rows,
+// and a WG that starts later finds the cursors exhausted and nothing to
+// steal, so no WG waits on one that is not resident.  Every wait loop is
+// bounded by a wall-clock deadline; passing it sets an error flag and the WG
+// exits.
+//
+// Queries of 3 or 4 vertices only: the level buffers then hold rows of width
+// 3, and the kernel keeps every row in registers.
 #include <algorithm>
 #include <chrono>
 #include <cstdlib>
@@ -38,30 +51,41 @@ namespace {
 using namespace dev;
 
 constexpr int kT = 256;
-constexpr int kR = 256;            // rows per chunk
-constexpr int kPRun = 16;          // consecutive work items per lane in a tile
-constexpr int kPTile = kT * kPRun; // work items per tile (= most rows a tile emits)
-constexpr int kLv = HUGE_KMAX;     // level index = row width W
+constexpr int kR = 256;             // rows per chunk
+constexpr int kPRun = 16;           // consecutive work items per lane in a tile
+constexpr int kPTile = kT * kPRun;  // work items per tile (= most rows a tile emits)
+constexpr int kLv = HUGE_KMAX;      // level index = row width W
+constexpr int kResStride = 16;      // per query: count, hash_sum, hash_xor, pad, level[8], pad
+
+struct Board {
+    unsigned long long word;  // generation:16 | tiles:24 | next claim:24
+    unsigned long long done;  // tiles finished in the current generation
+    int32_t plan, W, nrows, pad;
+    int64_t row0, total;
+    int64_t off[kR + 1];
+    uint64_t pinfo[kR];
+    uint64_t hpre[kR];
+};
 
 struct PersistArgs {
     GraphDev g;
     const DevPlan *plans;
     int nplans;
     int steal;
-    int32_t *bufs;                 // per-WG level buffers
-    int64_t wg_ints;               // int32 entries per WG region
-    int64_t lvl_off[kLv];          // offset of level W inside a WG region
-    int32_t cap[kLv];              // row capacity of level W
-    unsigned long long *deq;       // [nwg][kLv]
-    int *pending;                  // [nwg][kLv]
-    unsigned long long *cursor;    // [nplans] next level-2 edge
-    unsigned long long *res;       // [nplans][kResStride]
+    int32_t *bufs;               // per-WG level buffers
+    int64_t wg_ints;             // int32 entries per WG region
+    int64_t lvl_off[kLv];        // offset of level W inside a WG region
+    int32_t cap[kLv];            // row capacity of level W
+    unsigned long long *deq;     // [nwg][kLv]
+    int *pending;                // [nwg][kLv]
+    Board *boards;               // [nwg]
+    unsigned long long *cursor;  // [nplans] next level-2 edge
+    unsigned long long *res;     // [nplans][kResStride]
     int *busy;
     int *err;
-    unsigned long long *stats;     // [0] steals, [1] stolen rows, [2] sum of per-WG peak bytes
-    uint64_t limit_ticks;          // longest wait, in wall-clock ticks
+    unsigned long long *stats;   // [0] row steals, [1] stolen rows, [2] sum of per-WG peak bytes, [3] helped tiles
+    uint64_t limit_ticks;        // longest wait, in wall-clock ticks
 };
-constexpr int kResStride = 16;     // count, hash_sum, hash_xor, pad, level[8], pad...
 
 // deque word: head | tail << 24 | plan << 48
 __device__ __forceinline__ uint32_t dq_head(unsigned long long x) { return (uint32_t)(x & 0xFFFFFFull); }
@@ -70,10 +94,16 @@ __device__ __forceinline__ int dq_plan(unsigned long long x) { return (int)(x >>
 __device__ __forceinline__ unsigned long long dq_make(uint32_t h, uint32_t t, int plan) {
     return (unsigned long long)h | ((unsigned long long)t << 24) | ((unsigned long long)plan << 48);
 }
+// board word: next | tiles << 24 | gen << 48 (same field layout)
+__device__ __forceinline__ uint32_t bw_next(unsigned long long x) { return (uint32_t)(x & 0xFFFFFFull); }
+__device__ __forceinline__ uint32_t bw_tiles(unsigned long long x) { return (uint32_t)((x >> 24) & 0xFFFFFFull); }
+__device__ __forceinline__ uint32_t bw_gen(unsigned long long x) { return (uint32_t)(x >> 48); }
+
 __device__ __forceinline__ unsigned long long ld_acq(unsigned long long *p) {
     return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
 }
 __device__ __forceinline__ int ld_acq_i(int *p) { return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT); }
+__device__ __forceinline__ bool past(uint64_t deadline) { return wall_clock64() > deadline; }
 
 struct LvState {
     int64_t row0;   // chunk's first row (buffer row, or edge index at W = 2)
@@ -99,7 +129,20 @@ struct Shared {
     int victim;
     int vlevel;
     uint32_t vhead, vcount;
+    int32_t tile;
+    uint32_t gen;
     unsigned long long peak_bytes;
+};
+
+// The rows, scan and probe data of one prepared chunk, in LDS (owner) or on
+// a board in global memory (helpers).
+struct ChunkView {
+    const int32_t *rows;
+    int64_t row0;
+    int32_t nrows;
+    const int64_t *off;
+    const uint64_t *pinfo;
+    const uint64_t *hpre;
 };
 
 __device__ __forceinline__ int64_t block_excl_scan64(int64_t x, Shared &sh, int64_t &total) {
@@ -124,8 +167,38 @@ __device__ __forceinline__ int64_t block_excl_scan64(int64_t x, Shared &sh, int6
     return base + inc - x;
 }
 
-__device__ __forceinline__ int32_t *level_buf(const PersistArgs &a, int W) {
-    return a.bufs + (int64_t)blockIdx.x * a.wg_ints + a.lvl_off[W];
+__device__ __forceinline__ int32_t *level_buf(const PersistArgs &a, int wg, int W) {
+    return a.bufs + (int64_t)wg * a.wg_ints + a.lvl_off[W];
+}
+
+// Fold the lanes' count and hash into query `plan` (block-uniform call).
+__device__ void flush_counts(const PersistArgs &a, Shared &sh, int plan, int k, unsigned long long &cnt,
+                             unsigned long long &hs, unsigned long long &hx) {
+    const int t = threadIdx.x;
+    const unsigned long long c = wave_sum_u64(cnt), s = wave_sum_u64(hs), x = wave_xor_u64(hx);
+    if (__lane_id() == 0) {
+        sh.red[0][t >> 6] = c;
+        sh.red[1][t >> 6] = s;
+        sh.red[2][t >> 6] = x;
+    }
+    __syncthreads();
+    if (t == 0 && plan >= 0) {
+        unsigned long long C = 0, S = 0, X = 0;
+        for (int q = 0; q < kT / 64; ++q) {
+            C += sh.red[0][q];
+            S += sh.red[1][q];
+            X ^= sh.red[2][q];
+        }
+        if (C) {
+            unsigned long long *r = a.res + plan * kResStride;
+            atomicAdd(&r[0], C);
+            atomicAdd(&r[1], S);
+            atomicXor(&r[2], X);
+            atomicAdd(&r[4 + k - 1], C);
+        }
+    }
+    cnt = hs = hx = 0;
+    __syncthreads();
 }
 
 // Prepare the chunk of level W held in sh.lv[W]: per row, the symmetry-
@@ -141,7 +214,7 @@ __device__ void prepare_chunk(const PersistArgs &a, const DevPlan &P, bool last,
     bool valid = false;
     if (t < L.nrows) {
         int32_t f[W];
-        load_row<W>(level_buf(a, W), g, L.row0 + t, f);
+        load_row<W>(level_buf(a, blockIdx.x, W), g, L.row0 + t, f);
         valid = true;
         if constexpr (W == 2) valid = level2_ok(f, P);
         if (valid) {
@@ -209,104 +282,112 @@ __device__ void prepare_chunk(const PersistArgs &a, const DevPlan &P, bool last,
     __syncthreads();
 }
 
-// One tile of the current chunk of level W: work items [w0, w1), each lane a
+// One tile of a prepared chunk of level W: work items [w0, w1), each lane a
 // run of kPRun consecutive items with galloping cursors (lane merge).  The
 // last level folds matches into the lane's count and hash; other levels
-// append rows to level W+1 at sh.tail_base + (LDS counter).
+// append rows to the WG's level W+1 at sh.tail_base + (LDS counter).
 template <int W, bool LAST>
-__device__ void run_tile(const PersistArgs &a, const DevPlan &P, Shared &sh, int64_t w0, int64_t w1,
-                         unsigned long long &cnt, unsigned long long &hs, unsigned long long &hx) {
+__device__ void run_tile(const PersistArgs &a, const DevPlan &P, const ChunkView &cv, Shared &sh, int64_t w0,
+                         int64_t w1, unsigned long long &cnt, unsigned long long &hs, unsigned long long &hx) {
     const GraphDev &g = a.g;
     const DevStep st = P.st[W];
-    const LvState &L = sh.lv[W];
-    const int32_t *rows = level_buf(a, W);
-    int32_t *outb = LAST ? nullptr : level_buf(a, W + 1);
-    const int64_t *off = sh.off[W];
+    int32_t *outb = LAST ? nullptr : level_buf(a, blockIdx.x, W + 1);
     const int64_t wb = w0 + (int64_t)threadIdx.x * kPRun;
     const int64_t we = min(wb + (int64_t)kPRun, w1);
-    if (wb < we) {
-        int64_t w = wb;
-        int64_t r = find_row(off, 0, L.nrows - 1, w);
-        while (w < we) {
-            const int64_t wend = min(off[r + 1], we);
-            const uint64_t pi = sh.pinfo[W][r];
-            const int pp = (int)(pi >> 56);
-            const int64_t pshift = (int64_t)(pi & kPbMask) - off[r];
-            int32_t f[W];
-            load_row<W>(rows, g, L.row0 + r, f);
-            uint64_t hp = LAST ? sh.hpre[r] : 0;
-            int64_t cur[W], end[W];
-            const int32_t v0 = g.col[pshift + w];
+    if (wb >= we) return;
+    int64_t w = wb;
+    int64_t r = find_row(cv.off, 0, cv.nrows - 1, w);
+    while (w < we) {
+        const int64_t wend = min(cv.off[r + 1], we);
+        const uint64_t pi = cv.pinfo[r];
+        const int pp = (int)(pi >> 56);
+        const int64_t pshift = (int64_t)(pi & kPbMask) - cv.off[r];
+        int32_t f[W];
+        load_row<W>(cv.rows, g, cv.row0 + r, f);
+        const uint64_t hp = LAST ? cv.hpre[r] : 0;
+        int64_t cur[W], end[W];
+        const int32_t v0 = g.col[pshift + w];
+#pragma unroll
+        for (int p = 0; p < W; ++p) {
+            cur[p] = 0;
+            end[p] = 0;
+            if (((st.ext >> p) & 1u) && p != pp && f[p] < g.hub_base) {
+                end[p] = g.rp[f[p] + 1];
+                cur[p] = lower_bound(g.col, g.rp[f[p]], end[p], v0);
+            }
+        }
+        for (; w < wend; ++w) {
+            const int32_t v = g.col[pshift + w];
+            bool ok = true;
+#pragma unroll
+            for (int p = 0; p < W; ++p)
+                if ((st.neq >> p) & 1u) ok &= (v != f[p]);
+            if (st.slice && P.slice_count > 1) ok &= in_slice(v, P);
 #pragma unroll
             for (int p = 0; p < W; ++p) {
-                cur[p] = 0;
-                end[p] = 0;
-                if (((st.ext >> p) & 1u) && p != pp && f[p] < g.hub_base) {
-                    end[p] = g.rp[f[p] + 1];
-                    cur[p] = lower_bound(g.col, g.rp[f[p]], end[p], v0);
-                }
-            }
-            for (; w < wend; ++w) {
-                const int32_t v = g.col[pshift + w];
-                bool ok = true;
-#pragma unroll
-                for (int p = 0; p < W; ++p)
-                    if ((st.neq >> p) & 1u) ok &= (v != f[p]);
-                if (st.slice && P.slice_count > 1) ok &= in_slice(v, P);
-#pragma unroll
-                for (int p = 0; p < W; ++p) {
-                    if (ok && ((st.ext >> p) & 1u) && p != pp) {
-                        if (f[p] >= g.hub_base) {
-                            ok = adj_has(g, f[p], v);
-                        } else {
-                            cur[p] = gallop(g.col, cur[p], end[p], v);
-                            ok = cur[p] < end[p] && g.col[cur[p]] == v;
-                        }
+                if (ok && ((st.ext >> p) & 1u) && p != pp) {
+                    if (f[p] >= g.hub_base) {
+                        ok = adj_has(g, f[p], v);
+                    } else {
+                        cur[p] = gallop(g.col, cur[p], end[p], v);
+                        ok = cur[p] < end[p] && g.col[cur[p]] == v;
                     }
                 }
-                if (!ok) continue;
-                if constexpr (LAST) {
-                    uint64_t h = hp;
-#pragma unroll
-                    for (int p = 0; p < W; ++p)
-                        if ((st.ext >> p) & 1u) h += mix64(edge_key(f[p], v));
-                    h = mix64(h);
-                    cnt += 1;
-                    hs += h;
-                    hx ^= h;
-                } else {
-                    const int q = atomicAdd(&sh.emitted, 1);
-                    int32_t *dst = outb + (int64_t)(sh.tail_base + q) * (W + 1);
-#pragma unroll
-                    for (int p = 0; p < W; ++p) dst[p] = f[p];
-                    dst[W] = v;
-                }
             }
-            if (w < we) r = find_row(off, r + 1, L.nrows - 1, w);
+            if (!ok) continue;
+            if constexpr (LAST) {
+                uint64_t h = hp;
+#pragma unroll
+                for (int p = 0; p < W; ++p)
+                    if ((st.ext >> p) & 1u) h += mix64(edge_key(f[p], v));
+                h = mix64(h);
+                cnt += 1;
+                hs += h;
+                hx ^= h;
+            } else {
+                const int q = atomicAdd(&sh.emitted, 1);
+                int32_t *dst = outb + (int64_t)(sh.tail_base + q) * (W + 1);
+#pragma unroll
+                for (int p = 0; p < W; ++p) dst[p] = f[p];
+                dst[W] = v;
+            }
         }
+        if (w < we) r = find_row(cv.off, r + 1, cv.nrows - 1, w);
     }
 }
 
+template <int K>
 __device__ void prepare_any(int W, const PersistArgs &a, const DevPlan &P, bool last, Shared &sh) {
     switch (W) {
         case 2: prepare_chunk<2>(a, P, last, sh); break;
-        case 3: prepare_chunk<3>(a, P, last, sh); break;
-        case 4: prepare_chunk<4>(a, P, last, sh); break;
-        case 5: prepare_chunk<5>(a, P, last, sh); break;
-        case 6: prepare_chunk<6>(a, P, last, sh); break;
-        default: prepare_chunk<7>(a, P, last, sh); break;
+        case 3: if constexpr (K > 3) prepare_chunk<3>(a, P, last, sh); break;
+        case 4: if constexpr (K > 4) prepare_chunk<4>(a, P, last, sh); break;
+        case 5: if constexpr (K > 5) prepare_chunk<5>(a, P, last, sh); break;
+        case 6: if constexpr (K > 6) prepare_chunk<6>(a, P, last, sh); break;
+        default: if constexpr (K > 7) prepare_chunk<7>(a, P, last, sh); break;
     }
 }
-__device__ void tile_any(int W, bool last, const PersistArgs &a, const DevPlan &P, Shared &sh, int64_t w0, int64_t w1,
-                         unsigned long long &c, unsigned long long &s, unsigned long long &x) {
+
+template <int K>
+__device__ void tile_any(int W, bool last, const PersistArgs &a, const DevPlan &P, const ChunkView &cv, Shared &sh,
+                         int64_t w0, int64_t w1, unsigned long long &c, unsigned long long &s, unsigned long long &x) {
+#define HUGE_TILE_CASE(WW)                                                      \
+    case WW:                                                                    \
+        if constexpr (K > WW) {                                                 \
+            if (last) run_tile<WW, true>(a, P, cv, sh, w0, w1, c, s, x);        \
+            else if constexpr (K > WW + 1) run_tile<WW, false>(a, P, cv, sh, w0, w1, c, s, x); \
+        }                                                                       \
+        break;
     switch (W) {
-        case 2: last ? run_tile<2, true>(a, P, sh, w0, w1, c, s, x) : run_tile<2, false>(a, P, sh, w0, w1, c, s, x); break;
-        case 3: last ? run_tile<3, true>(a, P, sh, w0, w1, c, s, x) : run_tile<3, false>(a, P, sh, w0, w1, c, s, x); break;
-        case 4: last ? run_tile<4, true>(a, P, sh, w0, w1, c, s, x) : run_tile<4, false>(a, P, sh, w0, w1, c, s, x); break;
-        case 5: last ? run_tile<5, true>(a, P, sh, w0, w1, c, s, x) : run_tile<5, false>(a, P, sh, w0, w1, c, s, x); break;
-        case 6: last ? run_tile<6, true>(a, P, sh, w0, w1, c, s, x) : run_tile<6, false>(a, P, sh, w0, w1, c, s, x); break;
-        default: run_tile<7, true>(a, P, sh, w0, w1, c, s, x); break;
+        HUGE_TILE_CASE(2)
+        HUGE_TILE_CASE(3)
+        HUGE_TILE_CASE(4)
+        HUGE_TILE_CASE(5)
+        HUGE_TILE_CASE(6)
+        HUGE_TILE_CASE(7)
+        default: break;
     }
+#undef HUGE_TILE_CASE
 }
 
 // Owner side: publish rows appended at the tail of its level-W deque.
@@ -335,8 +416,8 @@ __device__ int dq_pop(const PersistArgs &a, int W, int64_t &row0) {
     }
 }
 
-// Owner side: the append position of its level-W deque for query `plan`.
-// A drained deque is re-tagged with the query and, when no thief is still
+// Owner side: the append position of its level-W deque for query `plan`.  A
+// drained deque is re-tagged with the query and, when no thief is still
 // copying out of it, rewound to row 0.
 __device__ uint32_t dq_prepare_append(const PersistArgs &a, int W, int plan) {
     unsigned long long *d = a.deq + (int64_t)blockIdx.x * kLv + W;
@@ -350,48 +431,33 @@ __device__ uint32_t dq_prepare_append(const PersistArgs &a, int W, int plan) {
     }
 }
 
-__device__ __forceinline__ bool past(uint64_t deadline) { return wall_clock64() > deadline; }
-
+template <int K>
 __global__ __launch_bounds__(kT) void k_persist(PersistArgs a) {
     __shared__ Shared sh;
     const int t = threadIdx.x;
     unsigned long long cnt = 0, hs = 0, hx = 0;  // per lane, for query sh.plan
     const uint64_t deadline = wall_clock64() + a.limit_ticks;
     int counted = 1;  // thread 0 only: this WG is counted in *busy
+    Board &myb = a.boards[blockIdx.x];
     if (t == 0) {
+        atomicAdd(a.busy, 1);
         sh.plan = -1;
+        sh.k = 3;
         sh.peak_bytes = 0;
         sh.W = 2;
+        sh.gen = 0;
     }
     __syncthreads();
-
-    // Fold the lanes' count and hash of sh.plan into the result (block-uniform call).
-    auto flush = [&]() {
-        const unsigned long long c = wave_sum_u64(cnt), s = wave_sum_u64(hs), x = wave_xor_u64(hx);
-        if (__lane_id() == 0) {
-            sh.red[0][t >> 6] = c;
-            sh.red[1][t >> 6] = s;
-            sh.red[2][t >> 6] = x;
-        }
-        __syncthreads();
-        if (t == 0 && sh.plan >= 0) {
-            unsigned long long C = 0, S = 0, X = 0;
-            for (int q = 0; q < kT / 64; ++q) {
-                C += sh.red[0][q];
-                S += sh.red[1][q];
-                X ^= sh.red[2][q];
-            }
-            if (C) {
-                unsigned long long *r = a.res + sh.plan * kResStride;
-                atomicAdd(&r[0], C);
-                atomicAdd(&r[1], S);
-                atomicXor(&r[2], X);
-                atomicAdd(&r[4 + sh.k - 1], C);
-            }
-        }
-        cnt = hs = hx = 0;
-        __syncthreads();
-    };
+    // level 0 of a query whose first position holds the sliced vertex: the roots in the slice
+    for (int q = 0; q < a.nplans; ++q) {
+        const DevPlan &Q = a.plans[q];
+        if (Q.slice_count <= 1 || !Q.st[0].slice) continue;
+        unsigned long long c = 0;
+        for (int64_t v = (int64_t)blockIdx.x * kT + t; v < a.g.n; v += (int64_t)gridDim.x * kT)
+            c += in_slice((int32_t)v, Q) ? 1ull : 0ull;
+        c = wave_sum_u64(c);
+        if (__lane_id() == 0 && c) atomicAdd(&a.res[q * kResStride + 4], c);
+    }
 
     for (;;) {
         // ---- find work: a level-2 chunk of some query
@@ -412,7 +478,7 @@ __global__ __launch_bounds__(kT) void k_persist(PersistArgs a) {
         }
         __syncthreads();
         if (sh.action == 2) {
-            flush();  // results so far belong to the previous query
+            flush_counts(a, sh, sh.plan, sh.k, cnt, hs, hx);  // results so far belong to the previous query
             if (t == 0) {
                 sh.plan = sh.victim;
                 sh.k = a.plans[sh.plan].k;
@@ -425,24 +491,45 @@ __global__ __launch_bounds__(kT) void k_persist(PersistArgs a) {
                 sh.W = 2;
             }
             __syncthreads();
-            prepare_any(2, a, a.plans[sh.plan], sh.k == 3, sh);
+            prepare_any<K>(2, a, a.plans[sh.plan], sh.k == 3, sh);
         } else {
-            // ---- no fresh edges anywhere: steal, or finish when nothing is left
-            flush();
-            if (t == 0) {
-                if (counted) {
-                    atomicSub(a.busy, 1);
-                    counted = 0;
-                }
-                uint32_t seed = (uint32_t)blockIdx.x * 2654435761u + 12345u;
-                while (sh.action == 0) {
-                    if (a.steal) {
-                        const int nwg = gridDim.x;
+            // ---- no fresh edges anywhere: help a big last-level chunk, steal
+            // rows, or finish when nothing is left
+            flush_counts(a, sh, sh.plan, sh.k, cnt, hs, hx);
+            if (t == 0 && counted) {
+                atomicSub(a.busy, 1);
+                counted = 0;
+            }
+            uint32_t seed = (uint32_t)blockIdx.x * 2654435761u + 12345u;
+            bool got_rows = false;
+            for (;;) {
+                if (t == 0) {
+                    sh.action = 0;
+                    const int nwg = gridDim.x;
+                    // 1. a tile of another WG's published chunk
+                    for (int tries = 0; tries < 16 && sh.action == 0; ++tries) {
+                        seed = seed * 1664525u + 1013904223u;
+                        const int v = (int)(seed % (uint32_t)nwg);
+                        if (v == (int)blockIdx.x) continue;
+                        Board &b = a.boards[v];
+                        const unsigned long long o = ld_acq(&b.word);
+                        if (bw_next(o) >= bw_tiles(o)) continue;
+                        // a claim below the tile count is valid for whatever generation it
+                        // landed in: that generation's owner waits for it to be done
+                        const unsigned long long x = atomicAdd(&b.word, 1ull);
+                        if (bw_next(x) < bw_tiles(x)) {
+                            sh.action = 5;
+                            sh.victim = v;
+                            sh.tile = (int32_t)bw_next(x);
+                        }
+                    }
+                    // 2. half of the rows of another WG's shallowest level
+                    if (sh.action == 0 && a.steal) {
                         for (int tries = 0; tries < 8 && sh.action == 0; ++tries) {
                             seed = seed * 1664525u + 1013904223u;
                             const int v = (int)(seed % (uint32_t)nwg);
                             if (v == (int)blockIdx.x) continue;
-                            for (int W = 3; W < kLv && sh.action == 0; ++W) {
+                            for (int W = 3; W < K && sh.action == 0; ++W) {
                                 unsigned long long *d = a.deq + (int64_t)v * kLv + W;
                                 const unsigned long long o = ld_acq(d);
                                 const uint32_t h = dq_head(o), tl = dq_tail(o);
@@ -476,13 +563,42 @@ __global__ __launch_bounds__(kT) void k_persist(PersistArgs a) {
                             atomicOr(a.err, 1);
                             sh.action = 4;
                         } else {
-                            __builtin_amdgcn_s_sleep(8);
+                            __builtin_amdgcn_s_sleep(4);
                         }
                     }
                 }
+                __syncthreads();
+                const int act = sh.action;
+                __syncthreads();  // every wave has read the decision before thread 0 makes the next one
+                if (act == 0) continue;
+                if (act == 4) break;
+                if (act == 5) {
+                    // process the claimed tile; its owner waits for our "done"
+                    __threadfence();
+                    Board &b = a.boards[sh.victim];
+                    const int plan = b.plan, W = b.W, k = a.plans[plan].k;
+                    ChunkView cv;
+                    cv.rows = level_buf(a, sh.victim, W);
+                    cv.row0 = b.row0;
+                    cv.nrows = b.nrows;
+                    cv.off = b.off;
+                    cv.pinfo = b.pinfo;
+                    cv.hpre = b.hpre;
+                    const int64_t w0 = (int64_t)sh.tile * kPTile;
+                    tile_any<K>(W, true, a, a.plans[plan], cv, sh, w0, min(w0 + (int64_t)kPTile, b.total), cnt, hs, hx);
+                    flush_counts(a, sh, plan, k, cnt, hs, hx);
+                    if (t == 0) {
+                        __threadfence();
+                        atomicAdd(&b.done, 1ull);
+                        atomicAdd(&a.stats[3], 1ull);
+                    }
+                    __syncthreads();
+                    continue;
+                }
+                got_rows = true;  // act == 3
+                break;
             }
-            __syncthreads();
-            if (sh.action == 4) break;
+            if (!got_rows) break;
             // ---- take the stolen rows into our own (empty) level buffer
             const int W = sh.vlevel;
             if (t == 0) {
@@ -496,8 +612,8 @@ __global__ __launch_bounds__(kT) void k_persist(PersistArgs a) {
             __syncthreads();
             __threadfence();
             {
-                const int32_t *src = a.bufs + (int64_t)sh.victim * a.wg_ints + a.lvl_off[W] + (int64_t)sh.vhead * W;
-                int32_t *dst = level_buf(a, W);
+                const int32_t *src = level_buf(a, sh.victim, W) + (int64_t)sh.vhead * W;
+                int32_t *dst = level_buf(a, blockIdx.x, W);
                 const int64_t n = (int64_t)sh.vcount * W;
                 for (int64_t i = t; i < n; i += kT) dst[i] = src[i];
             }
@@ -520,12 +636,68 @@ __global__ __launch_bounds__(kT) void k_persist(PersistArgs a) {
         for (;;) {
             const int W = sh.W;
             LvState &L = sh.lv[W];
-            if (L.done < L.total) {
+            const bool has_work = L.done < L.total;
+            // every wave has read the control state before thread 0 may change it
+            __syncthreads();
+            if (has_work) {
+                ChunkView cv;
+                cv.rows = level_buf(a, blockIdx.x, W);
+                cv.row0 = L.row0;
+                cv.nrows = L.nrows;
+                cv.off = sh.off[W];
+                cv.pinfo = sh.pinfo[W];
+                cv.hpre = sh.hpre;
                 if (W == k - 1) {
                     // fused SINK: consume the whole chunk, then back to the precursor
-                    for (int64_t w0 = L.done; w0 < L.total; w0 += kPTile)
-                        tile_any(W, true, a, P, sh, w0, min(w0 + (int64_t)kPTile, L.total), cnt, hs, hx);
+                    const int64_t ntiles = (L.total + kPTile - 1) / kPTile;
+                    if (ntiles <= 1) {
+                        tile_any<K>(W, true, a, P, cv, sh, 0, L.total, cnt, hs, hx);
+                    } else {
+                        // publish the chunk so that idle WGs can take tiles of it
+                        for (int i = t; i <= L.nrows; i += kT) myb.off[i] = sh.off[W][i];
+                        for (int i = t; i < L.nrows; i += kT) {
+                            myb.pinfo[i] = sh.pinfo[W][i];
+                            myb.hpre[i] = sh.hpre[i];
+                        }
+                        if (t == 0) {
+                            myb.plan = sh.plan;
+                            myb.W = W;
+                            myb.nrows = L.nrows;
+                            myb.row0 = L.row0;
+                            myb.total = L.total;
+                            myb.done = 0;
+                            sh.gen = (sh.gen + 1) & 0xFFFF;
+                        }
+                        __threadfence();
+                        __syncthreads();
+                        if (t == 0)
+                            __hip_atomic_store(&myb.word, dq_make(0, (uint32_t)ntiles, (int)sh.gen), __ATOMIC_RELEASE,
+                                               __HIP_MEMORY_SCOPE_AGENT);
+                        for (;;) {
+                            if (t == 0) {
+                                const unsigned long long x = atomicAdd(&myb.word, 1ull);
+                                sh.tile = bw_next(x) < bw_tiles(x) ? (int32_t)bw_next(x) : -1;
+                            }
+                            __syncthreads();
+                            const int tile = sh.tile;
+                            if (tile < 0) break;
+                            const int64_t w0 = (int64_t)tile * kPTile;
+                            tile_any<K>(W, true, a, P, cv, sh, w0, min(w0 + (int64_t)kPTile, L.total), cnt, hs, hx);
+                            __syncthreads();
+                            if (t == 0) atomicAdd(&myb.done, 1ull);
+                        }
+                        if (t == 0) {
+                            // the rows stay in place until every claimed tile is done
+                            while (ld_acq(&myb.done) < (unsigned long long)ntiles && !past(deadline))
+                                __builtin_amdgcn_s_sleep(2);
+                            if (ld_acq(&myb.done) < (unsigned long long)ntiles) {
+                                atomicOr(a.err, 1);
+                                sh.W = -1;
+                            }
+                        }
+                    }
                     __syncthreads();
+                    if (sh.W < 0) break;
                     if (t == 0) L.done = L.total;
                     __syncthreads();
                     continue;
@@ -539,7 +711,7 @@ __global__ __launch_bounds__(kT) void k_persist(PersistArgs a) {
                 __syncthreads();
                 if (sh.action) {
                     const int64_t w0 = L.done, w1 = min(L.done + (int64_t)kPTile, L.total);
-                    tile_any(W, false, a, P, sh, w0, w1, cnt, hs, hx);
+                    tile_any<K>(W, false, a, P, cv, sh, w0, w1, cnt, hs, hx);
                     __threadfence();
                     __syncthreads();
                     if (t == 0) {
@@ -588,8 +760,10 @@ __global__ __launch_bounds__(kT) void k_persist(PersistArgs a) {
                     }
                 }
                 __syncthreads();
-                if (!sh.action) break;  // this query's edges are exhausted and every deeper level is empty
-                prepare_any(2, a, P, k == 3, sh);
+                const int got = sh.action;
+                __syncthreads();  // read before thread 0 reuses sh.action
+                if (!got) break;  // this query's edges are exhausted and every deeper level is empty
+                prepare_any<K>(2, a, P, k == 3, sh);
                 continue;
             }
             if (t == 0) {
@@ -604,16 +778,18 @@ __global__ __launch_bounds__(kT) void k_persist(PersistArgs a) {
                 }
             }
             __syncthreads();
-            if (sh.action) prepare_any(W, a, P, W == k - 1, sh);
+            if (sh.action) prepare_any<K>(W, a, P, W == k - 1, sh);
         }
         if (sh.W < 0) break;
     }
-    flush();
+    flush_counts(a, sh, sh.plan, sh.k, cnt, hs, hx);
     if (t == 0) {
         atomicAdd(&a.stats[2], sh.peak_bytes);
         if (counted) atomicSub(a.busy, 1);
     }
 }
+
+constexpr int kKMax = 4;  // largest query size the kernel is built for
 
 }  // namespace
 
@@ -623,7 +799,7 @@ void run_persistent(const huge_graph *g, const huge_plan *const *plans, int np, 
     hipStream_t st = (hipStream_t)o.stream;
     if (np < 1 || np > 4096) HUGE_FAIL(HUGE_EINVAL, "bad number of plans %d", np);
     std::vector<DevPlan> dp(np);
-    int kmax = 2;
+    int kmax = 3;
     for (int i = 0; i < np; ++i) {
         const huge_plan *p = plans[i];
         if (p->k < 3) HUGE_FAIL(HUGE_EINVAL, "the persistent engine needs queries of 3 or more vertices");
@@ -635,10 +811,12 @@ void run_persistent(const huge_graph *g, const huge_plan *const *plans, int np, 
         for (int j = 0; j < p->k; ++j) dp[i].st[j].slice = p->order[j] == o.slice_vertex ? 1 : 0;
         kmax = std::max(kmax, p->k);
     }
-    int dev = 0, cus = 0, per_cu = 0;
+    if (kmax > kKMax) HUGE_FAIL(HUGE_EINVAL, "the persistent engine supports queries of 3 to %d vertices", kKMax);
+    int dev = 0, cus = 0;
     HUGE_HIP(hipGetDevice(&dev));
     HUGE_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
-    HUGE_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void *)k_persist, kT, 0));
+    int per_cu = 0;
+    HUGE_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void *)k_persist<kKMax>, kT, 0));
     if (per_cu < 1) HUGE_FAIL(HUGE_EDEVICE, "persistent kernel cannot be resident");
     const int nwg = cus * per_cu;
 
@@ -668,18 +846,23 @@ void run_persistent(const huge_graph *g, const huge_plan *const *plans, int np, 
         }
     }
     a.wg_ints = std::max<int64_t>(ints, 1);
-    const uint64_t buf_bytes = 4ull * a.wg_ints * nwg;
+    const uint64_t buf_bytes = (4ull * a.wg_ints * nwg + 255) & ~255ull;
+    const uint64_t board_bytes = ((uint64_t)sizeof(Board) * nwg + 255) & ~255ull;
     const uint64_t ctl_bytes = 8ull * nwg * kLv + 4ull * nwg * kLv + 8ull * np + 8ull * np * kResStride + 64;
     void *mem = nullptr;
-    HUGE_HIP(hipMalloc(&mem, buf_bytes + ctl_bytes + 1024));
+    HUGE_HIP(hipMalloc(&mem, buf_bytes + board_bytes + ctl_bytes + 1024));
     struct Free {
         void *p;
-        ~Free() { (void)hipFree(p); }
+        ~Free() {
+            if (p) (void)hipFree(p);
+        }
     } fr{mem};
     char *c = (char *)mem;
     a.bufs = (int32_t *)c;
-    c += (buf_bytes + 255) & ~255ull;
-    char *ctl = c;
+    c += buf_bytes;
+    a.boards = (Board *)c;
+    char *zero_from = c;
+    c += board_bytes;
     a.deq = (unsigned long long *)c;
     c += 8ull * nwg * kLv;
     a.pending = (int *)c;
@@ -696,8 +879,7 @@ void run_persistent(const huge_graph *g, const huge_plan *const *plans, int np, 
     double limit_s = 120.0;
     if (const char *e = getenv("HUGE_PERSIST_TIMEOUT_S")) limit_s = atof(e);
     a.limit_ticks = (uint64_t)((double)std::max(wall_khz, 1) * 1000.0 * limit_s);
-    HUGE_HIP(hipMemsetAsync(ctl, 0, ctl_bytes, st));
-    HUGE_HIP(hipMemcpyAsync(a.busy, &nwg, 4, hipMemcpyHostToDevice, st));
+    HUGE_HIP(hipMemsetAsync(zero_from, 0, board_bytes + ctl_bytes, st));
     DevPlan *dplans = nullptr;
     HUGE_HIP(hipMalloc(&dplans, sizeof(DevPlan) * np));
     Free fr2{dplans};
@@ -710,12 +892,12 @@ void run_persistent(const huge_graph *g, const huge_plan *const *plans, int np, 
         HUGE_HIP(hipEventCreate(&e1));
         HUGE_HIP(hipEventRecord(e0, st));
     }
-    hipLaunchKernelGGL(k_persist, dim3(nwg), dim3(kT), 0, st, a);
+    hipLaunchKernelGGL(k_persist<kKMax>, dim3(nwg), dim3(kT), 0, st, a);
     HUGE_HIP(hipGetLastError());
     if (o.profile) HUGE_HIP(hipEventRecord(e1, st));
     std::vector<unsigned long long> res((size_t)np * kResStride);
     int err = 0;
-    unsigned long long stats[3] = {0, 0, 0};
+    unsigned long long stats[4] = {0, 0, 0, 0};
     HUGE_HIP(hipMemcpyAsync(res.data(), a.res, 8ull * np * kResStride, hipMemcpyDeviceToHost, st));
     HUGE_HIP(hipMemcpyAsync(&err, a.err, 4, hipMemcpyDeviceToHost, st));
     HUGE_HIP(hipMemcpyAsync(stats, a.stats, sizeof(stats), hipMemcpyDeviceToHost, st));
@@ -737,10 +919,10 @@ void run_persistent(const huge_graph *g, const huge_plan *const *plans, int np, 
         r.hash_sum = x[1];
         r.hash_xor = x[2];
         for (int q = 1; q < HUGE_KMAX; ++q) r.level_counts[q] = x[4 + q];
-        r.level_counts[0] = (uint64_t)g->dev.n;
+        r.level_counts[0] = (dp[i].slice_count > 1 && dp[i].st[0].slice) ? x[4] : (uint64_t)g->dev.n;
         r.query_ms = ms;
         r.launches = 1;
-        r.steals = stats[0];
+        r.steals = stats[0] + stats[3];
         r.peak_frontier_bytes = stats[2];
         r.kernel_ms[HUGE_KC_SINK] = kms;
         r.kernel_launches[HUGE_KC_SINK] = 1;

@@ -9,6 +9,18 @@ from tests.gpu_common import assert_parity, cmp_key, need_gpu, oracle_run
 pytestmark = pytest.mark.gpu
 
 PERSIST = 2
+KMAX = 4  # largest query the persistent kernel is built for
+
+# A persistent-kernel variant for queries of 5 or more vertices hung on the
+# house query (k=5, stealing on) and the cause was not found; that variant is
+# switched off (the library rejects k > 4 on this engine) and these cases stay
+# skipped until it is rebuilt and shown correct.
+K5_OFF = "persistent engine is off for k >= 5 (a variant hung on house, cause not found)"
+
+
+def _k5(name):
+    k = P.NAMED[name][0]
+    return pytest.param(name, marks=pytest.mark.skip(reason=K5_OFF)) if k > KMAX else name
 
 
 @pytest.fixture(scope="module")
@@ -23,8 +35,8 @@ def small(H):
 
 
 @pytest.mark.parametrize("steal", [1, 0])
-@pytest.mark.parametrize("name", ["triangle", "4-cycle", "diamond", "4-clique", "house", "5-clique", "tailed-triangle",
-                                  "5-cycle", "6-cycle"])
+@pytest.mark.parametrize("name", [_k5(n) for n in ["triangle", "4-cycle", "diamond", "4-clique", "house", "5-clique",
+                                                   "tailed-triangle", "5-cycle", "6-cycle", "3-star", "4-path"]])
 def test_persistent_named(H, small, name, steal):
     g, G = small
     k, e = P.NAMED[name]
@@ -32,32 +44,47 @@ def test_persistent_named(H, small, name, steal):
     assert r["count"] > 0
 
 
-def test_persistent_small_frontier_steals(H, small):
+def test_persistent_rejects_large_queries(H, small):
+    _, G = small
+    k, e = P.NAMED["house"]
+    with pytest.raises(RuntimeError, match="persistent engine supports"):
+        H.count(G, H.plan(G, k, e), engine=PERSIST)
+
+
+@pytest.mark.parametrize("name", [_k5(n) for n in ["house", "5-clique", "4-cycle", "diamond", "4-clique"]])
+def test_persistent_small_frontier(H, small, name):
     """A small frontier budget keeps per-workgroup levels short, so rows move between workgroups."""
     g, G = small
-    for name in ["house", "5-clique", "4-cycle"]:
-        k, e = P.NAMED[name]
-        r, _ = assert_parity(H, G, g, k, e, engine=PERSIST, cap=0)
+    k, e = P.NAMED[name]
+    assert_parity(H, G, g, k, e, engine=PERSIST, cap=0)
+
+
+def test_persistent_small_frontier_skewed(H):
     big = gg.rmat(12, 16, seed=4)
     Gb = H.load(big.row_ptr, big.col)
-    k, e = P.NAMED["4-cycle"]
-    a = H.count(Gb, H.plan(Gb, k, e), engine=PERSIST, cap=0)
-    b = H.count(Gb, H.plan(Gb, k, e))
-    assert cmp_key(a, k) == cmp_key(b, k)
-    assert a["level_counts"][:k] == b["level_counts"][:k]
+    for name in ["4-cycle", "diamond"]:
+        k, e = P.NAMED[name]
+        p = H.plan(Gb, k, e)
+        a = H.count(Gb, p, engine=PERSIST, cap=0)
+        b = H.count(Gb, p)
+        assert cmp_key(a, k) == cmp_key(b, k)
+        assert a["level_counts"][:k] == b["level_counts"][:k]
 
 
-def test_persistent_slices(H, small):
+@pytest.mark.parametrize("name", [_k5("house"), "4-cycle", "diamond"])
+def test_persistent_slices(H, small, name):
     g, G = small
-    k, e = P.NAMED["house"]
+    k, e = P.NAMED[name]
     for s in range(3):
         assert_parity(H, G, g, k, e, engine=PERSIST, slice_count=3, slice_id=s, slice_vertex=1)
 
 
-def test_batched_patterns_match_single_runs(H):
+@pytest.mark.parametrize("kmax", [4, 5])
+def test_batched_patterns_match_single_runs(H, kmax):
+    """Queries of 3..4 vertices share one persistent launch; larger ones run on the level engine."""
     g = gg.chung_lu(2000, 8, 2.5, seed=33)
     G = H.load(g.row_ptr, g.col)
-    pats = P.random_patterns(16, seed=3, kmin=3, kmax=5)
+    pats = P.random_patterns(16, seed=3, kmin=3, kmax=kmax)
     plans = [H.plan(G, p["k"], p["edges"]) for p in pats]
     outs = H.count_batch(G, plans)
     for p, pl, r in zip(pats, plans, outs):
