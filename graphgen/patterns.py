@@ -85,13 +85,20 @@ def _family(rng, k):
     return fam, e
 
 
-def random_patterns(count, seed, kmin=3, kmax=6, accept=None, max_tries=100000):
-    """``count`` distinct (up to isomorphism) random connected patterns.
+def random_patterns(count, seed, kmin=3, kmax=6, accept=None, max_tries=100000, distinct="iso"):
+    """``count`` distinct random connected patterns.
 
-    ``accept(k, edges) -> bool`` lets the caller reject patterns (for example
-    by an estimated result budget).  Returns a list of dicts
-    {"k", "edges", "family"} with vertices relabelled by a seeded permutation.
+    ``distinct="iso"`` keeps one pattern per isomorphism class (there are only
+    139 connected graphs of 4..6 vertices); ``distinct="labelled"`` keeps
+    distinct labelled edge sets, so isomorphic patterns with different vertex
+    numbering (hence different symmetry-breaking constraints and prefixes)
+    count separately.  ``accept(k, edges) -> bool`` lets the caller reject
+    patterns (for example by an estimated result budget).  Returns a list of
+    dicts {"k", "edges", "family"} with vertices relabelled by a seeded
+    permutation.
     """
+    if distinct not in ("iso", "labelled"):
+        raise ValueError("distinct must be 'iso' or 'labelled'")
     rng = random.Random(seed)
     out, seen = [], set()
     tries = 0
@@ -104,7 +111,7 @@ def random_patterns(count, seed, kmin=3, kmax=6, accept=None, max_tries=100000):
         e = sorted({(min(perm[a], perm[b]), max(perm[a], perm[b])) for a, b in e})
         if not is_connected(k, e):
             continue
-        cf = (k, canonical_form(k, e))
+        cf = (k, canonical_form(k, e)) if distinct == "iso" else (k, tuple(e))
         if cf in seen:
             continue
         if accept is not None and not accept(k, e):

@@ -65,7 +65,7 @@ typedef struct huge_plan huge_plan;
 
 /* huge_plan flags */
 #define HUGE_PLAN_COST_MODEL 0x0u /* order from the cost model (Algorithm 1, wco plans) */
-#define HUGE_PLAN_LEARNED 0x1u    /* order from the learned cardinality model (see huge_mlp_*) */
+#define HUGE_PLAN_LEARNED 0x1u    /* order from the learned cardinality model (huge_plan_create_learned) */
 
 /* huge_exec_opts.engine */
 #define HUGE_ENGINE_AUTO 0
@@ -226,6 +226,76 @@ huge_status huge_enumerate(const huge_graph *g, const huge_plan *p, const huge_e
  */
 huge_status huge_count_batch(const huge_graph *g, const huge_plan *const *plans, int32_t np,
                              const huge_exec_opts *opts, huge_result *outs);
+
+/* ------------------------------------------------------------------------
+ * Learned cardinality model.  The optimiser of Section 3.3 (Algorithm 1)
+ * needs the result size |R(q')| of each order prefix and leaves the estimator
+ * open; this is a 2-layer MLP that predicts log(1 + |R(prefix)|) from
+ * HUGE_MLP_F features of the prefix and of the graph's degree sketch:
+ *     y = b2 + sum_h W2[h] relu(b1[h] + sum_f W1[f][h] xn[f]),
+ *     xn[f] = (x[f] - xmean[f]) * xinv[f],  label = y * tstd + tmean.
+ * Parameters (float, HUGE_MLP_PARAMS of them) are laid out as
+ * W1[f * HUGE_MLP_H + h] | b1[HUGE_MLP_H] | W2[HUGE_MLP_H] | b2.  The library
+ * keeps FP32 master weights and computes with their BF16 (round to nearest
+ * even) copies, accumulating in FP32.  A model lives on the device that was
+ * current when it was created; its calls must run there.
+ * ------------------------------------------------------------------------ */
+#define HUGE_MLP_F 128
+#define HUGE_MLP_H 256
+#define HUGE_MLP_PARAMS (HUGE_MLP_F * HUGE_MLP_H + 2 * HUGE_MLP_H + 1)
+typedef struct huge_model huge_model;
+
+/* A model with zero weights, xmean 0, xinv 1, tmean 0, tstd 1.  Errors: HUGE_ENOMEM, HUGE_EDEVICE. */
+huge_status huge_model_create(huge_model **out);
+void huge_model_free(huge_model *m);
+
+/*
+ * Set host-side values; NULL leaves that part unchanged.  Setting params also
+ * resets the Adam state.  Errors: HUGE_EINVAL (non-finite parameter, tstd <= 0).
+ */
+huge_status huge_model_set(huge_model *m, const float *params, const float *xmean, const float *xinv, float tmean,
+                           float tstd);
+huge_status huge_model_get(const huge_model *m, float *params, float *xmean, float *xinv, float *tmean, float *tstd);
+
+/* y[B] = predicted log(1 + |R|) for x[B][HUGE_MLP_F]; device pointers, asynchronous on stream. */
+huge_status huge_model_forward(const huge_model *m, const float *x, int64_t B, float *y, void *stream);
+
+/*
+ * Gradient of L = (1/B) sum_r (yn_r - (t_r - tmean)/tstd)^2, yn the network
+ * output before de-standardisation, at the current BF16 weights.  x, t device;
+ * grad host float[HUGE_MLP_PARAMS] (or NULL); loss host (or NULL).  Blocks.
+ */
+huge_status huge_model_grad(const huge_model *m, const float *x, const float *t, int64_t B, float *grad, double *loss,
+                            void *stream);
+
+/*
+ * Train with Adam (beta1 0.9, beta2 0.999, eps 1e-8, step size lr) on n
+ * samples x[n][HUGE_MLP_F], t[n] (device), `epochs` passes of minibatches of
+ * `batch` samples, reshuffled each pass from `seed`.  loss_out (host
+ * float[epochs] or NULL) receives each pass's mean squared error in
+ * standardised units.  Blocks.  Errors: HUGE_EINVAL, HUGE_ENOMEM, HUGE_EDEVICE.
+ */
+huge_status huge_model_train(huge_model *m, const float *x, const float *t, int64_t n, int32_t epochs, int64_t batch,
+                             float lr, uint64_t seed, float *loss_out, void *stream);
+
+/*
+ * The model's input for prefix `size` (2..k) of `order` (NULL = the plan's
+ * order) of plan p's query on graph g: out host float[HUGE_MLP_F].
+ */
+huge_status huge_plan_features(const huge_graph *g, const huge_plan *p, const int32_t *order, int32_t size,
+                               float *out);
+
+/*
+ * huge_plan_create with the learned model as the estimator: every connected
+ * order is scored in one batched forward pass on `stream` and the order with
+ * the smallest estimated sum of prefix sizes wins (ties to the
+ * lexicographically smallest), exactly as the cost model does with its own
+ * estimates.  The plan only decides the order (and chunk sizes): counts are
+ * exact whatever it picks.  huge_plan_create with HUGE_PLAN_LEARNED and no
+ * model returns HUGE_EINVAL.
+ */
+huge_status huge_plan_create_learned(const huge_graph *g, const huge_model *m, int32_t k, int32_t n_qedges,
+                                     const int32_t *qedges, const int32_t *order, void *stream, huge_plan **out);
 
 const char *huge_last_error(void);
 

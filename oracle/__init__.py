@@ -13,6 +13,8 @@ never imports this package, and this package never imports the library.
   distinct image edge sets.
 * ``set_hash`` is the per-subgraph hash h(g) written from its definition, used
   by ``brute_force``.
+* ``mlp_ref`` (a submodule) is the FP64 reference of the learned cardinality
+  model: forward pass, loss gradient and one Adam step.
 """
 from __future__ import annotations
 

@@ -30,7 +30,11 @@ EXPORTED = [
     "huge_exec_opts_default", "huge_load_csr", "huge_graph_free", "huge_graph_get_info", "huge_graph_export",
     "huge_plan_create", "huge_plan_free", "huge_plan_info", "huge_workspace_size", "huge_count",
     "huge_enumerate", "huge_count_batch", "huge_last_error",
+    "huge_model_create", "huge_model_free", "huge_model_set", "huge_model_get", "huge_model_forward",
+    "huge_model_grad", "huge_model_train", "huge_plan_features", "huge_plan_create_learned",
 ]
+MLP_F, MLP_H = 128, 256
+MLP_PARAMS = MLP_F * MLP_H + 2 * MLP_H + 1
 
 
 class HugeError(RuntimeError):
@@ -117,6 +121,25 @@ def load_library(path: str = LIB_PATH):
         lib.huge_count_batch.argtypes = [vp, ctypes.POINTER(vp), i32, ctypes.POINTER(ExecOpts), ctypes.POINTER(Result)]
         lib.huge_last_error.restype = ctypes.c_char_p
         lib.huge_last_error.argtypes = []
+        f32, f64 = ctypes.c_float, ctypes.c_double
+        lib.huge_model_create.restype = st
+        lib.huge_model_create.argtypes = [ctypes.POINTER(vp)]
+        lib.huge_model_free.restype = None
+        lib.huge_model_free.argtypes = [vp]
+        lib.huge_model_set.restype = st
+        lib.huge_model_set.argtypes = [vp, vp, vp, vp, f32, f32]
+        lib.huge_model_get.restype = st
+        lib.huge_model_get.argtypes = [vp, vp, vp, vp, ctypes.POINTER(f32), ctypes.POINTER(f32)]
+        lib.huge_model_forward.restype = st
+        lib.huge_model_forward.argtypes = [vp, vp, i64, vp, vp]
+        lib.huge_model_grad.restype = st
+        lib.huge_model_grad.argtypes = [vp, vp, vp, i64, vp, ctypes.POINTER(f64), vp]
+        lib.huge_model_train.restype = st
+        lib.huge_model_train.argtypes = [vp, vp, vp, i64, i32, i64, f32, ctypes.c_uint64, vp, vp]
+        lib.huge_plan_features.restype = st
+        lib.huge_plan_features.argtypes = [vp, vp, vp, i32, vp]
+        lib.huge_plan_create_learned.restype = st
+        lib.huge_plan_create_learned.argtypes = [vp, vp, i32, i32, vp, vp, vp, ctypes.POINTER(vp)]
         _lib = lib
         return lib
 
@@ -238,16 +261,122 @@ def load(row_ptr, col, validate=True, stream=None, hub_bitmaps=True) -> Graph:
     return Graph(h.value, int(n), int(nnz))
 
 
-def plan(g: Graph, k, edges, order=None, learned=False) -> Plan:
-    """huge_plan_create for query edges over vertices 0..k-1."""
+def plan(g: Graph, k, edges, order=None, learned=None) -> Plan:
+    """huge_plan_create for query edges over vertices 0..k-1; with a Model as
+    `learned`, huge_plan_create_learned (orders scored by the MLP on the GPU)."""
     lib = load_library()
     e = np.ascontiguousarray(np.asarray(edges, dtype=np.int32).reshape(-1, 2))
     o = None if order is None else np.ascontiguousarray(np.asarray(order, dtype=np.int32))
     h = ctypes.c_void_p()
-    _check(lib.huge_plan_create(None if g is None else g.handle, int(k), int(e.shape[0]), e.ctypes.data,
-                                None if o is None else o.ctypes.data, PLAN_LEARNED if learned else PLAN_COST_MODEL,
-                                ctypes.byref(h)))
+    if isinstance(learned, Model):
+        _check(lib.huge_plan_create_learned(g.handle, learned.handle, int(k), int(e.shape[0]), e.ctypes.data,
+                                            None if o is None else o.ctypes.data, _current_stream(),
+                                            ctypes.byref(h)))
+    else:
+        _check(lib.huge_plan_create(None if g is None else g.handle, int(k), int(e.shape[0]), e.ctypes.data,
+                                    None if o is None else o.ctypes.data,
+                                    PLAN_LEARNED if learned else PLAN_COST_MODEL, ctypes.byref(h)))
     return Plan(h.value, int(k))
+
+
+def plan_features(g: Graph, p: Plan, size: int, order=None) -> np.ndarray:
+    """huge_plan_features: the learned model's input for one order prefix."""
+    lib = load_library()
+    out = np.zeros(MLP_F, dtype=np.float32)
+    o = None if order is None else np.ascontiguousarray(np.asarray(order, dtype=np.int32))
+    _check(lib.huge_plan_features(g.handle, p.handle, None if o is None else o.ctypes.data, int(size),
+                                  out.ctypes.data))
+    return out
+
+
+class Model:
+    """The learned cardinality model (huge_model_*): parameters live on the GPU."""
+
+    def __init__(self):
+        lib = load_library()
+        h = ctypes.c_void_p()
+        _check(lib.huge_model_create(ctypes.byref(h)))
+        self._h = h
+
+    @property
+    def handle(self):
+        return self._h
+
+    def set(self, params=None, xmean=None, xinv=None, tmean=0.0, tstd=1.0):
+        arrs = []
+        for a, n in ((params, MLP_PARAMS), (xmean, MLP_F), (xinv, MLP_F)):
+            if a is None:
+                arrs.append(None)
+                continue
+            a = np.ascontiguousarray(a, dtype=np.float32)
+            if a.shape != (n,):
+                raise ValueError("expected %d values, got shape %s" % (n, a.shape))
+            arrs.append(a)
+        _check(_lib.huge_model_set(self._h, *[None if a is None else a.ctypes.data for a in arrs],
+                                   float(tmean), float(tstd)))
+        return self
+
+    def get(self):
+        p = np.empty(MLP_PARAMS, dtype=np.float32)
+        xm = np.empty(MLP_F, dtype=np.float32)
+        xi = np.empty(MLP_F, dtype=np.float32)
+        tm, ts = ctypes.c_float(), ctypes.c_float()
+        _check(_lib.huge_model_get(self._h, p.ctypes.data, xm.ctypes.data, xi.ctypes.data, ctypes.byref(tm),
+                                   ctypes.byref(ts)))
+        return {"params": p, "xmean": xm, "xinv": xi, "tmean": tm.value, "tstd": ts.value}
+
+    @staticmethod
+    def _dev(a):
+        torch = _torch()
+        return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).cuda()
+
+    def forward(self, X) -> np.ndarray:
+        torch = _torch()
+        x = self._dev(np.asarray(X, dtype=np.float32).reshape(-1, MLP_F))
+        y = torch.empty(x.shape[0], dtype=torch.float32, device=x.device)
+        _check(_lib.huge_model_forward(self._h, x.data_ptr(), int(x.shape[0]), y.data_ptr(), _current_stream()))
+        torch.cuda.synchronize()
+        return y.cpu().numpy()
+
+    def grad(self, X, t):
+        x = self._dev(np.asarray(X, dtype=np.float32).reshape(-1, MLP_F))
+        tt = self._dev(np.asarray(t, dtype=np.float32).reshape(-1))
+        g = np.empty(MLP_PARAMS, dtype=np.float32)
+        loss = ctypes.c_double()
+        _check(_lib.huge_model_grad(self._h, x.data_ptr(), tt.data_ptr(), int(x.shape[0]), g.ctypes.data,
+                                    ctypes.byref(loss), _current_stream()))
+        return g, loss.value
+
+    def train(self, X, t, epochs=100, batch=256, lr=1e-3, seed=0):
+        x = self._dev(np.asarray(X, dtype=np.float32).reshape(-1, MLP_F))
+        tt = self._dev(np.asarray(t, dtype=np.float32).reshape(-1))
+        losses = np.empty(int(epochs), dtype=np.float32)
+        _check(_lib.huge_model_train(self._h, x.data_ptr(), tt.data_ptr(), int(x.shape[0]), int(epochs), int(batch),
+                                     float(lr), int(seed) & ((1 << 64) - 1), losses.ctypes.data, _current_stream()))
+        return losses
+
+    def save(self, path):
+        d = self.get()
+        np.savez(path, params=d["params"], xmean=d["xmean"], xinv=d["xinv"],
+                 tnorm=np.array([d["tmean"], d["tstd"]], dtype=np.float32))
+
+    @classmethod
+    def load(cls, path):
+        with np.load(path, allow_pickle=False) as z:
+            m = cls()
+            m.set(z["params"], z["xmean"], z["xinv"], float(z["tnorm"][0]), float(z["tnorm"][1]))
+        return m
+
+    def free(self):
+        if self._h and self._h.value and _lib is not None:
+            _lib.huge_model_free(self._h)
+            self._h = ctypes.c_void_p(None)
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
 
 
 def exec_opts(cap=None, chunk_rows=0, strategy=-1, engine=ENGINE_AUTO, work_stealing=1, slice_count=1, slice_id=0,

@@ -96,7 +96,8 @@ huge_status huge_plan_create(const huge_graph *g, int32_t k, int32_t n_qedges, c
         if (!out) HUGE_FAIL(HUGE_EINVAL, "NULL argument");
         huge_plan *p = new huge_plan();
         try {
-            plan_build(g, k, n_qedges, qedges, order, flags, p);
+            if (flags & HUGE_PLAN_LEARNED) HUGE_FAIL(HUGE_EINVAL, "a learned plan needs a model: use huge_plan_create_learned");
+            plan_build(g, k, n_qedges, qedges, order, flags, nullptr, nullptr, p);
         } catch (...) {
             delete p;
             throw;
@@ -197,6 +198,87 @@ huge_status huge_count_batch(const huge_graph *g, const huge_plan *const *plans,
         for (int i = 0; i < np; ++i)
             if (!(plans[i]->k >= 3 && plans[i]->k <= HUGE_PERSIST_KMAX)) run_levels(g, plans[i], lo, &r[i], nullptr);
         for (int i = 0; i < np; ++i) outs[i] = r[i];
+        return HUGE_OK;
+    });
+}
+
+huge_status huge_model_create(huge_model **out) {
+    return guard([&] {
+        if (!out) HUGE_FAIL(HUGE_EINVAL, "out is NULL");
+        *out = model_create();
+        return HUGE_OK;
+    });
+}
+
+void huge_model_free(huge_model *m) { model_free(m); }
+
+huge_status huge_model_set(huge_model *m, const float *params, const float *xmean, const float *xinv, float tmean,
+                           float tstd) {
+    return guard([&] {
+        if (!m) HUGE_FAIL(HUGE_EINVAL, "NULL model");
+        model_set(m, params, xmean, xinv, tmean, tstd);
+        return HUGE_OK;
+    });
+}
+
+huge_status huge_model_get(const huge_model *m, float *params, float *xmean, float *xinv, float *tmean, float *tstd) {
+    return guard([&] {
+        if (!m) HUGE_FAIL(HUGE_EINVAL, "NULL model");
+        model_get(m, params, xmean, xinv, tmean, tstd);
+        return HUGE_OK;
+    });
+}
+
+huge_status huge_model_forward(const huge_model *m, const float *x, int64_t B, float *y, void *stream) {
+    return guard([&] {
+        if (!m || B < 0 || (B > 0 && (!x || !y))) HUGE_FAIL(HUGE_EINVAL, "bad arguments");
+        model_forward(m, x, B, y, (hipStream_t)stream);
+        return HUGE_OK;
+    });
+}
+
+huge_status huge_model_grad(const huge_model *m, const float *x, const float *t, int64_t B, float *grad, double *loss,
+                            void *stream) {
+    return guard([&] {
+        if (!m || !x || !t || B <= 0) HUGE_FAIL(HUGE_EINVAL, "bad arguments");
+        model_grad(m, x, t, B, grad, loss, (hipStream_t)stream);
+        return HUGE_OK;
+    });
+}
+
+huge_status huge_model_train(huge_model *m, const float *x, const float *t, int64_t n, int32_t epochs, int64_t batch,
+                             float lr, uint64_t seed, float *loss_out, void *stream) {
+    return guard([&] {
+        if (!m || !x || !t || !(lr > 0.f)) HUGE_FAIL(HUGE_EINVAL, "bad arguments");
+        model_train(m, x, t, n, epochs, batch, lr, seed, loss_out, (hipStream_t)stream);
+        return HUGE_OK;
+    });
+}
+
+huge_status huge_plan_features(const huge_graph *g, const huge_plan *p, const int32_t *order, int32_t size,
+                               float *out) {
+    return guard([&] {
+        if (!g || !p || !out) HUGE_FAIL(HUGE_EINVAL, "NULL argument");
+        if (size < 2 || size > p->k) HUGE_FAIL(HUGE_EINVAL, "prefix size %d outside 2..%d", size, p->k);
+        if (order && !order_connected(*p, order))
+            HUGE_FAIL(HUGE_EORDER, "order is not a permutation of 0..k-1 with connected prefixes");
+        plan_features(g->info, *p, order ? order : p->order, size, out);
+        return HUGE_OK;
+    });
+}
+
+huge_status huge_plan_create_learned(const huge_graph *g, const huge_model *m, int32_t k, int32_t n_qedges,
+                                     const int32_t *qedges, const int32_t *order, void *stream, huge_plan **out) {
+    return guard([&] {
+        if (!g || !m || !out) HUGE_FAIL(HUGE_EINVAL, "NULL argument");
+        huge_plan *p = new huge_plan();
+        try {
+            plan_build(g, k, n_qedges, qedges, order, HUGE_PLAN_LEARNED, m, (hipStream_t)stream, p);
+        } catch (...) {
+            delete p;
+            throw;
+        }
+        *out = p;
         return HUGE_OK;
     });
 }

@@ -103,15 +103,43 @@ struct huge_plan {
     huge::DevPlan dev{};
 };
 
+// learned cardinality model (mlp.hip): FP32 master weights, BF16 copies used
+// by the kernels, Adam moments and the feature / target standardisation
+struct huge_model {
+    void *mem = nullptr;
+    float *w = nullptr, *m = nullptr, *v = nullptr;  // [HUGE_MLP_PARAMS] each
+    uint16_t *wb = nullptr;                          // BF16 copy of w
+    float *xmean = nullptr, *xinv = nullptr;         // [HUGE_MLP_F]
+    float tmean = 0.f, tstd = 1.f;
+    int64_t step = 0;  // Adam steps taken
+    int device = 0;
+};
+
 namespace huge {
 
 // plan.cpp
 void plan_build(const huge_graph *g, int k, int ne, const int32_t *qe, const int32_t *order, uint32_t flags,
-                huge_plan *out);
+                const huge_model *model, hipStream_t st, huge_plan *out);
 bool order_connected(const huge_plan &p, const int32_t *order);
 void plan_set_order(huge_plan &p, const int32_t *order);
 double estimate_prefix(const huge_graph_info &gi, const huge_plan &p, const int32_t *order, int size);
 void all_connected_orders(const huge_plan &p, std::vector<std::vector<int32_t>> &out);
+
+// learn.cpp
+void plan_features(const huge_graph_info &gi, const huge_plan &p, const int32_t *order, int size, float *out);
+void learned_estimates(const huge_graph *g, const huge_model *m, const huge_plan &p,
+                       const std::vector<std::vector<int32_t>> &orders, hipStream_t st, std::vector<double> &est);
+
+// mlp.hip
+huge_model *model_create();
+void model_free(huge_model *m);
+void model_set(huge_model *m, const float *params, const float *xmean, const float *xinv, float tmean, float tstd);
+void model_get(const huge_model *m, float *params, float *xmean, float *xinv, float *tmean, float *tstd);
+void model_forward(const huge_model *m, const float *x, int64_t B, float *y, hipStream_t st);
+void model_grad(const huge_model *m, const float *x, const float *t, int64_t B, float *grad_host, double *loss,
+                hipStream_t st);
+void model_train(huge_model *m, const float *x, const float *t, int64_t N, int epochs, int64_t batch, float lr,
+                 uint64_t seed, float *loss_out, hipStream_t st);
 
 // graph.hip
 huge_graph *graph_load(int64_t n, int64_t nnz, const int64_t *rp, const int32_t *col, uint32_t flags,

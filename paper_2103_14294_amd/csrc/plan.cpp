@@ -219,36 +219,45 @@ void plan_set_order(huge_plan &p, const int32_t *order) {
 }
 
 void plan_build(const huge_graph *g, int k, int ne, const int32_t *qe, const int32_t *order, uint32_t flags,
-                huge_plan *p) {
+                const huge_model *model, hipStream_t st, huge_plan *p) {
     static const huge_graph_info no_stats{};
     const huge_graph_info &gi = g ? g->info : no_stats;
+    const bool learned = (flags & HUGE_PLAN_LEARNED) != 0;
+    if (learned && (!model || !g)) HUGE_FAIL(HUGE_EINVAL, "a learned plan needs a graph and a model");
     check_query(k, ne, qe, p);
     grochow_kellis(*p);
     p->flags = flags;
-    std::vector<int32_t> chosen(k);
+    std::vector<std::vector<int32_t>> orders;
     if (order) {
         if (!order_connected(*p, order))
             HUGE_FAIL(HUGE_EORDER, "order is not a permutation of 0..k-1 with connected prefixes");
-        for (int i = 0; i < k; ++i) chosen[i] = order[i];
+        orders.emplace_back(order, order + k);
     } else {
-        // plain cost-model plan: minimum estimated total partial matches,
-        // ties to the lexicographically smallest order
-        std::vector<std::vector<int32_t>> orders;
-        all_connected_orders(*p, orders);
-        double best = INFINITY;
-        for (auto &o : orders) {
-            double c = 0;
-            for (int s = 2; s <= k; ++s) c += estimate_prefix(gi, *p, o.data(), s);
-            if (c < best * (1 - 1e-12)) {
-                best = c;
-                chosen = o;
-            }
+        all_connected_orders(*p, orders);  // lexicographic
+    }
+    // estimated |R(prefix_s)| of every candidate order, s = 1..k
+    std::vector<double> est(orders.size() * (size_t)k, 0.0);
+    if (learned) {
+        learned_estimates(g, model, *p, orders, st, est);
+    } else {
+        for (size_t o = 0; o < orders.size(); ++o)
+            for (int s = 1; s <= k; ++s) est[o * k + s - 1] = estimate_prefix(gi, *p, orders[o].data(), s);
+    }
+    // minimum estimated total partial matches, ties to the lexicographically smallest order
+    size_t chosen = 0;
+    double best = INFINITY;
+    for (size_t o = 0; o < orders.size(); ++o) {
+        double c = 0;
+        for (int s = 2; s <= k; ++s) c += est[o * k + s - 1];
+        if (c < best * (1 - 1e-12)) {
+            best = c;
+            chosen = o;
         }
     }
-    plan_set_order(*p, chosen.data());
+    plan_set_order(*p, orders[chosen].data());
     p->est_cost = 0;
     for (int s = 1; s <= k; ++s) {
-        p->est_prefix[s - 1] = estimate_prefix(gi, *p, chosen.data(), s);
+        p->est_prefix[s - 1] = est[chosen * k + s - 1];
         if (s >= 2) p->est_cost += p->est_prefix[s - 1];
     }
 }

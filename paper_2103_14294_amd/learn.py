@@ -1,0 +1,222 @@
+"""Training of the learned cardinality model on counts the engine produces.
+
+Labels: for a query q and a matching order pi, the engine's per-level counts
+are |R(prefix_s)| for s = 2..k (level_counts[s-1]).  Runs on a root slice of
+S (matches whose first matched vertex u has mix(rank u) mod S == s0) scale
+each count by S; the slice count S is chosen from the cost model's estimate
+so that one run stays short.  Each labelled pattern is run on one training
+graph, with the cost-model order and with one random connected order, and
+every prefix of every run becomes one sample
+    x = huge_plan_features(graph, plan, s, order),  t = log(1 + S * level_counts[s-1]).
+
+Training runs in the library's HIP kernels (huge_model_train: minibatch Adam
+on the BF16/FP32 MLP).  This module only orchestrates.
+
+    python -m paper_2103_14294_amd.learn --out paper_2103_14294_amd/card_mlp.npz
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import random
+import sys
+import time
+
+import numpy as np
+
+import paper_2103_14294_amd as huge
+
+# training graphs: the power-law and R-MAT configurations plus smaller members
+# of the same families, so that the graph sketch features vary
+TRAIN_GRAPHS = [
+    ("rmat18", ("rmat", dict(scale=18, edge_factor=16, seed=11))),
+    ("rmat20", ("rmat", dict(scale=20, edge_factor=16, seed=12))),
+    ("rmat22", ("rmat", dict(scale=22, edge_factor=16, seed=2))),
+    ("cl500k", ("chung_lu", dict(n=500_000, dbar=20, gamma=2.5, seed=13))),
+    ("cl1m", ("chung_lu", dict(n=1_000_000, dbar=40, gamma=2.2, seed=14))),
+    ("cl3m", ("chung_lu", dict(n=3_072_441, dbar=76, gamma=2.2, seed=3))),
+    ("rmat24", ("rmat", dict(scale=24, edge_factor=16, seed=4))),
+]
+
+
+def log(*a):
+    print(*a, flush=True)
+
+
+def make_graph(spec):
+    import graphgen as gg
+
+    kind, kw = spec
+    if kind == "rmat":
+        return gg.rmat(kw["scale"], kw["edge_factor"], seed=kw["seed"])
+    return gg.chung_lu(kw["n"], kw["dbar"], kw["gamma"], seed=kw["seed"], exact=kw.get("exact", False))
+
+
+def random_connected_order(k, edges, rng):
+    adj = [[0] * k for _ in range(k)]
+    for a, b in edges:
+        adj[a][b] = adj[b][a] = 1
+    while True:
+        o = list(range(k))
+        rng.shuffle(o)
+        if all(any(adj[o[i]][o[j]] for j in range(i)) for i in range(1, k)):
+            return o
+
+
+def slice_count_for(est_cost, target):
+    if not (est_cost > target):
+        return 1
+    return int(min(1 << 20, 1 << math.ceil(math.log2(est_cost / target))))
+
+
+def label_runs(G, patterns, rng, work_target, deadline, ws, max_est=1e16):
+    """Run every pattern with two orders; returns feature rows, targets and run records."""
+    X, T, runs = [], [], []
+    for i, q in enumerate(patterns):
+        if time.time() > deadline:
+            log("  label budget reached after %d patterns" % i)
+            break
+        k, e = q["k"], q["edges"]
+        p0 = huge.plan(G, k, e)
+        orders = [p0.info()["order"]]
+        ro = random_connected_order(k, e, rng)
+        if ro != orders[0]:
+            orders.append(ro)
+        for o in orders:
+            p = huge.plan(G, k, e, order=o)
+            est = p.info()["est_cost"]
+            if not (est <= max_est):
+                continue  # 64-bit counts and run time are at risk
+            S = slice_count_for(est, work_target)
+            sid = rng.randrange(S)
+            t0 = time.perf_counter()
+            r = huge.count(G, p, slice_count=S, slice_id=sid, slice_vertex=o[0], workspace=ws, hash=False)
+            dt = time.perf_counter() - t0
+            lc = r["level_counts"]
+            for s in range(2, k + 1):
+                X.append(huge.plan_features(G, p, s, order=o))
+                T.append(math.log1p(float(lc[s - 1]) * S))
+            runs.append({"pattern": i, "k": k, "edges": e, "order": o, "S": S, "slice": sid, "ms": dt * 1e3,
+                         "levels": [int(c) for c in lc[:k]], "est_cost": est})
+        if (i + 1) % 50 == 0:
+            log("  %d patterns, %d samples" % (i + 1, len(T)))
+    return X, T, runs
+
+
+def q_error(est, true):
+    a, b = np.maximum(1.0, est), np.maximum(1.0, true)
+    return np.maximum(a / b, b / a)
+
+
+def he_init(seed):
+    rng = np.random.default_rng(seed)
+    F, H = huge.MLP_F, huge.MLP_H
+    w1 = rng.normal(0, math.sqrt(2.0 / F), F * H)
+    w2 = rng.normal(0, math.sqrt(1.0 / H), H)
+    return np.concatenate([w1, np.zeros(H), w2, [0.0]]).astype(np.float32)
+
+
+def fit(X, T, groups, epochs, lr, batch, seed, val_frac=0.1):
+    """Standardise, split by pattern group, train on the GPU; returns the model and a report."""
+    X = np.asarray(X, np.float32)
+    T = np.asarray(T, np.float32)
+    ug = np.unique(groups)
+    rng = np.random.default_rng(seed)
+    val_g = set(rng.choice(ug, max(1, int(len(ug) * val_frac)), replace=False).tolist())
+    val = np.array([g in val_g for g in groups])
+    xm = X[~val].mean(axis=0)
+    xs = X[~val].std(axis=0)
+    xinv = np.where(xs > 1e-6, 1.0 / np.maximum(xs, 1e-6), 0.0).astype(np.float32)
+    tm, ts = float(T[~val].mean()), float(max(T[~val].std(), 1e-3))
+    m = huge.Model().set(he_init(seed), xm.astype(np.float32), xinv, tm, ts)
+    t0 = time.perf_counter()
+    losses = m.train(X[~val], T[~val], epochs=epochs, batch=batch, lr=lr, seed=seed)
+    train_s = time.perf_counter() - t0
+    pv = m.forward(X[val]) if val.any() else np.zeros(0)
+    # Chung-Lu estimate is feature 126 (log(1 + estimate))
+    cl = X[val][:, 126]
+    true = np.expm1(T[val].astype(np.float64))
+    qe_mlp = q_error(np.expm1(pv.astype(np.float64)), true)
+    qe_cl = q_error(np.expm1(cl.astype(np.float64)), true)
+    rep = {"samples_train": int((~val).sum()), "samples_val": int(val.sum()), "patterns_val": len(val_g),
+           "epochs": epochs, "lr": lr, "batch": batch, "train_s": round(train_s, 2),
+           "loss_first": float(losses[0]), "loss_last": float(losses[-1]),
+           "val_rmse_log": float(np.sqrt(np.mean((pv - T[val]) ** 2))) if val.any() else None,
+           "val_qerror_mlp": {"median": float(np.median(qe_mlp)), "p90": float(np.percentile(qe_mlp, 90)),
+                              "geomean": float(np.exp(np.mean(np.log(qe_mlp))))},
+           "val_qerror_chung_lu": {"median": float(np.median(qe_cl)), "p90": float(np.percentile(qe_cl, 90)),
+                                   "geomean": float(np.exp(np.mean(np.log(qe_cl))))}}
+    return m, rep, losses
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--out", required=True, help="model file (.npz)")
+    ap.add_argument("--labels", default=None, help="write / reuse labelled samples (.npz)")
+    ap.add_argument("--patterns", type=int, default=2100)
+    ap.add_argument("--seed", type=int, default=1)
+    ap.add_argument("--work-target", type=float, default=2e9, help="estimated partial matches per labelling run")
+    ap.add_argument("--label-minutes", type=float, default=12.0)
+    ap.add_argument("--graphs", default=",".join(n for n, _ in TRAIN_GRAPHS))
+    ap.add_argument("--epochs", type=int, default=300)
+    ap.add_argument("--lr", type=float, default=1e-3)
+    ap.add_argument("--batch", type=int, default=256)
+    args = ap.parse_args(argv)
+
+    import torch
+
+    torch.cuda.set_device(0)
+    if args.labels and os.path.exists(args.labels):
+        with np.load(args.labels, allow_pickle=False) as z:
+            X, T, groups = z["X"], z["T"], z["groups"]
+        log("reusing %d samples from %s" % (len(T), args.labels))
+        meta = {"labels": args.labels}
+    else:
+        from graphgen import patterns as P
+
+        names = args.graphs.split(",")
+        specs = dict(TRAIN_GRAPHS)
+        pats = P.random_patterns(args.patterns, seed=args.seed, kmin=4, kmax=6, distinct="labelled")
+        log("%d labelled patterns (k: %s)" % (len(pats), {k: sum(p["k"] == k for p in pats) for k in (4, 5, 6)}))
+        rng = random.Random(args.seed)
+        X, T, groups, meta = [], [], [], {"graphs": {}, "patterns": len(pats)}
+        ws = huge.Workspace()
+        t_all = time.time()
+        per_graph = args.label_minutes * 60.0 / len(names)
+        for gi, name in enumerate(names):
+            mine = [p for j, p in enumerate(pats) if j % len(names) == gi]
+            t0 = time.perf_counter()
+            g = make_graph(specs[name])
+            G = huge.load(g.row_ptr, g.col)
+            log("graph %s: n=%d m=%d (%.1f s); %d patterns" % (name, g.n, g.m, time.perf_counter() - t0, len(mine)))
+            x, t, runs = label_runs(G, mine, rng, args.work_target, time.time() + per_graph, ws)
+            # samples of one pattern share a group (the validation split is by pattern)
+            for r in runs:
+                groups.extend([gi * 100000 + r["pattern"]] * (r["k"] - 1))
+            X.extend(x)
+            T.extend(t)
+            meta["graphs"][name] = {"n": g.n, "m": g.m, "runs": len(runs), "samples": len(t),
+                                    "run_ms_total": round(sum(r["ms"] for r in runs), 1)}
+            G.free()
+            del g
+            log("  %s: %d runs, %d samples, %.1f s" % (name, len(runs), len(t), time.perf_counter() - t0))
+        X = np.asarray(X, np.float32)
+        T = np.asarray(T, np.float32)
+        groups = np.asarray(groups, np.int64)
+        meta["label_s"] = round(time.time() - t_all, 1)
+        if args.labels:
+            np.savez(args.labels, X=X, T=T, groups=groups)
+    m, rep, losses = fit(X, T, groups, args.epochs, args.lr, args.batch, args.seed)
+    m.save(args.out)
+    rep.update(meta)
+    rep["loss_curve"] = [float(x) for x in losses[:: max(1, len(losses) // 30)]]
+    with open(os.path.splitext(args.out)[0] + ".json", "w") as f:
+        json.dump(rep, f, indent=1)
+    log(json.dumps({k: v for k, v in rep.items() if k != "loss_curve"}))
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())
