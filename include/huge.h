@@ -104,11 +104,38 @@ typedef struct {
  * the schedule or the symmetry-breaking scheme.
  */
 
+/* intersection strategies (huge_exec_opts.strategy, huge_tune_table.strategy) */
+#define HUGE_STRAT_AUTO -1        /* the tuned table's choice if one is given, else lane merge */
+#define HUGE_STRAT_BSEARCH 0      /* a thread per candidate, binary search (or bitmap) per other list */
+#define HUGE_STRAT_WAVE_STAGED 1  /* a wave stages each row's list windows in LDS, then searches there */
+#define HUGE_STRAT_LANE_MERGE 2   /* a lane per 16 consecutive candidates, galloping cursors per list */
+#define HUGE_STRAT_MERGE_SHORT 3  /* lane merge with 4 candidates per lane */
+#define HUGE_STRAT_MERGE_LONG 4   /* lane merge with 64 candidates per lane (16 when rows are emitted) */
+#define HUGE_STRAT_COUNT 5
+
+/*
+ * Autotuned dispatch (Section 7.3's batch-size knob, and the choice of
+ * intersection kernel): for each number j of intersected lists and each
+ * bucket of the probe (shortest trimmed) list length
+ *     bucket 0: < 2^6, 1: < 2^9, 2: < 2^12, 3: < 2^15, 4: >= 2^15,
+ * a strategy; and per j the rows per scheduling segment.  When a table is
+ * given and strategy is HUGE_STRAT_AUTO, every segment is partitioned by
+ * bucket (a stable counting partition of its rows) and each bucket's work
+ * runs with its own kernel.  Results never depend on the table.
+ */
+#define HUGE_TUNE_BUCKETS 5
+typedef struct {
+    int32_t strategy[HUGE_KMAX + 1][HUGE_TUNE_BUCKETS]; /* [j][bucket]; HUGE_STRAT_AUTO = library default */
+    int64_t chunk_rows[HUGE_KMAX + 1];                  /* [j]; 0 = library default */
+    double ms[HUGE_KMAX + 1][HUGE_TUNE_BUCKETS];        /* huge_autotune: sample time of the chosen strategy */
+    int64_t items[HUGE_KMAX + 1][HUGE_TUNE_BUCKETS];    /* huge_autotune: sample work items (0 = not seen) */
+} huge_tune_table;
+
 typedef struct {
     uint64_t frontier_cap_bytes; /* device bytes for intermediate partial matches;
                                     0 = smallest workable (DFS-like), UINT64_MAX = as large as fits */
     int64_t chunk_rows;          /* rows per scheduling segment; 0 = autotuned / default */
-    int32_t strategy;            /* intersection strategy; -1 = autotuned */
+    int32_t strategy;            /* HUGE_STRAT_*; HUGE_STRAT_AUTO = per the tune table, else lane merge */
     int32_t engine;              /* HUGE_ENGINE_* */
     int32_t work_stealing;       /* persistent engine: 1 = steal, 0 = static root split only */
     int32_t deterministic;       /* reserved: results are exact and order-free either way */
@@ -122,6 +149,10 @@ typedef struct {
                                     vertex partition the matches, so counts add and hashes add / xor */
     uint32_t exec_flags;         /* HUGE_EXEC_* bits */
     uint32_t reserved;
+    const huge_tune_table *tune; /* per-bucket dispatch table, or NULL (read during the call only) */
+    int64_t work_limit;          /* huge_count on the level engine: stop with HUGE_STOPPED once more than this
+                                    many candidates were examined (the result then covers part of the work
+                                    only); 0 = no limit */
 } huge_exec_opts;
 #define HUGE_EXEC_NO_HASH 0x1u /* count only: hash_sum / hash_xor are left 0 */
 
@@ -187,6 +218,14 @@ huge_status huge_plan_create(const huge_graph *g, int32_t k, int32_t n_qedges, c
 void huge_plan_free(huge_plan *p);
 
 /*
+ * huge_plan_prefix -- the plan of the first `size` vertices (2..k) of p's
+ * order: the induced prefix, numbered by order position, with p's
+ * symmetry-breaking constraints restricted to it.  Its count is p's
+ * level_counts[size-1] (the partial matches that p's run holds at that level).
+ */
+huge_status huge_plan_prefix(const huge_plan *p, int32_t size, huge_plan **out);
+
+/*
  * Plan details: order_out int32[k]; n_sb number of constraints; sb_pairs
  * int32[2*28] as (a, b) meaning rank(f(a)) < rank(f(b)); est_cost: the
  * model's estimated total partial matches (sum over prefixes).  NULL skips.
@@ -202,6 +241,7 @@ huge_status huge_workspace_size(const huge_graph *g, const huge_plan *p, const h
  * huge_count -- enumerate and count (SINK by counting, Section 4.2).  Fills
  * count, hash_sum, hash_xor, level_counts, timing and frontier statistics.
  * opts NULL = huge_exec_opts_default.  Blocks until the result is on the host.
+ * Returns HUGE_STOPPED (out filled, partial) when opts->work_limit ended the run.
  */
 huge_status huge_count(const huge_graph *g, const huge_plan *p, const huge_exec_opts *opts, huge_result *out);
 
@@ -296,6 +336,26 @@ huge_status huge_plan_features(const huge_graph *g, const huge_plan *p, const in
  */
 huge_status huge_plan_create_learned(const huge_graph *g, const huge_model *m, int32_t k, int32_t n_qedges,
                                      const int32_t *qedges, const int32_t *order, void *stream, huge_plan **out);
+
+/*
+ * huge_autotune -- fill a dispatch table by timing, on the graph itself, the
+ * work of the given plans on one root slice (opts->slice_count /
+ * slice_id / slice_vertex choose the sample; slice_count <= 1 means the
+ * whole graph): every strategy is run on the same sample and, per (j,
+ * bucket), the fastest is kept; then per j the segment size among
+ * {2^18, 2^20, 2^22} rows.  Uses the level engine on opts->stream with HIP
+ * events around every launch.  Buckets or j never seen keep
+ * HUGE_STRAT_AUTO.  Errors: as huge_count.
+ */
+huge_status huge_autotune(const huge_graph *g, const huge_plan *const *plans, int32_t np, const huge_exec_opts *opts,
+                          huge_tune_table *out);
+
+/*
+ * Content digest of the relabelled graph, the tune cache key: a 64-bit digest
+ * of the CSR computed on the device at load, with n and nnz, as text of at
+ * most 64 characters + NUL.
+ */
+huge_status huge_graph_digest(const huge_graph *g, char *out65);
 
 const char *huge_last_error(void);
 

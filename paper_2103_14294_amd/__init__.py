@@ -32,6 +32,7 @@ EXPORTED = [
     "huge_enumerate", "huge_count_batch", "huge_last_error",
     "huge_model_create", "huge_model_free", "huge_model_set", "huge_model_get", "huge_model_forward",
     "huge_model_grad", "huge_model_train", "huge_plan_features", "huge_plan_create_learned",
+    "huge_autotune", "huge_graph_digest", "huge_plan_prefix",
 ]
 MLP_F, MLP_H = 128, 256
 MLP_PARAMS = MLP_F * MLP_H + 2 * MLP_H + 1
@@ -66,7 +67,32 @@ class ExecOpts(ctypes.Structure):
                 ("deterministic", ctypes.c_int32), ("slice_count", ctypes.c_uint32), ("slice_id", ctypes.c_uint32),
                 ("stream", ctypes.c_void_p), ("workspace", ctypes.c_void_p), ("workspace_bytes", ctypes.c_uint64),
                 ("profile", ctypes.c_int32), ("slice_vertex", ctypes.c_int32), ("exec_flags", ctypes.c_uint32),
-                ("reserved", ctypes.c_uint32)]
+                ("reserved", ctypes.c_uint32), ("tune", ctypes.c_void_p), ("work_limit", ctypes.c_int64)]
+
+
+TUNE_BUCKETS = 5
+
+
+class TuneTable(ctypes.Structure):
+    _fields_ = [("strategy", (ctypes.c_int32 * TUNE_BUCKETS) * (KMAX + 1)),
+                ("chunk_rows", ctypes.c_int64 * (KMAX + 1)),
+                ("ms", (ctypes.c_double * TUNE_BUCKETS) * (KMAX + 1)),
+                ("items", (ctypes.c_int64 * TUNE_BUCKETS) * (KMAX + 1))]
+
+    def to_dict(self):
+        return {"strategy": [list(r) for r in self.strategy], "chunk_rows": list(self.chunk_rows),
+                "ms": [list(r) for r in self.ms], "items": [list(r) for r in self.items]}
+
+    @classmethod
+    def from_dict(cls, d):
+        t = cls()
+        for j in range(KMAX + 1):
+            t.chunk_rows[j] = int(d["chunk_rows"][j])
+            for c in range(TUNE_BUCKETS):
+                t.strategy[j][c] = int(d["strategy"][j][c])
+                t.ms[j][c] = float(d["ms"][j][c])
+                t.items[j][c] = int(d["items"][j][c])
+        return t
 
 
 class GraphInfo(ctypes.Structure):
@@ -138,6 +164,12 @@ def load_library(path: str = LIB_PATH):
         lib.huge_model_train.argtypes = [vp, vp, vp, i64, i32, i64, f32, ctypes.c_uint64, vp, vp]
         lib.huge_plan_features.restype = st
         lib.huge_plan_features.argtypes = [vp, vp, vp, i32, vp]
+        lib.huge_autotune.restype = st
+        lib.huge_autotune.argtypes = [vp, ctypes.POINTER(vp), i32, ctypes.POINTER(ExecOpts), ctypes.POINTER(TuneTable)]
+        lib.huge_graph_digest.restype = st
+        lib.huge_graph_digest.argtypes = [vp, ctypes.c_char_p]
+        lib.huge_plan_prefix.restype = st
+        lib.huge_plan_prefix.argtypes = [vp, i32, ctypes.POINTER(vp)]
         lib.huge_plan_create_learned.restype = st
         lib.huge_plan_create_learned.argtypes = [vp, vp, i32, i32, vp, vp, vp, ctypes.POINTER(vp)]
         _lib = lib
@@ -380,7 +412,8 @@ class Model:
 
 
 def exec_opts(cap=None, chunk_rows=0, strategy=-1, engine=ENGINE_AUTO, work_stealing=1, slice_count=1, slice_id=0,
-              stream=None, workspace=None, profile=False, slice_vertex=0, hash=True) -> ExecOpts:
+              stream=None, workspace=None, profile=False, slice_vertex=0, hash=True, tune=None,
+              work_limit=0) -> ExecOpts:
     lib = load_library()
     o = ExecOpts()
     lib.huge_exec_opts_default(ctypes.byref(o))
@@ -395,6 +428,9 @@ def exec_opts(cap=None, chunk_rows=0, strategy=-1, engine=ENGINE_AUTO, work_stea
     o.profile = 1 if profile else 0
     o.slice_vertex = int(slice_vertex)
     o.exec_flags = 0 if hash else EXEC_NO_HASH
+    o.work_limit = int(work_limit)
+    if tune is not None:
+        o.tune = ctypes.cast(ctypes.byref(tune), ctypes.c_void_p)
     o.stream = (stream if stream is not None else _current_stream()).value \
         if not isinstance(stream, int) else stream
     if workspace is not None:
@@ -435,8 +471,54 @@ def count(g: Graph, p: Plan, workspace: Workspace | None = _default_ws, **kw) ->
         opts.workspace = ws.data_ptr()
         opts.workspace_bytes = ws.numel()
     r = Result()
-    _check(lib.huge_count(g.handle, p.handle, ctypes.byref(opts), ctypes.byref(r)))
-    return r.to_dict()
+    status = _check(lib.huge_count(g.handle, p.handle, ctypes.byref(opts), ctypes.byref(r)))
+    d = r.to_dict()
+    d["stopped"] = status == HUGE_STOPPED
+    return d
+
+
+def plan_prefix(p: Plan, size: int) -> Plan:
+    """huge_plan_prefix: the plan of the first `size` order vertices of p."""
+    lib = load_library()
+    h = ctypes.c_void_p()
+    _check(lib.huge_plan_prefix(p.handle, int(size), ctypes.byref(h)))
+    return Plan(h.value, int(size))
+
+
+def graph_digest(g: Graph) -> str:
+    lib = load_library()
+    buf = ctypes.create_string_buffer(65)
+    _check(lib.huge_graph_digest(g.handle, buf))
+    return buf.value.decode()
+
+
+def autotune(g: Graph, plans, cache=None, **kw) -> TuneTable:
+    """huge_autotune on a sample chosen by the slice options in kw; with `cache` (a JSON file), the
+    table is stored under (graph digest, GPU name) and reused when present."""
+    import json
+
+    lib = load_library()
+    key = None
+    if cache is not None:
+        key = "%s|%s" % (graph_digest(g), _torch().cuda.get_device_name())
+        if os.path.exists(cache):
+            with open(cache) as f:
+                d = json.load(f)
+            if key in d:
+                return TuneTable.from_dict(d[key])
+    opts = exec_opts(**kw)
+    arr = (ctypes.c_void_p * len(plans))(*[p.handle.value for p in plans])
+    t = TuneTable()
+    _check(lib.huge_autotune(g.handle, arr, len(plans), ctypes.byref(opts), ctypes.byref(t)))
+    if cache is not None:
+        d = {}
+        if os.path.exists(cache):
+            with open(cache) as f:
+                d = json.load(f)
+        d[key] = t.to_dict()
+        with open(cache, "w") as f:
+            json.dump(d, f, indent=1)
+    return t
 
 
 def count_batch(g: Graph, plans, **kw):

@@ -1,4 +1,5 @@
 // The C ABI (include/huge.h): argument checks, error capture, dispatch.
+#include <algorithm>
 #include <chrono>
 #include <cstdarg>
 #include <cstring>
@@ -109,6 +110,17 @@ huge_status huge_plan_create(const huge_graph *g, int32_t k, int32_t n_qedges, c
 
 void huge_plan_free(huge_plan *p) { delete p; }
 
+huge_status huge_plan_prefix(const huge_plan *p, int32_t size, huge_plan **out) {
+    return guard([&] {
+        if (!p || !out) HUGE_FAIL(HUGE_EINVAL, "NULL argument");
+        if (size < 2 || size > p->k) HUGE_FAIL(HUGE_EINVAL, "prefix size %d outside 2..%d", size, p->k);
+        huge_plan *q = new huge_plan();
+        plan_prefix(*p, size, q);
+        *out = q;
+        return HUGE_OK;
+    });
+}
+
 huge_status huge_plan_info(const huge_plan *p, int32_t *k, int32_t *order_out, int32_t *n_sb, int32_t *sb_pairs,
                            double *est_cost) {
     return guard([&] {
@@ -141,15 +153,17 @@ huge_status huge_count(const huge_graph *g, const huge_plan *p, const huge_exec_
     return guard([&] {
         if (!g || !p || !out) HUGE_FAIL(HUGE_EINVAL, "NULL argument");
         huge_exec_opts o = resolve_opts(opts);
+        if (o.work_limit < 0) HUGE_FAIL(HUGE_EINVAL, "work_limit < 0");
         huge_result r;
+        bool limited = false;
         if (o.engine == HUGE_ENGINE_PERSISTENT) {
             const huge_plan *pl[1] = {p};
             run_persistent(g, pl, 1, o, &r);
         } else {
-            run_levels(g, p, o, &r, nullptr);
+            limited = run_levels(g, p, o, &r, nullptr);
         }
         *out = r;
-        return HUGE_OK;
+        return limited ? HUGE_STOPPED : HUGE_OK;
     });
 }
 
@@ -279,6 +293,30 @@ huge_status huge_plan_create_learned(const huge_graph *g, const huge_model *m, i
             throw;
         }
         *out = p;
+        return HUGE_OK;
+    });
+}
+
+huge_status huge_autotune(const huge_graph *g, const huge_plan *const *plans, int32_t np, const huge_exec_opts *opts,
+                          huge_tune_table *out) {
+    return guard([&] {
+        if (!g || !plans || np <= 0 || !out) HUGE_FAIL(HUGE_EINVAL, "bad arguments");
+        for (int i = 0; i < np; ++i)
+            if (!plans[i]) HUGE_FAIL(HUGE_EINVAL, "plan %d is NULL", i);
+        huge_exec_opts o = resolve_opts(opts);
+        huge_tune_table t;
+        autotune(g, plans, np, o, &t);
+        *out = t;
+        return HUGE_OK;
+    });
+}
+
+huge_status huge_graph_digest(const huge_graph *g, char *out65) {
+    return guard([&] {
+        if (!g || !out65) HUGE_FAIL(HUGE_EINVAL, "NULL argument");
+        const size_t n = std::min<size_t>(64, g->sha.size());
+        memcpy(out65, g->sha.data(), n);
+        out65[n] = 0;
         return HUGE_OK;
     });
 }

@@ -30,6 +30,11 @@ constexpr int64_t kMinQueueRows = 1 << 12;
 constexpr int64_t kMaxItems = 1ll << 30;
 constexpr uint64_t kDefaultCap = 4ull << 30;
 
+inline int ext_count(const huge_plan *p, int W) { return __builtin_popcount(p->dev.st[W].ext); }
+
+// per-bucket dispatch: a tune table and no fixed strategy
+inline bool partitioned(const huge_exec_opts &o) { return o.tune && (o.strategy < 0 || o.strategy >= STRAT_COUNT); }
+
 struct Layout {
     int64_t seg_cap[HUGE_KMAX] = {};
     int64_t q_cap[HUGE_KMAX + 1] = {};
@@ -55,17 +60,31 @@ Layout make_layout(const huge_graph *g, const huge_plan *p, const huge_exec_opts
         uint64_t share = nq ? cap / nq : 0;
         L.q_cap[w] = std::max<int64_t>(kMinQueueRows, (int64_t)(share / (4ull * w)));
     }
-    L.seg_cap[2] = std::min<int64_t>(seg, std::max<int64_t>(1, g->dev.nnz));
-    for (int w = 3; w <= k - 1; ++w) L.seg_cap[w] = std::min<int64_t>(seg, L.q_cap[w]);
+    auto seg_for = [&](int w) {
+        if (o.chunk_rows <= 0 && o.tune) {
+            const int64_t c = o.tune->chunk_rows[ext_count(p, w)];
+            if (c > 0) return c;
+        }
+        return seg;
+    };
+    L.seg_cap[2] = std::min<int64_t>(seg_for(2), std::max<int64_t>(1, g->dev.nnz));
+    for (int w = 3; w <= k - 1; ++w) L.seg_cap[w] = std::min<int64_t>(seg_for(w), L.q_cap[w]);
     L.stage_rows = stage_rows;
     int64_t maxseg = 1;
     for (int w = 2; w <= k - 1; ++w) maxseg = std::max(maxseg, L.seg_cap[w]);
-    L.scan_tmp = scan_tmp_elems(maxseg + 1);
+    const bool part = partitioned(o);
+    const int64_t maxblk = (maxseg + 255) / 256;
+    L.scan_tmp = scan_tmp_elems(std::max(maxseg + 1, HUGE_TUNE_BUCKETS * maxblk + 1));
     uint64_t t = align_up(sizeof(Ctrl));
     if (k >= 3)
         for (int w = 2; w <= k - 1; ++w) {
             int64_t c = L.seg_cap[w];
             t += align_up(8ull * (c + 1)) + align_up(8ull * c) * 2 + align_up(4ull * c);
+            if (part) {
+                const int64_t nb = (c + 255) / 256;
+                t += align_up(4ull * c) * 2 + align_up(8ull * c) * 2 + align_up(4ull * HUGE_TUNE_BUCKETS * nb) +
+                     align_up(8ull * (HUGE_TUNE_BUCKETS * nb + 1));
+            }
         }
     for (int w = 3; w <= k - 1; ++w) t += align_up(4ull * w * L.q_cap[w]);
     t += align_up(4ull * k * std::max<int64_t>(1, stage_rows));
@@ -106,11 +125,18 @@ int64_t read_i64(const void *dev, hipStream_t st) {
 struct Profiler {
     bool on = false;
     hipStream_t st = nullptr;
-    std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> ev;
+    TuneProbe *probe = nullptr;  // per-(j, bucket) attribution of tagged launches
+    struct Ev {
+        int cls, tag;
+        hipEvent_t a, b;
+    };
+    std::vector<Ev> ev;
     uint64_t launches[4] = {0, 0, 0, 0};
     double bytes[4] = {0, 0, 0, 0};
+    // tag = j * 8 + bucket for intersection launches, j * 8 + 7 for the
+    // segment's other launches, -1 untagged
     template <typename F>
-    void run(int cls, F &&launch) {
+    void run(int cls, F &&launch, int tag = -1) {
         launches[cls]++;
         if (!on) {
             launch();
@@ -119,7 +145,7 @@ struct Profiler {
         hipEvent_t a, b;
         HUGE_HIP(hipEventCreate(&a));
         HUGE_HIP(hipEventCreate(&b));
-        ev.push_back({cls, {a, b}});
+        ev.push_back({cls, tag, a, b});
         HUGE_HIP(hipEventRecord(a, st));
         launch();
         HUGE_HIP(hipEventRecord(b, st));
@@ -133,17 +159,24 @@ struct Profiler {
         if (on) HUGE_HIP(hipStreamSynchronize(st));
         for (auto &e : ev) {
             float ms = 0;
-            if (on) HUGE_HIP(hipEventElapsedTime(&ms, e.second.first, e.second.second));
-            out->kernel_ms[e.first] += ms;
-            (void)hipEventDestroy(e.second.first);
-            (void)hipEventDestroy(e.second.second);
+            if (on) HUGE_HIP(hipEventElapsedTime(&ms, e.a, e.b));
+            out->kernel_ms[e.cls] += ms;
+            if (probe && e.tag >= 0) {
+                const int j = e.tag / 8, c = e.tag % 8;
+                if (c < HUGE_TUNE_BUCKETS)
+                    probe->ms[j][c] += ms;
+                else
+                    probe->other_ms[j] += ms;
+            }
+            (void)hipEventDestroy(e.a);
+            (void)hipEventDestroy(e.b);
         }
         ev.clear();
     }
     ~Profiler() {
         for (auto &e : ev) {
-            (void)hipEventDestroy(e.second.first);
-            (void)hipEventDestroy(e.second.second);
+            (void)hipEventDestroy(e.a);
+            (void)hipEventDestroy(e.b);
         }
     }
 };
@@ -152,7 +185,8 @@ uint64_t workspace_bytes(const huge_graph *g, const huge_plan *p, const huge_exe
     return make_layout(g, p, o, 1 << 16).total;
 }
 
-void run_levels(const huge_graph *g, const huge_plan *p, const huge_exec_opts &o, huge_result *out, EmitSink *emit) {
+bool run_levels(const huge_graph *g, const huge_plan *p, const huge_exec_opts &o, huge_result *out, EmitSink *emit,
+                TuneProbe *probe) {
     auto t0 = std::chrono::steady_clock::now();
     hipStream_t st = (hipStream_t)o.stream;
     const int k = p->k;
@@ -182,9 +216,11 @@ void run_levels(const huge_graph *g, const huge_plan *p, const huge_exec_opts &o
     }
     Carver cv{ws};
     Ctrl *ctrl = cv.take<Ctrl>(1);
+    const bool part = partitioned(o);
     struct Lv {
         int64_t nrows = 0, next = 0;
         int64_t seg_row0 = 0, seg_n = 0, seg_total = 0, seg_done = 0;
+        int64_t bw[HUGE_TUNE_BUCKETS + 1] = {};  // partitioned segment: first work item of each bucket, total
         double seg_bytes = 0;
         SegBufs s{};
         int32_t *q = nullptr;
@@ -198,6 +234,15 @@ void run_levels(const huge_graph *g, const huge_plan *p, const huge_exec_opts &o
             lv[w].s.hpre = cv.take<uint64_t>(c);
             lv[w].s.bound = cv.take<int32_t>(c);
             lv[w].s.cap = c;
+            if (part) {
+                const int64_t nb = (c + 255) / 256;
+                lv[w].s.bound_in = cv.take<int32_t>(c);
+                lv[w].s.rid = cv.take<int32_t>(c);
+                lv[w].s.pinfo_in = cv.take<uint64_t>(c);
+                lv[w].s.hpre_in = cv.take<uint64_t>(c);
+                lv[w].s.bcnt = cv.take<int32_t>(HUGE_TUNE_BUCKETS * nb);
+                lv[w].s.bscan = cv.take<int64_t>(HUGE_TUNE_BUCKETS * nb + 1);
+            }
         }
     for (int w = 3; w <= k - 1; ++w) {
         lv[w].q = cv.take<int32_t>((uint64_t)w * L.q_cap[w]);
@@ -209,12 +254,14 @@ void run_levels(const huge_graph *g, const huge_plan *p, const huge_exec_opts &o
     HUGE_HIP(hipMemsetAsync(ctrl, 0, sizeof(Ctrl), st));
     ExecStats stats;
     Profiler prof;
-    prof.on = o.profile != 0;
+    prof.on = o.profile != 0 || probe;
+    prof.probe = probe;
     prof.st = st;
     const GraphDev &G = g->dev;
     const int strat = (o.strategy >= 0 && o.strategy < STRAT_COUNT) ? o.strategy : STRAT_LANE_MERGE;
     const int count_mode = (o.exec_flags & HUGE_EXEC_NO_HASH) ? MODE_COUNT_NOHASH : MODE_COUNT;
     const bool root_slice = P.slice_count > 1 && P.st[0].slice;
+    bool limited = false;
     if (root_slice) {
         launch_root_count(G, P, ctrl, st);
         stats.launches++;
@@ -226,6 +273,32 @@ void run_levels(const huge_graph *g, const huge_plan *p, const huge_exec_opts &o
         HUGE_HIP(hipStreamSynchronize(st));
         emit->delivered += (uint64_t)nout;
         if (emit->cb(emit->user, emit->host_buf, nout, k) != 0) emit->stopped = true;
+    };
+
+    // intersection launches over work items [w0, w1) of level l's segment: one
+    // launch, or one per probe-length bucket with the tuned strategy
+    auto extend_range = [&](int cls, int W, int mode, Lv &l, int64_t w0, int64_t w1, int32_t *outp) {
+        const int jW = ext_count(p, W);
+        if (!part) {
+            prof.run(cls, [&] {
+                launch_extend(W, mode, strat, G, P, l.q, l.seg_row0, l.s, l.seg_n, w0, w1, outp, ctrl, g->inv_rank,
+                              st, false);
+            });
+            stats.launches++;
+            return;
+        }
+        for (int c = 0; c < HUGE_TUNE_BUCKETS; ++c) {
+            const int64_t a = std::max(w0, l.bw[c]), b = std::min(w1, l.bw[c + 1]);
+            if (a >= b) continue;
+            int sc = o.tune->strategy[jW][c];
+            if (sc < 0 || sc >= STRAT_COUNT) sc = STRAT_LANE_MERGE;
+            prof.run(cls, [&] {
+                launch_extend(W, mode, sc, G, P, l.q, l.seg_row0, l.s, l.seg_n, a, b, outp, ctrl, g->inv_rank, st,
+                              true);
+            }, jW * 8 + c);
+            if (probe) probe->items[jW][c] += b - a;
+            stats.launches++;
+        }
     };
 
     if (k == 2) {
@@ -247,6 +320,7 @@ void run_levels(const huge_graph *g, const huge_plan *p, const huge_exec_opts &o
     } else {
         const int lastW = k - 1;
         lv[2].nrows = G.nnz;
+        int64_t work_done = 0;  // candidates examined (work items launched)
         int W = 2;
         uint64_t cur_bytes = 0;
         auto has_input = [](const Lv &l) { return l.seg_done < l.seg_total || l.next < l.nrows; };
@@ -268,18 +342,38 @@ void run_levels(const huge_graph *g, const huge_plan *p, const huge_exec_opts &o
                     if (l.next == l.nrows) break;
                     int64_t cnt = std::min(l.s.cap, l.nrows - l.next);
                     HUGE_HIP(hipMemsetAsync(&ctrl->segbytes[W], 0, 8, st));
+                    const int otag = ext_count(p, W) * 8 + 7;
+                    SegBufs pre = l.s;
+                    if (part) {
+                        pre.bound = l.s.bound_in;
+                        pre.pinfo = l.s.pinfo_in;
+                        pre.hpre = l.s.hpre_in;
+                    }
                     prof.run(HUGE_KC_PREPARE,
-                             [&] { launch_prepare(W, W == lastW, G, P, lv[W].q, l.next, cnt, l.s, ctrl, st); });
-                    prof.run(HUGE_KC_SCAN, [&] { launch_scan_bounds(l.s, cnt, scan_tmp, st); });
+                             [&] { launch_prepare(W, W == lastW, G, P, lv[W].q, l.next, cnt, pre, ctrl, st); }, otag);
+                    if (part) {
+                        prof.run(HUGE_KC_SCAN,
+                                 [&] { launch_bucket_partition(l.s, cnt, W == lastW, scan_tmp, ctrl, st); }, otag);
+                        stats.launches += 3;
+                    }
+                    prof.run(HUGE_KC_SCAN, [&] { launch_scan_bounds(l.s, cnt, scan_tmp, st); }, otag);
                     stats.launches += 2;
+                    if (part) {
+                        launch_bucket_bounds(l.s, cnt, ctrl, st);
+                        stats.launches += 1;
+                    }
                     l.seg_row0 = l.next;
                     l.seg_n = cnt;
-                    int64_t hv[2] = {0, 0};
+                    int64_t hv[2 + HUGE_TUNE_BUCKETS + 1] = {};
                     HUGE_HIP(hipMemcpyAsync(&hv[0], l.s.off + cnt, 8, hipMemcpyDeviceToHost, st));
                     HUGE_HIP(hipMemcpyAsync(&hv[1], &ctrl->segbytes[W], 8, hipMemcpyDeviceToHost, st));
+                    if (part)
+                        HUGE_HIP(hipMemcpyAsync(&hv[2], ctrl->scratch, 8 * (HUGE_TUNE_BUCKETS + 1),
+                                                hipMemcpyDeviceToHost, st));
                     HUGE_HIP(hipStreamSynchronize(st));
                     l.seg_total = hv[0];
                     l.seg_bytes = (double)(uint64_t)hv[1];
+                    for (int c = 0; c <= HUGE_TUNE_BUCKETS; ++c) l.bw[c] = part ? hv[2 + c] : 0;
                     l.seg_done = 0;
                     l.next += cnt;
                     if (l.seg_total == 0) continue;
@@ -288,20 +382,17 @@ void run_levels(const huge_graph *g, const huge_plan *p, const huge_exec_opts &o
                 if (W == lastW) {
                     if (!emit) {
                         int64_t chunk = std::min(remaining, kMaxItems);
-                        prof.run(HUGE_KC_SINK, [&] {
-                            launch_extend(W, count_mode, strat, G, P, l.q, l.seg_row0, l.s, l.seg_n, l.seg_done,
-                                          l.seg_done + chunk, nullptr, ctrl, g->inv_rank, st);
-                        });
+                        extend_range(HUGE_KC_SINK, W, count_mode, l, l.seg_done, l.seg_done + chunk, nullptr);
                         prof.bytes[HUGE_KC_SINK] += l.seg_bytes * (double)chunk / (double)l.seg_total;
-                        stats.launches++;
                         l.seg_done += chunk;
+                        work_done += chunk;
+                        if (o.work_limit > 0 && work_done > o.work_limit) {
+                            stop = limited = true;
+                            break;
+                        }
                     } else {
                         int64_t chunk = std::min(remaining, stage_rows);
-                        prof.run(HUGE_KC_SINK, [&] {
-                            launch_extend(W, MODE_OUTPUT, strat, G, P, l.q, l.seg_row0, l.s, l.seg_n, l.seg_done,
-                                          l.seg_done + chunk, stage, ctrl, g->inv_rank, st);
-                        });
-                        stats.launches++;
+                        extend_range(HUGE_KC_SINK, W, MODE_OUTPUT, l, l.seg_done, l.seg_done + chunk, stage);
                         l.seg_done += chunk;
                         int64_t nout = read_i64(&ctrl->qcount[HUGE_KMAX], st);
                         deliver(nout);
@@ -316,18 +407,19 @@ void run_levels(const huge_graph *g, const huge_plan *p, const huge_exec_opts &o
                     const int64_t free = q.qcap - q.nrows;
                     if (free <= 0 || (free < remaining && free < q.qcap / 8)) break;  // Q_O full: yield
                     const int64_t chunk = std::min(std::min(free, remaining), kMaxItems);
-                    prof.run(HUGE_KC_EXTEND, [&] {
-                        launch_extend(W, MODE_EMIT, strat, G, P, l.q, l.seg_row0, l.s, l.seg_n, l.seg_done,
-                                      l.seg_done + chunk, q.q, ctrl, g->inv_rank, st);
-                    });
-                    stats.launches++;
+                    extend_range(HUGE_KC_EXTEND, W, MODE_EMIT, l, l.seg_done, l.seg_done + chunk, q.q);
                     l.seg_done += chunk;
+                    work_done += chunk;
                     int64_t nr = read_i64(&ctrl->qcount[W + 1], st);
                     prof.bytes[HUGE_KC_EXTEND] +=
                         l.seg_bytes * (double)chunk / (double)l.seg_total + 4.0 * (W + 1) * (double)(nr - q.nrows);
                     cur_bytes += (uint64_t)(nr - q.nrows) * 4ull * (W + 1);
                     q.nrows = nr;
                     stats.peak_frontier_bytes = std::max(stats.peak_frontier_bytes, cur_bytes);
+                    if (o.work_limit > 0 && work_done > o.work_limit) {
+                        stop = limited = true;
+                        break;
+                    }
                 }
             }
             if (W == lastW) {
@@ -352,6 +444,7 @@ void run_levels(const huge_graph *g, const huge_plan *p, const huge_exec_opts &o
     prof.finish(out);
     auto t1 = std::chrono::steady_clock::now();
     out->query_ms = std::chrono::duration<double, std::milli>(t1 - t0).count();
+    return limited;
 }
 
 }  // namespace huge

@@ -129,6 +129,7 @@ __global__ __launch_bounds__(kT) void k_prepare(const int32_t *__restrict__ rows
 struct ExtArgs {
     const int32_t *rows;
     int64_t row0;
+    const int32_t *rid;  // segment row r holds input row row0 + rid[r] (NULL: row0 + r)
     const int64_t *off;
     const uint64_t *pinfo;
     const uint64_t *hpre;
@@ -141,6 +142,10 @@ struct ExtArgs {
     DevPlan P;
 };
 
+
+__device__ __forceinline__ int64_t row_at(const ExtArgs &a, int64_t r) {
+    return a.row0 + (a.rid ? (int64_t)a.rid[r] : r);
+}
 
 __device__ __forceinline__ bool lds_contains(const int32_t *s, int32_t n, int32_t key) {
     int32_t lo = 0, hi = n;
@@ -275,7 +280,7 @@ __global__ __launch_bounds__(kT) void k_extend(ExtArgs a) {
             const uint64_t pi = a.pinfo[r];
             pp = (int)(pi >> 56);
             v = g.col[(int64_t)(pi & kPbMask) + (w - a.off[r])];
-            load_row<W>(a.rows, g, a.row0 + r, f);
+            load_row<W>(a.rows, g, row_at(a, r), f);
         }
         bool ok = active;
 #pragma unroll
@@ -390,7 +395,7 @@ __global__ __launch_bounds__(kT) void k_extend(ExtArgs a) {
         for (int j = 0; j < kIPT; ++j) {
             if (!((okmask >> j) & 1u)) continue;
             int32_t f[W];
-            load_row<W>(a.rows, g, a.row0 + rr[j], f);
+            load_row<W>(a.rows, g, row_at(a, rr[j]), f);
             if constexpr (MODE == MODE_EMIT) {
                 int32_t *dst = a.out + o * (W + 1);
 #pragma unroll
@@ -502,25 +507,24 @@ void prepare_w(bool last, const GraphDev &g, const DevPlan &P, const int32_t *ro
 }
 
 // ---------------------------------------------------------------------------
-// lane merge: every lane owns a run of kRun consecutive work items (probe
+// lane merge: every lane owns a run of RUN consecutive work items (probe
 // elements, usually of one row).  For each other Ext list it finds the first
 // entry >= its first candidate once, then advances that cursor by galloping
 // (exponential then binary search, Bentley-Yao) as the sorted candidates
 // increase, so a membership test costs O(log gap) instead of O(log degree).
 // Hub lists are answered by their bitmap.
 // ---------------------------------------------------------------------------
-constexpr int kRun = 16;
-constexpr int kMTile = kT * kRun;
-
-
-template <int W, int MODE>
+template <int W, int MODE, int RUN>
 __global__ __launch_bounds__(kT) void k_extend_merge(ExtArgs a) {
+    constexpr int kRun = RUN;
+    constexpr int kMTile = kT * RUN;
     constexpr bool kEmit = MODE == MODE_EMIT || MODE == MODE_OUTPUT;
     constexpr bool kHash = MODE == MODE_COUNT;
     __shared__ int64_t s_rng[2];
     __shared__ unsigned long long s_red[3][kT / 64];
     __shared__ int32_t s_cnt[kT / 64];
     __shared__ unsigned long long s_base;
+    static_assert(!kEmit || RUN <= 16, "emitting kernels stage RUN rows per lane in LDS");
     __shared__ int32_t s_ov[kEmit ? kT * kRun : 1];
     __shared__ int32_t s_or[kEmit ? kT * kRun : 1];
     // hits waiting to be hashed, per wave (hashing them 64 at a time keeps
@@ -547,7 +551,7 @@ __global__ __launch_bounds__(kT) void k_extend_merge(ExtArgs a) {
     int npend = 0;  // wave-uniform
     auto hash_hit = [&](int32_t v, int32_t rr) {
         int32_t ff[W];
-        load_row<W>(a.rows, g, a.row0 + rr, ff);
+        load_row<W>(a.rows, g, row_at(a, rr), ff);
         uint64_t h = a.hpre[rr];
 #pragma unroll
         for (int p = 0; p < W; ++p)
@@ -582,7 +586,7 @@ __global__ __launch_bounds__(kT) void k_extend_merge(ExtArgs a) {
                 const uint64_t pi = a.pinfo[r];
                 pp = (int)(pi >> 56);
                 pshift = (int64_t)(pi & kPbMask) - a.off[r];
-                load_row<W>(a.rows, g, a.row0 + r, f);
+                load_row<W>(a.rows, g, row_at(a, r), f);
                 const int32_t v0 = g.col[pshift + w];
 #pragma unroll
                 for (int p = 0; p < W; ++p) {
@@ -705,7 +709,7 @@ __global__ __launch_bounds__(kT) void k_extend_merge(ExtArgs a) {
         for (int q = 0; q < nout; ++q, ++o) {
             const int32_t v = s_ov[threadIdx.x * kRun + q];
             int32_t ff[W];
-            load_row<W>(a.rows, g, a.row0 + s_or[threadIdx.x * kRun + q], ff);
+            load_row<W>(a.rows, g, row_at(a, s_or[threadIdx.x * RUN + q]), ff);
             int32_t *dst = a.out + o * (W + 1);
             if constexpr (MODE == MODE_EMIT) {
 #pragma unroll
@@ -726,40 +730,111 @@ __global__ __launch_bounds__(kT) void k_extend_merge(ExtArgs a) {
     }
 }
 
+template <int W, int MODE, int RUN>
+void merge_launch(const ExtArgs &a, hipStream_t st) {
+    const int64_t items = a.w1 - a.w0;
+    dim3 grid((unsigned)((items + (int64_t)kT * RUN - 1) / ((int64_t)kT * RUN)));
+    hipLaunchKernelGGL((k_extend_merge<W, MODE, RUN>), grid, dim3(kT), 0, st, a);
+}
+
+template <int W, int RUN>
+void merge_mode(int mode, const ExtArgs &a, hipStream_t st) {
+    if (mode == MODE_COUNT)
+        merge_launch<W, MODE_COUNT, RUN>(a, st);
+    else if (mode == MODE_COUNT_NOHASH)
+        merge_launch<W, MODE_COUNT_NOHASH, RUN>(a, st);
+    else if (mode == MODE_EMIT)
+        merge_launch<W, MODE_EMIT, (RUN > 16 ? 16 : RUN)>(a, st);
+    else
+        merge_launch<W, MODE_OUTPUT, (RUN > 16 ? 16 : RUN)>(a, st);
+}
+
 template <int W, int STRAT>
 void extend_ws(int mode, const ExtArgs &a, hipStream_t st) {
     const int64_t items = a.w1 - a.w0;
-    if constexpr (STRAT == STRAT_LANE_MERGE) {
-        dim3 grid((unsigned)((items + kMTile - 1) / kMTile));
-        if (mode == MODE_COUNT)
-            hipLaunchKernelGGL((k_extend_merge<W, MODE_COUNT>), grid, dim3(kT), 0, st, a);
-        else if (mode == MODE_COUNT_NOHASH)
-            hipLaunchKernelGGL((k_extend_merge<W, MODE_COUNT_NOHASH>), grid, dim3(kT), 0, st, a);
-        else if (mode == MODE_EMIT)
-            hipLaunchKernelGGL((k_extend_merge<W, MODE_EMIT>), grid, dim3(kT), 0, st, a);
-        else
-            hipLaunchKernelGGL((k_extend_merge<W, MODE_OUTPUT>), grid, dim3(kT), 0, st, a);
-    } else {
-        dim3 grid((unsigned)((items + kTile - 1) / kTile));
-        if (mode == MODE_COUNT)
-            hipLaunchKernelGGL((k_extend<W, MODE_COUNT, STRAT>), grid, dim3(kT), 0, st, a);
-        else if (mode == MODE_COUNT_NOHASH)
-            hipLaunchKernelGGL((k_extend<W, MODE_COUNT_NOHASH, STRAT>), grid, dim3(kT), 0, st, a);
-        else if (mode == MODE_EMIT)
-            hipLaunchKernelGGL((k_extend<W, MODE_EMIT, STRAT>), grid, dim3(kT), 0, st, a);
-        else
-            hipLaunchKernelGGL((k_extend<W, MODE_OUTPUT, STRAT>), grid, dim3(kT), 0, st, a);
-    }
+    dim3 grid((unsigned)((items + kTile - 1) / kTile));
+    if (mode == MODE_COUNT)
+        hipLaunchKernelGGL((k_extend<W, MODE_COUNT, STRAT>), grid, dim3(kT), 0, st, a);
+    else if (mode == MODE_COUNT_NOHASH)
+        hipLaunchKernelGGL((k_extend<W, MODE_COUNT_NOHASH, STRAT>), grid, dim3(kT), 0, st, a);
+    else if (mode == MODE_EMIT)
+        hipLaunchKernelGGL((k_extend<W, MODE_EMIT, STRAT>), grid, dim3(kT), 0, st, a);
+    else
+        hipLaunchKernelGGL((k_extend<W, MODE_OUTPUT, STRAT>), grid, dim3(kT), 0, st, a);
 }
 
 template <int W>
 void extend_w(int mode, int strategy, const ExtArgs &a, hipStream_t st) {
-    if (strategy == STRAT_BSEARCH)
-        extend_ws<W, STRAT_BSEARCH>(mode, a, st);
-    else if (strategy == STRAT_WAVE_STAGED)
-        extend_ws<W, STRAT_WAVE_STAGED>(mode, a, st);
-    else
-        extend_ws<W, STRAT_LANE_MERGE>(mode, a, st);
+    switch (strategy) {
+        case STRAT_BSEARCH: extend_ws<W, STRAT_BSEARCH>(mode, a, st); break;
+        case STRAT_WAVE_STAGED: extend_ws<W, STRAT_WAVE_STAGED>(mode, a, st); break;
+        case STRAT_MERGE_SHORT: merge_mode<W, 4>(mode, a, st); break;
+        case STRAT_MERGE_LONG: merge_mode<W, 64>(mode, a, st); break;
+        default: merge_mode<W, 16>(mode, a, st); break;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// probe-length buckets: a stable counting partition of a prepared segment by
+// the bucket of each row's probe length, so that every bucket's work items
+// are contiguous and can run with their own strategy
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int probe_bucket(int32_t len) {
+    return len < (1 << 6) ? 0 : len < (1 << 9) ? 1 : len < (1 << 12) ? 2 : len < (1 << 15) ? 3 : 4;
+}
+
+// bcnt[c * nblk + b] = rows of bucket c in block b
+__global__ __launch_bounds__(kT) void k_bucket_count(const int32_t *bound, int64_t n, int32_t *bcnt, int64_t nblk) {
+    __shared__ int32_t s_c[kT / 64][HUGE_TUNE_BUCKETS];
+    const int64_t i = (int64_t)blockIdx.x * kT + threadIdx.x;
+    const int c = i < n ? probe_bucket(bound[i]) : -1;
+    const int wv = threadIdx.x >> 6;
+#pragma unroll
+    for (int q = 0; q < HUGE_TUNE_BUCKETS; ++q) {
+        const uint64_t m = __ballot(c == q);
+        if (__lane_id() == 0) s_c[wv][q] = (int32_t)__popcll(m);
+    }
+    __syncthreads();
+    if (threadIdx.x < HUGE_TUNE_BUCKETS) {
+        int32_t t = 0;
+        for (int q = 0; q < kT / 64; ++q) t += s_c[q][threadIdx.x];
+        bcnt[(int64_t)threadIdx.x * nblk + blockIdx.x] = t;
+    }
+}
+
+// Moves row i's prepared data to its stable position in bucket order.
+__global__ __launch_bounds__(kT) void k_bucket_scatter(const int32_t *bound_in, const uint64_t *pinfo_in,
+                                                       const uint64_t *hpre_in, int64_t n, int64_t nblk,
+                                                       const int64_t *bscan, int32_t *bound, uint64_t *pinfo,
+                                                       uint64_t *hpre, int32_t *rid) {
+    __shared__ int32_t s_c[kT / 64][HUGE_TUNE_BUCKETS];
+    const int64_t i = (int64_t)blockIdx.x * kT + threadIdx.x;
+    const int32_t b = i < n ? bound_in[i] : 0;
+    const int c = i < n ? probe_bucket(b) : -1;
+    const int wv = threadIdx.x >> 6, lane = __lane_id();
+    const uint64_t lt = (lane == 0) ? 0ull : ((~0ull) >> (64 - lane));
+    int rank = 0;
+#pragma unroll
+    for (int q = 0; q < HUGE_TUNE_BUCKETS; ++q) {
+        const uint64_t m = __ballot(c == q);
+        if (lane == 0) s_c[wv][q] = (int32_t)__popcll(m);
+        if (c == q) rank = (int)__popcll(m & lt);
+    }
+    __syncthreads();
+    if (i < n) {
+        int64_t pos = bscan[(int64_t)c * nblk + blockIdx.x] + rank;
+        for (int q = 0; q < wv; ++q) pos += s_c[q][c];
+        bound[pos] = b;
+        pinfo[pos] = pinfo_in[i];
+        if (hpre_in) hpre[pos] = hpre_in[i];
+        rid[pos] = (int32_t)i;
+    }
+}
+
+// out[c] = first work item of bucket c (c = 0..B-1), out[B] = total
+__global__ void k_bucket_bounds(const int64_t *bscan, int64_t nblk, int64_t n, const int64_t *off, long long *out) {
+    const int t = threadIdx.x;
+    if (t <= HUGE_TUNE_BUCKETS) out[t] = off[t < HUGE_TUNE_BUCKETS ? bscan[(int64_t)t * nblk] : n];
 }
 
 }  // namespace
@@ -786,11 +861,12 @@ void launch_scan_bounds(const SegBufs &s, int64_t nrows, int64_t *tmp, hipStream
 
 void launch_extend(int width, int mode, int strategy, const GraphDev &g, const DevPlan &P, const int32_t *rows,
                    int64_t row0, const SegBufs &s, int64_t nrows, int64_t w0, int64_t w1, int32_t *out_rows,
-                   Ctrl *ctrl, const int32_t *inv_rank, hipStream_t st) {
+                   Ctrl *ctrl, const int32_t *inv_rank, hipStream_t st, bool partitioned) {
     if (w1 <= w0) return;
     ExtArgs a;
     a.rows = rows;
     a.row0 = row0;
+    a.rid = partitioned ? s.rid : nullptr;
     a.off = s.off;
     a.pinfo = s.pinfo;
     a.hpre = s.hpre;
@@ -811,6 +887,25 @@ void launch_extend(int width, int mode, int strategy, const GraphDev &g, const D
         case 7: extend_w<7>(mode, strategy, a, st); break;
         default: HUGE_FAIL(HUGE_EINVAL, "bad width %d", width);
     }
+    HUGE_HIP(hipGetLastError());
+}
+
+void launch_bucket_partition(const SegBufs &s, int64_t nrows, bool last, int64_t *scan_tmp, Ctrl *ctrl,
+                             hipStream_t st) {
+    if (nrows <= 0) return;
+    const int64_t nblk = (nrows + kT - 1) / kT;
+    hipLaunchKernelGGL(k_bucket_count, dim3((unsigned)nblk), dim3(kT), 0, st, s.bound_in, nrows, s.bcnt, nblk);
+    scan_excl(s.bcnt, s.bscan, HUGE_TUNE_BUCKETS * nblk, s.bscan + HUGE_TUNE_BUCKETS * nblk, scan_tmp, st);
+    hipLaunchKernelGGL(k_bucket_scatter, dim3((unsigned)nblk), dim3(kT), 0, st, s.bound_in, s.pinfo_in,
+                       last ? s.hpre_in : (const uint64_t *)nullptr, nrows, nblk, s.bscan, s.bound, s.pinfo, s.hpre,
+                       s.rid);
+    HUGE_HIP(hipGetLastError());
+    (void)ctrl;
+}
+
+void launch_bucket_bounds(const SegBufs &s, int64_t nrows, Ctrl *ctrl, hipStream_t st) {
+    const int64_t nblk = (nrows + kT - 1) / kT;
+    hipLaunchKernelGGL(k_bucket_bounds, dim3(1), dim3(64), 0, st, s.bscan, nblk, nrows, s.off, ctrl->scratch);
     HUGE_HIP(hipGetLastError());
 }
 

@@ -123,6 +123,7 @@ void plan_build(const huge_graph *g, int k, int ne, const int32_t *qe, const int
 bool order_connected(const huge_plan &p, const int32_t *order);
 void plan_set_order(huge_plan &p, const int32_t *order);
 double estimate_prefix(const huge_graph_info &gi, const huge_plan &p, const int32_t *order, int size);
+void plan_prefix(const huge_plan &p, int size, huge_plan *q);
 void all_connected_orders(const huge_plan &p, std::vector<std::vector<int32_t>> &out);
 
 // learn.cpp
@@ -147,6 +148,12 @@ huge_graph *graph_load(int64_t n, int64_t nnz, const int64_t *rp, const int32_t 
 void graph_free(huge_graph *g);
 
 // engine.cpp
+// per-(j, bucket) device time of tuning runs
+struct TuneProbe {
+    double ms[HUGE_KMAX + 1][HUGE_TUNE_BUCKETS] = {};
+    double other_ms[HUGE_KMAX + 1] = {};  // prepare, partition and scan launches, per j
+    int64_t items[HUGE_KMAX + 1][HUGE_TUNE_BUCKETS] = {};
+};
 struct ExecStats {
     uint64_t launches = 0;
     uint64_t steals = 0;
@@ -161,7 +168,11 @@ struct EmitSink {
     uint64_t delivered = 0;
 };
 uint64_t workspace_bytes(const huge_graph *g, const huge_plan *p, const huge_exec_opts &o);
-void run_levels(const huge_graph *g, const huge_plan *p, const huge_exec_opts &o, huge_result *out, EmitSink *emit);
+// returns true when the run stopped at o.work_limit
+bool run_levels(const huge_graph *g, const huge_plan *p, const huge_exec_opts &o, huge_result *out, EmitSink *emit,
+                TuneProbe *probe = nullptr);
+void autotune(const huge_graph *g, const huge_plan *const *plans, int np, const huge_exec_opts &o,
+              huge_tune_table *out);
 void run_persistent(const huge_graph *g, const huge_plan *const *plans, int np, const huge_exec_opts &o,
                     huge_result *outs);
 
@@ -174,6 +185,14 @@ struct SegBufs {
     uint64_t *hpre;     // [cap] prefix hash (last level only)
     int32_t *bound;     // [cap]
     int64_t cap;
+    // probe-length bucket partition (tuned runs): the prepare pass writes the
+    // *_in arrays, the partition moves them into bucket order above, and
+    // rid[r] is the input row of segment row r
+    int32_t *bound_in;
+    uint64_t *pinfo_in, *hpre_in;
+    int32_t *rid;
+    int32_t *bcnt;      // [HUGE_TUNE_BUCKETS * blocks]
+    int64_t *bscan;     // [HUGE_TUNE_BUCKETS * blocks + 1]
 };
 
 struct Ctrl {                      // device-resident counters
@@ -189,7 +208,11 @@ void launch_prepare(int width, bool last, const GraphDev &g, const DevPlan &P, c
 void launch_scan_bounds(const SegBufs &s, int64_t nrows, int64_t *tmp, hipStream_t st);
 void launch_extend(int width, int mode, int strategy, const GraphDev &g, const DevPlan &P, const int32_t *rows,
                    int64_t row0, const SegBufs &s, int64_t nrows, int64_t w0, int64_t w1, int32_t *out_rows,
-                   Ctrl *ctrl, const int32_t *inv_rank, hipStream_t st);
+                   Ctrl *ctrl, const int32_t *inv_rank, hipStream_t st, bool partitioned);
+void launch_bucket_partition(const SegBufs &s, int64_t nrows, bool last, int64_t *scan_tmp, Ctrl *ctrl,
+                             hipStream_t st);
+// ctrl->scratch[c] = first work item of bucket c, scratch[HUGE_TUNE_BUCKETS] = total
+void launch_bucket_bounds(const SegBufs &s, int64_t nrows, Ctrl *ctrl, hipStream_t st);
 void launch_edge_sink(const GraphDev &g, const DevPlan &P, int64_t e0, int64_t e1, int mode, int32_t *out,
                       const int32_t *inv_rank, Ctrl *ctrl, hipStream_t st);
 void launch_root_count(const GraphDev &g, const DevPlan &P, Ctrl *ctrl, hipStream_t st);
@@ -197,7 +220,15 @@ int64_t scan_tmp_elems(int64_t n);
 
 // extend modes
 enum { MODE_EMIT = 0, MODE_COUNT = 1, MODE_OUTPUT = 2, MODE_COUNT_NOHASH = 3 };
-// intersection strategies (huge_exec_opts.strategy)
-enum { STRAT_BSEARCH = 0, STRAT_WAVE_STAGED = 1, STRAT_LANE_MERGE = 2, STRAT_COUNT = 3 };
+// intersection strategies (huge_exec_opts.strategy, HUGE_STRAT_*)
+enum {
+    STRAT_BSEARCH = HUGE_STRAT_BSEARCH,
+    STRAT_WAVE_STAGED = HUGE_STRAT_WAVE_STAGED,
+    STRAT_LANE_MERGE = HUGE_STRAT_LANE_MERGE,
+    STRAT_MERGE_SHORT = HUGE_STRAT_MERGE_SHORT,
+    STRAT_MERGE_LONG = HUGE_STRAT_MERGE_LONG,
+    STRAT_COUNT = HUGE_STRAT_COUNT
+};
+
 
 }  // namespace huge

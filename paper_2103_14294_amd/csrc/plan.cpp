@@ -262,4 +262,35 @@ void plan_build(const huge_graph *g, int k, int ne, const int32_t *qe, const int
     }
 }
 
+void plan_prefix(const huge_plan &p, int size, huge_plan *q) {
+    int pos[HUGE_KMAX];
+    for (int i = 0; i < p.k; ++i) pos[p.order[i]] = i;
+    q->k = size;
+    q->flags = p.flags;
+    q->naut = 0;
+    memset(q->adj, 0, sizeof(q->adj));
+    q->edges.clear();
+    for (auto &e : p.edges) {
+        const int a = pos[e.first], b = pos[e.second];
+        if (a < size && b < size) {
+            q->edges.push_back({std::min(a, b), std::max(a, b)});
+            q->adj[a][b] = q->adj[b][a] = 1;
+        }
+    }
+    std::sort(q->edges.begin(), q->edges.end());
+    q->sb.clear();
+    for (auto &c : p.sb) {
+        const int a = pos[c.first], b = pos[c.second];
+        if (a < size && b < size) q->sb.push_back({a, b});
+    }
+    int32_t ident[HUGE_KMAX];
+    for (int i = 0; i < size; ++i) ident[i] = i;
+    plan_set_order(*q, ident);
+    q->est_cost = 0;
+    for (int s = 1; s <= size; ++s) {
+        q->est_prefix[s - 1] = p.est_prefix[s - 1];
+        if (s >= 2) q->est_cost += q->est_prefix[s - 1];
+    }
+}
+
 }  // namespace huge

@@ -1,13 +1,16 @@
 """Training of the learned cardinality model on counts the engine produces.
 
-Labels: for a query q and a matching order pi, the engine's per-level counts
-are |R(prefix_s)| for s = 2..k (level_counts[s-1]).  Runs on a root slice of
-S (matches whose first matched vertex u has mix(rank u) mod S == s0) scale
-each count by S; the slice count S is chosen from the cost model's estimate
-so that one run stays short.  Each labelled pattern is run on one training
-graph, with the cost-model order and with one random connected order, and
-every prefix of every run becomes one sample
-    x = huge_plan_features(graph, plan, s, order),  t = log(1 + S * level_counts[s-1]).
+Labels: for a query q and a matching order pi, |R(prefix_s)| (s = 2..k) is
+the count of the prefix plan (huge_plan_prefix), which equals the engine's
+level_counts[s-1] for pi.  Each prefix is counted on one root slice of S
+(matches whose first matched vertex u has mix(rank u) mod S == s0), scaled
+by S; S is sized from the previous prefix's count and raised when a run hits
+its work limit, so that every run stays short.  Each labelled pattern is run
+on one training graph, with the cost-model order and with one random
+connected order, and every prefix becomes one sample
+    x = huge_plan_features(graph, plan, s, order),  t = log(1 + S * count).
+Prefixes that repeat (same edges and constraints in order positions) are
+counted once per graph.
 
 Training runs in the library's HIP kernels (huge_model_train: minibatch Adam
 on the BF16/FP32 MLP).  This module only orchestrates.
@@ -65,15 +68,44 @@ def random_connected_order(k, edges, rng):
             return o
 
 
-def slice_count_for(est_cost, target):
-    if not (est_cost > target):
-        return 1
-    return int(min(1 << 20, 1 << math.ceil(math.log2(est_cost / target))))
+def pow2_at_least(x):
+    return 1 << max(0, math.ceil(math.log2(max(1.0, x))))
 
 
-def label_runs(G, patterns, rng, work_target, deadline, ws, max_est=1e16):
-    """Run every pattern with two orders; returns feature rows, targets and run records."""
-    X, T, runs = [], [], []
+def prefix_key(p_info, k, edges, order, size):
+    """The labelled prefix in order positions: its edges and symmetry-breaking pairs."""
+    pos = {v: i for i, v in enumerate(order)}
+    pe = tuple(sorted((min(pos[a], pos[b]), max(pos[a], pos[b])) for a, b in edges
+                      if pos[a] < size and pos[b] < size))
+    sb = tuple(sorted((pos[a], pos[b]) for a, b in p_info["sb_pairs"] if pos[a] < size and pos[b] < size))
+    return size, pe, sb
+
+
+def measure_prefix(G, q, size, prev_count, avg_deg, work_target, rng, ws, n):
+    """|R| of prefix plan q on a root slice sized from the previous prefix's count;
+    returns (estimate of the full count, slices used) or None when every try hits the work limit."""
+    S = pow2_at_least(prev_count * max(1.0, avg_deg) * 4.0 / work_target) if size > 2 else 1
+    s_max = max(1, pow2_at_least(n / 16.0) // 2)
+    for _ in range(4):
+        S = min(S, s_max)
+        sid = rng.randrange(S)
+        r = huge.count(G, q, slice_count=S, slice_id=sid, slice_vertex=0, workspace=ws, hash=False,
+                       work_limit=int(work_target))
+        if not r["stopped"]:
+            return float(r["count"]) * S, S
+        if S >= s_max:
+            return None
+        S *= 32
+    return None
+
+
+def label_runs(G, patterns, rng, work_target, deadline, ws, n, m):
+    """Label every prefix of every pattern under two orders (the cost model's and a
+    random connected one); returns feature rows, targets and per-sample records."""
+    X, T, recs = [], [], []
+    cache = {}
+    avg_deg = 2.0 * m / max(1, n)
+    runs = 0
     for i, q in enumerate(patterns):
         if time.time() > deadline:
             log("  label budget reached after %d patterns" % i)
@@ -86,23 +118,24 @@ def label_runs(G, patterns, rng, work_target, deadline, ws, max_est=1e16):
             orders.append(ro)
         for o in orders:
             p = huge.plan(G, k, e, order=o)
-            est = p.info()["est_cost"]
-            if not (est <= max_est):
-                continue  # 64-bit counts and run time are at risk
-            S = slice_count_for(est, work_target)
-            sid = rng.randrange(S)
-            t0 = time.perf_counter()
-            r = huge.count(G, p, slice_count=S, slice_id=sid, slice_vertex=o[0], workspace=ws, hash=False)
-            dt = time.perf_counter() - t0
-            lc = r["level_counts"]
+            info = p.info()
+            prev = float(n)
             for s in range(2, k + 1):
+                key = prefix_key(info, k, e, o, s)
+                if key not in cache:
+                    runs += 1
+                    cache[key] = measure_prefix(G, huge.plan_prefix(p, s), s, prev, avg_deg, work_target, rng, ws, n)
+                got = cache[key]
+                if got is None:
+                    break  # deeper prefixes are at least as expensive
+                cnt, S = got
                 X.append(huge.plan_features(G, p, s, order=o))
-                T.append(math.log1p(float(lc[s - 1]) * S))
-            runs.append({"pattern": i, "k": k, "edges": e, "order": o, "S": S, "slice": sid, "ms": dt * 1e3,
-                         "levels": [int(c) for c in lc[:k]], "est_cost": est})
+                T.append(math.log1p(cnt))
+                recs.append({"pattern": i, "size": s, "count": cnt, "S": S})
+                prev = max(cnt, 1.0)
         if (i + 1) % 50 == 0:
-            log("  %d patterns, %d samples" % (i + 1, len(T)))
-    return X, T, runs
+            log("  %d patterns, %d prefix runs, %d samples" % (i + 1, runs, len(T)))
+    return X, T, recs
 
 
 def q_error(est, true):
@@ -157,10 +190,10 @@ def main(argv=None):
     ap.add_argument("--labels", default=None, help="write / reuse labelled samples (.npz)")
     ap.add_argument("--patterns", type=int, default=2100)
     ap.add_argument("--seed", type=int, default=1)
-    ap.add_argument("--work-target", type=float, default=2e9, help="estimated partial matches per labelling run")
+    ap.add_argument("--work-target", type=float, default=5e8, help="candidates examined per labelling run, at most")
     ap.add_argument("--label-minutes", type=float, default=12.0)
     ap.add_argument("--graphs", default=",".join(n for n, _ in TRAIN_GRAPHS))
-    ap.add_argument("--epochs", type=int, default=300)
+    ap.add_argument("--epochs", type=int, default=2000)
     ap.add_argument("--lr", type=float, default=1e-3)
     ap.add_argument("--batch", type=int, default=256)
     args = ap.parse_args(argv)
@@ -191,17 +224,17 @@ def main(argv=None):
             g = make_graph(specs[name])
             G = huge.load(g.row_ptr, g.col)
             log("graph %s: n=%d m=%d (%.1f s); %d patterns" % (name, g.n, g.m, time.perf_counter() - t0, len(mine)))
-            x, t, runs = label_runs(G, mine, rng, args.work_target, time.time() + per_graph, ws)
+            x, t, recs = label_runs(G, mine, rng, args.work_target, time.time() + per_graph, ws, g.n, g.m)
             # samples of one pattern share a group (the validation split is by pattern)
-            for r in runs:
-                groups.extend([gi * 100000 + r["pattern"]] * (r["k"] - 1))
+            groups.extend([gi * 100000 + r["pattern"] for r in recs])
             X.extend(x)
             T.extend(t)
-            meta["graphs"][name] = {"n": g.n, "m": g.m, "runs": len(runs), "samples": len(t),
-                                    "run_ms_total": round(sum(r["ms"] for r in runs), 1)}
+            meta["graphs"][name] = {"n": g.n, "m": g.m, "samples": len(t),
+                                    "patterns": len({r["pattern"] for r in recs}),
+                                    "label_s": round(time.perf_counter() - t0, 1)}
             G.free()
             del g
-            log("  %s: %d runs, %d samples, %.1f s" % (name, len(runs), len(t), time.perf_counter() - t0))
+            log("  %s: %d samples, %.1f s" % (name, len(t), time.perf_counter() - t0))
         X = np.asarray(X, np.float32)
         T = np.asarray(T, np.float32)
         groups = np.asarray(groups, np.int64)
