@@ -54,7 +54,24 @@ WORKLOADS = {
         "cap": 32 << 30,
         "batches": 16,
     },
+    "c4": {
+        "desc": "R-MAT scale 24, edge factor 16, (0.57,0.19,0.19,0.05), seed 4: 64 random connected 3-6 vertex "
+                "patterns (seed 4; estimate <= 1e15)",
+        "graph": ("rmat", dict(scale=24, edge_factor=16, seed=4)),
+        "queries": ("random", dict(count=64, seed=4, kmin=3, kmax=6, max_est=1e15)),
+        "cap": 8 << 30,
+        "batches": 1024,
+    },
+    "c5": {
+        "desc": "R-MAT scale 26, edge factor 16, (0.57,0.19,0.19,0.05), seed 5: 32 held-out random 4-6 vertex "
+                "patterns (seed 5; estimate <= 1e15)",
+        "graph": ("rmat", dict(scale=26, edge_factor=16, seed=5)),
+        "queries": ("random", dict(count=32, seed=5, kmin=4, kmax=6, max_est=1e15)),
+        "cap": 16 << 30,
+        "batches": 4096,
+    },
 }
+MODEL_PATH = os.path.join(ROOT, "paper_2103_14294_amd", "card_mlp.npz")
 
 
 def log(*a):
@@ -73,13 +90,11 @@ def make_graph(spec):
 def cpu_baseline(g, queries, budget_s, threads):
     """The oracle, as it stands, on root slices of the same graph and queries."""
     import oracle
-    from graphgen import patterns as P
 
     S = 1 << 20
     per_q = budget_s / len(queries)
     tot_cnt, tot_t, slices = 0, 0.0, {}
-    for name in queries:
-        k, e = P.NAMED[name]
+    for name, k, e in queries:
         t_q, s = 0.0, 0
         while t_q < per_q and s < S:
             t0 = time.perf_counter()
@@ -100,6 +115,24 @@ def cpu_baseline(g, queries, budget_s, threads):
     }
 
 
+def build_queries(W, G, huge, P):
+    """[(name, k, edges)] for the workload: named queries, or seeded random patterns
+    whose cost-model estimate on this graph is within the budget."""
+    q = W["queries"]
+    if isinstance(q, list):
+        return [(n,) + tuple(P.NAMED[n]) for n in q]
+    kw = dict(q[1])
+    max_est = kw.pop("max_est")
+    out = []
+    for pat in P.random_patterns(kw["count"] * 8, seed=kw["seed"], kmin=kw["kmin"], kmax=kw["kmax"]):
+        if len(out) == kw["count"]:
+            break
+        est = huge.plan(G, pat["k"], pat["edges"]).info()["est_cost"]
+        if est <= max_est:
+            out.append(("%s-k%d-%d" % (pat["family"], pat["k"], len(out)), pat["k"], pat["edges"]))
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -108,7 +141,13 @@ def main():
     ap.add_argument("--workload", default="c2", choices=sorted(WORKLOADS))
     ap.add_argument("--cpu-budget", type=float, default=20.0)
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--learned", action="store_true", help="plan with the learned cardinality model")
+    ap.add_argument("--learned", nargs="?", const=MODEL_PATH, default=None,
+                    help="plan with the learned cardinality model (default model file if no path)")
+    ap.add_argument("--compare", action="store_true",
+                    help="time the cost-model plans and the learned plans on the same batches")
+    ap.add_argument("--tune", action="store_true", help="autotune the per-bucket dispatch before timing")
+    ap.add_argument("--batched", action="store_true", help="one huge_count_batch call per step")
+    ap.add_argument("--cap", type=float, default=None, help="frontier cap in bytes (default: the workload's)")
     ap.add_argument("--strategy", type=int, default=-1, help="intersection strategy (-1 = library default)")
     ap.add_argument("--no-hash", action="store_true", help="count only (no set-hash)")
     args = ap.parse_args()
@@ -134,51 +173,86 @@ def main():
     G = huge.load(g.row_ptr, g.col)
     info = G.info()
     log("loaded on GPU in %.1f ms (max degree %d)" % (info["load_ms"], info["max_degree"]))
-    plans = []
-    for name in W["queries"]:
-        k, e = P.NAMED[name]
-        p = huge.plan(G, k, e, learned=args.learned)
-        plans.append((name, p))
-        log("plan %s: order %s est_cost %.3g" % (name, p.info()["order"], p.info()["est_cost"]))
+    queries = build_queries(W, G, huge, P)
+    model = huge.Model.load(args.learned if args.learned else MODEL_PATH) \
+        if (args.learned or args.compare) else None
+    modes = ["cost-model", "learned"] if args.compare else (["learned"] if args.learned else ["cost-model"])
+    plans = {m: [] for m in modes}
+    for name, k, e in queries:
+        for m in modes:
+            t_p = time.perf_counter()
+            p = huge.plan(G, k, e, learned=model if m == "learned" else None)
+            plan_ms = (time.perf_counter() - t_p) * 1e3
+            plans[m].append((name, k, p, plan_ms))
+            log("plan %s [%s]: order %s est_cost %.3g (%.1f ms)" % (name, m, p.info()["order"],
+                                                                   p.info()["est_cost"], plan_ms))
     ws = huge.Workspace()
     nb = W["batches"]
-    kw = dict(cap=W["cap"], workspace=ws, strategy=args.strategy, hash=not args.no_hash)
+    cap = int(args.cap) if args.cap is not None else W["cap"]
+    kw = dict(cap=cap, workspace=ws, strategy=args.strategy, hash=not args.no_hash)
+    by_order0 = isinstance(W["queries"], list) and not args.batched
 
-    def batch_kw(name, p, b):
+    def batch_kw(p, b):
         if nb <= 1:
             return {}
-        return dict(slice_count=nb, slice_id=b % nb, slice_vertex=p.info()["order"][0])
+        return dict(slice_count=nb, slice_id=b % nb, slice_vertex=p.info()["order"][0] if by_order0 else 0)
 
-    # warmup on the last batches, time the first ones: no batch is seen twice
-    for i in range(args.warmup):
-        b = nb - 1 - i
-        for name, p in plans:
-            r = huge.count(G, p, **kw, **batch_kw(name, p, b))
-            log("warmup batch %d %s: count=%d %.1f ms launches=%d peak_frontier=%.2f GB" % (
-                b, name, r["count"], r["query_ms"], r["launches"], r["peak_frontier_bytes"] / 1e9))
+    tune_info = None
+    if args.tune:
+        t_t = time.perf_counter()
+        sample = [p for _, _, p, _ in plans[modes[-1]]]
+        table = huge.autotune(G, sample, cache=os.environ.get("HUGE_TUNE_CACHE"),
+                              slice_count=max(nb, 64), slice_id=max(nb, 64) - 1, slice_vertex=0, cap=cap)
+        kw["tune"] = table
+        tune_info = {"tune_s": round(time.perf_counter() - t_t, 2),
+                     "strategy": {str(j): table.to_dict()["strategy"][j] for j in range(huge.KMAX + 1)
+                                  if any(table.items[j][c] for c in range(huge.TUNE_BUCKETS))},
+                     "chunk_rows": {str(j): table.chunk_rows[j] for j in range(huge.KMAX + 1) if table.chunk_rows[j]}}
+        log("autotuned in %.1f s: %s" % (tune_info["tune_s"], json.dumps(tune_info)))
 
-    kms = [0.0] * 4
-    kl = [0] * 4
-    kb = [0.0] * 4
-    total = 0
-    per_q = {name: [] for name, _ in plans}
-    counts = {name: [] for name, _ in plans}
-    torch.cuda.synchronize()
-    t_start = time.perf_counter()
-    for s in range(args.steps):
-        for name, p in plans:
-            r = huge.count(G, p, profile=True, **kw, **batch_kw(name, p, s))
-            total += r["count"]
-            counts[name].append(r["count"])
-            per_q[name].append(r["query_ms"])
+    def run_step(m, b, profile, acc):
+        pl = plans[m]
+        if args.batched:
+            rs = huge.count_batch(G, [p for _, _, p, _ in pl], **{k2: v for k2, v in kw.items() if k2 != "workspace"},
+                                  profile=profile, **batch_kw(pl[0][2], b))
+        else:
+            rs = [huge.count(G, p, profile=profile, **kw, **batch_kw(p, b)) for _, _, p, _ in pl]
+        for (name, k, p, _), r in zip(pl, rs):
+            a = acc.setdefault(name, {"count": 0, "ms": [], "keys": []})
+            a["count"] += r["count"]
+            a["ms"].append(r["query_ms"])
+            a["keys"].append((r["count"], r["hash_sum"], r["hash_xor"]))
             for c in range(4):
-                kms[c] += r["kernel_ms"][c]
-                kl[c] += r["kernel_launches"][c]
-                kb[c] += r["alg_bytes"][c]
-        log("step %d (batch %d) done" % (s, s % max(1, nb)))
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t_start
+                acc["_kms"][c] += r["kernel_ms"][c]
+                acc["_kl"][c] += r["kernel_launches"][c]
+                acc["_kb"][c] += r["alg_bytes"][c]
 
+    results = {}
+    for m in modes:
+        # warmup on the last batches, time the first ones: no batch is seen twice
+        for i in range(args.warmup):
+            run_step(m, nb - 1 - i, False, {"_kms": [0.0] * 4, "_kl": [0] * 4, "_kb": [0.0] * 4})
+            log("warmup [%s] batch %d done" % (m, nb - 1 - i))
+        acc = {"_kms": [0.0] * 4, "_kl": [0] * 4, "_kb": [0.0] * 4}
+        torch.cuda.synchronize()
+        t_start = time.perf_counter()
+        for s_ in range(args.steps):
+            run_step(m, s_, True, acc)
+            log("step %d [%s] (batch %d) done" % (s_, m, s_ % max(1, nb)))
+        torch.cuda.synchronize()
+        elapsed = time.perf_counter() - t_start
+        results[m] = (acc, elapsed)
+    if args.compare:
+        a0, a1 = results["cost-model"][0], results["learned"][0]
+        for name, _, _ in queries:
+            if a0[name]["keys"] != a1[name]["keys"]:
+                raise SystemExit("learned and cost-model plans disagree on %s: %s vs %s" % (
+                    name, a0[name]["keys"], a1[name]["keys"]))
+
+    main_mode = modes[-1]
+    acc, elapsed = results[main_mode]
+    total = sum(v["count"] for k_, v in acc.items() if not k_.startswith("_"))
+    kms, kl, kb = acc["_kms"], acc["_kl"], acc["_kb"]
     dom = max(range(4), key=lambda c: kms[c])
     avg_ms = kms[dom] / max(1, kl[dom])
     bytes_per_launch = kb[dom] / max(1, kl[dom])
@@ -189,7 +263,36 @@ def main():
             "avg_launch_ms": round(avg_ms, 4),
             "alg_bytes_per_launch": bytes_per_launch, "launches": kl[dom],
             "kernel_ms_by_class": {KC_NAMES[c]: round(kms[c], 3) for c in range(4)}}
-
+    cfg = {"workload": W["desc"], "plan": main_mode,
+           "batches": "%d root batches, batch i timed at step i" % nb if nb > 1 else "whole graph per step",
+           "engine": "levels" if not args.batched else "batch", "strategy": args.strategy,
+           "hash": not args.no_hash, "frontier_cap_bytes": cap, "graph_load_ms": info["load_ms"],
+           "n": g.n, "m": g.m, "queries": len(queries)}
+    if len(queries) <= 4:
+        cfg["counts"] = {k_: [x[0] for x in v["keys"]] for k_, v in acc.items() if not k_.startswith("_")}
+        cfg["query_ms_median"] = {k_: sorted(v["ms"])[len(v["ms"]) // 2] for k_, v in acc.items()
+                                  if not k_.startswith("_")}
+    if tune_info:
+        cfg["autotune"] = tune_info
+    if args.compare:
+        e0, e1 = results["cost-model"][1], results["learned"][1]
+        a0 = results["cost-model"][0]
+        ratios = []
+        per = {}
+        for (name, k, p0, _), (_, _, p1, _) in zip(plans["cost-model"], plans["learned"]):
+            t0_ = sum(a0[name]["ms"])
+            t1_ = sum(acc[name]["ms"])
+            ratios.append(t0_ / max(t1_, 1e-9))
+            per[name] = {"order_cost_model": p0.info()["order"], "order_learned": p1.info()["order"],
+                         "ms_cost_model": round(t0_, 2), "ms_learned": round(t1_, 2)}
+        import math
+        cfg["compare"] = {"cost_model_s": round(e0, 3), "learned_s": round(e1, 3),
+                          "speedup_total": round(e0 / max(e1, 1e-9), 4),
+                          "speedup_geomean": round(math.exp(sum(math.log(r) for r in ratios) / len(ratios)), 4),
+                          "orders_changed": sum(1 for v in per.values() if v["order_cost_model"] != v["order_learned"]),
+                          "counts_equal": True,
+                          "plan_ms_learned": round(sum(x[3] for x in plans["learned"]), 1),
+                          "per_query": per if len(per) <= 64 else None}
     out = {
         "metric": "embeddings/sec + query time, learned/batched vs cost-model plan, 1 GPU",
         "value": total / elapsed,
@@ -203,20 +306,13 @@ def main():
         "vs_baseline": None,
         "dtype": "int32",
         "data": "synthetic",
-        "config": {"workload": W["desc"], "plan": "learned" if args.learned else "cost-model",
-                   "batches": "%d root batches (first matched vertex), batch i timed at step i" % nb
-                   if nb > 1 else "whole graph per step",
-                   "engine": "levels", "strategy": args.strategy, "hash": not args.no_hash,
-                   "frontier_cap_bytes": W["cap"],
-                   "counts": counts,
-                   "query_ms_median": {k: sorted(v)[len(v) // 2] for k, v in per_q.items()},
-                   "graph_load_ms": info["load_ms"], "n": g.n, "m": g.m},
+        "config": cfg,
         "roofline": roof,
     }
     if not args.no_cpu:
         threads = min(16, os.cpu_count() or 1)
         log("cpu baseline: oracle on root slices, %d threads, budget %.0f s" % (threads, args.cpu_budget))
-        out["cpu_baseline"] = cpu_baseline(g, W["queries"], args.cpu_budget, threads)
+        out["cpu_baseline"] = cpu_baseline(g, queries, args.cpu_budget, threads)
     else:
         out["cpu_baseline"] = None
     print(json.dumps(out), flush=True)
