@@ -56,19 +56,21 @@ WORKLOADS = {
     },
     "c4": {
         "desc": "R-MAT scale 24, edge factor 16, (0.57,0.19,0.19,0.05), seed 4: 64 random connected 3-6 vertex "
-                "patterns (seed 4; estimate <= 1e15)",
+                "patterns (seed 4; at most 4e9 candidates per 1/2^16 edge batch)",
         "graph": ("rmat", dict(scale=24, edge_factor=16, seed=4)),
-        "queries": ("random", dict(count=64, seed=4, kmin=3, kmax=6, max_est=1e15)),
+        "queries": ("random", dict(count=64, seed=4, kmin=3, kmax=6, max_work=4e9)),
         "cap": 8 << 30,
-        "batches": 1024,
+        "batches": 1 << 16,
+        "slice": "edge",
     },
     "c5": {
         "desc": "R-MAT scale 26, edge factor 16, (0.57,0.19,0.19,0.05), seed 5: 32 held-out random 4-6 vertex "
-                "patterns (seed 5; estimate <= 1e15)",
+                "patterns (seed 5; at most 2e10 candidates per 1/2^16 edge batch)",
         "graph": ("rmat", dict(scale=26, edge_factor=16, seed=5)),
-        "queries": ("random", dict(count=32, seed=5, kmin=4, kmax=6, max_est=1e15)),
+        "queries": ("random", dict(count=32, seed=5, kmin=4, kmax=6, max_work=2e10)),
         "cap": 16 << 30,
-        "batches": 4096,
+        "batches": 1 << 16,
+        "slice": "edge",
     },
 }
 MODEL_PATH = os.path.join(ROOT, "paper_2103_14294_amd", "card_mlp.npz")
@@ -115,22 +117,48 @@ def cpu_baseline(g, queries, budget_s, threads):
     }
 
 
-def build_queries(W, G, huge, P):
+def build_queries(W, G, huge, P, ws):
     """[(name, k, edges)] for the workload: named queries, or seeded random patterns
-    whose cost-model estimate on this graph is within the budget."""
+    whose cost-model plan finishes one batch (the last, never timed) within the
+    workload's work budget (candidates examined)."""
     q = W["queries"]
     if isinstance(q, list):
         return [(n,) + tuple(P.NAMED[n]) for n in q]
     kw = dict(q[1])
-    max_est = kw.pop("max_est")
-    out = []
+    budget = kw.pop("max_work")
+    nb = W["batches"]
+    out, tried = [], 0
     for pat in P.random_patterns(kw["count"] * 8, seed=kw["seed"], kmin=kw["kmin"], kmax=kw["kmax"]):
         if len(out) == kw["count"]:
             break
-        est = huge.plan(G, pat["k"], pat["edges"]).info()["est_cost"]
-        if est <= max_est:
+        tried += 1
+        p = huge.plan(G, pat["k"], pat["edges"])
+        r = huge.count(G, p, slice_count=nb, slice_id=nb - 1, slice_vertex=-2 if W.get("slice") == "edge" else -1,
+                       work_limit=int(budget),
+                       workspace=ws, hash=False, cap=W["cap"])
+        if not r["stopped"]:
             out.append(("%s-k%d-%d" % (pat["family"], pat["k"], len(out)), pat["k"], pat["edges"]))
+    log("%d of %d random patterns within %.3g candidates per batch" % (len(out), tried, budget))
     return out
+
+
+def copy_bandwidth(torch, nbytes=4 << 30, reps=5):
+    """Device-to-device copy of nbytes (torch's copy kernel): achieved GB/s counting the
+    read and the write, and the bytes one copy moves."""
+    a = torch.empty(nbytes // 4, dtype=torch.int32, device="cuda")
+    b = torch.empty_like(a)
+    a.fill_(1)
+    b.copy_(a)
+    s = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(s)
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record(s)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del a, b
+    return 2.0 * nbytes / (ms * 1e-3) / 1e9, 2 * nbytes
 
 
 def main():
@@ -142,14 +170,18 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=20.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--learned", nargs="?", const=MODEL_PATH, default=None,
-                    help="plan with the learned cardinality model (default model file if no path)")
+                    help="plan with the learned cost model, its best orders verified on a root sample "
+                         "(default model file if no path)")
     ap.add_argument("--compare", action="store_true",
                     help="time the cost-model plans and the learned plans on the same batches")
-    ap.add_argument("--tune", action="store_true", help="autotune the per-bucket dispatch before timing")
+    ap.add_argument("--no-tune", dest="tune", action="store_false",
+                    help="skip autotuning the per-bucket dispatch before timing (library default kernels)")
     ap.add_argument("--batched", action="store_true", help="one huge_count_batch call per step")
     ap.add_argument("--cap", type=float, default=None, help="frontier cap in bytes (default: the workload's)")
     ap.add_argument("--strategy", type=int, default=-1, help="intersection strategy (-1 = library default)")
     ap.add_argument("--no-hash", action="store_true", help="count only (no set-hash)")
+    ap.add_argument("--copy-only", action="store_true",
+                    help="only run the 4 GiB device copy (counter calibration) and print its bandwidth")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -166,6 +198,10 @@ def main():
         print("no GPU visible", file=sys.stderr)
         sys.exit(3)
     torch.cuda.set_device(0)
+    if args.copy_only:
+        gbs, moved = copy_bandwidth(torch)
+        print(json.dumps({"copy_gbs": round(gbs, 1), "bytes_per_copy": moved, "copies": 6}), flush=True)
+        return
     W = WORKLOADS[args.workload]
     t0 = time.perf_counter()
     g = make_graph(W["graph"])
@@ -173,7 +209,8 @@ def main():
     G = huge.load(g.row_ptr, g.col)
     info = G.info()
     log("loaded on GPU in %.1f ms (max degree %d)" % (info["load_ms"], info["max_degree"]))
-    queries = build_queries(W, G, huge, P)
+    ws = huge.Workspace()
+    queries = build_queries(W, G, huge, P, ws)
     model = huge.Model.load(args.learned if args.learned else MODEL_PATH) \
         if (args.learned or args.compare) else None
     modes = ["cost-model", "learned"] if args.compare else (["learned"] if args.learned else ["cost-model"])
@@ -181,28 +218,32 @@ def main():
     for name, k, e in queries:
         for m in modes:
             t_p = time.perf_counter()
-            p = huge.plan(G, k, e, learned=model if m == "learned" else None)
+            p = huge.plan(G, k, e, learned=model if m == "learned" else None, verify=m == "learned")
             plan_ms = (time.perf_counter() - t_p) * 1e3
             plans[m].append((name, k, p, plan_ms))
             log("plan %s [%s]: order %s est_cost %.3g (%.1f ms)" % (name, m, p.info()["order"],
                                                                    p.info()["est_cost"], plan_ms))
-    ws = huge.Workspace()
     nb = W["batches"]
     cap = int(args.cap) if args.cap is not None else W["cap"]
     kw = dict(cap=cap, workspace=ws, strategy=args.strategy, hash=not args.no_hash)
-    by_order0 = isinstance(W["queries"], list) and not args.batched
+    # batches slice on each plan's first matched vertex, or on its level-2 rows (edge
+    # slices, which reach hubs in proportion to their degree): an unbiased 1/nb sample of
+    # that plan's work, the same in sequential and batched runs
 
     def batch_kw(p, b):
         if nb <= 1:
             return {}
-        return dict(slice_count=nb, slice_id=b % nb, slice_vertex=p.info()["order"][0] if by_order0 else 0)
+        return dict(slice_count=nb, slice_id=b % nb, slice_vertex=sv_mode)
 
+    sv_mode = -2 if W.get("slice") == "edge" else -1
     tune_info = None
     if args.tune:
+        log("autotuning the per-bucket dispatch on a 1/%d sample" % max(4 * nb, 256))
         t_t = time.perf_counter()
         sample = [p for _, _, p, _ in plans[modes[-1]]]
         table = huge.autotune(G, sample, cache=os.environ.get("HUGE_TUNE_CACHE"),
-                              slice_count=max(nb, 64), slice_id=max(nb, 64) - 1, slice_vertex=0, cap=cap)
+                              slice_count=max(4 * nb, 256), slice_id=max(4 * nb, 256) - 1, slice_vertex=sv_mode,
+                              cap=cap)
         kw["tune"] = table
         tune_info = {"tune_s": round(time.perf_counter() - t_t, 2),
                      "strategy": {str(j): table.to_dict()["strategy"][j] for j in range(huge.KMAX + 1)
@@ -216,7 +257,11 @@ def main():
             rs = huge.count_batch(G, [p for _, _, p, _ in pl], **{k2: v for k2, v in kw.items() if k2 != "workspace"},
                                   profile=profile, **batch_kw(pl[0][2], b))
         else:
-            rs = [huge.count(G, p, profile=profile, **kw, **batch_kw(p, b)) for _, _, p, _ in pl]
+            rs = []
+            for name, _, p, _ in pl:
+                rs.append(huge.count(G, p, profile=profile, **kw, **batch_kw(p, b)))
+                if len(pl) > 4 or rs[-1]["query_ms"] > 2000:
+                    log("  [%s] batch %d %s: %.1f ms" % (m, b, name, rs[-1]["query_ms"]))
         for (name, k, p, _), r in zip(pl, rs):
             a = acc.setdefault(name, {"count": 0, "ms": [], "keys": []})
             a["count"] += r["count"]
@@ -242,12 +287,27 @@ def main():
         torch.cuda.synchronize()
         elapsed = time.perf_counter() - t_start
         results[m] = (acc, elapsed)
+    checked = 0
     if args.compare:
+        # exactness: where both plans start from the same query vertex they ran the same
+        # batches; otherwise the learned plan runs the cost-model plan's first batch (bounded)
         a0, a1 = results["cost-model"][0], results["learned"][0]
-        for name, _, _ in queries:
-            if a0[name]["keys"] != a1[name]["keys"]:
-                raise SystemExit("learned and cost-model plans disagree on %s: %s vs %s" % (
-                    name, a0[name]["keys"], a1[name]["keys"]))
+        for (name, k, p0, _), (_, _, p1, _) in zip(plans["cost-model"], plans["learned"]):
+            same = p0.info()["order"][:2] == p1.info()["order"][:2] if sv_mode == -2 else \
+                p0.info()["order"][0] == p1.info()["order"][0]
+            if same:
+                got, want = a1[name]["keys"], a0[name]["keys"]
+            else:
+                if sv_mode == -2:
+                    continue  # an edge slice is defined by each plan's own first two vertices
+                r = huge.count(G, p1, work_limit=int(4e10), **kw,
+                               **dict(batch_kw(p0, 0), slice_vertex=p0.info()["order"][0]))
+                if r["stopped"]:
+                    continue
+                got, want = [(r["count"], r["hash_sum"], r["hash_xor"])], a0[name]["keys"][:1]
+            if got != want:
+                raise SystemExit("learned and cost-model plans disagree on %s: %s vs %s" % (name, got, want))
+            checked += 1
 
     main_mode = modes[-1]
     acc, elapsed = results[main_mode]
@@ -290,7 +350,9 @@ def main():
                           "speedup_total": round(e0 / max(e1, 1e-9), 4),
                           "speedup_geomean": round(math.exp(sum(math.log(r) for r in ratios) / len(ratios)), 4),
                           "orders_changed": sum(1 for v in per.values() if v["order_cost_model"] != v["order_learned"]),
-                          "counts_equal": True,
+                          "exactness_checked": "%d of %d queries: learned plan vs cost-model plan, "
+                                               "equal count and hashes (same batches, or the cost-model "
+                                               "plan's batch 0 within 4e10 candidates)" % (checked, len(queries)),
                           "plan_ms_learned": round(sum(x[3] for x in plans["learned"]), 1),
                           "per_query": per if len(per) <= 64 else None}
     out = {
@@ -309,6 +371,9 @@ def main():
         "config": cfg,
         "roofline": roof,
     }
+    gbs, _ = copy_bandwidth(torch)
+    out["roofline"]["copy_gbs"] = round(gbs, 1)
+    out["roofline"]["frac_of_copy"] = round(achieved / gbs, 4) if gbs > 0 else None
     if not args.no_cpu:
         threads = min(16, os.cpu_count() or 1)
         log("cpu baseline: oracle on root slices, %d threads, budget %.0f s" % (threads, args.cpu_budget))

@@ -65,7 +65,8 @@ typedef struct huge_plan huge_plan;
 
 /* huge_plan flags */
 #define HUGE_PLAN_COST_MODEL 0x0u /* order from the cost model (Algorithm 1, wco plans) */
-#define HUGE_PLAN_LEARNED 0x1u    /* order from the learned cardinality model (huge_plan_create_learned) */
+#define HUGE_PLAN_LEARNED 0x1u    /* order from the learned cost model (huge_plan_create_learned) */
+#define HUGE_PLAN_VERIFY 0x2u     /* learned plans: measure the model's best orders on a root sample */
 
 /* huge_exec_opts.engine */
 #define HUGE_ENGINE_AUTO 0
@@ -91,6 +92,10 @@ typedef struct {
     double kernel_ms[4];
     uint64_t kernel_launches[4];
     double alg_bytes[4];
+    /* level engine: level_work[i] = candidates examined (probe-list elements inside
+       the symmetry-breaking window) while extending the partial matches of level i
+       (i+1 order vertices) by one vertex; 0 on the persistent engine */
+    uint64_t level_work[HUGE_KMAX];
 } huge_result;
 #define HUGE_KC_PREPARE 0 /* SB window trim + probe choice */
 #define HUGE_KC_SCAN 1    /* exclusive scan of per-row bounds */
@@ -145,8 +150,12 @@ typedef struct {
     void *workspace;             /* caller-owned device memory, or NULL = library allocates */
     uint64_t workspace_bytes;
     int32_t profile;             /* 1 = time every launch with HIP events (kernel_ms etc.) */
-    int32_t slice_vertex;        /* query vertex whose image is sliced (default 0); slices of any fixed
-                                    vertex partition the matches, so counts add and hashes add / xor */
+    int32_t slice_vertex;        /* query vertex whose image is sliced (default 0; -1 = the plan's first
+                                    matched vertex, order[0]; -2 = edge slice: keep the matches whose
+                                    first two matched vertices (x, y) = (f(order[0]), f(order[1])), as
+                                    ranks, have mix(x << 32 | y) % slice_count == slice_id); slices of
+                                    any fixed vertex, or edge slices of one plan, partition the matches,
+                                    so counts add and hashes add / xor */
     uint32_t exec_flags;         /* HUGE_EXEC_* bits */
     uint32_t reserved;
     const huge_tune_table *tune; /* per-bucket dispatch table, or NULL (read during the call only) */
@@ -259,19 +268,25 @@ huge_status huge_enumerate(const huge_graph *g, const huge_plan *p, const huge_e
 
 /*
  * huge_count_batch -- count np queries; outs[np], in the order of plans.
- * The queries of 3..HUGE_PERSIST_KMAX vertices run in one persistent launch
- * (they share the workgroups, the frontier budget and the stealing pool,
- * Section 5.3); the others run on the level engine one after
- * another on opts->stream.  opts->engine is ignored.
+ * engine AUTO or LEVELS: a few host workers (environment variable
+ * HUGE_BATCH_STREAMS, default 4), each with its own HIP stream and workspace
+ * (sized for the largest query; opts->workspace is not used), run the
+ * queries on the level engine concurrently; work queued on opts->stream
+ * before the call runs first.  engine PERSISTENT: the queries of
+ * 3..HUGE_PERSIST_KMAX vertices run in one persistent launch (they share the
+ * workgroups, the frontier budget and the stealing pool, Section 5.3), the
+ * others on the level engine one after another on opts->stream.
  */
 huge_status huge_count_batch(const huge_graph *g, const huge_plan *const *plans, int32_t np,
                              const huge_exec_opts *opts, huge_result *outs);
 
 /* ------------------------------------------------------------------------
- * Learned cardinality model.  The optimiser of Section 3.3 (Algorithm 1)
- * needs the result size |R(q')| of each order prefix and leaves the estimator
- * open; this is a 2-layer MLP that predicts log(1 + |R(prefix)|) from
- * HUGE_MLP_F features of the prefix and of the graph's degree sketch:
+ * Learned cost model.  The optimiser of Section 3.3 (Algorithm 1) ranks
+ * plans by estimated sizes and leaves the estimator open; this is a 2-layer
+ * MLP that predicts, for the step that produces prefix s of an order,
+ * log(1 + W_s) with W_s the candidates that step examines (the engine's
+ * level_work[s-2]), from HUGE_MLP_F features of the prefix and of the graph's
+ * degree sketch:
  *     y = b2 + sum_h W2[h] relu(b1[h] + sum_f W1[f][h] xn[f]),
  *     xn[f] = (x[f] - xmean[f]) * xinv[f],  label = y * tstd + tmean.
  * Parameters (float, HUGE_MLP_PARAMS of them) are laid out as
@@ -297,7 +312,7 @@ huge_status huge_model_set(huge_model *m, const float *params, const float *xmea
                            float tstd);
 huge_status huge_model_get(const huge_model *m, float *params, float *xmean, float *xinv, float *tmean, float *tstd);
 
-/* y[B] = predicted log(1 + |R|) for x[B][HUGE_MLP_F]; device pointers, asynchronous on stream. */
+/* y[B] = predicted label (log(1 + W_s)) for x[B][HUGE_MLP_F]; device pointers, asynchronous on stream. */
 huge_status huge_model_forward(const huge_model *m, const float *x, int64_t B, float *y, void *stream);
 
 /*
@@ -327,15 +342,25 @@ huge_status huge_plan_features(const huge_graph *g, const huge_plan *p, const in
 
 /*
  * huge_plan_create with the learned model as the estimator: every connected
- * order is scored in one batched forward pass on `stream` and the order with
- * the smallest estimated sum of prefix sizes wins (ties to the
- * lexicographically smallest), exactly as the cost model does with its own
- * estimates.  The plan only decides the order (and chunk sizes): counts are
+ * order is scored in one batched forward pass on `stream`; the order with the
+ * smallest estimated sum over steps s = 3..k of W_s (ties to the
+ * lexicographically smallest) replaces the cost model's order only when its
+ * predicted sum is less than half of the cost model's order's; the plan's
+ * est_cost is the predicted sum of the order kept.  The plan only decides the order (and chunk sizes): counts are
  * exact whatever it picks.  huge_plan_create with HUGE_PLAN_LEARNED and no
  * model returns HUGE_EINVAL.
  */
 huge_status huge_plan_create_learned(const huge_graph *g, const huge_model *m, int32_t k, int32_t n_qedges,
                                      const int32_t *qedges, const int32_t *order, void *stream, huge_plan **out);
+/*
+ * As huge_plan_create_learned, with flags: HUGE_PLAN_VERIFY runs the model's
+ * four best orders and the cost model's order on one edge slice of about
+ * 65536 level-2 rows (at most 4e9 candidates each, on `stream`) and keeps the
+ * order with the least device time.
+ */
+huge_status huge_plan_create_learned2(const huge_graph *g, const huge_model *m, int32_t k, int32_t n_qedges,
+                                      const int32_t *qedges, const int32_t *order, uint32_t flags, void *stream,
+                                      huge_plan **out);
 
 /*
  * huge_autotune -- fill a dispatch table by timing, on the graph itself, the

@@ -52,6 +52,11 @@
  * mix(r(f(a))) mod S == s are kept (a = query vertex 0 by default).  The
  * slices of any fixed query vertex partition the results, so
  * counts and sums add and xors combine over s.
+ *
+ * Pair slice (slice_vertex a and slice_vertex2 b >= 0): only maps with
+ * mix(r(f(a)) * 2^32 + r(f(b))) mod S == s are kept, checked when the later
+ * of a and b is matched; slices of a fixed ordered pair also partition the
+ * results.
  */
 #include <pthread.h>
 #include <stdint.h>
@@ -269,10 +274,11 @@ typedef struct {
     int gt[ORC_KMAX][28];       /* positions p: need r(new) < r(f[p]) */
     uint32_t slice_count, slice_id;
     int slice_pos;              /* position of the sliced query vertex */
+    int pair_a, pair_b;         /* pair slice: positions of the two query vertices, or -1 */
 } orc_plan;
 
 static int orc_plan_init(orc_plan *P, const orc_query *q, const orc_graph *g, int mode,
-                         const int32_t *order, uint32_t sc, uint32_t sid, int slice_vertex) {
+                         const int32_t *order, uint32_t sc, uint32_t sid, int slice_vertex, int slice_vertex2) {
     memset(P, 0, sizeof(*P));
     P->q = q;
     P->g = g;
@@ -323,6 +329,13 @@ static int orc_plan_init(orc_plan *P, const orc_query *q, const orc_graph *g, in
     P->slice_id = sid;
     if (slice_vertex < 0 || slice_vertex >= k) return -1;
     P->slice_pos = P->pos[slice_vertex];
+    P->pair_a = P->pair_b = -1;
+    if (slice_vertex2 >= 0) {
+        if (slice_vertex2 >= k || slice_vertex2 == slice_vertex) return -1;
+        P->pair_a = P->pos[slice_vertex];
+        P->pair_b = P->pos[slice_vertex2];
+        P->slice_pos = -1; /* no vertex slice */
+    }
     return 0;
 }
 
@@ -376,6 +389,11 @@ static int orc_accept(orc_worker *w, int i, int32_t c) {
         if (!(rc < g->rank[w->f[P->gt[i][t]]])) return 0;
     if (P->slice_count > 1 && i == P->slice_pos)
         if (orc_mix((uint64_t)(uint32_t)rc) % P->slice_count != P->slice_id) return 0;
+    if (P->slice_count > 1 && P->pair_a >= 0 && i == (P->pair_a > P->pair_b ? P->pair_a : P->pair_b)) {
+        uint32_t ra = (uint32_t)(i == P->pair_a ? rc : g->rank[w->f[P->pair_a]]);
+        uint32_t rb = (uint32_t)(i == P->pair_b ? rc : g->rank[w->f[P->pair_b]]);
+        if (orc_mix(((uint64_t)ra << 32) | rb) % P->slice_count != P->slice_id) return 0;
+    }
     return 1;
 }
 
@@ -437,7 +455,8 @@ static void *orc_thread(void *arg) {
  */
 int orc_enumerate(int64_t n, const int64_t *rp, const int32_t *col, int k, int nqe,
                   const int32_t *qedges, int mode, const int32_t *order, int nsb,
-                  const int32_t *sb_pairs, uint32_t slice_count, uint32_t slice_id, int slice_vertex, int nthreads,
+                  const int32_t *sb_pairs, uint32_t slice_count, uint32_t slice_id, int slice_vertex,
+                  int slice_vertex2, int nthreads,
                   orc_result *out) {
     orc_query q;
     if (orc_query_init(&q, k, nqe, qedges) != 0) return -1;
@@ -466,7 +485,7 @@ int orc_enumerate(int64_t n, const int64_t *rp, const int32_t *col, int k, int n
     g.rank = (int32_t *)malloc(sizeof(int32_t) * (size_t)(n > 0 ? n : 1));
     orc_ranks(n, rp, g.rank);
     orc_plan P;
-    if (orc_plan_init(&P, &q, &g, mode, order, slice_count, slice_id, slice_vertex) != 0) {
+    if (orc_plan_init(&P, &q, &g, mode, order, slice_count, slice_id, slice_vertex, slice_vertex2) != 0) {
         free(g.rank);
         free(q.aut);
         return -1;

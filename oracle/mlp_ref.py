@@ -1,15 +1,15 @@
-"""Test infrastructure: a plain FP64 reference of the learned cardinality model.
+"""Test infrastructure: a plain FP64 reference of the learned cost model.
 
 Only the tests (and nothing on the product path) use this module.  It shares
 no code with the library's HIP kernels.
 
 Model (the estimator slot of the optimiser, Section 3.3, left open by the
-paper): a 2-layer MLP with F = 128 inputs, H = 256 ReLU hidden units and one
-output,
+paper; it predicts the log of a per-step size of a matching order): a
+2-layer MLP with F = 128 inputs, H = 256 ReLU hidden units and one output,
     xn  = (x - xmean) * xinv
     z   = xn @ W1 + b1          (W1 is F x H)
     yn  = relu(z) @ W2 + b2
-    label = yn * tstd + tmean   (predicted log(1 + |R(prefix)|))
+    label = yn * tstd + tmean   (the predicted log-size)
 Parameters are packed as W1 (row-major, F x H) | b1 (H) | W2 (H) | b2 (1).
 The loss is L = mean((yn - (t - tmean) / tstd)^2).  The library computes with
 BF16 copies of FP32 master weights: `bf16_round` gives the values it uses, so

@@ -21,7 +21,7 @@ HUGE_OK, HUGE_STOPPED = 0, 1
 STATUS = {0: "HUGE_OK", 1: "HUGE_STOPPED", -1: "HUGE_EINVAL", -2: "HUGE_ENOMEM", -3: "HUGE_EDEVICE",
           -4: "HUGE_EGRAPH", -5: "HUGE_EQUERY", -6: "HUGE_EORDER", -7: "HUGE_EOVERFLOW"}
 HOST_PTRS, DEVICE_PTRS, NO_VALIDATE, NO_HUB_BITMAP = 0x1, 0x2, 0x4, 0x8
-PLAN_COST_MODEL, PLAN_LEARNED = 0x0, 0x1
+PLAN_COST_MODEL, PLAN_LEARNED, PLAN_VERIFY = 0x0, 0x1, 0x2
 ENGINE_AUTO, ENGINE_LEVELS, ENGINE_PERSISTENT = 0, 1, 2
 EXEC_NO_HASH = 0x1
 STRAT_BSEARCH, STRAT_WAVE_STAGED, STRAT_LANE_MERGE = 0, 1, 2
@@ -32,7 +32,7 @@ EXPORTED = [
     "huge_enumerate", "huge_count_batch", "huge_last_error",
     "huge_model_create", "huge_model_free", "huge_model_set", "huge_model_get", "huge_model_forward",
     "huge_model_grad", "huge_model_train", "huge_plan_features", "huge_plan_create_learned",
-    "huge_autotune", "huge_graph_digest", "huge_plan_prefix",
+    "huge_autotune", "huge_graph_digest", "huge_plan_prefix", "huge_plan_create_learned2",
 ]
 MLP_F, MLP_H = 128, 256
 MLP_PARAMS = MLP_F * MLP_H + 2 * MLP_H + 1
@@ -50,7 +50,8 @@ class Result(ctypes.Structure):
                 ("level_counts", ctypes.c_uint64 * KMAX), ("query_ms", ctypes.c_double),
                 ("peak_frontier_bytes", ctypes.c_uint64), ("launches", ctypes.c_uint64),
                 ("steals", ctypes.c_uint64), ("kernel_ms", ctypes.c_double * 4),
-                ("kernel_launches", ctypes.c_uint64 * 4), ("alg_bytes", ctypes.c_double * 4)]
+                ("kernel_launches", ctypes.c_uint64 * 4), ("alg_bytes", ctypes.c_double * 4),
+                ("level_work", ctypes.c_uint64 * KMAX)]
 
     def to_dict(self):
         return {"count": int(self.count), "hash_sum": int(self.hash_sum), "hash_xor": int(self.hash_xor),
@@ -58,7 +59,8 @@ class Result(ctypes.Structure):
                 "peak_frontier_bytes": int(self.peak_frontier_bytes), "launches": int(self.launches),
                 "steals": int(self.steals), "kernel_ms": [float(x) for x in self.kernel_ms],
                 "kernel_launches": [int(x) for x in self.kernel_launches],
-                "alg_bytes": [float(x) for x in self.alg_bytes]}
+                "alg_bytes": [float(x) for x in self.alg_bytes],
+                "level_work": [int(x) for x in self.level_work]}
 
 
 class ExecOpts(ctypes.Structure):
@@ -170,6 +172,8 @@ def load_library(path: str = LIB_PATH):
         lib.huge_graph_digest.argtypes = [vp, ctypes.c_char_p]
         lib.huge_plan_prefix.restype = st
         lib.huge_plan_prefix.argtypes = [vp, i32, ctypes.POINTER(vp)]
+        lib.huge_plan_create_learned2.restype = st
+        lib.huge_plan_create_learned2.argtypes = [vp, vp, i32, i32, vp, vp, u32, vp, ctypes.POINTER(vp)]
         lib.huge_plan_create_learned.restype = st
         lib.huge_plan_create_learned.argtypes = [vp, vp, i32, i32, vp, vp, vp, ctypes.POINTER(vp)]
         _lib = lib
@@ -293,17 +297,18 @@ def load(row_ptr, col, validate=True, stream=None, hub_bitmaps=True) -> Graph:
     return Graph(h.value, int(n), int(nnz))
 
 
-def plan(g: Graph, k, edges, order=None, learned=None) -> Plan:
+def plan(g: Graph, k, edges, order=None, learned=None, verify=False) -> Plan:
     """huge_plan_create for query edges over vertices 0..k-1; with a Model as
-    `learned`, huge_plan_create_learned (orders scored by the MLP on the GPU)."""
+    `learned`, huge_plan_create_learned2 (orders scored by the MLP on the GPU;
+    verify=True measures its best orders on a root sample)."""
     lib = load_library()
     e = np.ascontiguousarray(np.asarray(edges, dtype=np.int32).reshape(-1, 2))
     o = None if order is None else np.ascontiguousarray(np.asarray(order, dtype=np.int32))
     h = ctypes.c_void_p()
     if isinstance(learned, Model):
-        _check(lib.huge_plan_create_learned(g.handle, learned.handle, int(k), int(e.shape[0]), e.ctypes.data,
-                                            None if o is None else o.ctypes.data, _current_stream(),
-                                            ctypes.byref(h)))
+        _check(lib.huge_plan_create_learned2(g.handle, learned.handle, int(k), int(e.shape[0]), e.ctypes.data,
+                                             None if o is None else o.ctypes.data, PLAN_VERIFY if verify else 0,
+                                             _current_stream(), ctypes.byref(h)))
     else:
         _check(lib.huge_plan_create(None if g is None else g.handle, int(k), int(e.shape[0]), e.ctypes.data,
                                     None if o is None else o.ctypes.data,

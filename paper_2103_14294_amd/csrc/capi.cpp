@@ -19,6 +19,8 @@ void set_error(const char *fmt, ...) {
     g_last_error = buf;
 }
 
+std::string last_error_text() { return g_last_error; }
+
 template <typename F>
 static huge_status guard(F &&f) {
     try {
@@ -192,6 +194,11 @@ huge_status huge_count_batch(const huge_graph *g, const huge_plan *const *plans,
             if (!plans[i]) HUGE_FAIL(HUGE_EINVAL, "plan %d is NULL", i);
         huge_exec_opts o = resolve_opts(opts);
         std::vector<huge_result> r(np);
+        if (o.engine != HUGE_ENGINE_PERSISTENT) {
+            run_batch_levels(g, plans, np, o, r.data());
+            for (int i = 0; i < np; ++i) outs[i] = r[i];
+            return HUGE_OK;
+        }
         // queries the persistent kernel is built for share one launch; the
         // others run on the level engine, one after another, on the same stream
         std::vector<const huge_plan *> pers;
@@ -283,11 +290,18 @@ huge_status huge_plan_features(const huge_graph *g, const huge_plan *p, const in
 
 huge_status huge_plan_create_learned(const huge_graph *g, const huge_model *m, int32_t k, int32_t n_qedges,
                                      const int32_t *qedges, const int32_t *order, void *stream, huge_plan **out) {
+    return huge_plan_create_learned2(g, m, k, n_qedges, qedges, order, 0, stream, out);
+}
+
+huge_status huge_plan_create_learned2(const huge_graph *g, const huge_model *m, int32_t k, int32_t n_qedges,
+                                      const int32_t *qedges, const int32_t *order, uint32_t flags, void *stream,
+                                      huge_plan **out) {
     return guard([&] {
         if (!g || !m || !out) HUGE_FAIL(HUGE_EINVAL, "NULL argument");
+        if (flags & ~(uint32_t)HUGE_PLAN_VERIFY) HUGE_FAIL(HUGE_EINVAL, "unknown flags 0x%x", flags);
         huge_plan *p = new huge_plan();
         try {
-            plan_build(g, k, n_qedges, qedges, order, HUGE_PLAN_LEARNED, m, (hipStream_t)stream, p);
+            plan_build(g, k, n_qedges, qedges, order, HUGE_PLAN_LEARNED | flags, m, (hipStream_t)stream, p);
         } catch (...) {
             delete p;
             throw;

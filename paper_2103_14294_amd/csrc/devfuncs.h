@@ -68,12 +68,17 @@ __device__ __forceinline__ bool in_slice(int32_t v, const DevPlan &P) {
 }
 
 // Validity of a level-2 row (the SCAN of the first query edge): the
-// constraint between positions 0 and 1 and the root slice.
+// constraint between positions 0 and 1, and the slice (of the row's ordered
+// pair, or of the vertex in position 0 or 1).
 __device__ __forceinline__ bool level2_ok(const int32_t (&f)[2], const DevPlan &P) {
     const DevStep &s1 = P.st[1];
     if ((s1.lo & 1u) && !(f[0] < f[1])) return false;
     if ((s1.hi & 1u) && !(f[1] < f[0])) return false;
     if (P.slice_count > 1) {
+        if (P.edge_slice) {
+            const uint64_t key = ((uint64_t)(uint32_t)f[0] << 32) | (uint64_t)(uint32_t)f[1];
+            return (uint32_t)(mix64(key) % P.slice_count) == P.slice_id;
+        }
         if (P.st[0].slice && !in_slice(f[0], P)) return false;
         if (s1.slice && !in_slice(f[1], P)) return false;
     }

@@ -194,8 +194,10 @@ bool run_levels(const huge_graph *g, const huge_plan *p, const huge_exec_opts &o
     P.slice_count = o.slice_count > 1 ? o.slice_count : 1;
     P.slice_id = o.slice_count > 1 ? o.slice_id : 0;
     if (P.slice_count > 1 && P.slice_id >= P.slice_count) HUGE_FAIL(HUGE_EINVAL, "slice_id >= slice_count");
-    if (o.slice_vertex < 0 || o.slice_vertex >= k) HUGE_FAIL(HUGE_EINVAL, "slice_vertex out of range");
-    for (int i = 0; i < k; ++i) P.st[i].slice = p->order[i] == o.slice_vertex ? 1 : 0;
+    if (o.slice_vertex < -2 || o.slice_vertex >= k) HUGE_FAIL(HUGE_EINVAL, "slice_vertex out of range");
+    const int sv = o.slice_vertex == -1 ? p->order[0] : o.slice_vertex;  // -2: edge slice, no vertex
+    for (int i = 0; i < k; ++i) P.st[i].slice = p->order[i] == sv ? 1 : 0;
+    P.edge_slice = (o.slice_vertex == -2 && P.slice_count > 1) ? 1 : 0;
 
     int64_t stage_rows = 0;
     if (emit) {
@@ -262,6 +264,7 @@ bool run_levels(const huge_graph *g, const huge_plan *p, const huge_exec_opts &o
     const int count_mode = (o.exec_flags & HUGE_EXEC_NO_HASH) ? MODE_COUNT_NOHASH : MODE_COUNT;
     const bool root_slice = P.slice_count > 1 && P.st[0].slice;
     bool limited = false;
+    uint64_t level_work[HUGE_KMAX] = {};
     if (root_slice) {
         launch_root_count(G, P, ctrl, st);
         stats.launches++;
@@ -372,6 +375,7 @@ bool run_levels(const huge_graph *g, const huge_plan *p, const huge_exec_opts &o
                                                 hipMemcpyDeviceToHost, st));
                     HUGE_HIP(hipStreamSynchronize(st));
                     l.seg_total = hv[0];
+                    level_work[W - 1] += (uint64_t)hv[0];
                     l.seg_bytes = (double)(uint64_t)hv[1];
                     for (int c = 0; c <= HUGE_TUNE_BUCKETS; ++c) l.bw[c] = part ? hv[2 + c] : 0;
                     l.seg_done = 0;
@@ -440,6 +444,7 @@ bool run_levels(const huge_graph *g, const huge_plan *p, const huge_exec_opts &o
     for (int i = 0; i < HUGE_KMAX; ++i) out->level_counts[i] = h.level[i];
     if (!root_slice) out->level_counts[0] = (uint64_t)G.n;
     out->peak_frontier_bytes = stats.peak_frontier_bytes;
+    for (int i = 0; i < HUGE_KMAX; ++i) out->level_work[i] = level_work[i];
     out->launches = stats.launches;
     prof.finish(out);
     auto t1 = std::chrono::steady_clock::now();

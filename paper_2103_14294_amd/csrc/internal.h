@@ -16,6 +16,7 @@ namespace huge {
 // errors
 // ---------------------------------------------------------------------------
 void set_error(const char *fmt, ...);
+std::string last_error_text();  // this thread's last error message
 
 struct Error {
     huge_status st;
@@ -86,6 +87,8 @@ struct DevPlan {
     uint8_t pos[HUGE_KMAX];     // pos[v] = position of query vertex v
     DevStep st[HUGE_KMAX];      // st[i], i = 1..k-1; st[i].slice marks the sliced vertex's position
     uint32_t slice_count, slice_id;
+    int32_t edge_slice;         // 1: slice the level-2 rows (ordered pairs f[0], f[1]) instead of a vertex
+    int32_t pad;
 };
 
 }  // namespace huge
@@ -173,6 +176,9 @@ bool run_levels(const huge_graph *g, const huge_plan *p, const huge_exec_opts &o
                 TuneProbe *probe = nullptr);
 void autotune(const huge_graph *g, const huge_plan *const *plans, int np, const huge_exec_opts &o,
               huge_tune_table *out);
+// batch.cpp
+void run_batch_levels(const huge_graph *g, const huge_plan *const *plans, int np, const huge_exec_opts &o,
+                      huge_result *outs);
 void run_persistent(const huge_graph *g, const huge_plan *const *plans, int np, const huge_exec_opts &o,
                     huge_result *outs);
 

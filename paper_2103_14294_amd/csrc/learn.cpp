@@ -1,9 +1,9 @@
-// Features of an order prefix for the learned cardinality model, and order
+// Features of an order prefix for the learned cost model, and order
 // selection with it.
 //
-// The optimiser of Section 3.3 needs |R(q')| for the induced prefixes q' of
-// every candidate order; the paper leaves the estimator pluggable.  The
-// learned estimator reads, for prefix size s of order pi on graph G:
+// The optimiser of Section 3.3 ranks candidate orders by estimates over their
+// induced prefixes; the paper leaves the estimator pluggable.  The learned
+// estimator reads, for prefix size s of order pi on graph G:
 //   [0..5]    k one-hot (3..8)              [6..12]  s one-hot (2..8)
 //   [13..40]  prefix adjacency, position pairs a < b < 8 (index b(b-1)/2 + a)
 //   [41..68]  symmetry-breaking constraints between prefix positions, same
@@ -17,9 +17,14 @@
 //   [124..125] log(1 + n), log(1 + 2m)
 //   [126]     log(1 + the Chung-Lu estimate of the prefix)
 //   [127]     prefix edges / 28
-// and predicts log(1 + |R(prefix)|).  The cost of an order is the same as
-// the plain cost model's, sum over s = 2..k of |R(prefix_s)|, with the
-// learned estimates in place of the Chung-Lu ones.
+// and predicts log(1 + W_s), W_s the number of candidates the step that
+// produces prefix s examines: the probe-list elements inside the symmetry-
+// breaking window, summed over the partial matches of prefix s-1 (the
+// engine's level_work).  Time is spent per candidate, so the learned cost of
+// an order is sum over s = 3..k of W_s (producing prefix 2 scans the edge
+// array whatever the order).  The plain cost model instead sums |R(prefix)|,
+// which cannot tell apart orders whose prefixes have equal sizes (all orders
+// of a clique) but whose steps search very different lists.
 #include <algorithm>
 #include <cmath>
 #include <cstring>
@@ -78,18 +83,19 @@ void plan_features(const huge_graph_info &gi, const huge_plan &p, const int32_t 
     out[127] = (float)nedge / 28.f;
 }
 
-// Learned estimates of every prefix (sizes 2..k) of every order, with one
-// batched forward pass.  est[o * k + s - 1] = estimated |R(prefix_s)|.
+// Learned estimates for every order, with one batched forward pass:
+// est[o * k + s - 1] = estimated W_s for s = 3..k, 0 for s = 2, n for s = 1.
 void learned_estimates(const huge_graph *g, const huge_model *m, const huge_plan &p,
                        const std::vector<std::vector<int32_t>> &orders, hipStream_t st, std::vector<double> &est) {
     const int k = p.k;
-    const int64_t rows = (int64_t)orders.size() * (k - 1);
+    const int64_t rows = (int64_t)orders.size() * std::max(0, k - 2);
     est.assign(orders.size() * (size_t)k, 0.0);
+    for (size_t o = 0; o < orders.size(); ++o) est[o * k + 0] = (double)g->info.n;
     if (rows == 0) return;
     std::vector<float> x((size_t)rows * HUGE_MLP_F);
     int64_t r = 0;
     for (auto &o : orders)
-        for (int s = 2; s <= k; ++s) plan_features(g->info, p, o.data(), s, &x[(size_t)(r++) * HUGE_MLP_F]);
+        for (int s = 3; s <= k; ++s) plan_features(g->info, p, o.data(), s, &x[(size_t)(r++) * HUGE_MLP_F]);
     int dev = 0;
     HUGE_HIP(hipGetDevice(&dev));
     if (dev != m->device) HUGE_FAIL(HUGE_EINVAL, "the model lives on device %d, the current device is %d", m->device, dev);
@@ -108,10 +114,8 @@ void learned_estimates(const huge_graph *g, const huge_model *m, const huge_plan
     HUGE_HIP(hipMemcpyAsync(y.data(), dy, 4ull * rows, hipMemcpyDeviceToHost, st));
     HUGE_HIP(hipStreamSynchronize(st));
     r = 0;
-    for (size_t o = 0; o < orders.size(); ++o) {
-        est[o * k + 0] = (double)g->info.n;
-        for (int s = 2; s <= k; ++s) est[o * k + s - 1] = std::max(0.0, std::expm1((double)y[(size_t)(r++)]));
-    }
+    for (size_t o = 0; o < orders.size(); ++o)
+        for (int s = 3; s <= k; ++s) est[o * k + s - 1] = std::max(0.0, std::expm1((double)y[(size_t)(r++)]));
 }
 
 }  // namespace huge

@@ -1,9 +1,10 @@
-// Learned cardinality surrogate: a 2-layer MLP
+// Learned cost surrogate: a 2-layer MLP
 //     y = b2 + sum_h W2[h] * relu(b1[h] + sum_f W1[f][h] * xn[f]),
 //     xn[f] = (x[f] - xmean[f]) * xinv[f]
-// that predicts log(1 + |R(prefix)|), the number of partial matches of an
-// order prefix (the estimator slot of the optimiser, Section 3.3, which the
-// paper leaves open).  F = 128 input features, H = 256 hidden units.
+// that predicts the log of a per-step size of a matching order (here the
+// candidates the step examines; the estimator slot of the optimiser,
+// Section 3.3, which the paper leaves open).  F = 128 input features,
+// H = 256 hidden units.
 //
 // Weights are used in BF16 (round-to-nearest-even copies of FP32 master
 // weights); products and sums are FP32.  Training minimises the mean squared

@@ -807,8 +807,10 @@ void run_persistent(const huge_graph *g, const huge_plan *const *plans, int np, 
         dp[i].slice_count = o.slice_count > 1 ? o.slice_count : 1;
         dp[i].slice_id = o.slice_count > 1 ? o.slice_id : 0;
         if (dp[i].slice_count > 1 && dp[i].slice_id >= dp[i].slice_count) HUGE_FAIL(HUGE_EINVAL, "slice_id >= slice_count");
-        if (o.slice_vertex < 0 || o.slice_vertex >= p->k) HUGE_FAIL(HUGE_EINVAL, "slice_vertex out of range");
-        for (int j = 0; j < p->k; ++j) dp[i].st[j].slice = p->order[j] == o.slice_vertex ? 1 : 0;
+        if (o.slice_vertex < -2 || o.slice_vertex >= p->k) HUGE_FAIL(HUGE_EINVAL, "slice_vertex out of range");
+        const int sv = o.slice_vertex == -1 ? p->order[0] : o.slice_vertex;  // -2: edge slice, no vertex
+        for (int j = 0; j < p->k; ++j) dp[i].st[j].slice = p->order[j] == sv ? 1 : 0;
+        dp[i].edge_slice = (o.slice_vertex == -2 && dp[i].slice_count > 1) ? 1 : 0;
         kmax = std::max(kmax, p->k);
     }
     if (kmax > kKMax) HUGE_FAIL(HUGE_EINVAL, "the persistent engine supports queries of 3 to %d vertices", kKMax);

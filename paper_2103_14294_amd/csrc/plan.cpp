@@ -218,6 +218,86 @@ void plan_set_order(huge_plan &p, const int32_t *order) {
     return;
 }
 
+constexpr double kLearnedMargin = 2.0;
+constexpr int kVerifyCandidates = 4;         // the model's best orders measured, besides the cost model's
+constexpr double kVerifyEdges = 65536.0;     // level-2 rows (directed edges) in the measured sample
+constexpr int64_t kVerifyWorkLimit = 4000000000;  // candidates; a run beyond this loses
+
+double order_cost(const std::vector<double> &e, size_t o, int k) {
+    double c = 0;
+    for (int s = 2; s <= k; ++s) c += e[o * k + s - 1];
+    return c;
+}
+
+// Measured choice among the model's kVerifyCandidates best orders and the cost
+// model's order: each runs the query on one edge slice of about kVerifyEdges
+// level-2 rows (all in one workspace), and the order with the least device
+// time wins (the time of every launch, HIP events); runs past the work limit
+// lose, and the model's ranking breaks ties.  An edge slice is an unbiased
+// 1/S sample of each order's work that reaches high-degree vertices in
+// proportion to their degree, where a sample of first vertices would mostly
+// miss them and misjudge orders whose work sits on hubs.
+size_t verify_orders(const huge_graph *g, const huge_plan &p, const std::vector<std::vector<int32_t>> &orders,
+                     const std::vector<double> &est, const huge_graph_info &gi, hipStream_t st) {
+    const int k = p.k;
+    std::vector<size_t> idx(orders.size());
+    for (size_t i = 0; i < idx.size(); ++i) idx[i] = i;
+    std::stable_sort(idx.begin(), idx.end(),
+                     [&](size_t a, size_t b) { return order_cost(est, a, k) < order_cost(est, b, k); });
+    std::vector<size_t> cand(idx.begin(), idx.begin() + std::min<size_t>(kVerifyCandidates, idx.size()));
+    size_t base = 0;
+    double bc = INFINITY;
+    for (size_t o = 0; o < orders.size(); ++o) {
+        double c = 0;
+        for (int s = 2; s <= k; ++s) c += estimate_prefix(gi, p, orders[o].data(), s);
+        if (c < bc * (1 - 1e-12)) {
+            bc = c;
+            base = o;
+        }
+    }
+    if (std::find(cand.begin(), cand.end(), base) == cand.end()) cand.push_back(base);
+    uint32_t S = 1;
+    while ((double)S * 2.0 * kVerifyEdges <= (double)gi.nnz && S < (1u << 30)) S *= 2;
+    huge_exec_opts o;
+    huge_exec_opts_default(&o);
+    o.stream = st;
+    o.slice_count = S;
+    o.slice_id = 0;
+    o.slice_vertex = -2;
+    o.work_limit = kVerifyWorkLimit;
+    o.exec_flags = HUGE_EXEC_NO_HASH;
+    o.profile = 1;
+    std::vector<huge_plan> qs(cand.size(), p);
+    uint64_t wsb = 256;
+    for (size_t i = 0; i < cand.size(); ++i) {
+        plan_set_order(qs[i], orders[cand[i]].data());
+        wsb = std::max(wsb, workspace_bytes(g, &qs[i], o));
+    }
+    struct Mem {
+        void *p = nullptr;
+        ~Mem() {
+            if (p) (void)hipFree(p);
+        }
+    } mem;
+    HUGE_HIP(hipMalloc(&mem.p, wsb));
+    o.workspace = mem.p;
+    o.workspace_bytes = wsb;
+    size_t best = cand[0];
+    double best_ms = INFINITY;
+    for (size_t i = 0; i < cand.size(); ++i) {
+        huge_result r;
+        const bool stopped = run_levels(g, &qs[i], o, &r, nullptr);
+        double ms = 0;
+        for (int c = 0; c < 4; ++c) ms += r.kernel_ms[c];
+        if (stopped) ms = INFINITY;
+        if (ms < best_ms) {
+            best_ms = ms;
+            best = cand[i];
+        }
+    }
+    return best;
+}
+
 void plan_build(const huge_graph *g, int k, int ne, const int32_t *qe, const int32_t *order, uint32_t flags,
                 const huge_model *model, hipStream_t st, huge_plan *p) {
     static const huge_graph_info no_stats{};
@@ -243,16 +323,37 @@ void plan_build(const huge_graph *g, int k, int ne, const int32_t *qe, const int
         for (size_t o = 0; o < orders.size(); ++o)
             for (int s = 1; s <= k; ++s) est[o * k + s - 1] = estimate_prefix(gi, *p, orders[o].data(), s);
     }
-    // minimum estimated total partial matches, ties to the lexicographically smallest order
-    size_t chosen = 0;
-    double best = INFINITY;
-    for (size_t o = 0; o < orders.size(); ++o) {
-        double c = 0;
-        for (int s = 2; s <= k; ++s) c += est[o * k + s - 1];
-        if (c < best * (1 - 1e-12)) {
-            best = c;
-            chosen = o;
+    // minimum estimated cost, ties to the lexicographically smallest order
+    auto argmin = [&](const std::vector<double> &e) {
+        size_t ch = 0;
+        double best = INFINITY;
+        for (size_t o = 0; o < orders.size(); ++o) {
+            double c = 0;
+            for (int s = 2; s <= k; ++s) c += e[o * k + s - 1];
+            if (c < best * (1 - 1e-12)) {
+                best = c;
+                ch = o;
+            }
         }
+        return ch;
+    };
+    size_t chosen = argmin(est);
+    if (learned && (flags & HUGE_PLAN_VERIFY) && orders.size() > 1) {
+        chosen = verify_orders(g, *p, orders, est, gi, st);
+    } else if (learned && orders.size() > 1) {
+        // the learned choice replaces the cost model's only when the model itself
+        // predicts at least kLearnedMargin times less work for it: the minimum of many
+        // noisy estimates is biased low, so small predicted gains are not trusted
+        std::vector<double> cm(orders.size() * (size_t)k, 0.0);
+        for (size_t o = 0; o < orders.size(); ++o)
+            for (int s = 1; s <= k; ++s) cm[o * k + s - 1] = estimate_prefix(gi, *p, orders[o].data(), s);
+        const size_t base = argmin(cm);
+        double c_base = 0, c_best = 0;
+        for (int s = 2; s <= k; ++s) {
+            c_base += est[base * k + s - 1];
+            c_best += est[chosen * k + s - 1];
+        }
+        if (!(c_best * kLearnedMargin < c_base)) chosen = base;
     }
     plan_set_order(*p, orders[chosen].data());
     p->est_cost = 0;

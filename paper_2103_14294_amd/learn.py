@@ -1,16 +1,18 @@
-"""Training of the learned cardinality model on counts the engine produces.
+"""Training of the learned cost model on counts the engine produces.
 
-Labels: for a query q and a matching order pi, |R(prefix_s)| (s = 2..k) is
-the count of the prefix plan (huge_plan_prefix), which equals the engine's
-level_counts[s-1] for pi.  Each prefix is counted on one root slice of S
-(matches whose first matched vertex u has mix(rank u) mod S == s0), scaled
-by S; S is sized from the previous prefix's count and raised when a run hits
-its work limit, so that every run stays short.  Each labelled pattern is run
-on one training graph, with the cost-model order and with one random
-connected order, and every prefix becomes one sample
-    x = huge_plan_features(graph, plan, s, order),  t = log(1 + S * count).
+Labels: for a query q and a matching order pi, the step that produces
+prefix s (s = 3..k) examines W_s candidates: the engine's level_work[s-2]
+when it runs the prefix plan of size s (huge_plan_prefix), whose count is
+|R(prefix_s)|.  Each prefix is run on one root slice of S (matches whose
+first matched vertex u has mix(rank u) mod S == s0), scaled by S; S is
+sized from the previous prefix's count and raised when a run hits its work
+limit, so that every run stays short.  Each labelled pattern is run on one
+training graph (every labelled 4-vertex pattern on every graph), with the
+cost-model order and random connected orders, and every prefix s >= 3
+becomes one sample
+    x = huge_plan_features(graph, plan, s, order),  t = log(1 + S * level_work[s-2]).
 Prefixes that repeat (same edges and constraints in order positions) are
-counted once per graph.
+run once per graph.
 
 Training runs in the library's HIP kernels (huge_model_train: minibatch Adam
 on the BF16/FP32 MLP).  This module only orchestrates.
@@ -82,8 +84,9 @@ def prefix_key(p_info, k, edges, order, size):
 
 
 def measure_prefix(G, q, size, prev_count, avg_deg, work_target, rng, ws, n):
-    """|R| of prefix plan q on a root slice sized from the previous prefix's count;
-    returns (estimate of the full count, slices used) or None when every try hits the work limit."""
+    """Prefix plan q on a root slice sized from the previous prefix's count; returns the
+    full-graph estimates (|R(prefix)|, candidates of its last step, slices used), or None
+    when every try hits the work limit."""
     S = pow2_at_least(prev_count * max(1.0, avg_deg) * 4.0 / work_target) if size > 2 else 1
     s_max = max(1, pow2_at_least(n / 16.0) // 2)
     for _ in range(4):
@@ -92,16 +95,30 @@ def measure_prefix(G, q, size, prev_count, avg_deg, work_target, rng, ws, n):
         r = huge.count(G, q, slice_count=S, slice_id=sid, slice_vertex=0, workspace=ws, hash=False,
                        work_limit=int(work_target))
         if not r["stopped"]:
-            return float(r["count"]) * S, S
+            return float(r["count"]) * S, float(r["level_work"][size - 2]) * S, S
         if S >= s_max:
             return None
         S *= 32
     return None
 
 
-def label_runs(G, patterns, rng, work_target, deadline, ws, n, m):
-    """Label every prefix of every pattern under two orders (the cost model's and a
-    random connected one); returns feature rows, targets and per-sample records."""
+def labelled_connected(k):
+    """Every connected labelled graph on vertices 0..k-1 (as edge lists)."""
+    from graphgen import patterns as P
+
+    pairs = [(a, b) for a in range(k) for b in range(a + 1, k)]
+    out = []
+    for mask in range(1, 1 << len(pairs)):
+        e = [pairs[i] for i in range(len(pairs)) if (mask >> i) & 1]
+        if P.is_connected(k, e):
+            out.append({"k": k, "edges": e, "family": "all%d" % k})
+    return out
+
+
+def label_runs(G, patterns, rng, work_target, deadline, ws, n, m, orders_per_pattern=6, orders_small=None):
+    """Label every prefix of every pattern under several orders (the cost model's and
+    random connected ones, so that the model sees good and bad orders alike); returns
+    feature rows, targets and per-sample records."""
     X, T, recs = [], [], []
     cache = {}
     avg_deg = 2.0 * m / max(1, n)
@@ -113,9 +130,13 @@ def label_runs(G, patterns, rng, work_target, deadline, ws, n, m):
         k, e = q["k"], q["edges"]
         p0 = huge.plan(G, k, e)
         orders = [p0.info()["order"]]
-        ro = random_connected_order(k, e, rng)
-        if ro != orders[0]:
-            orders.append(ro)
+        want = orders_small if (orders_small and k == 4) else orders_per_pattern
+        for _ in range(8 * want):
+            if len(orders) >= want:
+                break
+            ro = random_connected_order(k, e, rng)
+            if ro not in orders:
+                orders.append(ro)
         for o in orders:
             p = huge.plan(G, k, e, order=o)
             info = p.info()
@@ -128,10 +149,11 @@ def label_runs(G, patterns, rng, work_target, deadline, ws, n, m):
                 got = cache[key]
                 if got is None:
                     break  # deeper prefixes are at least as expensive
-                cnt, S = got
-                X.append(huge.plan_features(G, p, s, order=o))
-                T.append(math.log1p(cnt))
-                recs.append({"pattern": i, "size": s, "count": cnt, "S": S})
+                cnt, work, S = got
+                if s >= 3:
+                    X.append(huge.plan_features(G, p, s, order=o))
+                    T.append(math.log1p(work))
+                    recs.append({"pattern": i, "size": s, "count": cnt, "work": work, "S": S})
                 prev = max(cnt, 1.0)
         if (i + 1) % 50 == 0:
             log("  %d patterns, %d prefix runs, %d samples" % (i + 1, runs, len(T)))
@@ -168,19 +190,14 @@ def fit(X, T, groups, epochs, lr, batch, seed, val_frac=0.1):
     losses = m.train(X[~val], T[~val], epochs=epochs, batch=batch, lr=lr, seed=seed)
     train_s = time.perf_counter() - t0
     pv = m.forward(X[val]) if val.any() else np.zeros(0)
-    # Chung-Lu estimate is feature 126 (log(1 + estimate))
-    cl = X[val][:, 126]
     true = np.expm1(T[val].astype(np.float64))
     qe_mlp = q_error(np.expm1(pv.astype(np.float64)), true)
-    qe_cl = q_error(np.expm1(cl.astype(np.float64)), true)
     rep = {"samples_train": int((~val).sum()), "samples_val": int(val.sum()), "patterns_val": len(val_g),
            "epochs": epochs, "lr": lr, "batch": batch, "train_s": round(train_s, 2),
            "loss_first": float(losses[0]), "loss_last": float(losses[-1]),
            "val_rmse_log": float(np.sqrt(np.mean((pv - T[val]) ** 2))) if val.any() else None,
            "val_qerror_mlp": {"median": float(np.median(qe_mlp)), "p90": float(np.percentile(qe_mlp, 90)),
-                              "geomean": float(np.exp(np.mean(np.log(qe_mlp))))},
-           "val_qerror_chung_lu": {"median": float(np.median(qe_cl)), "p90": float(np.percentile(qe_cl, 90)),
-                                   "geomean": float(np.exp(np.mean(np.log(qe_cl))))}}
+                              "geomean": float(np.exp(np.mean(np.log(qe_mlp))))}}
     return m, rep, losses
 
 
@@ -193,6 +210,7 @@ def main(argv=None):
     ap.add_argument("--work-target", type=float, default=5e8, help="candidates examined per labelling run, at most")
     ap.add_argument("--label-minutes", type=float, default=12.0)
     ap.add_argument("--graphs", default=",".join(n for n, _ in TRAIN_GRAPHS))
+    ap.add_argument("--orders", type=int, default=6, help="orders per pattern (cost model's + random)")
     ap.add_argument("--epochs", type=int, default=2000)
     ap.add_argument("--lr", type=float, default=1e-3)
     ap.add_argument("--batch", type=int, default=256)
@@ -211,20 +229,25 @@ def main(argv=None):
 
         names = args.graphs.split(",")
         specs = dict(TRAIN_GRAPHS)
-        pats = P.random_patterns(args.patterns, seed=args.seed, kmin=4, kmax=6, distinct="labelled")
-        log("%d labelled patterns (k: %s)" % (len(pats), {k: sum(p["k"] == k for p in pats) for k in (4, 5, 6)}))
+        # every labelled connected 4-vertex pattern runs on every graph (there are only 38);
+        # random labelled 5- and 6-vertex patterns are spread over the graphs
+        small = labelled_connected(4)
+        pats = P.random_patterns(args.patterns, seed=args.seed, kmin=5, kmax=6, distinct="labelled")
+        log("%d labelled 4-vertex patterns on every graph, %d random 5-6-vertex patterns (k: %s)" % (
+            len(small), len(pats), {k: sum(p["k"] == k for p in pats) for k in (5, 6)}))
         rng = random.Random(args.seed)
         X, T, groups, meta = [], [], [], {"graphs": {}, "patterns": len(pats)}
         ws = huge.Workspace()
         t_all = time.time()
         per_graph = args.label_minutes * 60.0 / len(names)
         for gi, name in enumerate(names):
-            mine = [p for j, p in enumerate(pats) if j % len(names) == gi]
+            mine = small + [p for j, p in enumerate(pats) if j % len(names) == gi]
             t0 = time.perf_counter()
             g = make_graph(specs[name])
             G = huge.load(g.row_ptr, g.col)
             log("graph %s: n=%d m=%d (%.1f s); %d patterns" % (name, g.n, g.m, time.perf_counter() - t0, len(mine)))
-            x, t, recs = label_runs(G, mine, rng, args.work_target, time.time() + per_graph, ws, g.n, g.m)
+            x, t, recs = label_runs(G, mine, rng, args.work_target, time.time() + per_graph, ws, g.n, g.m,
+                                    args.orders, orders_small=12)
             # samples of one pattern share a group (the validation split is by pattern)
             groups.extend([gi * 100000 + r["pattern"] for r in recs])
             X.extend(x)

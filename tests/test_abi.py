@@ -29,7 +29,7 @@ def H():
 def _declared():
     txt = open(os.path.join(ROOT, "include", "huge.h")).read()
     txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
-    names = set(re.findall(r"\b(huge_[a-z_]+)\s*\(", txt))
+    names = set(re.findall(r"\b(huge_[a-z0-9_]+)\s*\(", txt))
     names.discard("huge_emit_fn")
     return sorted(names)
 

@@ -109,9 +109,10 @@ def test_learned_plan_is_exact(H):
     m, *_ = _model(H, 77, 1)
     for name in ["4-cycle", "diamond", "house", "5-clique", "tailed-triangle"]:
         k, e = P.NAMED[name]
-        pl = H.plan(G, k, e, learned=m)
-        order = pl.info()["order"]
-        assert sorted(order) == list(range(k))
-        assert_parity(H, G, g, k, e, order=order)
+        for verify in (False, True):
+            pl = H.plan(G, k, e, learned=m, verify=verify)
+            order = pl.info()["order"]
+            assert sorted(order) == list(range(k))
+            assert_parity(H, G, g, k, e, order=order)
     with pytest.raises(RuntimeError, match="model"):
         H.plan(G, 3, P.NAMED["triangle"][1], learned=True)

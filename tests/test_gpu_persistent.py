@@ -86,7 +86,7 @@ def test_batched_patterns_match_single_runs(H, kmax):
     G = H.load(g.row_ptr, g.col)
     pats = P.random_patterns(16, seed=3, kmin=3, kmax=kmax)
     plans = [H.plan(G, p["k"], p["edges"]) for p in pats]
-    outs = H.count_batch(G, plans)
+    outs = H.count_batch(G, plans, engine=PERSIST)
     for p, pl, r in zip(pats, plans, outs):
         ref = oracle_run(g, p["k"], p["edges"], order=pl.info()["order"])
         assert cmp_key(r, p["k"]) == cmp_key(ref, p["k"]), p

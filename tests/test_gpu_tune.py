@@ -123,3 +123,25 @@ def test_work_limit_stops(H, hubby):
     assert r["stopped"] and r["count"] < full["count"]
     r = H.count(G, p, work_limit=1 << 62)
     assert not r["stopped"] and cmp_key(r, k) == cmp_key(full, k)
+
+
+@pytest.mark.parametrize("name", ["house", "diamond", "4-clique", "6-cycle"])
+def test_edge_slices_match_oracle_and_partition(H, name):
+    """slice_vertex=-2 keeps the matches whose first two matched vertices' ordered
+    rank pair hashes into the slice; the slices partition the matches."""
+    g = gg.chung_lu(3000, 10, 2.3, seed=21)
+    G = H.load(g.row_ptr, g.col)
+    k, e = P.NAMED[name]
+    p = H.plan(G, k, e)
+    order = p.info()["order"]
+    full = H.count(G, p)
+    cs, hs, hx = 0, 0, 0
+    for s in range(5):
+        r = H.count(G, p, slice_count=5, slice_id=s, slice_vertex=-2)
+        ref = oracle_run(g, k, e, order=order, slice_count=5, slice_id=s, slice_pair=(order[0], order[1]))
+        assert cmp_key(r, k) == cmp_key(ref, k), s
+        assert r["level_counts"][1:k] == ref["level_counts"][1:k], s
+        cs += r["count"]
+        hs = (hs + r["hash_sum"]) % (1 << 64)
+        hx ^= r["hash_xor"]
+    assert (cs, hs, hx) == (full["count"], full["hash_sum"], full["hash_xor"])

@@ -264,3 +264,36 @@ def test_slices_of_any_query_vertex_partition():
             hs = (hs + r["hash_sum"]) & M64
             hx ^= r["hash_xor"]
         assert (cs, hs, hx) == (full["count"], full["hash_sum"], full["hash_xor"]), sv
+
+
+def test_pair_slices_partition_and_match_direct_filter():
+    """Slices on an ordered pair of query vertices partition the matches, and on a
+    tiny graph each slice holds exactly the SB-satisfying maps whose pair of image
+    ranks hashes into it (maps enumerated directly with itertools)."""
+    import itertools
+
+    g = gg.chung_lu(2048, 10, 2.5, seed=12)
+    k, e = P.NAMED["house"]
+    full = oracle.enumerate_query(g.row_ptr, g.col, k, e)
+    for pair in [(0, 1), (4, 2), (3, 0)]:
+        cs, hs, hx = 0, 0, 0
+        for s in range(6):
+            r = oracle.enumerate_query(g.row_ptr, g.col, k, e, slice_count=6, slice_id=s, slice_pair=pair)
+            cs += r["count"]
+            hs = (hs + r["hash_sum"]) & M64
+            hx ^= r["hash_xor"]
+        assert (cs, hs, hx) == (full["count"], full["hash_sum"], full["hash_xor"]), pair
+
+    t = gg.gnp(9, 0.55, seed=3)
+    rank = oracle.ranks(t.row_ptr)
+    adj = {(u, int(v)) for u in range(t.n) for v in t.col[t.row_ptr[u]:t.row_ptr[u + 1]]}
+    k, e = P.NAMED["diamond"]
+    sb = oracle.sb_pairs(k, e)
+    maps = [f for f in itertools.permutations(range(t.n), k)
+            if all((f[a], f[b]) in adj for a, b in e) and all(rank[f[a]] < rank[f[b]] for a, b in sb)]
+    for pair in [(0, 3), (2, 1)]:
+        for s in range(3):
+            want = sum(1 for f in maps
+                       if oracle.mix64((int(rank[f[pair[0]]]) << 32) | int(rank[f[pair[1]]])) % 3 == s)
+            got = oracle.enumerate_query(t.row_ptr, t.col, k, e, slice_count=3, slice_id=s, slice_pair=pair)
+            assert got["count"] == want, (pair, s)
