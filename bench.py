@@ -56,11 +56,11 @@ WORKLOADS = {
     },
     "c4": {
         "desc": "R-MAT scale 24, edge factor 16, (0.57,0.19,0.19,0.05), seed 4: 64 random connected 3-6 vertex "
-                "patterns (seed 4; at most 4e9 candidates per 1/2^16 edge batch)",
+                "patterns (seed 4; at most 4e9 candidates per 1/2^20 edge batch)",
         "graph": ("rmat", dict(scale=24, edge_factor=16, seed=4)),
         "queries": ("random", dict(count=64, seed=4, kmin=3, kmax=6, max_work=4e9)),
         "cap": 8 << 30,
-        "batches": 1 << 16,
+        "batches": 1 << 20,
         "slice": "edge",
     },
     "c5": {
@@ -73,7 +73,7 @@ WORKLOADS = {
         "slice": "edge",
     },
 }
-MODEL_PATH = os.path.join(ROOT, "paper_2103_14294_amd", "card_mlp.npz")
+MODEL_PATH = os.path.join(ROOT, "paper_2103_14294_amd", "mlp_work.npz")
 
 
 def log(*a):

@@ -269,10 +269,12 @@ huge_status huge_enumerate(const huge_graph *g, const huge_plan *p, const huge_e
 /*
  * huge_count_batch -- count np queries; outs[np], in the order of plans.
  * engine AUTO or LEVELS: a few host workers (environment variable
- * HUGE_BATCH_STREAMS, default 4), each with its own HIP stream and workspace
- * (sized for the largest query; opts->workspace is not used), run the
- * queries on the level engine concurrently; work queued on opts->stream
- * before the call runs first.  engine PERSISTENT: the queries of
+ * HUGE_BATCH_STREAMS, default 4), each with its own HIP stream, workspace
+ * (sized for the largest query; opts->workspace is not used; kept allocated
+ * between calls, one pool per device, until the process ends) and an equal
+ * share of frontier_cap_bytes, run the queries on the level engine
+ * concurrently; work queued on opts->stream before the call runs first;
+ * batch calls on one device take turns.  engine PERSISTENT: the queries of
  * 3..HUGE_PERSIST_KMAX vertices run in one persistent launch (they share the
  * workgroups, the frontier budget and the stealing pool, Section 5.3), the
  * others on the level engine one after another on opts->stream.
@@ -353,10 +355,11 @@ huge_status huge_plan_features(const huge_graph *g, const huge_plan *p, const in
 huge_status huge_plan_create_learned(const huge_graph *g, const huge_model *m, int32_t k, int32_t n_qedges,
                                      const int32_t *qedges, const int32_t *order, void *stream, huge_plan **out);
 /*
- * As huge_plan_create_learned, with flags: HUGE_PLAN_VERIFY runs the model's
- * four best orders and the cost model's order on one edge slice of about
- * 65536 level-2 rows (at most 4e9 candidates each, on `stream`) and keeps the
- * order with the least device time.
+ * As huge_plan_create_learned, with flags: HUGE_PLAN_VERIFY runs the cost
+ * model's order and the model's four best orders on the same edge slice of
+ * about 16384 level-2 rows (halved until the cost model's order examines at
+ * most 2e10 candidates; the others stop at 8 times its candidates), on
+ * `stream`, and keeps the order with the least device time.
  */
 huge_status huge_plan_create_learned2(const huge_graph *g, const huge_model *m, int32_t k, int32_t n_qedges,
                                       const int32_t *qedges, const int32_t *order, uint32_t flags, void *stream,

@@ -219,9 +219,10 @@ void plan_set_order(huge_plan &p, const int32_t *order) {
 }
 
 constexpr double kLearnedMargin = 2.0;
-constexpr int kVerifyCandidates = 4;         // the model's best orders measured, besides the cost model's
-constexpr double kVerifyEdges = 65536.0;     // level-2 rows (directed edges) in the measured sample
-constexpr int64_t kVerifyWorkLimit = 4000000000;  // candidates; a run beyond this loses
+constexpr int kVerifyCandidates = 4;          // the model's best orders measured, besides the cost model's
+constexpr double kVerifyEdges = 16384.0;      // level-2 rows (directed edges) in the measured sample
+constexpr int64_t kVerifyBaseLimit = 20000000000ll;  // candidates of the cost model's order on the sample
+constexpr double kVerifyRelLimit = 8.0;       // other orders stop at this multiple of its candidates
 
 double order_cost(const std::vector<double> &e, size_t o, int k) {
     double c = 0;
@@ -230,11 +231,13 @@ double order_cost(const std::vector<double> &e, size_t o, int k) {
 }
 
 // Measured choice among the model's kVerifyCandidates best orders and the cost
-// model's order: each runs the query on one edge slice of about kVerifyEdges
-// level-2 rows (all in one workspace), and the order with the least device
-// time wins (the time of every launch, HIP events); runs past the work limit
-// lose, and the model's ranking breaks ties.  An edge slice is an unbiased
-// 1/S sample of each order's work that reaches high-degree vertices in
+// model's order: each runs the query on the same edge slice of about
+// kVerifyEdges level-2 rows (all in one workspace), and the order with the
+// least device time wins (the time of every launch, HIP events).  The cost
+// model's order runs first; its sample is halved until it finishes within
+// kVerifyBaseLimit candidates, and the other orders stop (and lose) past
+// kVerifyRelLimit times its candidates.  An edge slice is an unbiased 1/S
+// sample of each order's work that reaches high-degree vertices in
 // proportion to their degree, where a sample of first vertices would mostly
 // miss them and misjudge orders whose work sits on hubs.
 size_t verify_orders(const huge_graph *g, const huge_plan &p, const std::vector<std::vector<int32_t>> &orders,
@@ -255,7 +258,9 @@ size_t verify_orders(const huge_graph *g, const huge_plan &p, const std::vector<
             base = o;
         }
     }
-    if (std::find(cand.begin(), cand.end(), base) == cand.end()) cand.push_back(base);
+    // the cost model's order first
+    cand.erase(std::remove(cand.begin(), cand.end(), base), cand.end());
+    cand.insert(cand.begin(), base);
     uint32_t S = 1;
     while ((double)S * 2.0 * kVerifyEdges <= (double)gi.nnz && S < (1u << 30)) S *= 2;
     huge_exec_opts o;
@@ -264,7 +269,7 @@ size_t verify_orders(const huge_graph *g, const huge_plan &p, const std::vector<
     o.slice_count = S;
     o.slice_id = 0;
     o.slice_vertex = -2;
-    o.work_limit = kVerifyWorkLimit;
+    o.work_limit = kVerifyBaseLimit;
     o.exec_flags = HUGE_EXEC_NO_HASH;
     o.profile = 1;
     std::vector<huge_plan> qs(cand.size(), p);
@@ -282,14 +287,26 @@ size_t verify_orders(const huge_graph *g, const huge_plan &p, const std::vector<
     HUGE_HIP(hipMalloc(&mem.p, wsb));
     o.workspace = mem.p;
     o.workspace_bytes = wsb;
-    size_t best = cand[0];
-    double best_ms = INFINITY;
-    for (size_t i = 0; i < cand.size(); ++i) {
-        huge_result r;
-        const bool stopped = run_levels(g, &qs[i], o, &r, nullptr);
+    auto device_ms = [](const huge_result &r) {
         double ms = 0;
         for (int c = 0; c < 4; ++c) ms += r.kernel_ms[c];
-        if (stopped) ms = INFINITY;
+        return ms;
+    };
+    huge_result r0;
+    for (int tries = 0;; ++tries) {
+        if (!run_levels(g, &qs[0], o, &r0, nullptr)) break;
+        if (tries == 6 || o.slice_count >= (1u << 30)) return base;  // no workable sample: keep the cost model's
+        o.slice_count *= 2;
+    }
+    double base_work = 0;
+    for (int i = 0; i < HUGE_KMAX; ++i) base_work += (double)r0.level_work[i];
+    size_t best = base;
+    double best_ms = device_ms(r0);
+    o.work_limit = (int64_t)std::max(1.0, std::min(9.0e18, kVerifyRelLimit * base_work));
+    for (size_t i = 1; i < cand.size(); ++i) {
+        huge_result r;
+        if (run_levels(g, &qs[i], o, &r, nullptr)) continue;
+        const double ms = device_ms(r);
         if (ms < best_ms) {
             best_ms = ms;
             best = cand[i];

@@ -3,7 +3,9 @@
 Labels: for a query q and a matching order pi, the step that produces
 prefix s (s = 3..k) examines W_s candidates: the engine's level_work[s-2]
 when it runs the prefix plan of size s (huge_plan_prefix), whose count is
-|R(prefix_s)|.  Each prefix is run on one root slice of S (matches whose
+|R(prefix_s)|.  --target work (the planner's model, mlp_work.npz) learns
+log(1 + W_s); --target count (a cardinality estimator, mlp_count.npz)
+learns log(1 + |R(prefix_s)|) for s = 2..k.  Each prefix is run on one root slice of S (matches whose
 first matched vertex u has mix(rank u) mod S == s0), scaled by S; S is
 sized from the previous prefix's count and raised when a run hits its work
 limit, so that every run stays short.  Each labelled pattern is run on one
@@ -17,7 +19,7 @@ run once per graph.
 Training runs in the library's HIP kernels (huge_model_train: minibatch Adam
 on the BF16/FP32 MLP).  This module only orchestrates.
 
-    python -m paper_2103_14294_amd.learn --out paper_2103_14294_amd/card_mlp.npz
+    python -m paper_2103_14294_amd.learn --target work --out paper_2103_14294_amd/mlp_work.npz
 """
 from __future__ import annotations
 
@@ -115,7 +117,8 @@ def labelled_connected(k):
     return out
 
 
-def label_runs(G, patterns, rng, work_target, deadline, ws, n, m, orders_per_pattern=6, orders_small=None):
+def label_runs(G, patterns, rng, work_target, deadline, ws, n, m, orders_per_pattern=6, orders_small=None,
+               target="work"):
     """Label every prefix of every pattern under several orders (the cost model's and
     random connected ones, so that the model sees good and bad orders alike); returns
     feature rows, targets and per-sample records."""
@@ -150,9 +153,9 @@ def label_runs(G, patterns, rng, work_target, deadline, ws, n, m, orders_per_pat
                 if got is None:
                     break  # deeper prefixes are at least as expensive
                 cnt, work, S = got
-                if s >= 3:
+                if target == "count" or s >= 3:
                     X.append(huge.plan_features(G, p, s, order=o))
-                    T.append(math.log1p(work))
+                    T.append(math.log1p(cnt if target == "count" else work))
                     recs.append({"pattern": i, "size": s, "count": cnt, "work": work, "S": S})
                 prev = max(cnt, 1.0)
         if (i + 1) % 50 == 0:
@@ -211,6 +214,9 @@ def main(argv=None):
     ap.add_argument("--label-minutes", type=float, default=12.0)
     ap.add_argument("--graphs", default=",".join(n for n, _ in TRAIN_GRAPHS))
     ap.add_argument("--orders", type=int, default=6, help="orders per pattern (cost model's + random)")
+    ap.add_argument("--target", choices=["work", "count"], default="work",
+                    help="work: candidates of the step producing each prefix (the planner's cost); "
+                         "count: |R(prefix)| (cardinality estimation)")
     ap.add_argument("--epochs", type=int, default=2000)
     ap.add_argument("--lr", type=float, default=1e-3)
     ap.add_argument("--batch", type=int, default=256)
@@ -247,7 +253,7 @@ def main(argv=None):
             G = huge.load(g.row_ptr, g.col)
             log("graph %s: n=%d m=%d (%.1f s); %d patterns" % (name, g.n, g.m, time.perf_counter() - t0, len(mine)))
             x, t, recs = label_runs(G, mine, rng, args.work_target, time.time() + per_graph, ws, g.n, g.m,
-                                    args.orders, orders_small=12)
+                                    args.orders, orders_small=12, target=args.target)
             # samples of one pattern share a group (the validation split is by pattern)
             groups.extend([gi * 100000 + r["pattern"] for r in recs])
             X.extend(x)
