@@ -176,10 +176,14 @@ def he_init(seed):
     return np.concatenate([w1, np.zeros(H), w2, [0.0]]).astype(np.float32)
 
 
-def fit(X, T, groups, epochs, lr, batch, seed, val_frac=0.1):
-    """Standardise, split by pattern group, train on the GPU; returns the model and a report."""
+def fit(X, T, groups, epochs, lr, batch, seed, val_frac=0.1, residual=False):
+    """Standardise, split by pattern group, train on the GPU; returns the model and a report.
+    residual: the network learns the correction to the Chung-Lu log-estimate (feature 126),
+    so that an estimate is expm1(feature 126 + output)."""
     X = np.asarray(X, np.float32)
     T = np.asarray(T, np.float32)
+    base = X[:, 126].astype(np.float32) if residual else np.zeros(len(T), np.float32)
+    T = T - base
     ug = np.unique(groups)
     rng = np.random.default_rng(seed)
     val_g = set(rng.choice(ug, max(1, int(len(ug) * val_frac)), replace=False).tolist())
@@ -192,15 +196,19 @@ def fit(X, T, groups, epochs, lr, batch, seed, val_frac=0.1):
     t0 = time.perf_counter()
     losses = m.train(X[~val], T[~val], epochs=epochs, batch=batch, lr=lr, seed=seed)
     train_s = time.perf_counter() - t0
-    pv = m.forward(X[val]) if val.any() else np.zeros(0)
-    true = np.expm1(T[val].astype(np.float64))
+    pv = (m.forward(X[val]) if val.any() else np.zeros(0)) + base[val]
+    true = np.expm1((T[val] + base[val]).astype(np.float64))
     qe_mlp = q_error(np.expm1(pv.astype(np.float64)), true)
+    qe_cl = q_error(np.expm1(X[val][:, 126].astype(np.float64)), true)
     rep = {"samples_train": int((~val).sum()), "samples_val": int(val.sum()), "patterns_val": len(val_g),
            "epochs": epochs, "lr": lr, "batch": batch, "train_s": round(train_s, 2),
            "loss_first": float(losses[0]), "loss_last": float(losses[-1]),
-           "val_rmse_log": float(np.sqrt(np.mean((pv - T[val]) ** 2))) if val.any() else None,
+           "residual": bool(residual),
+           "val_rmse_log": float(np.sqrt(np.mean((pv - T[val] - base[val]) ** 2))) if val.any() else None,
            "val_qerror_mlp": {"median": float(np.median(qe_mlp)), "p90": float(np.percentile(qe_mlp, 90)),
-                              "geomean": float(np.exp(np.mean(np.log(qe_mlp))))}}
+                              "geomean": float(np.exp(np.mean(np.log(qe_mlp))))},
+           "val_qerror_chung_lu_feature": {"median": float(np.median(qe_cl)), "p90": float(np.percentile(qe_cl, 90)),
+                                           "geomean": float(np.exp(np.mean(np.log(qe_cl))))}}
     return m, rep, losses
 
 
@@ -217,6 +225,8 @@ def main(argv=None):
     ap.add_argument("--target", choices=["work", "count"], default="work",
                     help="work: candidates of the step producing each prefix (the planner's cost); "
                          "count: |R(prefix)| (cardinality estimation)")
+    ap.add_argument("--residual", action="store_true",
+                    help="learn the correction to the Chung-Lu log-estimate (feature 126)")
     ap.add_argument("--epochs", type=int, default=2000)
     ap.add_argument("--lr", type=float, default=1e-3)
     ap.add_argument("--batch", type=int, default=256)
@@ -270,7 +280,8 @@ def main(argv=None):
         meta["label_s"] = round(time.time() - t_all, 1)
         if args.labels:
             np.savez(args.labels, X=X, T=T, groups=groups)
-    m, rep, losses = fit(X, T, groups, args.epochs, args.lr, args.batch, args.seed)
+    m, rep, losses = fit(X, T, groups, args.epochs, args.lr, args.batch, args.seed, residual=args.residual)
+    rep["target"] = args.target
     m.save(args.out)
     rep.update(meta)
     rep["loss_curve"] = [float(x) for x in losses[:: max(1, len(losses) // 30)]]
