@@ -385,6 +385,10 @@ huge_status huge_autotune(const huge_graph *g, const huge_plan *const *plans, in
  */
 huge_status huge_graph_digest(const huge_graph *g, char *out65);
 
+/* The current device's architecture name and compute-unit count, e.g. "gfx950:sramecc+:xnack- 256CU"
+   (at most len-1 characters + NUL): the GPU part of the tune cache key. */
+huge_status huge_device_name(char *out, int32_t len);
+
 const char *huge_last_error(void);
 
 #ifdef __cplusplus

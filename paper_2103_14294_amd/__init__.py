@@ -32,7 +32,7 @@ EXPORTED = [
     "huge_enumerate", "huge_count_batch", "huge_last_error",
     "huge_model_create", "huge_model_free", "huge_model_set", "huge_model_get", "huge_model_forward",
     "huge_model_grad", "huge_model_train", "huge_plan_features", "huge_plan_create_learned",
-    "huge_autotune", "huge_graph_digest", "huge_plan_prefix", "huge_plan_create_learned2",
+    "huge_autotune", "huge_graph_digest", "huge_plan_prefix", "huge_plan_create_learned2", "huge_device_name",
 ]
 MLP_F, MLP_H = 128, 256
 MLP_PARAMS = MLP_F * MLP_H + 2 * MLP_H + 1
@@ -170,6 +170,8 @@ def load_library(path: str = LIB_PATH):
         lib.huge_autotune.argtypes = [vp, ctypes.POINTER(vp), i32, ctypes.POINTER(ExecOpts), ctypes.POINTER(TuneTable)]
         lib.huge_graph_digest.restype = st
         lib.huge_graph_digest.argtypes = [vp, ctypes.c_char_p]
+        lib.huge_device_name.restype = st
+        lib.huge_device_name.argtypes = [ctypes.c_char_p, i32]
         lib.huge_plan_prefix.restype = st
         lib.huge_plan_prefix.argtypes = [vp, i32, ctypes.POINTER(vp)]
         lib.huge_plan_create_learned2.restype = st
@@ -497,6 +499,14 @@ def graph_digest(g: Graph) -> str:
     return buf.value.decode()
 
 
+def device_name() -> str:
+    """huge_device_name: architecture and compute units of the current device."""
+    lib = load_library()
+    buf = ctypes.create_string_buffer(128)
+    _check(lib.huge_device_name(buf, 128))
+    return buf.value.decode()
+
+
 def autotune(g: Graph, plans, cache=None, **kw) -> TuneTable:
     """huge_autotune on a sample chosen by the slice options in kw; with `cache` (a JSON file), the
     table is stored under (graph digest, GPU name) and reused when present."""
@@ -505,7 +515,7 @@ def autotune(g: Graph, plans, cache=None, **kw) -> TuneTable:
     lib = load_library()
     key = None
     if cache is not None:
-        key = "%s|%s" % (graph_digest(g), _torch().cuda.get_device_name())
+        key = "%s|%s" % (graph_digest(g), device_name())
         if os.path.exists(cache):
             with open(cache) as f:
                 d = json.load(f)

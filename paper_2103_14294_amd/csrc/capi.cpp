@@ -335,6 +335,18 @@ huge_status huge_graph_digest(const huge_graph *g, char *out65) {
     });
 }
 
+huge_status huge_device_name(char *out, int32_t len) {
+    return guard([&] {
+        if (!out || len <= 0) HUGE_FAIL(HUGE_EINVAL, "bad buffer");
+        int dev = 0;
+        HUGE_HIP(hipGetDevice(&dev));
+        hipDeviceProp_t prop;
+        HUGE_HIP(hipGetDeviceProperties(&prop, dev));
+        snprintf(out, (size_t)len, "%s %dCU", prop.gcnArchName, prop.multiProcessorCount);
+        return HUGE_OK;
+    });
+}
+
 const char *huge_last_error(void) { return huge::g_last_error.c_str(); }
 
 }  // extern "C"
