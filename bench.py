@@ -284,6 +284,7 @@ def main():
                 if len(pl) > 4 or rs[-1]["query_ms"] > 2000:
                     log("  [%s] batch %d %s: %.1f ms" % (m, b, name, rs[-1]["query_ms"]))
         for (name, k, p, _), r in zip(pl, rs):
+            acc["_peak"] = max(acc.get("_peak", 0), r["peak_frontier_bytes"])
             a = acc.setdefault(name, {"count": 0, "ms": [], "keys": []})
             a["count"] += r["count"]
             a["ms"].append(r["query_ms"])
@@ -352,7 +353,8 @@ def main():
     cfg = {"workload": W["desc"], "plan": main_mode,
            "batches": "%d root batches, batch i timed at step i" % nb if nb > 1 else "whole graph per step",
            "engine": "levels" if not args.batched else "batch", "strategy": args.strategy,
-           "hash": not args.no_hash, "frontier_cap_bytes": cap, "graph_load_ms": info["load_ms"],
+           "hash": not args.no_hash, "frontier_cap_bytes": cap, "peak_frontier_bytes": acc.get("_peak", 0),
+           "graph_load_ms": info["load_ms"],
            "n": g.n, "m": g.m, "queries": len(queries)}
     if len(queries) <= 4:
         cfg["counts"] = {k_: [x[0] for x in v["keys"]] for k_, v in acc.items() if not k_.startswith("_")}
