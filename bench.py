@@ -52,7 +52,7 @@ WORKLOADS = {
         "graph": ("chung_lu", dict(n=3072441, dbar=76, gamma=2.2, seed=3)),
         "queries": ["5-clique", "house"],
         "cap": 32 << 30,
-        "batches": 16,
+        "batches": 1 << 14,
     },
     "c4": {
         "desc": "R-MAT scale 24, edge factor 16, (0.57,0.19,0.19,0.05), seed 4: 64 random connected 3-6 vertex "
@@ -259,12 +259,19 @@ def main():
     sv_mode = -2 if W.get("slice") == "edge" else -1
     tune_info = None
     if args.tune:
-        log("autotuning the per-bucket dispatch on a 1/%d sample" % max(4 * nb, 256))
         t_t = time.perf_counter()
         sample = [p for _, _, p, _ in plans[modes[-1]]]
+        # the sample: the largest slice on which every plan examines at most 2e9 candidates
+        S = max(4 * nb, 256)
+        while S < (1 << 30):
+            if all(not huge.count(G, p, slice_count=S, slice_id=S - 1, slice_vertex=sv_mode, work_limit=int(2e9),
+                                  cap=cap, workspace=ws, hash=False)["stopped"] for p in sample):
+                break
+            S *= 4
+            log("tuning sample: trying 1/%d" % S)
+        log("autotuning the per-bucket dispatch on a 1/%d sample" % S)
         table = huge.autotune(G, sample, cache=os.environ.get("HUGE_TUNE_CACHE"),
-                              slice_count=max(4 * nb, 256), slice_id=max(4 * nb, 256) - 1, slice_vertex=sv_mode,
-                              cap=cap)
+                              slice_count=S, slice_id=S - 1, slice_vertex=sv_mode, cap=cap)
         kw["tune"] = table
         tune_info = {"tune_s": round(time.perf_counter() - t_t, 2),
                      "strategy": {str(j): table.to_dict()["strategy"][j] for j in range(huge.KMAX + 1)
