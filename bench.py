@@ -78,10 +78,12 @@ MODEL_PATH = os.path.join(ROOT, "paper_2103_14294_amd", "mlp_work.npz")
 # HBM traffic of the last-level intersection class on the default workload, from two
 # rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE; KiB per dispatch) of this benchmark,
 # scaled by what the same counters read for the benchmark's own 4 GiB device copy
-# (FETCH_SIZE x2.0, WRITE_SIZE x1.0); recorded for the kernel sources whose digest is
-# given, and reported as null for any other sources or workload.
-TRAFFIC = {"c2": {"sources_sha256_16": "51e6766ba8468ce7", "bytes_per_launch": 5.724e9}}
-KERNEL_SOURCES = ["paper_2103_14294_amd/csrc/extend.hip", "paper_2103_14294_amd/csrc/devfuncs.h"]
+# (FETCH_SIZE x2.0, WRITE_SIZE x1.0); recorded for the kernel and graph-load sources
+# (hub bitmaps change the traffic) whose digest is given, and reported as null for any
+# other sources or workload.
+TRAFFIC = {"c2": {"sources_sha256_16": "38f1159ccd02dcd0", "bytes_per_launch": 6.714e9}}
+KERNEL_SOURCES = ["paper_2103_14294_amd/csrc/extend.hip", "paper_2103_14294_amd/csrc/devfuncs.h",
+                  "paper_2103_14294_amd/csrc/graph.hip"]
 
 
 def recorded_traffic(workload):

@@ -180,7 +180,8 @@ huge_status huge_exec_opts_default(huge_exec_opts *opts);
  * builds a degree sketch; the inputs are not retained.  Unless
  * HUGE_NO_HUB_BITMAP is given it also keeps an n-bit adjacency bitmap for each
  * of the highest-degree vertices (degree >= 256, at most HUGE_HUB_BYTES bytes
- * in total, environment variable, default 4 GiB), so that a membership test
+ * in total, environment variable, default 16 GiB, and at most a quarter of the
+ * free device memory), so that a membership test
  * against a hub's list is one load.  Errors: HUGE_EGRAPH
  * (hygiene), HUGE_ENOMEM, HUGE_EDEVICE, HUGE_EINVAL.
  */

@@ -380,7 +380,7 @@ huge_graph *graph_load(int64_t n, int64_t nnz, const int64_t *rp_in, const int32
     int64_t words = (n + 31) / 32;
     int64_t H = 0;
     if (!(flags & HUGE_NO_HUB_BITMAP) && nnz) {
-        uint64_t budget = 4ull << 30;
+        uint64_t budget = 16ull << 30;
         if (const char *e = getenv("HUGE_HUB_BYTES")) budget = strtoull(e, nullptr, 10);
         size_t fr = 0, tot = 0;
         HUGE_HIP(hipMemGetInfo(&fr, &tot));
