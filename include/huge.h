@@ -116,7 +116,9 @@ typedef struct {
 #define HUGE_STRAT_LANE_MERGE 2   /* a lane per 16 consecutive candidates, galloping cursors per list */
 #define HUGE_STRAT_MERGE_SHORT 3  /* lane merge with 4 candidates per lane */
 #define HUGE_STRAT_MERGE_LONG 4   /* lane merge with 64 candidates per lane (16 when rows are emitted) */
-#define HUGE_STRAT_COUNT 5
+#define HUGE_STRAT_BLOCK_MERGE 5  /* lane merge, 16 per lane, every list read as register-cached 16-byte blocks */
+#define HUGE_STRAT_BLOCK_MERGE_LONG 6 /* the same with 64 candidates per lane (16 when rows are emitted) */
+#define HUGE_STRAT_COUNT 7
 
 /*
  * Autotuned dispatch (Section 7.3's batch-size knob, and the choice of

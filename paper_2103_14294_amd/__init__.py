@@ -24,7 +24,9 @@ HOST_PTRS, DEVICE_PTRS, NO_VALIDATE, NO_HUB_BITMAP = 0x1, 0x2, 0x4, 0x8
 PLAN_COST_MODEL, PLAN_LEARNED, PLAN_VERIFY = 0x0, 0x1, 0x2
 ENGINE_AUTO, ENGINE_LEVELS, ENGINE_PERSISTENT = 0, 1, 2
 EXEC_NO_HASH = 0x1
-STRAT_BSEARCH, STRAT_WAVE_STAGED, STRAT_LANE_MERGE = 0, 1, 2
+STRAT_BSEARCH, STRAT_WAVE_STAGED, STRAT_LANE_MERGE, STRAT_MERGE_SHORT, STRAT_MERGE_LONG = 0, 1, 2, 3, 4
+STRAT_BLOCK_MERGE, STRAT_BLOCK_MERGE_LONG = 5, 6
+STRAT_COUNT = 7
 
 EXPORTED = [
     "huge_exec_opts_default", "huge_load_csr", "huge_graph_free", "huge_graph_get_info", "huge_graph_export",

@@ -513,8 +513,58 @@ void prepare_w(bool last, const GraphDev &g, const DevPlan &P, const int32_t *ro
 // (exponential then binary search, Bentley-Yao) as the sorted candidates
 // increase, so a membership test costs O(log gap) instead of O(log degree).
 // Hub lists are answered by their bitmap.
+//
+// With BLK, every list read goes through one aligned 16-byte block kept in
+// registers per list (and one for the lane's own candidates): a cursor that
+// stays inside its block, which is the common case when the lists have similar
+// density, costs no load at all, and a short gallop ending in the next block
+// costs one.  The kernel is limited by how many lane-divergent gathers the
+// memory pipeline accepts per clock, so fewer of them is what pays.
 // ---------------------------------------------------------------------------
-template <int W, int MODE, int RUN>
+__device__ __forceinline__ int32_t pick4(const int4 &q, int64_t i) {
+    const int t = (int)(i & 3);
+    return t == 0 ? q.x : t == 1 ? q.y : t == 2 ? q.z : q.w;
+}
+
+// First index i in [c, e) with col[i] >= key (e if none), given that every
+// index before c holds a smaller value.  blk/q cache the aligned block
+// col[4*blk .. 4*blk+3]; the result's value is returned in x when i < e.
+__device__ __forceinline__ int64_t gallop_blk(const int32_t *__restrict__ col, int64_t c, int64_t e, int32_t key,
+                                              int32_t &blk, int4 &q, int32_t &x) {
+    if (c >= e) return e;
+    const int32_t b = (int32_t)(c >> 2);
+    if (b != blk) {
+        q = reinterpret_cast<const int4 *>(col)[b];
+        blk = b;
+    }
+    const int64_t base = (int64_t)b << 2;
+    // first slot t >= c - base of the block (and before e) with a value >= key
+    int64_t hit = -1;
+    int32_t hv = 0;
+    const int32_t qv[4] = {q.x, q.y, q.z, q.w};
+#pragma unroll
+    for (int t = 3; t >= 0; --t) {
+        const int64_t i = base + t;
+        if (i >= c && i < e && qv[t] >= key) {
+            hit = i;
+            hv = qv[t];
+        }
+    }
+    if (hit >= 0) {
+        x = hv;
+        return hit;
+    }
+    if (base + 4 >= e) return e;
+    const int64_t r = gallop(col, base + 4, e, key);
+    if (r < e) {
+        blk = (int32_t)(r >> 2);
+        q = reinterpret_cast<const int4 *>(col)[blk];
+        x = pick4(q, r);
+    }
+    return r;
+}
+
+template <int W, int MODE, int RUN, bool BLK>
 __global__ __launch_bounds__(kT) void k_extend_merge(ExtArgs a) {
     constexpr int kRun = RUN;
     constexpr int kMTile = kT * RUN;
@@ -568,12 +618,34 @@ __global__ __launch_bounds__(kT) void k_extend_merge(ExtArgs a) {
     int pp = 0;
     int32_t f[W];
     int64_t cur[W], end[W];
+    // BLK: the cached block of each list, and of the lane's candidates
+    int32_t cblk[BLK ? W : 1];
+    int4 cq[BLK ? W : 1];
+    int32_t vblk = -1;
+    int4 vq = make_int4(0, 0, 0, 0);
 #pragma unroll
     for (int p = 0; p < W; ++p) {
         f[p] = 0;
         cur[p] = 0;
         end[p] = 0;
     }
+#pragma unroll
+    for (int p = 0; p < (BLK ? W : 1); ++p) {
+        cblk[p] = -1;
+        cq[p] = make_int4(0, 0, 0, 0);
+    }
+    auto cand = [&](int64_t i) -> int32_t {
+        if constexpr (BLK) {
+            const int32_t b = (int32_t)(i >> 2);
+            if (b != vblk) {
+                vq = reinterpret_cast<const int4 *>(g.col)[b];
+                vblk = b;
+            }
+            return pick4(vq, i);
+        } else {
+            return g.col[i];
+        }
+    };
     for (int it = 0; it < kRun; ++it) {
         const int64_t w = wb + it;
         bool ok = false;
@@ -587,7 +659,7 @@ __global__ __launch_bounds__(kT) void k_extend_merge(ExtArgs a) {
                 pp = (int)(pi >> 56);
                 pshift = (int64_t)(pi & kPbMask) - a.off[r];
                 load_row<W>(a.rows, g, row_at(a, r), f);
-                const int32_t v0 = g.col[pshift + w];
+                const int32_t v0 = cand(pshift + w);
 #pragma unroll
                 for (int p = 0; p < W; ++p) {
                     if (((st.ext >> p) & 1u) && p != pp && f[p] < g.hub_base) {
@@ -596,7 +668,7 @@ __global__ __launch_bounds__(kT) void k_extend_merge(ExtArgs a) {
                     }
                 }
             }
-            v = g.col[pshift + w];
+            v = cand(pshift + w);
             ok = true;
 #pragma unroll
             for (int p = 0; p < W; ++p)
@@ -607,6 +679,10 @@ __global__ __launch_bounds__(kT) void k_extend_merge(ExtArgs a) {
                 if (ok && ((st.ext >> p) & 1u) && p != pp) {
                     if (f[p] >= g.hub_base) {
                         ok = adj_has(g, f[p], v);
+                    } else if constexpr (BLK) {
+                        int32_t x = 0;
+                        cur[p] = gallop_blk(g.col, cur[p], end[p], v, cblk[p], cq[p], x);
+                        ok = cur[p] < end[p] && x == v;
                     } else {
                         cur[p] = gallop(g.col, cur[p], end[p], v);
                         ok = cur[p] < end[p] && g.col[cur[p]] == v;
@@ -730,23 +806,23 @@ __global__ __launch_bounds__(kT) void k_extend_merge(ExtArgs a) {
     }
 }
 
-template <int W, int MODE, int RUN>
+template <int W, int MODE, int RUN, bool BLK>
 void merge_launch(const ExtArgs &a, hipStream_t st) {
     const int64_t items = a.w1 - a.w0;
     dim3 grid((unsigned)((items + (int64_t)kT * RUN - 1) / ((int64_t)kT * RUN)));
-    hipLaunchKernelGGL((k_extend_merge<W, MODE, RUN>), grid, dim3(kT), 0, st, a);
+    hipLaunchKernelGGL((k_extend_merge<W, MODE, RUN, BLK>), grid, dim3(kT), 0, st, a);
 }
 
-template <int W, int RUN>
+template <int W, int RUN, bool BLK = false>
 void merge_mode(int mode, const ExtArgs &a, hipStream_t st) {
     if (mode == MODE_COUNT)
-        merge_launch<W, MODE_COUNT, RUN>(a, st);
+        merge_launch<W, MODE_COUNT, RUN, BLK>(a, st);
     else if (mode == MODE_COUNT_NOHASH)
-        merge_launch<W, MODE_COUNT_NOHASH, RUN>(a, st);
+        merge_launch<W, MODE_COUNT_NOHASH, RUN, BLK>(a, st);
     else if (mode == MODE_EMIT)
-        merge_launch<W, MODE_EMIT, (RUN > 16 ? 16 : RUN)>(a, st);
+        merge_launch<W, MODE_EMIT, (RUN > 16 ? 16 : RUN), BLK>(a, st);
     else
-        merge_launch<W, MODE_OUTPUT, (RUN > 16 ? 16 : RUN)>(a, st);
+        merge_launch<W, MODE_OUTPUT, (RUN > 16 ? 16 : RUN), BLK>(a, st);
 }
 
 template <int W, int STRAT>
@@ -770,6 +846,8 @@ void extend_w(int mode, int strategy, const ExtArgs &a, hipStream_t st) {
         case STRAT_WAVE_STAGED: extend_ws<W, STRAT_WAVE_STAGED>(mode, a, st); break;
         case STRAT_MERGE_SHORT: merge_mode<W, 4>(mode, a, st); break;
         case STRAT_MERGE_LONG: merge_mode<W, 64>(mode, a, st); break;
+        case STRAT_BLOCK_MERGE: merge_mode<W, 16, true>(mode, a, st); break;
+        case STRAT_BLOCK_MERGE_LONG: merge_mode<W, 64, true>(mode, a, st); break;
         default: merge_mode<W, 16>(mode, a, st); break;
     }
 }

@@ -233,6 +233,8 @@ enum {
     STRAT_LANE_MERGE = HUGE_STRAT_LANE_MERGE,
     STRAT_MERGE_SHORT = HUGE_STRAT_MERGE_SHORT,
     STRAT_MERGE_LONG = HUGE_STRAT_MERGE_LONG,
+    STRAT_BLOCK_MERGE = HUGE_STRAT_BLOCK_MERGE,
+    STRAT_BLOCK_MERGE_LONG = HUGE_STRAT_BLOCK_MERGE_LONG,
     STRAT_COUNT = HUGE_STRAT_COUNT
 };
 

@@ -39,7 +39,7 @@ def test_concurrent_batch_with_slices_and_table(H, graph):
     t = H.TuneTable()
     for j in range(H.KMAX + 1):
         for c in range(H.TUNE_BUCKETS):
-            t.strategy[j][c] = (j + c) % 5
+            t.strategy[j][c] = (j + c) % H.STRAT_COUNT
     for s in range(2):
         outs = H.count_batch(G, plans, slice_count=2, slice_id=s, slice_vertex=-1, tune=t, cap=0)
         for n, pl, r in zip(names, plans, outs):

@@ -233,7 +233,7 @@ def test_bad_graphs_rejected(H, defect):
     assert ei.value.name == "HUGE_EGRAPH", str(ei.value)
 
 
-@pytest.mark.parametrize("strategy", [0, 1, 2])
+@pytest.mark.parametrize("strategy", [0, 1, 2, 3, 4, 5, 6])
 def test_strategies_agree(H, small, strategy):
     g, G = small
     for name in ["4-clique", "diamond", "4-cycle", "house", "5-clique"]:
@@ -276,7 +276,7 @@ def test_hub_bitmaps_do_not_change_results(H, monkeypatch):
         k, e = P.NAMED[name]
         ref = H.count(base, H.plan(base, k, e))
         for G in (full, part):
-            for strategy in (0, 1, 2):
+            for strategy in (0, 1, 2, 5, 6):
                 r = H.count(G, H.plan(G, k, e), strategy=strategy)
                 assert cmp_key(r, k) == cmp_key(ref, k), (name, strategy)
 
@@ -287,7 +287,7 @@ def test_count_without_hash(H, small):
         k, e = P.NAMED[name]
         p = H.plan(G, k, e)
         ref = oracle_run(g, k, e, order=p.info()["order"])
-        for strategy in (0, 1, 2):
+        for strategy in (0, 1, 2, 5, 6):
             r = H.count(G, p, hash=False, strategy=strategy)
             assert r["count"] == ref["count"] and r["hash_sum"] == 0 and r["hash_xor"] == 0
             assert r["level_counts"][:k] == ref["level_counts"][:k]
