@@ -19,9 +19,10 @@ def H():
 
 
 def _table(H):
-    """A mixed dispatch like the tuned ones: binary search, 4-, 16- and 64-wide lane merge."""
+    """A mixed dispatch like the tuned ones: binary search, 4-, 16- and 64-wide
+    lane merge, and both block-cached lane merges."""
     t = H.TuneTable()
-    rows = {1: [3, 3, 3, 3, 3], 2: [0, 4, 4, 4, 4], 3: [2, 4, 4, 4, 4], 4: [0, 2, 4, 4, 4]}
+    rows = {1: [3, 3, 3, 3, 3], 2: [0, 4, 6, 6, 6], 3: [2, 5, 4, 6, 6], 4: [0, 2, 5, 6, 4]}
     for j in range(H.KMAX + 1):
         for c in range(H.TUNE_BUCKETS):
             t.strategy[j][c] = rows.get(j, [2] * 5)[c]
