@@ -201,6 +201,9 @@ def main():
     ap.add_argument("--no-tune", dest="tune", action="store_false",
                     help="skip autotuning the per-bucket dispatch before timing (library default kernels)")
     ap.add_argument("--batched", action="store_true", help="one huge_count_batch call per step")
+    ap.add_argument("--engine", choices=["levels", "graph"], default="levels",
+                    help="levels: host-driven scheduler (default); graph: device scheduler, rounds replayed "
+                         "from a hipGraph (one strategy everywhere, no tuning)")
     ap.add_argument("--cap", type=float, default=None, help="frontier cap in bytes (default: the workload's)")
     ap.add_argument("--strategy", type=int, default=-1, help="intersection strategy (-1 = library default)")
     ap.add_argument("--no-hash", action="store_true", help="count only (no set-hash)")
@@ -250,6 +253,9 @@ def main():
     nb = W["batches"]
     cap = int(args.cap) if args.cap is not None else W["cap"]
     kw = dict(cap=cap, workspace=ws, strategy=args.strategy, hash=not args.no_hash)
+    if args.engine == "graph":
+        kw["engine"] = huge.ENGINE_GRAPH
+        args.tune = False  # the graph engine runs one strategy everywhere
     # batches slice on each plan's first matched vertex, or on its level-2 rows (edge
     # slices, which reach hubs in proportion to their degree): an unbiased 1/nb sample of
     # that plan's work, the same in sequential and batched runs
@@ -351,8 +357,11 @@ def main():
     achieved = (bytes_per_launch / (avg_ms * 1e-3)) / 1e9 if avg_ms > 0 else 0.0
     traffic = recorded_traffic(args.workload) if (args.tune and args.strategy < 0 and not args.batched
                                                   and dom == 3 and main_mode == "cost-model") else None
-    roof = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+    if args.engine == "graph":  # no per-launch timing inside replays
+        achieved = None
+    roof = {"bound": "hbm", "achieved": round(achieved, 2) if achieved is not None else None,
+            "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4) if achieved is not None else None, "traffic": traffic,
             "traffic_gbs": round(traffic / (avg_ms * 1e-3) / 1e9, 1) if traffic and avg_ms > 0 else None,
             "kernel": ("last-level intersection + counting SINK: k_extend*<W,COUNT> launches, one per probe-length "
                        "bucket with its tuned strategy") if (dom == 3 and args.tune)
@@ -362,7 +371,7 @@ def main():
             "kernel_ms_by_class": {KC_NAMES[c]: round(kms[c], 3) for c in range(4)}}
     cfg = {"workload": W["desc"], "plan": main_mode,
            "batches": "%d root batches, batch i timed at step i" % nb if nb > 1 else "whole graph per step",
-           "engine": "levels" if not args.batched else "batch", "strategy": args.strategy,
+           "engine": args.engine if not args.batched else "batch", "strategy": args.strategy,
            "hash": not args.no_hash, "frontier_cap_bytes": cap, "peak_frontier_bytes": acc.get("_peak", 0),
            "graph_load_ms": info["load_ms"],
            "n": g.n, "m": g.m, "queries": len(queries)}
@@ -411,7 +420,7 @@ def main():
     }
     gbs, _ = copy_bandwidth(torch)
     out["roofline"]["copy_gbs"] = round(gbs, 1)
-    out["roofline"]["frac_of_copy"] = round(achieved / gbs, 4) if gbs > 0 else None
+    out["roofline"]["frac_of_copy"] = round(achieved / gbs, 4) if gbs > 0 and achieved is not None else None
     if not args.no_cpu:
         threads = min(16, os.cpu_count() or 1)
         log("cpu baseline: oracle on root slices, %d threads, budget %.0f s" % (threads, args.cpu_budget))

@@ -72,6 +72,17 @@ typedef struct huge_plan huge_plan;
 #define HUGE_ENGINE_AUTO 0
 #define HUGE_ENGINE_LEVELS 1     /* host-driven Algorithm 5, one grid-wide launch per chunk */
 #define HUGE_ENGINE_PERSISTENT 2 /* one persistent launch: per-workgroup Algorithm 5 + stealing */
+/* Algorithm 5 with its scheduler on the device: one round (a one-thread
+ * scheduler launch, then fixed-grid prepare / scan / extend launches of every
+ * level, idle unless the round's action is theirs) is recorded once in a
+ * hipGraph and replayed until a device flag says the query is done; the host
+ * reads that flag once per 8 replays of 4 rounds.  huge_count and
+ * huge_count_batch only (huge_enumerate: HUGE_EINVAL).  Runs the lane merge of
+ * HUGE_STRAT_LANE_MERGE or HUGE_STRAT_BLOCK_MERGE_LONG (AUTO: the latter; any
+ * other strategy: HUGE_EINVAL) everywhere, ignores the tune table and
+ * work_limit must be 0.  Segments are capped at 2^24 rows.  Results equal the
+ * other engines' bit for bit; huge_result.launches counts graph launches. */
+#define HUGE_ENGINE_GRAPH 3
 #define HUGE_PERSIST_KMAX 4      /* largest query the persistent engine runs (HUGE_EINVAL above) */
 
 typedef struct {
@@ -263,7 +274,8 @@ huge_status huge_count(const huge_graph *g, const huge_plan *p, const huge_exec_
  * vertex, original IDs) and cb(user, host_buf, nrows, k) is called on the
  * calling thread each time the buffer is full and once at the end.  A nonzero
  * return from cb stops the run with HUGE_STOPPED; out->count is then the
- * number of rows delivered.  Row order is unspecified.
+ * number of rows delivered.  Row order is unspecified.  Runs on the level
+ * engine (HUGE_ENGINE_GRAPH: HUGE_EINVAL).
  */
 typedef int (*huge_emit_fn)(void *user, const int32_t *rows, int64_t nrows, int32_t k);
 huge_status huge_enumerate(const huge_graph *g, const huge_plan *p, const huge_exec_opts *opts, int32_t *host_buf,
@@ -280,7 +292,9 @@ huge_status huge_enumerate(const huge_graph *g, const huge_plan *p, const huge_e
  * batch calls on one device take turns.  engine PERSISTENT: the queries of
  * 3..HUGE_PERSIST_KMAX vertices run in one persistent launch (they share the
  * workgroups, the frontier budget and the stealing pool, Section 5.3), the
- * others on the level engine one after another on opts->stream.
+ * others on the level engine one after another on opts->stream.  engine
+ * GRAPH: the queries run one after another on opts->stream, each through
+ * its own recorded round.
  */
 huge_status huge_count_batch(const huge_graph *g, const huge_plan *const *plans, int32_t np,
                              const huge_exec_opts *opts, huge_result *outs);

@@ -22,7 +22,7 @@ STATUS = {0: "HUGE_OK", 1: "HUGE_STOPPED", -1: "HUGE_EINVAL", -2: "HUGE_ENOMEM",
           -4: "HUGE_EGRAPH", -5: "HUGE_EQUERY", -6: "HUGE_EORDER", -7: "HUGE_EOVERFLOW"}
 HOST_PTRS, DEVICE_PTRS, NO_VALIDATE, NO_HUB_BITMAP = 0x1, 0x2, 0x4, 0x8
 PLAN_COST_MODEL, PLAN_LEARNED, PLAN_VERIFY = 0x0, 0x1, 0x2
-ENGINE_AUTO, ENGINE_LEVELS, ENGINE_PERSISTENT = 0, 1, 2
+ENGINE_AUTO, ENGINE_LEVELS, ENGINE_PERSISTENT, ENGINE_GRAPH = 0, 1, 2, 3
 EXEC_NO_HASH = 0x1
 STRAT_BSEARCH, STRAT_WAVE_STAGED, STRAT_LANE_MERGE, STRAT_MERGE_SHORT, STRAT_MERGE_LONG = 0, 1, 2, 3, 4
 STRAT_BLOCK_MERGE, STRAT_BLOCK_MERGE_LONG = 5, 6

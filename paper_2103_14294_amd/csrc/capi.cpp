@@ -161,6 +161,8 @@ huge_status huge_count(const huge_graph *g, const huge_plan *p, const huge_exec_
         if (o.engine == HUGE_ENGINE_PERSISTENT) {
             const huge_plan *pl[1] = {p};
             run_persistent(g, pl, 1, o, &r);
+        } else if (o.engine == HUGE_ENGINE_GRAPH) {
+            run_graph(g, p, o, &r);
         } else {
             limited = run_levels(g, p, o, &r, nullptr);
         }
@@ -174,6 +176,7 @@ huge_status huge_enumerate(const huge_graph *g, const huge_plan *p, const huge_e
     return guard([&] {
         if (!g || !p || !out) HUGE_FAIL(HUGE_EINVAL, "NULL argument");
         huge_exec_opts o = resolve_opts(opts);
+        if (o.engine == HUGE_ENGINE_GRAPH) HUGE_FAIL(HUGE_EINVAL, "huge_enumerate does not run on the graph engine");
         EmitSink sink;
         sink.host_buf = host_buf;
         sink.buf_rows = buf_rows;
@@ -194,6 +197,11 @@ huge_status huge_count_batch(const huge_graph *g, const huge_plan *const *plans,
             if (!plans[i]) HUGE_FAIL(HUGE_EINVAL, "plan %d is NULL", i);
         huge_exec_opts o = resolve_opts(opts);
         std::vector<huge_result> r(np);
+        if (o.engine == HUGE_ENGINE_GRAPH) {  // one query after another, each through its own graph
+            for (int i = 0; i < np; ++i) run_graph(g, plans[i], o, &r[i]);
+            for (int i = 0; i < np; ++i) outs[i] = r[i];
+            return HUGE_OK;
+        }
         if (o.engine != HUGE_ENGINE_PERSISTENT) {
             run_batch_levels(g, plans, np, o, r.data());
             for (int i = 0; i < np; ++i) outs[i] = r[i];

@@ -182,6 +182,12 @@ struct Profiler {
 };
 
 uint64_t workspace_bytes(const huge_graph *g, const huge_plan *p, const huge_exec_opts &o) {
+    if (o.engine == HUGE_ENGINE_GRAPH) {
+        huge_exec_opts q = o;
+        q.tune = nullptr;
+        if (q.chunk_rows > scan_devn_max()) q.chunk_rows = scan_devn_max();
+        return make_layout(g, p, q, 0).total + align_up(sizeof(GState));
+    }
     return make_layout(g, p, o, 1 << 16).total;
 }
 
@@ -450,6 +456,157 @@ bool run_levels(const huge_graph *g, const huge_plan *p, const huge_exec_opts &o
     auto t1 = std::chrono::steady_clock::now();
     out->query_ms = std::chrono::duration<double, std::milli>(t1 - t0).count();
     return limited;
+}
+
+
+// ---------------------------------------------------------------------------
+// Graph engine: the same Algorithm 5, with its scheduler on the device
+// (k_round_sched) so that no host decision sits between launches.  One round
+// is: the scheduler picks one action (prepare + scan a segment of level W, or
+// extend a range of its work items), then every level's fixed-grid prepare,
+// scan and extend launches run, idle unless the action is theirs.  kRounds
+// rounds are recorded once in a hipGraph; the host replays it and reads the
+// done flag every kBatch replays.  Rounds after the end are idle.  No memset
+// or copy is recorded: counters are cleared by the scheduler kernel itself.
+// ---------------------------------------------------------------------------
+namespace {
+constexpr int kRounds = 4;                 // rounds recorded in the graph
+constexpr int kBatch = 8;                  // graph launches between done checks
+constexpr int64_t kMaxRoundsTotal = 1ll << 26;
+
+struct GraphRes {
+    hipStream_t cs = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    ~GraphRes() {
+        if (exec) (void)hipGraphExecDestroy(exec);
+        if (graph) (void)hipGraphDestroy(graph);
+        if (cs) (void)hipStreamDestroy(cs);
+    }
+};
+}  // namespace
+
+void run_graph(const huge_graph *g, const huge_plan *p, const huge_exec_opts &o_in, huge_result *out) {
+    auto t0 = std::chrono::steady_clock::now();
+    if (o_in.work_limit > 0) HUGE_FAIL(HUGE_EINVAL, "the graph engine has no work limit");
+    int strat = o_in.strategy;
+    if (strat < 0 || strat >= STRAT_COUNT) strat = STRAT_BLOCK_MERGE_LONG;
+    if (strat != STRAT_LANE_MERGE && strat != STRAT_BLOCK_MERGE_LONG)
+        HUGE_FAIL(HUGE_EINVAL, "the graph engine runs strategy %d or %d, not %d", STRAT_LANE_MERGE,
+                  STRAT_BLOCK_MERGE_LONG, strat);
+    const int k = p->k;
+    if (k < 3) {  // one edge-array launch: nothing to replay
+        huge_exec_opts o = o_in;
+        o.engine = HUGE_ENGINE_LEVELS;
+        o.tune = nullptr;
+        run_levels(g, p, o, out, nullptr, nullptr);
+        return;
+    }
+    huge_exec_opts o = o_in;
+    o.tune = nullptr;  // one strategy everywhere, no bucket partition
+    if (o.chunk_rows > scan_devn_max()) o.chunk_rows = scan_devn_max();
+    hipStream_t st = (hipStream_t)o.stream;
+    DevPlan P = p->dev;
+    P.slice_count = o.slice_count > 1 ? o.slice_count : 1;
+    P.slice_id = o.slice_count > 1 ? o.slice_id : 0;
+    if (P.slice_count > 1 && P.slice_id >= P.slice_count) HUGE_FAIL(HUGE_EINVAL, "slice_id >= slice_count");
+    if (o.slice_vertex < -2 || o.slice_vertex >= k) HUGE_FAIL(HUGE_EINVAL, "slice_vertex out of range");
+    const int sv = o.slice_vertex == -1 ? p->order[0] : o.slice_vertex;
+    for (int i = 0; i < k; ++i) P.st[i].slice = p->order[i] == sv ? 1 : 0;
+    P.edge_slice = (o.slice_vertex == -2 && P.slice_count > 1) ? 1 : 0;
+    const bool root_slice = P.slice_count > 1 && P.st[0].slice;
+
+    Layout L = make_layout(g, p, o, 0);
+    const uint64_t gs_off = L.total;
+    const uint64_t total = gs_off + align_up(sizeof(GState));
+    DevMem own;
+    char *ws = (char *)o.workspace;
+    if (ws) {
+        if (o.workspace_bytes < total)
+            HUGE_FAIL(HUGE_ENOMEM, "workspace too small: %llu bytes given, %llu needed",
+                      (unsigned long long)o.workspace_bytes, (unsigned long long)total);
+    } else {
+        HUGE_HIP(hipMalloc(&own.p, total));
+        ws = (char *)own.p;
+    }
+    Carver cv{ws};
+    Ctrl *ctrl = cv.take<Ctrl>(1);
+    SegBufs sb[HUGE_KMAX + 1] = {};
+    int32_t *q[HUGE_KMAX + 1] = {};
+    for (int w = 2; w <= k - 1; ++w) {
+        const int64_t c = L.seg_cap[w];
+        sb[w].off = cv.take<int64_t>(c + 1);
+        sb[w].pinfo = cv.take<uint64_t>(c);
+        sb[w].hpre = cv.take<uint64_t>(c);
+        sb[w].bound = cv.take<int32_t>(c);
+        sb[w].cap = c;
+    }
+    for (int w = 3; w <= k - 1; ++w) q[w] = cv.take<int32_t>((uint64_t)w * L.q_cap[w]);
+    (void)cv.take<int32_t>((uint64_t)k);  // staging (unused here): the level engine's layout
+    int64_t *scan_tmp = cv.take<int64_t>(L.scan_tmp);
+    GState *gs = (GState *)(ws + gs_off);
+
+    GConst gc{};
+    gc.k = k;
+    gc.lastW = k - 1;
+    for (int w = 2; w <= k - 1; ++w) {
+        gc.seg_cap[w] = L.seg_cap[w];
+        gc.off[w] = sb[w].off;
+    }
+    for (int w = 3; w <= k - 1; ++w) gc.q_cap[w] = L.q_cap[w];
+    GState init{};
+    init.W = 2;
+    init.lv[2].nrows = g->dev.nnz;
+    HUGE_HIP(hipMemsetAsync(ctrl, 0, sizeof(Ctrl), st));
+    HUGE_HIP(hipMemcpyAsync(gs, &init, sizeof(GState), hipMemcpyHostToDevice, st));
+    const GraphDev &G = g->dev;
+    if (root_slice) launch_root_count(G, P, ctrl, st);
+    const int count_mode = (o.exec_flags & HUGE_EXEC_NO_HASH) ? MODE_COUNT_NOHASH : MODE_COUNT;
+
+    // record kRounds rounds on a private stream
+    GraphRes gr;
+    HUGE_HIP(hipStreamCreateWithFlags(&gr.cs, hipStreamNonBlocking));
+    HUGE_HIP(hipStreamBeginCapture(gr.cs, hipStreamCaptureModeThreadLocal));
+    for (int r = 0; r < kRounds; ++r) {
+        launch_round_sched(gs, gc, ctrl, gr.cs);
+        for (int w = 2; w <= k - 1; ++w) {
+            const bool last = w == k - 1;
+            launch_round_prepare(w, last, G, P, q[w], sb[w], ctrl, gs, L.seg_cap[w], gr.cs);
+            launch_round_scan(w, sb[w], gs, L.seg_cap[w], scan_tmp, gr.cs);
+            launch_round_extend(w, last ? count_mode : MODE_EMIT, strat, G, P, q[w], sb[w], last ? nullptr : q[w + 1],
+                                ctrl, g->inv_rank, gs, gr.cs);
+        }
+    }
+    HUGE_HIP(hipStreamEndCapture(gr.cs, &gr.graph));
+    HUGE_HIP(hipGraphInstantiate(&gr.exec, gr.graph, nullptr, nullptr, 0));
+
+    int32_t done = 0;
+    int64_t replays = 0;
+    while (!done) {
+        for (int b = 0; b < kBatch; ++b) HUGE_HIP(hipGraphLaunch(gr.exec, st));
+        replays += kBatch;
+        HUGE_HIP(hipMemcpyAsync(&done, &gs->done, sizeof(done), hipMemcpyDeviceToHost, st));
+        HUGE_HIP(hipStreamSynchronize(st));
+        if (!done && replays * kRounds > kMaxRoundsTotal)
+            HUGE_FAIL(HUGE_EINVAL, "graph engine: no end after %lld rounds", (long long)(replays * kRounds));
+    }
+    Ctrl h;
+    GState hs;
+    HUGE_HIP(hipMemcpyAsync(&h, ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, st));
+    HUGE_HIP(hipMemcpyAsync(&hs, gs, sizeof(GState), hipMemcpyDeviceToHost, st));
+    HUGE_HIP(hipStreamSynchronize(st));
+    if (hs.error) HUGE_FAIL(HUGE_EINVAL, "graph engine: the device scheduler found no action");
+    memset(out, 0, sizeof(*out));
+    out->count = h.acc[0];
+    out->hash_sum = h.acc[1];
+    out->hash_xor = h.acc[2];
+    for (int i = 0; i < HUGE_KMAX; ++i) out->level_counts[i] = h.level[i];
+    if (!root_slice) out->level_counts[0] = (uint64_t)G.n;
+    out->peak_frontier_bytes = (uint64_t)hs.peak_bytes;
+    for (int i = 0; i < HUGE_KMAX; ++i) out->level_work[i] = (uint64_t)hs.work[i];
+    out->launches = (uint64_t)replays;  // graph launches
+    auto t1 = std::chrono::steady_clock::now();
+    out->query_ms = std::chrono::duration<double, std::milli>(t1 - t0).count();
 }
 
 }  // namespace huge

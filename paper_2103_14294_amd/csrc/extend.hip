@@ -20,6 +20,8 @@
 //               extended row to the next level's queue (wave ballot +
 //               one atomic per workgroup) or, at the last level, fold it into
 //               the counting SINK (count, set-hash sum and xor).
+#include <algorithm>
+
 #include "devfuncs.h"
 #include "internal.h"
 #include "prims.h"
@@ -37,12 +39,14 @@ constexpr int kTile = kT * kIPT;
 // ---------------------------------------------------------------------------
 // prepare
 // ---------------------------------------------------------------------------
+// Prepares segment row i (every thread of the workgroup calls it: it ends
+// with a workgroup reduction).
 template <int W, bool LAST>
-__global__ __launch_bounds__(kT) void k_prepare(const int32_t *__restrict__ rows, int64_t row0, int64_t nrows,
-                                                GraphDev g, DevPlan P, SegBufs s, Ctrl *ctrl) {
+__device__ __forceinline__ void prepare_row(const int32_t *__restrict__ rows, int64_t row0, int64_t nrows,
+                                            const GraphDev &g, const DevPlan &P, const SegBufs &s, Ctrl *ctrl,
+                                            int64_t i) {
     __shared__ unsigned long long s_valid[kT / 64];
     __shared__ unsigned long long s_bytes[kT / 64];
-    const int64_t i = (int64_t)blockIdx.x * kT + threadIdx.x;
     bool valid = false;
     unsigned long long abytes = 0;  // algorithmic bytes of a merge intersection for this row
     if (i < nrows) {
@@ -121,6 +125,12 @@ __global__ __launch_bounds__(kT) void k_prepare(const int32_t *__restrict__ rows
             if (tb) atomicAdd(&ctrl->segbytes[W], tb);
         }
     }
+}
+
+template <int W, bool LAST>
+__global__ __launch_bounds__(kT) void k_prepare(const int32_t *__restrict__ rows, int64_t row0, int64_t nrows,
+                                                GraphDev g, DevPlan P, SegBufs s, Ctrl *ctrl) {
+    prepare_row<W, LAST>(rows, row0, nrows, g, P, s, ctrl, (int64_t)blockIdx.x * kT + threadIdx.x);
 }
 
 // ---------------------------------------------------------------------------
@@ -564,8 +574,9 @@ __device__ __forceinline__ int64_t gallop_blk(const int32_t *__restrict__ col, i
     return r;
 }
 
+// One tile of kT * RUN work items (every thread of the workgroup calls it).
 template <int W, int MODE, int RUN, bool BLK>
-__global__ __launch_bounds__(kT) void k_extend_merge(ExtArgs a) {
+__device__ __forceinline__ void merge_tile(const ExtArgs &a, int64_t tile) {
     constexpr int kRun = RUN;
     constexpr int kMTile = kT * RUN;
     constexpr bool kEmit = MODE == MODE_EMIT || MODE == MODE_OUTPUT;
@@ -582,7 +593,7 @@ __global__ __launch_bounds__(kT) void k_extend_merge(ExtArgs a) {
     __shared__ int32_t s_pv[kHash ? kT / 64 : 1][128];
     __shared__ int32_t s_pr[kHash ? kT / 64 : 1][128];
 
-    const int64_t tile0 = a.w0 + (int64_t)blockIdx.x * kMTile;
+    const int64_t tile0 = a.w0 + tile * kMTile;
     const int64_t tile1 = min(tile0 + (int64_t)kMTile, a.w1);
     if (threadIdx.x == 0) {
         s_rng[0] = find_row(a.off, 0, a.nrows - 1, tile0);
@@ -807,6 +818,11 @@ __global__ __launch_bounds__(kT) void k_extend_merge(ExtArgs a) {
 }
 
 template <int W, int MODE, int RUN, bool BLK>
+__global__ __launch_bounds__(kT) void k_extend_merge(ExtArgs a) {
+    merge_tile<W, MODE, RUN, BLK>(a, blockIdx.x);
+}
+
+template <int W, int MODE, int RUN, bool BLK>
 void merge_launch(const ExtArgs &a, hipStream_t st) {
     const int64_t items = a.w1 - a.w0;
     dim3 grid((unsigned)((items + (int64_t)kT * RUN - 1) / ((int64_t)kT * RUN)));
@@ -850,6 +866,158 @@ void extend_w(int mode, int strategy, const ExtArgs &a, hipStream_t st) {
         case STRAT_BLOCK_MERGE_LONG: merge_mode<W, 64, true>(mode, a, st); break;
         default: merge_mode<W, 16>(mode, a, st); break;
     }
+}
+
+// ---------------------------------------------------------------------------
+// device-driven rounds: one scheduler thread takes Algorithm 5's next step
+// (a segment to prepare, or a range of work items to extend), and fixed-grid
+// prepare / scan / extend launches of every level read it and stay idle
+// unless it is theirs.  The same round can then be replayed from a graph.
+// ---------------------------------------------------------------------------
+constexpr int64_t kRoundMaxItems = 1ll << 30;
+constexpr unsigned kRoundGrid = 4096;  // workgroups of a round's extend launches (grid-stride)
+
+__global__ void k_round_sched(GState *gs, GConst c, Ctrl *ctrl) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    GState &s = *gs;
+    for (int w = 0; w <= HUGE_KMAX; ++w) {
+        s.n_prep[w] = 0;
+        s.ext_w0[w] = 0;
+        s.ext_w1[w] = 0;
+    }
+    if (s.done) return;
+    // results of the previous round's action
+    if (s.last_kind == GACT_PREPARE) {
+        GLevel &l = s.lv[s.last_W];
+        l.seg_total = c.off[s.last_W][l.seg_n];
+        s.work[s.last_W - 1] += l.seg_total;
+    } else if (s.last_kind == GACT_EMIT) {
+        const int w1 = s.last_W + 1;
+        const int64_t nr = (int64_t)ctrl->qcount[w1];
+        s.cur_bytes += (nr - s.lv[w1].nrows) * 4 * w1;
+        if (s.cur_bytes > s.peak_bytes) s.peak_bytes = s.cur_bytes;
+        s.lv[w1].nrows = nr;
+    }
+    s.last_kind = GACT_NONE;
+    int W = s.W;
+    for (int guard = 0; guard < 8 * HUGE_KMAX; ++guard) {
+        GLevel &l = s.lv[W];
+        if (!s.inner) {
+            if (!(l.seg_done < l.seg_total || l.next < l.nrows)) {
+                // input empty: backtrack (level 2 empty: the query is done)
+                if (W == 2) {
+                    s.done = 1;
+                    s.W = W;
+                    return;
+                }
+                s.cur_bytes -= l.nrows * 4 * W;
+                l.nrows = l.next = l.seg_row0 = l.seg_n = l.seg_total = l.seg_done = 0;
+                ctrl->qcount[W] = 0;
+                --W;
+                continue;
+            }
+            s.inner = 1;
+        }
+        // run level W until its output queue is full or its input is empty
+        bool leave = false;
+        if (l.seg_done == l.seg_total) {
+            if (l.next == l.nrows) {
+                leave = true;
+            } else {
+                const int64_t cnt = min(c.seg_cap[W], l.nrows - l.next);
+                l.seg_row0 = l.next;
+                l.seg_n = cnt;
+                l.next += cnt;
+                l.seg_total = l.seg_done = 0;
+                s.n_prep[W] = cnt;
+                s.last_kind = GACT_PREPARE;
+                s.last_W = W;
+                s.W = W;
+                s.rounds++;
+                return;
+            }
+        }
+        if (!leave) {
+            const int64_t rem = l.seg_total - l.seg_done;
+            if (W == c.lastW) {  // SINK: count the rest of the segment
+                const int64_t chunk = min(rem, kRoundMaxItems);
+                s.ext_w0[W] = l.seg_done;
+                s.ext_w1[W] = l.seg_done + chunk;
+                l.seg_done += chunk;
+                s.last_kind = GACT_SINK;
+                s.last_W = W;
+                s.W = W;
+                s.rounds++;
+                return;
+            }
+            const int64_t fr = c.q_cap[W + 1] - s.lv[W + 1].nrows;
+            if (fr <= 0 || (fr < rem && fr < c.q_cap[W + 1] / 8)) {
+                leave = true;  // output queue full
+            } else {
+                const int64_t chunk = min(min(fr, rem), kRoundMaxItems);
+                s.ext_w0[W] = l.seg_done;
+                s.ext_w1[W] = l.seg_done + chunk;
+                l.seg_done += chunk;
+                s.last_kind = GACT_EMIT;
+                s.last_W = W;
+                s.W = W;
+                s.rounds++;
+                return;
+            }
+        }
+        // leaving level W: the SINK hands back to its precursor, any other
+        // operator moves on to its successor
+        s.inner = 0;
+        W = (W == c.lastW) ? (W > 2 ? W - 1 : W) : W + 1;
+    }
+    s.error = 1;  // no action found: stop instead of spinning
+    s.done = 1;
+}
+
+template <int W, bool LAST>
+__global__ __launch_bounds__(kT) void k_round_prepare(const int32_t *__restrict__ rows, const GState *gs, GraphDev g,
+                                                      DevPlan P, SegBufs s, Ctrl *ctrl) {
+    const int64_t n = gs->n_prep[W];
+    if (n <= 0) return;
+    const int64_t row0 = gs->lv[W].seg_row0;
+    for (int64_t b = (int64_t)blockIdx.x * kT; b < n; b += (int64_t)gridDim.x * kT) {
+        prepare_row<W, LAST>(rows, row0, n, g, P, s, ctrl, b + threadIdx.x);
+        __syncthreads();
+    }
+}
+
+template <int W, int MODE, int RUN, bool BLK>
+__global__ __launch_bounds__(kT) void k_round_extend(ExtArgs a, const GState *gs) {
+    const int64_t w0 = gs->ext_w0[W], w1 = gs->ext_w1[W];
+    if (w1 <= w0) return;
+    a.row0 = gs->lv[W].seg_row0;
+    a.nrows = gs->lv[W].seg_n;
+    a.w0 = w0;
+    a.w1 = w1;
+    const int64_t tiles = (w1 - w0 + (int64_t)kT * RUN - 1) / ((int64_t)kT * RUN);
+    for (int64_t t = blockIdx.x; t < tiles; t += gridDim.x) {
+        merge_tile<W, MODE, RUN, BLK>(a, t);
+        __syncthreads();
+    }
+}
+
+template <int W, int RUN, bool BLK>
+void round_extend_mode(int mode, const ExtArgs &a, const GState *gs, hipStream_t st) {
+    const dim3 grid(kRoundGrid), blk(kT);
+    if (mode == MODE_COUNT)
+        hipLaunchKernelGGL((k_round_extend<W, MODE_COUNT, RUN, BLK>), grid, blk, 0, st, a, gs);
+    else if (mode == MODE_COUNT_NOHASH)
+        hipLaunchKernelGGL((k_round_extend<W, MODE_COUNT_NOHASH, RUN, BLK>), grid, blk, 0, st, a, gs);
+    else
+        hipLaunchKernelGGL((k_round_extend<W, MODE_EMIT, (RUN > 16 ? 16 : RUN), BLK>), grid, blk, 0, st, a, gs);
+}
+
+template <int W>
+void round_extend_w(int mode, int strategy, const ExtArgs &a, const GState *gs, hipStream_t st) {
+    if (strategy == STRAT_BLOCK_MERGE_LONG)
+        round_extend_mode<W, 64, true>(mode, a, gs, st);
+    else
+        round_extend_mode<W, 16, false>(mode, a, gs, st);
 }
 
 // ---------------------------------------------------------------------------
@@ -998,6 +1166,64 @@ void launch_edge_sink(const GraphDev &g, const DevPlan &P, int64_t e0, int64_t e
 void launch_root_count(const GraphDev &g, const DevPlan &P, Ctrl *ctrl, hipStream_t st) {
     dim3 grid((unsigned)((g.n + kT - 1) / kT));
     hipLaunchKernelGGL(k_root_count, grid, dim3(kT), 0, st, g.n, P, ctrl);
+    HUGE_HIP(hipGetLastError());
+}
+
+void launch_round_sched(GState *s, const GConst &c, Ctrl *ctrl, hipStream_t st) {
+    hipLaunchKernelGGL(k_round_sched, dim3(1), dim3(64), 0, st, s, c, ctrl);
+    HUGE_HIP(hipGetLastError());
+}
+
+void launch_round_prepare(int width, bool last, const GraphDev &g, const DevPlan &P, const int32_t *rows,
+                          const SegBufs &s, Ctrl *ctrl, GState *gs, int64_t seg_cap, hipStream_t st) {
+    const dim3 grid((unsigned)std::min<int64_t>((seg_cap + kT - 1) / kT, kRoundGrid)), blk(kT);
+    switch (width * 2 + (last ? 1 : 0)) {
+#define HUGE_ROUND_PREP(W)                                                                                  \
+    case 2 * W: hipLaunchKernelGGL((k_round_prepare<W, false>), grid, blk, 0, st, rows, gs, g, P, s, ctrl); break; \
+    case 2 * W + 1: hipLaunchKernelGGL((k_round_prepare<W, true>), grid, blk, 0, st, rows, gs, g, P, s, ctrl); break;
+        HUGE_ROUND_PREP(2)
+        HUGE_ROUND_PREP(3)
+        HUGE_ROUND_PREP(4)
+        HUGE_ROUND_PREP(5)
+        HUGE_ROUND_PREP(6)
+        HUGE_ROUND_PREP(7)
+#undef HUGE_ROUND_PREP
+        default: HUGE_FAIL(HUGE_EINVAL, "bad width %d", width);
+    }
+    HUGE_HIP(hipGetLastError());
+}
+
+void launch_round_scan(int width, const SegBufs &s, GState *gs, int64_t seg_cap, int64_t *tmp, hipStream_t st) {
+    scan_excl_devn(s.bound, s.off, &gs->n_prep[width], seg_cap, tmp, st);
+    HUGE_HIP(hipGetLastError());
+}
+
+void launch_round_extend(int width, int mode, int strategy, const GraphDev &g, const DevPlan &P, const int32_t *rows,
+                         const SegBufs &s, int32_t *out_rows, Ctrl *ctrl, const int32_t *inv_rank, GState *gs,
+                         hipStream_t st) {
+    ExtArgs a;
+    a.rows = rows;
+    a.row0 = 0;
+    a.rid = nullptr;
+    a.off = s.off;
+    a.pinfo = s.pinfo;
+    a.hpre = s.hpre;
+    a.nrows = 0;
+    a.w0 = a.w1 = 0;
+    a.out = out_rows;
+    a.ctrl = ctrl;
+    a.inv_rank = inv_rank;
+    a.g = g;
+    a.P = P;
+    switch (width) {
+        case 2: round_extend_w<2>(mode, strategy, a, gs, st); break;
+        case 3: round_extend_w<3>(mode, strategy, a, gs, st); break;
+        case 4: round_extend_w<4>(mode, strategy, a, gs, st); break;
+        case 5: round_extend_w<5>(mode, strategy, a, gs, st); break;
+        case 6: round_extend_w<6>(mode, strategy, a, gs, st); break;
+        case 7: round_extend_w<7>(mode, strategy, a, gs, st); break;
+        default: HUGE_FAIL(HUGE_EINVAL, "bad width %d", width);
+    }
     HUGE_HIP(hipGetLastError());
 }
 

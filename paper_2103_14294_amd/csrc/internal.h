@@ -174,6 +174,8 @@ uint64_t workspace_bytes(const huge_graph *g, const huge_plan *p, const huge_exe
 // returns true when the run stopped at o.work_limit
 bool run_levels(const huge_graph *g, const huge_plan *p, const huge_exec_opts &o, huge_result *out, EmitSink *emit,
                 TuneProbe *probe = nullptr);
+// counting through replays of a recorded round (HUGE_ENGINE_GRAPH)
+void run_graph(const huge_graph *g, const huge_plan *p, const huge_exec_opts &o, huge_result *out);
 void autotune(const huge_graph *g, const huge_plan *const *plans, int np, const huge_exec_opts &o,
               huge_tune_table *out);
 // batch.cpp
@@ -223,6 +225,46 @@ void launch_edge_sink(const GraphDev &g, const DevPlan &P, int64_t e0, int64_t e
                       const int32_t *inv_rank, Ctrl *ctrl, hipStream_t st);
 void launch_root_count(const GraphDev &g, const DevPlan &P, Ctrl *ctrl, hipStream_t st);
 int64_t scan_tmp_elems(int64_t n);
+
+// ---------------------------------------------------------------------------
+// device-driven rounds (graph engine): Algorithm 5's scheduler runs on the
+// device, one action per round, so that a round of fixed launches can be
+// recorded once in a hipGraph and replayed until the query is done
+// ---------------------------------------------------------------------------
+struct GLevel {
+    int64_t nrows;      // rows in this level's input (queue rows; level 2: the edge array)
+    int64_t next;       // first row not yet taken into a segment
+    int64_t seg_row0, seg_n;        // current segment's rows
+    int64_t seg_total, seg_done;    // its work items, and those already extended
+};
+enum { GACT_NONE = 0, GACT_PREPARE = 1, GACT_EMIT = 2, GACT_SINK = 3 };
+struct GState {
+    GLevel lv[HUGE_KMAX + 1];
+    int64_t n_prep[HUGE_KMAX + 1];  // this round: rows to prepare at level W (0: none)
+    int64_t ext_w0[HUGE_KMAX + 1];  // this round: work items [w0, w1) to extend at level W
+    int64_t ext_w1[HUGE_KMAX + 1];
+    int64_t work[HUGE_KMAX];        // work items per level (huge_result.level_work)
+    int64_t cur_bytes, peak_bytes;  // frontier bytes held in queues
+    int64_t rounds;                 // rounds that took an action
+    int32_t W;                      // level the scheduler is on
+    int32_t inner;                  // 1: inside level W's run (its input was checked on entry)
+    int32_t last_kind, last_W;      // the previous round's action
+    int32_t done, error;
+};
+struct GConst {                      // fixed for a query (kernel argument)
+    int32_t k, lastW;
+    int64_t seg_cap[HUGE_KMAX + 1];
+    int64_t q_cap[HUGE_KMAX + 1];
+    const int64_t *off[HUGE_KMAX + 1];  // each level's scanned bounds (off[seg_n] = segment total)
+};
+void launch_round_sched(GState *s, const GConst &c, Ctrl *ctrl, hipStream_t st);
+void launch_round_prepare(int width, bool last, const GraphDev &g, const DevPlan &P, const int32_t *rows,
+                          const SegBufs &s, Ctrl *ctrl, GState *gs, int64_t seg_cap, hipStream_t st);
+void launch_round_scan(int width, const SegBufs &s, GState *gs, int64_t seg_cap, int64_t *tmp, hipStream_t st);
+// strategy: STRAT_LANE_MERGE or STRAT_BLOCK_MERGE_LONG
+void launch_round_extend(int width, int mode, int strategy, const GraphDev &g, const DevPlan &P, const int32_t *rows,
+                         const SegBufs &s, int32_t *out_rows, Ctrl *ctrl, const int32_t *inv_rank, GState *gs,
+                         hipStream_t st);
 
 // extend modes
 enum { MODE_EMIT = 0, MODE_COUNT = 1, MODE_OUTPUT = 2, MODE_COUNT_NOHASH = 3 };

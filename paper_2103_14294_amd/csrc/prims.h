@@ -9,6 +9,14 @@ namespace huge {
 void scan_excl(const uint32_t *in, int64_t *out, int64_t n, int64_t *total, int64_t *tmp, hipStream_t st);
 void scan_excl(const int32_t *in, int64_t *out, int64_t n, int64_t *total, int64_t *tmp, hipStream_t st);
 
+// The same scan with n read from device memory when the kernels run (*n_dev,
+// at most nmax <= scan_devn_max()); out[n] receives the total, and nothing is
+// written when n is 0.  The launches have fixed grids, so a graph can record
+// them once.  tmp must hold scan_tmp_elems(nmax) int64 values.
+int64_t scan_devn_max();
+void scan_excl_devn(const int32_t *in, int64_t *out, const int64_t *n_dev, int64_t nmax, int64_t *tmp,
+                    hipStream_t st);
+
 // Stable LSD radix sort of n (key, value) pairs on key bits [0, bits).
 // hist: radix_sort_hist_elems(n) uint32; offs: the same count of int64;
 // scan_tmp: scan_tmp_elems(radix_sort_hist_elems(n)) int64.

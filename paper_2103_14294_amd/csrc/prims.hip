@@ -42,11 +42,11 @@ __device__ __forceinline__ int64_t block_excl_scan(int64_t x, int64_t *warp_sums
     return tot;
 }
 
+// Sum of tile t of in[0, n) (every thread of the workgroup calls it).
 template <typename Tin>
-__global__ __launch_bounds__(kScanThreads) void k_tile_reduce(const Tin *__restrict__ in, int64_t n,
-                                                              int64_t *__restrict__ partial) {
+__device__ __forceinline__ int64_t tile_sum(const Tin *__restrict__ in, int64_t n, int64_t t) {
     __shared__ int64_t ws[kScanThreads / 64];
-    int64_t base = (int64_t)blockIdx.x * kScanTile;
+    int64_t base = t * kScanTile;
     int64_t s = 0;
 #pragma unroll
     for (int j = 0; j < kScanPer; ++j) {
@@ -54,18 +54,17 @@ __global__ __launch_bounds__(kScanThreads) void k_tile_reduce(const Tin *__restr
         if (i < n) s += (int64_t)in[i];
     }
     int64_t ex;
-    int64_t tot = block_excl_scan(s, ws, ex);
-    if (threadIdx.x == 0) partial[blockIdx.x] = tot;
+    return block_excl_scan(s, ws, ex);
 }
 
-// Scan one tile: out[i] = carry[tile] + exclusive prefix within the tile.
+// Scans tile t of in[0, n): out[i] = c + exclusive prefix within the tile;
+// returns the tile's sum (every thread of the workgroup calls it).
 template <typename Tin>
-__global__ __launch_bounds__(kScanThreads) void k_tile_scan(const Tin *__restrict__ in, int64_t n,
-                                                            const int64_t *__restrict__ carry,
-                                                            int64_t *__restrict__ out, int64_t *__restrict__ total) {
+__device__ __forceinline__ int64_t tile_scan(const Tin *__restrict__ in, int64_t n, int64_t c, int64_t *__restrict__ out,
+                                             int64_t t) {
     __shared__ int64_t buf[kScanTile];
     __shared__ int64_t ws[kScanThreads / 64];
-    int64_t base = (int64_t)blockIdx.x * kScanTile;
+    int64_t base = t * kScanTile;
 #pragma unroll
     for (int j = 0; j < kScanPer; ++j) {
         int64_t i = base + j * kScanThreads + threadIdx.x;
@@ -81,7 +80,6 @@ __global__ __launch_bounds__(kScanThreads) void k_tile_scan(const Tin *__restric
     }
     int64_t ex;
     int64_t tot = block_excl_scan(s, ws, ex);
-    int64_t c = carry ? carry[blockIdx.x] : 0;
 #pragma unroll
     for (int j = 0; j < kScanPer; ++j) buf[threadIdx.x * kScanPer + j] = c + ex + loc[j];
     __syncthreads();
@@ -90,7 +88,57 @@ __global__ __launch_bounds__(kScanThreads) void k_tile_scan(const Tin *__restric
         int64_t i = base + j * kScanThreads + threadIdx.x;
         if (i < n) out[i] = buf[j * kScanThreads + threadIdx.x];
     }
+    return tot;
+}
+
+template <typename Tin>
+__global__ __launch_bounds__(kScanThreads) void k_tile_reduce(const Tin *__restrict__ in, int64_t n,
+                                                              int64_t *__restrict__ partial) {
+    const int64_t tot = tile_sum(in, n, blockIdx.x);
+    if (threadIdx.x == 0) partial[blockIdx.x] = tot;
+}
+
+// Scan one tile: out[i] = carry[tile] + exclusive prefix within the tile.
+template <typename Tin>
+__global__ __launch_bounds__(kScanThreads) void k_tile_scan(const Tin *__restrict__ in, int64_t n,
+                                                            const int64_t *__restrict__ carry,
+                                                            int64_t *__restrict__ out, int64_t *__restrict__ total) {
+    const int64_t c = carry ? carry[blockIdx.x] : 0;
+    const int64_t tot = tile_scan(in, n, c, out, blockIdx.x);
     if (total && blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) *total = c + tot;
+}
+
+// The same three steps with the element count read from device memory at run
+// time (fixed grids sized for the largest count; tiles past the count and
+// every kernel of a zero count do nothing), so that they can be recorded once
+// in a graph.  out[n] receives the total.
+__global__ __launch_bounds__(kScanThreads) void k_tile_reduce_dn(const int32_t *__restrict__ in,
+                                                                 const int64_t *__restrict__ n_dev,
+                                                                 int64_t *__restrict__ partial) {
+    const int64_t n = *n_dev;
+    if ((int64_t)blockIdx.x * kScanTile >= n) return;
+    const int64_t tot = tile_sum(in, n, blockIdx.x);
+    if (threadIdx.x == 0) partial[blockIdx.x] = tot;
+}
+
+__global__ __launch_bounds__(kScanThreads) void k_partial_scan_dn(const int64_t *__restrict__ n_dev,
+                                                                  int64_t *__restrict__ partial) {
+    const int64_t n = *n_dev;
+    if (n <= kScanTile) return;  // a single tile needs no carries
+    const int64_t nb = (n + kScanTile - 1) / kScanTile;  // <= kScanTile
+    tile_scan(partial, nb, 0, partial, 0);
+}
+
+__global__ __launch_bounds__(kScanThreads) void k_tile_scan_dn(const int32_t *__restrict__ in,
+                                                               const int64_t *__restrict__ n_dev,
+                                                               const int64_t *__restrict__ partial,
+                                                               int64_t *__restrict__ out) {
+    const int64_t n = *n_dev;
+    const int64_t base = (int64_t)blockIdx.x * kScanTile;
+    if (base >= n) return;
+    const int64_t c = n > kScanTile ? partial[blockIdx.x] : 0;
+    const int64_t tot = tile_scan(in, n, c, out, blockIdx.x);
+    if (base + kScanTile >= n && threadIdx.x == 0) out[n] = c + tot;
 }
 
 template <typename Tin>
@@ -209,6 +257,18 @@ void scan_excl(const int32_t *in, int64_t *out, int64_t n, int64_t *total, int64
         return;
     }
     scan_rec<int32_t>(in, out, n, total, tmp, st);
+}
+
+int64_t scan_devn_max() { return (int64_t)kScanTile * kScanTile; }
+
+void scan_excl_devn(const int32_t *in, int64_t *out, const int64_t *n_dev, int64_t nmax, int64_t *tmp,
+                    hipStream_t st) {
+    if (nmax <= 0) return;
+    if (nmax > scan_devn_max()) HUGE_FAIL(HUGE_EINVAL, "scan_excl_devn: %lld elements exceed the limit", (long long)nmax);
+    const unsigned nb = (unsigned)((nmax + kScanTile - 1) / kScanTile);
+    hipLaunchKernelGGL(k_tile_reduce_dn, dim3(nb), dim3(kScanThreads), 0, st, in, n_dev, tmp);
+    hipLaunchKernelGGL(k_partial_scan_dn, dim3(1), dim3(kScanThreads), 0, st, n_dev, tmp);
+    hipLaunchKernelGGL(k_tile_scan_dn, dim3(nb), dim3(kScanThreads), 0, st, in, n_dev, (const int64_t *)tmp, out);
 }
 
 int64_t radix_sort_hist_elems(int64_t n) {
