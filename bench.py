@@ -203,7 +203,7 @@ def main():
     ap.add_argument("--batched", action="store_true", help="one huge_count_batch call per step")
     ap.add_argument("--engine", choices=["levels", "graph"], default="levels",
                     help="levels: host-driven scheduler (default); graph: device scheduler, rounds replayed "
-                         "from a hipGraph (one strategy everywhere, no tuning)")
+                         "from a hipGraph")
     ap.add_argument("--cap", type=float, default=None, help="frontier cap in bytes (default: the workload's)")
     ap.add_argument("--strategy", type=int, default=-1, help="intersection strategy (-1 = library default)")
     ap.add_argument("--no-hash", action="store_true", help="count only (no set-hash)")
@@ -255,7 +255,6 @@ def main():
     kw = dict(cap=cap, workspace=ws, strategy=args.strategy, hash=not args.no_hash)
     if args.engine == "graph":
         kw["engine"] = huge.ENGINE_GRAPH
-        args.tune = False  # the graph engine runs one strategy everywhere
     # batches slice on each plan's first matched vertex, or on its level-2 rows (edge
     # slices, which reach hubs in proportion to their degree): an unbiased 1/nb sample of
     # that plan's work, the same in sequential and batched runs

@@ -77,11 +77,12 @@ typedef struct huge_plan huge_plan;
  * level, idle unless the round's action is theirs) is recorded once in a
  * hipGraph and replayed until a device flag says the query is done; the host
  * reads that flag once per 8 replays of 4 rounds.  huge_count and
- * huge_count_batch only (huge_enumerate: HUGE_EINVAL).  Runs the lane merge of
- * HUGE_STRAT_LANE_MERGE or HUGE_STRAT_BLOCK_MERGE_LONG (AUTO: the latter; any
- * other strategy: HUGE_EINVAL) everywhere, ignores the tune table and
- * work_limit must be 0.  Segments are capped at 2^24 rows.  Results equal the
- * other engines' bit for bit; huge_result.launches counts graph launches. */
+ * huge_count_batch only (huge_enumerate: HUGE_EINVAL).  Strategies as on the
+ * level engine: a tune table with strategy AUTO gives the per-bucket dispatch
+ * (and its rows per segment), a fixed strategy runs everywhere, and AUTO
+ * without a table runs HUGE_STRAT_BLOCK_MERGE_LONG.  work_limit must be 0.
+ * Segments are capped at 2^24 rows.  Results equal the other engines' bit for
+ * bit; huge_result.launches counts graph launches. */
 #define HUGE_ENGINE_GRAPH 3
 #define HUGE_PERSIST_KMAX 4      /* largest query the persistent engine runs (HUGE_EINVAL above) */
 

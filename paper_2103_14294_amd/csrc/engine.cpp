@@ -45,7 +45,8 @@ struct Layout {
 
 inline uint64_t align_up(uint64_t x) { return (x + 255) & ~uint64_t(255); }
 
-Layout make_layout(const huge_graph *g, const huge_plan *p, const huge_exec_opts &o, int64_t stage_rows) {
+Layout make_layout(const huge_graph *g, const huge_plan *p, const huge_exec_opts &o, int64_t stage_rows,
+                   int64_t seg_limit = INT64_MAX) {
     Layout L;
     const int k = p->k;
     int64_t seg = o.chunk_rows > 0 ? o.chunk_rows : kDefaultSeg;
@@ -63,9 +64,9 @@ Layout make_layout(const huge_graph *g, const huge_plan *p, const huge_exec_opts
     auto seg_for = [&](int w) {
         if (o.chunk_rows <= 0 && o.tune) {
             const int64_t c = o.tune->chunk_rows[ext_count(p, w)];
-            if (c > 0) return c;
+            if (c > 0) return std::min(c, seg_limit);
         }
-        return seg;
+        return std::min(seg, seg_limit);
     };
     L.seg_cap[2] = std::min<int64_t>(seg_for(2), std::max<int64_t>(1, g->dev.nnz));
     for (int w = 3; w <= k - 1; ++w) L.seg_cap[w] = std::min<int64_t>(seg_for(w), L.q_cap[w]);
@@ -182,12 +183,7 @@ struct Profiler {
 };
 
 uint64_t workspace_bytes(const huge_graph *g, const huge_plan *p, const huge_exec_opts &o) {
-    if (o.engine == HUGE_ENGINE_GRAPH) {
-        huge_exec_opts q = o;
-        q.tune = nullptr;
-        if (q.chunk_rows > scan_devn_max()) q.chunk_rows = scan_devn_max();
-        return make_layout(g, p, q, 0).total + align_up(sizeof(GState));
-    }
+    if (o.engine == HUGE_ENGINE_GRAPH) return make_layout(g, p, o, 0, scan_devn_max()).total + align_up(sizeof(GState));
     return make_layout(g, p, o, 1 << 16).total;
 }
 
@@ -489,11 +485,8 @@ struct GraphRes {
 void run_graph(const huge_graph *g, const huge_plan *p, const huge_exec_opts &o_in, huge_result *out) {
     auto t0 = std::chrono::steady_clock::now();
     if (o_in.work_limit > 0) HUGE_FAIL(HUGE_EINVAL, "the graph engine has no work limit");
-    int strat = o_in.strategy;
-    if (strat < 0 || strat >= STRAT_COUNT) strat = STRAT_BLOCK_MERGE_LONG;
-    if (strat != STRAT_LANE_MERGE && strat != STRAT_BLOCK_MERGE_LONG)
-        HUGE_FAIL(HUGE_EINVAL, "the graph engine runs strategy %d or %d, not %d", STRAT_LANE_MERGE,
-                  STRAT_BLOCK_MERGE_LONG, strat);
+    const bool part = partitioned(o_in);
+    const int strat = (o_in.strategy >= 0 && o_in.strategy < STRAT_COUNT) ? o_in.strategy : STRAT_BLOCK_MERGE_LONG;
     const int k = p->k;
     if (k < 3) {  // one edge-array launch: nothing to replay
         huge_exec_opts o = o_in;
@@ -502,9 +495,7 @@ void run_graph(const huge_graph *g, const huge_plan *p, const huge_exec_opts &o_
         run_levels(g, p, o, out, nullptr, nullptr);
         return;
     }
-    huge_exec_opts o = o_in;
-    o.tune = nullptr;  // one strategy everywhere, no bucket partition
-    if (o.chunk_rows > scan_devn_max()) o.chunk_rows = scan_devn_max();
+    const huge_exec_opts &o = o_in;
     hipStream_t st = (hipStream_t)o.stream;
     DevPlan P = p->dev;
     P.slice_count = o.slice_count > 1 ? o.slice_count : 1;
@@ -516,7 +507,7 @@ void run_graph(const huge_graph *g, const huge_plan *p, const huge_exec_opts &o_
     P.edge_slice = (o.slice_vertex == -2 && P.slice_count > 1) ? 1 : 0;
     const bool root_slice = P.slice_count > 1 && P.st[0].slice;
 
-    Layout L = make_layout(g, p, o, 0);
+    Layout L = make_layout(g, p, o, 0, scan_devn_max());  // segments within the device-count scan's limit
     const uint64_t gs_off = L.total;
     const uint64_t total = gs_off + align_up(sizeof(GState));
     DevMem own;
@@ -540,6 +531,15 @@ void run_graph(const huge_graph *g, const huge_plan *p, const huge_exec_opts &o_
         sb[w].hpre = cv.take<uint64_t>(c);
         sb[w].bound = cv.take<int32_t>(c);
         sb[w].cap = c;
+        if (part) {
+            const int64_t nb = (c + 255) / 256;
+            sb[w].bound_in = cv.take<int32_t>(c);
+            sb[w].rid = cv.take<int32_t>(c);
+            sb[w].pinfo_in = cv.take<uint64_t>(c);
+            sb[w].hpre_in = cv.take<uint64_t>(c);
+            sb[w].bcnt = cv.take<int32_t>(HUGE_TUNE_BUCKETS * nb);
+            sb[w].bscan = cv.take<int64_t>(HUGE_TUNE_BUCKETS * nb + 1);
+        }
     }
     for (int w = 3; w <= k - 1; ++w) q[w] = cv.take<int32_t>((uint64_t)w * L.q_cap[w]);
     (void)cv.take<int32_t>((uint64_t)k);  // staging (unused here): the level engine's layout
@@ -566,15 +566,35 @@ void run_graph(const huge_graph *g, const huge_plan *p, const huge_exec_opts &o_
     // record kRounds rounds on a private stream
     GraphRes gr;
     HUGE_HIP(hipStreamCreateWithFlags(&gr.cs, hipStreamNonBlocking));
-    HUGE_HIP(hipStreamBeginCapture(gr.cs, hipStreamCaptureModeThreadLocal));
+    HUGE_HIP(hipStreamBeginCapture(gr.cs, hipStreamCaptureModeRelaxed));  // occupancy queries run while recording
     for (int r = 0; r < kRounds; ++r) {
         launch_round_sched(gs, gc, ctrl, gr.cs);
         for (int w = 2; w <= k - 1; ++w) {
             const bool last = w == k - 1;
-            launch_round_prepare(w, last, G, P, q[w], sb[w], ctrl, gs, L.seg_cap[w], gr.cs);
+            const int mode = last ? count_mode : MODE_EMIT;
+            int32_t *outq = last ? nullptr : q[w + 1];
+            if (!part) {
+                launch_round_prepare(w, last, G, P, q[w], sb[w], ctrl, gs, L.seg_cap[w], gr.cs);
+                launch_round_scan(w, sb[w], gs, L.seg_cap[w], scan_tmp, gr.cs);
+                launch_round_extend(w, mode, strat, G, P, q[w], sb[w], outq, ctrl, g->inv_rank, gs, -1, gr.cs);
+                continue;
+            }
+            // tuned dispatch, as in the level engine: prepare into the *_in
+            // arrays, partition by probe-length bucket, scan, one launch per bucket
+            SegBufs pre = sb[w];
+            pre.bound = sb[w].bound_in;
+            pre.pinfo = sb[w].pinfo_in;
+            pre.hpre = sb[w].hpre_in;
+            launch_round_prepare(w, last, G, P, q[w], pre, ctrl, gs, L.seg_cap[w], gr.cs);
+            launch_round_partition(w, last, sb[w], gs, L.seg_cap[w], scan_tmp, gr.cs);
             launch_round_scan(w, sb[w], gs, L.seg_cap[w], scan_tmp, gr.cs);
-            launch_round_extend(w, last ? count_mode : MODE_EMIT, strat, G, P, q[w], sb[w], last ? nullptr : q[w + 1],
-                                ctrl, g->inv_rank, gs, gr.cs);
+            launch_round_bucket_bounds(w, sb[w], gs, gr.cs);
+            const int jW = ext_count(p, w);
+            for (int c = 0; c < HUGE_TUNE_BUCKETS; ++c) {
+                int sc = o.tune->strategy[jW][c];
+                if (sc < 0 || sc >= STRAT_COUNT) sc = STRAT_LANE_MERGE;
+                launch_round_extend(w, mode, sc, G, P, q[w], sb[w], outq, ctrl, g->inv_rank, gs, c, gr.cs);
+            }
         }
     }
     HUGE_HIP(hipStreamEndCapture(gr.cs, &gr.graph));

@@ -245,8 +245,9 @@ __device__ __forceinline__ bool wave_member(const GraphDev &g, bool need_any, in
     return found;
 }
 
+// One tile of kTile work items (every thread of the workgroup calls it).
 template <int W, int MODE, int STRAT>
-__global__ __launch_bounds__(kT) void k_extend(ExtArgs a) {
+__device__ __forceinline__ void extend_tile(const ExtArgs &a, int64_t tile) {
     __shared__ int64_t s_rng[2];
     __shared__ unsigned long long s_red[3][kT / 64];
     __shared__ int32_t s_cnt[kT / 64];
@@ -255,7 +256,7 @@ __global__ __launch_bounds__(kT) void k_extend(ExtArgs a) {
     __shared__ int32_t s_pref[STRAT == 1 ? kT / 64 : 1][65];
     __shared__ int64_t s_lb[STRAT == 1 ? kT / 64 : 1][64];
 
-    const int64_t tile0 = a.w0 + (int64_t)blockIdx.x * kTile;
+    const int64_t tile0 = a.w0 + tile * kTile;
     const int64_t tile1 = min(tile0 + (int64_t)kTile, a.w1);
     if (threadIdx.x == 0) {
         s_rng[0] = find_row(a.off, 0, a.nrows - 1, tile0);
@@ -427,6 +428,11 @@ __global__ __launch_bounds__(kT) void k_extend(ExtArgs a) {
             ++o;
         }
     }
+}
+
+template <int W, int MODE, int STRAT>
+__global__ __launch_bounds__(kT) void k_extend(ExtArgs a) {
+    extend_tile<W, MODE, STRAT>(a, blockIdx.x);
 }
 
 // k == 2: every valid level-2 row is a match.
@@ -875,15 +881,30 @@ void extend_w(int mode, int strategy, const ExtArgs &a, hipStream_t st) {
 // unless it is theirs.  The same round can then be replayed from a graph.
 // ---------------------------------------------------------------------------
 constexpr int64_t kRoundMaxItems = 1ll << 30;
-constexpr unsigned kRoundGrid = 4096;  // workgroups of a round's extend launches (grid-stride)
+constexpr unsigned kRoundGrid = 4096;  // workgroups of a round's prepare and partition launches (grid-stride)
+
+// Claims the workgroup's next tile from a per-round counter, so that tiles are
+// taken in order, as the hardware dispatches the workgroups of a plain launch
+// (neighbouring rows share lists in L2), and a slow tile delays no other.
+// Returns -1 when every tile is taken.
+__device__ __forceinline__ int64_t claim_tile(unsigned long long *next, int64_t tiles) {
+    __shared__ int64_t s_tile;
+    if (threadIdx.x == 0) s_tile = (int64_t)atomicAdd(next, 1ull);
+    __syncthreads();
+    const int64_t t = s_tile;
+    __syncthreads();
+    return t < tiles ? t : -1;
+}
 
 __global__ void k_round_sched(GState *gs, GConst c, Ctrl *ctrl) {
     if (threadIdx.x != 0 || blockIdx.x != 0) return;
     GState &s = *gs;
     for (int w = 0; w <= HUGE_KMAX; ++w) {
         s.n_prep[w] = 0;
+        s.n_part[w] = 0;
         s.ext_w0[w] = 0;
         s.ext_w1[w] = 0;
+        for (int c = 0; c <= HUGE_TUNE_BUCKETS; ++c) s.tile_next[w][c] = 0;
     }
     if (s.done) return;
     // results of the previous round's action
@@ -986,38 +1007,95 @@ __global__ __launch_bounds__(kT) void k_round_prepare(const int32_t *__restrict_
     }
 }
 
+// This round's work items of level W, restricted to bucket c (c < 0: all).
+template <int W>
+__device__ __forceinline__ bool round_range(const GState *gs, int c, int64_t &w0, int64_t &w1) {
+    w0 = gs->ext_w0[W];
+    w1 = gs->ext_w1[W];
+    if (c >= 0) {
+        w0 = max(w0, gs->bw[W][c]);
+        w1 = min(w1, gs->bw[W][c + 1]);
+    }
+    return w1 > w0;
+}
+
 template <int W, int MODE, int RUN, bool BLK>
-__global__ __launch_bounds__(kT) void k_round_extend(ExtArgs a, const GState *gs) {
-    const int64_t w0 = gs->ext_w0[W], w1 = gs->ext_w1[W];
-    if (w1 <= w0) return;
+__global__ __launch_bounds__(kT) void k_round_extend(ExtArgs a, GState *gs, int c) {
+    int64_t w0, w1;
+    if (!round_range<W>(gs, c, w0, w1)) return;
     a.row0 = gs->lv[W].seg_row0;
     a.nrows = gs->lv[W].seg_n;
     a.w0 = w0;
     a.w1 = w1;
     const int64_t tiles = (w1 - w0 + (int64_t)kT * RUN - 1) / ((int64_t)kT * RUN);
-    for (int64_t t = blockIdx.x; t < tiles; t += gridDim.x) {
+    for (int64_t t; (t = claim_tile(&gs->tile_next[W][c + 1], tiles)) >= 0;) {
         merge_tile<W, MODE, RUN, BLK>(a, t);
         __syncthreads();
     }
 }
 
+template <int W, int MODE, int STRAT>
+__global__ __launch_bounds__(kT) void k_round_extend_ws(ExtArgs a, GState *gs, int c) {
+    int64_t w0, w1;
+    if (!round_range<W>(gs, c, w0, w1)) return;
+    a.row0 = gs->lv[W].seg_row0;
+    a.nrows = gs->lv[W].seg_n;
+    a.w0 = w0;
+    a.w1 = w1;
+    const int64_t tiles = (w1 - w0 + kTile - 1) / kTile;
+    for (int64_t t; (t = claim_tile(&gs->tile_next[W][c + 1], tiles)) >= 0;) {
+        extend_tile<W, MODE, STRAT>(a, t);
+        __syncthreads();
+    }
+}
+
+// Workgroups of kernel f that fit on the device at once: the grid of a
+// round's extend launches (each claims tiles until none is left).
+template <typename F>
+unsigned resident_grid(F f) {
+    int dev = 0, cus = 0, per = 0;
+    HUGE_HIP(hipGetDevice(&dev));
+    HUGE_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    HUGE_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, f, kT, 0));
+    return (unsigned)std::max(1, cus * std::max(1, per));
+}
+
+template <typename F>
+void round_launch(F f, const ExtArgs &a, GState *gs, int c, hipStream_t st) {
+    hipLaunchKernelGGL(f, dim3(resident_grid(f)), dim3(kT), 0, st, a, gs, c);
+}
+
 template <int W, int RUN, bool BLK>
-void round_extend_mode(int mode, const ExtArgs &a, const GState *gs, hipStream_t st) {
-    const dim3 grid(kRoundGrid), blk(kT);
+void round_extend_mode(int mode, const ExtArgs &a, GState *gs, int c, hipStream_t st) {
     if (mode == MODE_COUNT)
-        hipLaunchKernelGGL((k_round_extend<W, MODE_COUNT, RUN, BLK>), grid, blk, 0, st, a, gs);
+        round_launch(k_round_extend<W, MODE_COUNT, RUN, BLK>, a, gs, c, st);
     else if (mode == MODE_COUNT_NOHASH)
-        hipLaunchKernelGGL((k_round_extend<W, MODE_COUNT_NOHASH, RUN, BLK>), grid, blk, 0, st, a, gs);
+        round_launch(k_round_extend<W, MODE_COUNT_NOHASH, RUN, BLK>, a, gs, c, st);
     else
-        hipLaunchKernelGGL((k_round_extend<W, MODE_EMIT, (RUN > 16 ? 16 : RUN), BLK>), grid, blk, 0, st, a, gs);
+        round_launch(k_round_extend<W, MODE_EMIT, (RUN > 16 ? 16 : RUN), BLK>, a, gs, c, st);
+}
+
+template <int W, int STRAT>
+void round_extend_ws(int mode, const ExtArgs &a, GState *gs, int c, hipStream_t st) {
+    if (mode == MODE_COUNT)
+        round_launch(k_round_extend_ws<W, MODE_COUNT, STRAT>, a, gs, c, st);
+    else if (mode == MODE_COUNT_NOHASH)
+        round_launch(k_round_extend_ws<W, MODE_COUNT_NOHASH, STRAT>, a, gs, c, st);
+    else
+        round_launch(k_round_extend_ws<W, MODE_EMIT, STRAT>, a, gs, c, st);
 }
 
 template <int W>
-void round_extend_w(int mode, int strategy, const ExtArgs &a, const GState *gs, hipStream_t st) {
-    if (strategy == STRAT_BLOCK_MERGE_LONG)
-        round_extend_mode<W, 64, true>(mode, a, gs, st);
-    else
-        round_extend_mode<W, 16, false>(mode, a, gs, st);
+void round_extend_w(int mode, int strategy, const ExtArgs &a, GState *gs, int c, hipStream_t st) {
+    switch (strategy) {
+        case STRAT_BSEARCH: round_extend_ws<W, STRAT_BSEARCH>(mode, a, gs, c, st); break;
+        case STRAT_WAVE_STAGED: round_extend_ws<W, STRAT_WAVE_STAGED>(mode, a, gs, c, st); break;
+        case STRAT_MERGE_SHORT: round_extend_mode<W, 4, false>(mode, a, gs, c, st); break;
+        case STRAT_MERGE_LONG: round_extend_mode<W, 64, false>(mode, a, gs, c, st); break;
+        case STRAT_BLOCK_MERGE: round_extend_mode<W, 16, true>(mode, a, gs, c, st); break;
+        case STRAT_BLOCK_MERGE_LONG: round_extend_mode<W, 64, true>(mode, a, gs, c, st); break;
+        default: round_extend_mode<W, 16, false>(mode, a, gs, c, st); break;
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -1030,9 +1108,10 @@ __device__ __forceinline__ int probe_bucket(int32_t len) {
 }
 
 // bcnt[c * nblk + b] = rows of bucket c in block b
-__global__ __launch_bounds__(kT) void k_bucket_count(const int32_t *bound, int64_t n, int32_t *bcnt, int64_t nblk) {
+__device__ __forceinline__ void bucket_count_block(const int32_t *bound, int64_t n, int32_t *bcnt, int64_t nblk,
+                                                   int64_t b) {
     __shared__ int32_t s_c[kT / 64][HUGE_TUNE_BUCKETS];
-    const int64_t i = (int64_t)blockIdx.x * kT + threadIdx.x;
+    const int64_t i = b * kT + threadIdx.x;
     const int c = i < n ? probe_bucket(bound[i]) : -1;
     const int wv = threadIdx.x >> 6;
 #pragma unroll
@@ -1044,17 +1123,20 @@ __global__ __launch_bounds__(kT) void k_bucket_count(const int32_t *bound, int64
     if (threadIdx.x < HUGE_TUNE_BUCKETS) {
         int32_t t = 0;
         for (int q = 0; q < kT / 64; ++q) t += s_c[q][threadIdx.x];
-        bcnt[(int64_t)threadIdx.x * nblk + blockIdx.x] = t;
+        bcnt[(int64_t)threadIdx.x * nblk + b] = t;
     }
+}
+__global__ __launch_bounds__(kT) void k_bucket_count(const int32_t *bound, int64_t n, int32_t *bcnt, int64_t nblk) {
+    bucket_count_block(bound, n, bcnt, nblk, blockIdx.x);
 }
 
 // Moves row i's prepared data to its stable position in bucket order.
-__global__ __launch_bounds__(kT) void k_bucket_scatter(const int32_t *bound_in, const uint64_t *pinfo_in,
-                                                       const uint64_t *hpre_in, int64_t n, int64_t nblk,
-                                                       const int64_t *bscan, int32_t *bound, uint64_t *pinfo,
-                                                       uint64_t *hpre, int32_t *rid) {
+__device__ __forceinline__ void bucket_scatter_block(const int32_t *bound_in, const uint64_t *pinfo_in,
+                                                     const uint64_t *hpre_in, int64_t n, int64_t nblk,
+                                                     const int64_t *bscan, int32_t *bound, uint64_t *pinfo,
+                                                     uint64_t *hpre, int32_t *rid, int64_t blk) {
     __shared__ int32_t s_c[kT / 64][HUGE_TUNE_BUCKETS];
-    const int64_t i = (int64_t)blockIdx.x * kT + threadIdx.x;
+    const int64_t i = blk * kT + threadIdx.x;
     const int32_t b = i < n ? bound_in[i] : 0;
     const int c = i < n ? probe_bucket(b) : -1;
     const int wv = threadIdx.x >> 6, lane = __lane_id();
@@ -1068,13 +1150,54 @@ __global__ __launch_bounds__(kT) void k_bucket_scatter(const int32_t *bound_in, 
     }
     __syncthreads();
     if (i < n) {
-        int64_t pos = bscan[(int64_t)c * nblk + blockIdx.x] + rank;
+        int64_t pos = bscan[(int64_t)c * nblk + blk] + rank;
         for (int q = 0; q < wv; ++q) pos += s_c[q][c];
         bound[pos] = b;
         pinfo[pos] = pinfo_in[i];
         if (hpre_in) hpre[pos] = hpre_in[i];
         rid[pos] = (int32_t)i;
     }
+}
+__global__ __launch_bounds__(kT) void k_bucket_scatter(const int32_t *bound_in, const uint64_t *pinfo_in,
+                                                       const uint64_t *hpre_in, int64_t n, int64_t nblk,
+                                                       const int64_t *bscan, int32_t *bound, uint64_t *pinfo,
+                                                       uint64_t *hpre, int32_t *rid) {
+    bucket_scatter_block(bound_in, pinfo_in, hpre_in, n, nblk, bscan, bound, pinfo, hpre, rid, blockIdx.x);
+}
+
+// The partition with the row count read from device memory (graph engine):
+// fixed grids, blocks past the count idle; gs->n_part[W] receives the length
+// of the per-block counts so that the device-count scan can take them.
+template <int W>
+__global__ __launch_bounds__(kT) void k_round_bucket_count(const int32_t *bound, GState *gs, int32_t *bcnt) {
+    const int64_t n = gs->n_prep[W];
+    const int64_t nblk = (n + kT - 1) / kT;
+    if (blockIdx.x == 0 && threadIdx.x == 0) gs->n_part[W] = HUGE_TUNE_BUCKETS * nblk;
+    for (int64_t b = blockIdx.x; b < nblk; b += gridDim.x) {
+        bucket_count_block(bound, n, bcnt, nblk, b);
+        __syncthreads();
+    }
+}
+
+template <int W>
+__global__ __launch_bounds__(kT) void k_round_bucket_scatter(const GState *gs, SegBufs s, bool last) {
+    const int64_t n = gs->n_prep[W];
+    const int64_t nblk = (n + kT - 1) / kT;
+    for (int64_t b = blockIdx.x; b < nblk; b += gridDim.x) {
+        bucket_scatter_block(s.bound_in, s.pinfo_in, last ? s.hpre_in : nullptr, n, nblk, s.bscan, s.bound,
+                             s.pinfo, s.hpre, s.rid, b);
+        __syncthreads();
+    }
+}
+
+// gs->bw[W][c] = first work item of bucket c, bw[W][B] = total
+template <int W>
+__global__ void k_round_bucket_bounds(GState *gs, const int64_t *bscan, const int64_t *off) {
+    const int64_t n = gs->n_prep[W];
+    if (n <= 0) return;
+    const int64_t nblk = (n + kT - 1) / kT;
+    const int t = threadIdx.x;
+    if (t <= HUGE_TUNE_BUCKETS) gs->bw[W][t] = off[t < HUGE_TUNE_BUCKETS ? bscan[(int64_t)t * nblk] : n];
 }
 
 // out[c] = first work item of bucket c (c = 0..B-1), out[B] = total
@@ -1198,13 +1321,49 @@ void launch_round_scan(int width, const SegBufs &s, GState *gs, int64_t seg_cap,
     HUGE_HIP(hipGetLastError());
 }
 
+void launch_round_partition(int width, bool last, const SegBufs &s, GState *gs, int64_t seg_cap, int64_t *tmp,
+                            hipStream_t st) {
+    const int64_t nblk_max = (seg_cap + kT - 1) / kT;
+    const dim3 grid((unsigned)std::min<int64_t>(nblk_max, kRoundGrid)), blk(kT);
+    switch (width) {
+#define HUGE_ROUND_PART(W)                                                                                     \
+    case W:                                                                                                    \
+        hipLaunchKernelGGL(k_round_bucket_count<W>, grid, blk, 0, st, (const int32_t *)s.bound_in, gs, s.bcnt); \
+        scan_excl_devn(s.bcnt, s.bscan, &gs->n_part[W], HUGE_TUNE_BUCKETS * nblk_max, tmp, st);                \
+        hipLaunchKernelGGL(k_round_bucket_scatter<W>, grid, blk, 0, st, (const GState *)gs, s, last);           \
+        break;
+        HUGE_ROUND_PART(2)
+        HUGE_ROUND_PART(3)
+        HUGE_ROUND_PART(4)
+        HUGE_ROUND_PART(5)
+        HUGE_ROUND_PART(6)
+        HUGE_ROUND_PART(7)
+#undef HUGE_ROUND_PART
+        default: HUGE_FAIL(HUGE_EINVAL, "bad width %d", width);
+    }
+    HUGE_HIP(hipGetLastError());
+}
+
+void launch_round_bucket_bounds(int width, const SegBufs &s, GState *gs, hipStream_t st) {
+    switch (width) {
+        case 2: hipLaunchKernelGGL(k_round_bucket_bounds<2>, dim3(1), dim3(64), 0, st, gs, (const int64_t *)s.bscan, (const int64_t *)s.off); break;
+        case 3: hipLaunchKernelGGL(k_round_bucket_bounds<3>, dim3(1), dim3(64), 0, st, gs, (const int64_t *)s.bscan, (const int64_t *)s.off); break;
+        case 4: hipLaunchKernelGGL(k_round_bucket_bounds<4>, dim3(1), dim3(64), 0, st, gs, (const int64_t *)s.bscan, (const int64_t *)s.off); break;
+        case 5: hipLaunchKernelGGL(k_round_bucket_bounds<5>, dim3(1), dim3(64), 0, st, gs, (const int64_t *)s.bscan, (const int64_t *)s.off); break;
+        case 6: hipLaunchKernelGGL(k_round_bucket_bounds<6>, dim3(1), dim3(64), 0, st, gs, (const int64_t *)s.bscan, (const int64_t *)s.off); break;
+        case 7: hipLaunchKernelGGL(k_round_bucket_bounds<7>, dim3(1), dim3(64), 0, st, gs, (const int64_t *)s.bscan, (const int64_t *)s.off); break;
+        default: HUGE_FAIL(HUGE_EINVAL, "bad width %d", width);
+    }
+    HUGE_HIP(hipGetLastError());
+}
+
 void launch_round_extend(int width, int mode, int strategy, const GraphDev &g, const DevPlan &P, const int32_t *rows,
                          const SegBufs &s, int32_t *out_rows, Ctrl *ctrl, const int32_t *inv_rank, GState *gs,
-                         hipStream_t st) {
+                         int bucket, hipStream_t st) {
     ExtArgs a;
     a.rows = rows;
     a.row0 = 0;
-    a.rid = nullptr;
+    a.rid = bucket >= 0 ? s.rid : nullptr;
     a.off = s.off;
     a.pinfo = s.pinfo;
     a.hpre = s.hpre;
@@ -1216,12 +1375,12 @@ void launch_round_extend(int width, int mode, int strategy, const GraphDev &g, c
     a.g = g;
     a.P = P;
     switch (width) {
-        case 2: round_extend_w<2>(mode, strategy, a, gs, st); break;
-        case 3: round_extend_w<3>(mode, strategy, a, gs, st); break;
-        case 4: round_extend_w<4>(mode, strategy, a, gs, st); break;
-        case 5: round_extend_w<5>(mode, strategy, a, gs, st); break;
-        case 6: round_extend_w<6>(mode, strategy, a, gs, st); break;
-        case 7: round_extend_w<7>(mode, strategy, a, gs, st); break;
+        case 2: round_extend_w<2>(mode, strategy, a, gs, bucket, st); break;
+        case 3: round_extend_w<3>(mode, strategy, a, gs, bucket, st); break;
+        case 4: round_extend_w<4>(mode, strategy, a, gs, bucket, st); break;
+        case 5: round_extend_w<5>(mode, strategy, a, gs, bucket, st); break;
+        case 6: round_extend_w<6>(mode, strategy, a, gs, bucket, st); break;
+        case 7: round_extend_w<7>(mode, strategy, a, gs, bucket, st); break;
         default: HUGE_FAIL(HUGE_EINVAL, "bad width %d", width);
     }
     HUGE_HIP(hipGetLastError());

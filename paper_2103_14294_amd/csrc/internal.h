@@ -241,6 +241,10 @@ enum { GACT_NONE = 0, GACT_PREPARE = 1, GACT_EMIT = 2, GACT_SINK = 3 };
 struct GState {
     GLevel lv[HUGE_KMAX + 1];
     int64_t n_prep[HUGE_KMAX + 1];  // this round: rows to prepare at level W (0: none)
+    int64_t n_part[HUGE_KMAX + 1];  // this round: per-block bucket counts of level W's partition
+    int64_t bw[HUGE_KMAX + 1][HUGE_TUNE_BUCKETS + 1];  // level W's segment: first work item per bucket, total
+    unsigned long long tile_next[HUGE_KMAX + 1][HUGE_TUNE_BUCKETS + 1];  // this round: next tile to claim,
+                                                                        // per level and bucket (+1; 0: unpartitioned)
     int64_t ext_w0[HUGE_KMAX + 1];  // this round: work items [w0, w1) to extend at level W
     int64_t ext_w1[HUGE_KMAX + 1];
     int64_t work[HUGE_KMAX];        // work items per level (huge_result.level_work)
@@ -261,10 +265,17 @@ void launch_round_sched(GState *s, const GConst &c, Ctrl *ctrl, hipStream_t st);
 void launch_round_prepare(int width, bool last, const GraphDev &g, const DevPlan &P, const int32_t *rows,
                           const SegBufs &s, Ctrl *ctrl, GState *gs, int64_t seg_cap, hipStream_t st);
 void launch_round_scan(int width, const SegBufs &s, GState *gs, int64_t seg_cap, int64_t *tmp, hipStream_t st);
-// strategy: STRAT_LANE_MERGE or STRAT_BLOCK_MERGE_LONG
+// tuned dispatch: the probe-length partition of the prepared segment (reads
+// the *_in arrays, like launch_bucket_partition) and its bucket bounds
+// (after the scan), into gs->bw[width]
+void launch_round_partition(int width, bool last, const SegBufs &s, GState *gs, int64_t seg_cap, int64_t *tmp,
+                            hipStream_t st);
+void launch_round_bucket_bounds(int width, const SegBufs &s, GState *gs, hipStream_t st);
+// extend this round's work items of level `width` with `strategy`; bucket >= 0
+// restricts them to that probe-length bucket of a partitioned segment
 void launch_round_extend(int width, int mode, int strategy, const GraphDev &g, const DevPlan &P, const int32_t *rows,
                          const SegBufs &s, int32_t *out_rows, Ctrl *ctrl, const int32_t *inv_rank, GState *gs,
-                         hipStream_t st);
+                         int bucket, hipStream_t st);
 
 // extend modes
 enum { MODE_EMIT = 0, MODE_COUNT = 1, MODE_OUTPUT = 2, MODE_COUNT_NOHASH = 3 };

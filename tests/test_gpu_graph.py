@@ -39,7 +39,7 @@ def test_named_patterns_match_oracle(H, small, name):
     assert_parity(H, G, g, k, e, engine=GRAPH)
 
 
-@pytest.mark.parametrize("strategy", [-1, 2, 6])
+@pytest.mark.parametrize("strategy", [-1, 0, 1, 2, 3, 4, 5, 6])
 @pytest.mark.parametrize("cap,chunk", [(0, 0), (1 << 20, 300), (4 << 30, 4096), (4 << 30, 0)])
 def test_caps_chunks_strategies(H, small, cap, chunk, strategy):
     g, G = small
@@ -115,10 +115,52 @@ def test_edgeless_and_errors(H):
     g = gg.chung_lu(500, 6, 2.5, seed=2)
     G = H.load(g.row_ptr, g.col)
     p = H.plan(G, *P.NAMED["diamond"])
-    for bad in [dict(strategy=0), dict(strategy=1), dict(strategy=4), dict(work_limit=10)]:
+    for bad in [dict(work_limit=10)]:
         with pytest.raises(H.HugeError) as ei:
             H.count(G, p, engine=GRAPH, **bad)
         assert ei.value.name == "HUGE_EINVAL", bad
     with pytest.raises(H.HugeError) as ei:
         H.enumerate_matches(G, p, buf_rows=100, engine=GRAPH)
     assert ei.value.name == "HUGE_EINVAL"
+
+
+def _table(H, seed):
+    import random
+
+    rng = random.Random(seed)
+    t = H.TuneTable()
+    for j in range(H.KMAX + 1):
+        t.chunk_rows[j] = rng.choice([0, 300, 4096, 1 << 20])
+        for c in range(H.TUNE_BUCKETS):
+            t.strategy[j][c] = rng.choice([-1] + list(range(H.STRAT_COUNT)))
+    return t
+
+
+@pytest.mark.parametrize("seed", [1, 2, 3])
+def test_tuned_dispatch_matches_level_engine_and_oracle(H, small, hubby, seed):
+    """Per-bucket dispatch inside the recorded round: every strategy, random
+    segment sizes, both frontier extremes."""
+    t = _table(H, seed)
+    g, G = small
+    for name in ["4-clique", "house", "diamond"]:
+        k, e = P.NAMED[name]
+        assert_parity(H, G, g, k, e, engine=GRAPH, tune=t)
+        assert_parity(H, G, g, k, e, engine=GRAPH, tune=t, cap=0, slice_count=3, slice_id=1, slice_vertex=2)
+    g2, G2 = hubby
+    for name in ["4-clique", "4-cycle", "tailed-triangle"]:
+        k, e = P.NAMED[name]
+        p = H.plan(G2, k, e)
+        ref = H.count(G2, p, engine=1, tune=t)
+        r = H.count(G2, p, engine=GRAPH, tune=t)
+        assert cmp_key(r, k) == cmp_key(ref, k), name
+        assert r["level_counts"][:k] == ref["level_counts"][:k] and r["level_work"] == ref["level_work"], name
+
+
+def test_autotuned_table_on_graph_engine(H, hubby):
+    g, G = hubby
+    plans = [H.plan(G, *P.NAMED[n]) for n in ["diamond", "4-clique"]]
+    t = H.autotune(G, plans, slice_count=4, slice_id=0)
+    for p in plans:
+        ref = H.count(G, p, engine=1, tune=t)
+        for _ in range(2):
+            assert cmp_key(H.count(G, p, engine=GRAPH, tune=t), p.k) == cmp_key(ref, p.k)
