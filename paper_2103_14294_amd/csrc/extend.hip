@@ -587,6 +587,12 @@ __device__ __forceinline__ void merge_tile(const ExtArgs &a, int64_t tile) {
     constexpr int kMTile = kT * RUN;
     constexpr bool kEmit = MODE == MODE_EMIT || MODE == MODE_OUTPUT;
     constexpr bool kHash = MODE == MODE_COUNT;
+    // hashing: BLK kernels hash each hit in the lane that finds it, from the
+    // row in registers and the row's prefix hash loaded once per row (VALU is
+    // idle there, memory instructions are not); the others queue hits in LDS
+    // and hash them 64 at a time, reloading each hit's row
+    constexpr bool kHashInline = kHash && BLK;
+    constexpr bool kHashQueued = kHash && !BLK;
     __shared__ int64_t s_rng[2];
     __shared__ unsigned long long s_red[3][kT / 64];
     __shared__ int32_t s_cnt[kT / 64];
@@ -596,8 +602,8 @@ __device__ __forceinline__ void merge_tile(const ExtArgs &a, int64_t tile) {
     __shared__ int32_t s_or[kEmit ? kT * kRun : 1];
     // hits waiting to be hashed, per wave (hashing them 64 at a time keeps
     // every lane busy even when hits are sparse across lanes)
-    __shared__ int32_t s_pv[kHash ? kT / 64 : 1][128];
-    __shared__ int32_t s_pr[kHash ? kT / 64 : 1][128];
+    __shared__ int32_t s_pv[kHashQueued ? kT / 64 : 1][kHashQueued ? 128 : 1];
+    __shared__ int32_t s_pr[kHashQueued ? kT / 64 : 1][kHashQueued ? 128 : 1];
 
     const int64_t tile0 = a.w0 + tile * kMTile;
     const int64_t tile1 = min(tile0 + (int64_t)kMTile, a.w1);
@@ -640,6 +646,7 @@ __device__ __forceinline__ void merge_tile(const ExtArgs &a, int64_t tile) {
     int4 cq[BLK ? W : 1];
     int32_t vblk = -1;
     int4 vq = make_int4(0, 0, 0, 0);
+    uint64_t hrow = 0;  // kHashInline: prefix hash of the lane's current row
 #pragma unroll
     for (int p = 0; p < W; ++p) {
         f[p] = 0;
@@ -676,6 +683,7 @@ __device__ __forceinline__ void merge_tile(const ExtArgs &a, int64_t tile) {
                 pp = (int)(pi >> 56);
                 pshift = (int64_t)(pi & kPbMask) - a.off[r];
                 load_row<W>(a.rows, g, row_at(a, r), f);
+                if constexpr (kHashInline) hrow = a.hpre[r];
                 const int32_t v0 = cand(pshift + w);
 #pragma unroll
                 for (int p = 0; p < W; ++p) {
@@ -707,7 +715,18 @@ __device__ __forceinline__ void merge_tile(const ExtArgs &a, int64_t tile) {
                 }
             }
         }
-        if constexpr (kHash) {
+        if constexpr (kHashInline) {
+            if (ok) {
+                uint64_t h = hrow;
+#pragma unroll
+                for (int p = 0; p < W; ++p)
+                    if ((st.ext >> p) & 1u) h += mix64(edge_key(f[p], v));
+                h = mix64(h);
+                cnt += 1;
+                hs += h;
+                hx ^= h;
+            }
+        } else if constexpr (kHashQueued) {
             const uint64_t m = __ballot(ok);
             if (ok) {
                 const int q = npend + (int)__popcll(m & lt);
@@ -742,7 +761,7 @@ __device__ __forceinline__ void merge_tile(const ExtArgs &a, int64_t tile) {
             }
         }
     }
-    if constexpr (kHash) {
+    if constexpr (kHashQueued) {
         wave_sync();
         if (lane < npend) hash_hit(s_pv[wv][lane], s_pr[wv][lane]);
     }
