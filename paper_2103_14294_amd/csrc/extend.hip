@@ -687,9 +687,13 @@ __device__ __forceinline__ void merge_tile(const ExtArgs &a, int64_t tile) {
                 const int32_t v0 = cand(pshift + w);
 #pragma unroll
                 for (int p = 0; p < W; ++p) {
-                    if (((st.ext >> p) & 1u) && p != pp && f[p] < g.hub_base) {
-                        end[p] = g.rp[f[p] + 1];
-                        cur[p] = lower_bound(g.col, g.rp[f[p]], end[p], v0);
+                    if (((st.ext >> p) & 1u) && p != pp) {
+                        if (f[p] < g.hub_base) {
+                            end[p] = g.rp[f[p] + 1];
+                            cur[p] = lower_bound(g.col, g.rp[f[p]], end[p], v0);
+                        } else if constexpr (BLK) {
+                            cblk[p] = -1;  // a new hub: its cached bitmap block is not valid
+                        }
                     }
                 }
             }
@@ -703,7 +707,19 @@ __device__ __forceinline__ void merge_tile(const ExtArgs &a, int64_t tile) {
             for (int p = 0; p < W; ++p) {
                 if (ok && ((st.ext >> p) & 1u) && p != pp) {
                     if (f[p] >= g.hub_base) {
-                        ok = adj_has(g, f[p], v);
+                        if constexpr (BLK) {
+                            // hub: the 16-byte bitmap block of 128 vertex IDs around v, cached
+                            // under a negative key (list blocks have keys >= 0)
+                            const int32_t key = -2 - (v >> 7);
+                            if (cblk[p] != key) {
+                                cq[p] = reinterpret_cast<const int4 *>(
+                                    g.hub_bm + (int64_t)(f[p] - g.hub_base) * g.hub_words)[v >> 7];
+                                cblk[p] = key;
+                            }
+                            ok = (((uint32_t)pick4(cq[p], (v >> 5) & 3)) >> (v & 31)) & 1u;
+                        } else {
+                            ok = adj_has(g, f[p], v);
+                        }
                     } else if constexpr (BLK) {
                         int32_t x = 0;
                         cur[p] = gallop_blk(g.col, cur[p], end[p], v, cblk[p], cq[p], x);

@@ -377,7 +377,7 @@ huge_graph *graph_load(int64_t n, int64_t nnz, const int64_t *rp_in, const int32
     g->dev.src = g->src;
 
     // ---- hub bitmaps for the highest-degree ranks
-    int64_t words = (n + 31) / 32;
+    int64_t words = ((n + 127) / 128) * 4;  // rows padded to 16 bytes: block-cached readers load 4 words
     int64_t H = 0;
     if (!(flags & HUGE_NO_HUB_BITMAP) && nnz) {
         uint64_t budget = 16ull << 30;
