@@ -581,18 +581,41 @@ __device__ __forceinline__ int64_t gallop_blk(const int32_t *__restrict__ col, i
 }
 
 // One tile of kT * RUN work items (every thread of the workgroup calls it).
+// First index in [lo, hi) with col[i] >= key (hi if none), by binary search
+// over whole aligned blocks; leaves the block of the result in (blk, q).
+__device__ __forceinline__ int64_t lower_bound_blk(const int32_t *__restrict__ col, int64_t lo, int64_t hi,
+                                                   int32_t key, int32_t &blk, int4 &q) {
+    if (lo >= hi) return hi;
+    int32_t bl = (int32_t)(lo >> 2), bh = (int32_t)((hi - 1) >> 2);
+    // the result's block is in [bl, bh]: the last entry of every block before
+    // bh lies inside [lo, hi) and decides which side the result is on
+    while (bl < bh) {
+        const int32_t mid = (bl + bh) >> 1;
+        if (col[((int64_t)mid << 2) + 3] < key) bl = mid + 1; else bh = mid;
+    }
+    if (bl != blk) {
+        q = reinterpret_cast<const int4 *>(col)[bl];
+        blk = bl;
+    }
+    const int32_t qv[4] = {q.x, q.y, q.z, q.w};
+    const int64_t base = (int64_t)bl << 2;
+    int64_t r = hi;
+#pragma unroll
+    for (int t = 3; t >= 0; --t)
+        if (base + t >= lo && base + t < hi && qv[t] >= key) r = base + t;
+    return r;
+}
+
 template <int W, int MODE, int RUN, bool BLK>
 __device__ __forceinline__ void merge_tile(const ExtArgs &a, int64_t tile) {
     constexpr int kRun = RUN;
     constexpr int kMTile = kT * RUN;
     constexpr bool kEmit = MODE == MODE_EMIT || MODE == MODE_OUTPUT;
+    // each hit is hashed in the lane that finds it, from the row in registers
+    // and the row's prefix hash loaded once per row: the kernel is bound by
+    // memory instructions, not VALU, so divergent hashing beats batching hits
+    // and reloading their rows
     constexpr bool kHash = MODE == MODE_COUNT;
-    // hashing: BLK kernels hash each hit in the lane that finds it, from the
-    // row in registers and the row's prefix hash loaded once per row (VALU is
-    // idle there, memory instructions are not); the others queue hits in LDS
-    // and hash them 64 at a time, reloading each hit's row
-    constexpr bool kHashInline = kHash && BLK;
-    constexpr bool kHashQueued = kHash && !BLK;
     __shared__ int64_t s_rng[2];
     __shared__ unsigned long long s_red[3][kT / 64];
     __shared__ int32_t s_cnt[kT / 64];
@@ -602,8 +625,6 @@ __device__ __forceinline__ void merge_tile(const ExtArgs &a, int64_t tile) {
     __shared__ int32_t s_or[kEmit ? kT * kRun : 1];
     // hits waiting to be hashed, per wave (hashing them 64 at a time keeps
     // every lane busy even when hits are sparse across lanes)
-    __shared__ int32_t s_pv[kHashQueued ? kT / 64 : 1][kHashQueued ? 128 : 1];
-    __shared__ int32_t s_pr[kHashQueued ? kT / 64 : 1][kHashQueued ? 128 : 1];
 
     const int64_t tile0 = a.w0 + tile * kMTile;
     const int64_t tile1 = min(tile0 + (int64_t)kMTile, a.w1);
@@ -617,23 +638,9 @@ __device__ __forceinline__ void merge_tile(const ExtArgs &a, int64_t tile) {
     const GraphDev &g = a.g;
     const int wv = threadIdx.x >> 6;
     const int lane = __lane_id();
-    const uint64_t lt = (lane == 0) ? 0ull : ((~0ull) >> (64 - lane));
 
     unsigned long long cnt = 0, hs = 0, hx = 0;
     int nout = 0;
-    int npend = 0;  // wave-uniform
-    auto hash_hit = [&](int32_t v, int32_t rr) {
-        int32_t ff[W];
-        load_row<W>(a.rows, g, row_at(a, rr), ff);
-        uint64_t h = a.hpre[rr];
-#pragma unroll
-        for (int p = 0; p < W; ++p)
-            if ((st.ext >> p) & 1u) h += mix64(edge_key(ff[p], v));
-        h = mix64(h);
-        cnt += 1;
-        hs += h;
-        hx ^= h;
-    };
 
     const int64_t wb = tile0 + (int64_t)threadIdx.x * kRun;
     const int64_t we = min(wb + (int64_t)kRun, tile1);
@@ -646,7 +653,7 @@ __device__ __forceinline__ void merge_tile(const ExtArgs &a, int64_t tile) {
     int4 cq[BLK ? W : 1];
     int32_t vblk = -1;
     int4 vq = make_int4(0, 0, 0, 0);
-    uint64_t hrow = 0;  // kHashInline: prefix hash of the lane's current row
+    uint64_t hrow = 0;  // hashing: prefix hash of the lane's current row
 #pragma unroll
     for (int p = 0; p < W; ++p) {
         f[p] = 0;
@@ -683,14 +690,18 @@ __device__ __forceinline__ void merge_tile(const ExtArgs &a, int64_t tile) {
                 pp = (int)(pi >> 56);
                 pshift = (int64_t)(pi & kPbMask) - a.off[r];
                 load_row<W>(a.rows, g, row_at(a, r), f);
-                if constexpr (kHashInline) hrow = a.hpre[r];
+                if constexpr (kHash) hrow = a.hpre[r];
                 const int32_t v0 = cand(pshift + w);
 #pragma unroll
                 for (int p = 0; p < W; ++p) {
                     if (((st.ext >> p) & 1u) && p != pp) {
                         if (f[p] < g.hub_base) {
                             end[p] = g.rp[f[p] + 1];
-                            cur[p] = lower_bound(g.col, g.rp[f[p]], end[p], v0);
+                            if constexpr (BLK) {
+                                cur[p] = lower_bound_blk(g.col, g.rp[f[p]], end[p], v0, cblk[p], cq[p]);
+                            } else {
+                                cur[p] = lower_bound(g.col, g.rp[f[p]], end[p], v0);
+                            }
                         } else if constexpr (BLK) {
                             cblk[p] = -1;  // a new hub: its cached bitmap block is not valid
                         }
@@ -731,7 +742,7 @@ __device__ __forceinline__ void merge_tile(const ExtArgs &a, int64_t tile) {
                 }
             }
         }
-        if constexpr (kHashInline) {
+        if constexpr (kHash) {
             if (ok) {
                 uint64_t h = hrow;
 #pragma unroll
@@ -742,31 +753,6 @@ __device__ __forceinline__ void merge_tile(const ExtArgs &a, int64_t tile) {
                 hs += h;
                 hx ^= h;
             }
-        } else if constexpr (kHashQueued) {
-            const uint64_t m = __ballot(ok);
-            if (ok) {
-                const int q = npend + (int)__popcll(m & lt);
-                s_pv[wv][q] = v;
-                s_pr[wv][q] = (int32_t)r;
-            }
-            npend += (int)__popcll(m);
-            if (npend >= 64) {
-                wave_sync();
-                hash_hit(s_pv[wv][lane], s_pr[wv][lane]);
-                const int rest = npend - 64;
-                int32_t tv = 0, tr = 0;
-                if (lane < rest) {
-                    tv = s_pv[wv][64 + lane];
-                    tr = s_pr[wv][64 + lane];
-                }
-                wave_sync();
-                if (lane < rest) {
-                    s_pv[wv][lane] = tv;
-                    s_pr[wv][lane] = tr;
-                }
-                wave_sync();
-                npend = rest;
-            }
         } else if constexpr (MODE == MODE_COUNT_NOHASH) {
             cnt += ok ? 1 : 0;
         } else {
@@ -776,10 +762,6 @@ __device__ __forceinline__ void merge_tile(const ExtArgs &a, int64_t tile) {
                 ++nout;
             }
         }
-    }
-    if constexpr (kHashQueued) {
-        wave_sync();
-        if (lane < npend) hash_hit(s_pv[wv][lane], s_pr[wv][lane]);
     }
 
     if constexpr (!kEmit) {
