@@ -78,15 +78,19 @@ MODEL_PATH = os.path.join(ROOT, "paper_2103_14294_amd", "mlp_work.npz")
 # HBM traffic of the last-level intersection class on the default workload, from two
 # rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE; KiB per dispatch) of this benchmark,
 # scaled by what the same counters read for the benchmark's own 4 GiB device copy
-# (FETCH_SIZE x2.0, WRITE_SIZE x1.0); recorded for the kernel and graph-load sources
-# (hub bitmaps change the traffic) whose digest is given, and reported as null for any
-# other sources or workload.
-TRAFFIC = {"c2": {"sources_sha256_16": "ead9eedc50a79adc", "bytes_per_launch": 3.516e9}}
+# (FETCH_SIZE x2.0, WRITE_SIZE x1.0).  Recorded per algorithmic byte, because the tuned
+# table (which kernel runs each probe-length bucket, hence the launches per step) can
+# differ between tuning runs: a run's traffic per launch is that ratio times its own
+# algorithmic bytes per launch (bytes_per_launch: the profiled run's own figure).  Valid
+# for the kernel and graph-load sources (hub bitmaps change the traffic) whose digest is
+# given; null for any other sources or workload.
+TRAFFIC = {"c2": {"sources_sha256_16": "12732020934828ec", "bytes_per_launch": 3.079e9,
+                  "per_alg_byte": 0.3166}}
 KERNEL_SOURCES = ["paper_2103_14294_amd/csrc/extend.hip", "paper_2103_14294_amd/csrc/devfuncs.h",
                   "paper_2103_14294_amd/csrc/graph.hip"]
 
 
-def recorded_traffic(workload):
+def recorded_traffic(workload, alg_bytes_per_launch):
     import hashlib
 
     rec = TRAFFIC.get(workload)
@@ -96,7 +100,9 @@ def recorded_traffic(workload):
     for f in KERNEL_SOURCES:
         with open(os.path.join(ROOT, f), "rb") as fh:
             h.update(fh.read())
-    return rec["bytes_per_launch"] if h.hexdigest()[:16] == rec["sources_sha256_16"] else None
+    if h.hexdigest()[:16] != rec["sources_sha256_16"]:
+        return None
+    return rec["per_alg_byte"] * alg_bytes_per_launch
 
 
 def log(*a):
@@ -354,7 +360,7 @@ def main():
     avg_ms = kms[dom] / max(1, kl[dom])
     bytes_per_launch = kb[dom] / max(1, kl[dom])
     achieved = (bytes_per_launch / (avg_ms * 1e-3)) / 1e9 if avg_ms > 0 else 0.0
-    traffic = recorded_traffic(args.workload) if (args.tune and args.strategy < 0 and not args.batched
+    traffic = recorded_traffic(args.workload, bytes_per_launch) if (args.tune and args.strategy < 0 and not args.batched
                                                   and dom == 3 and main_mode == "cost-model") else None
     if args.engine == "graph":  # no per-launch timing inside replays
         achieved = None
