@@ -623,8 +623,6 @@ __device__ __forceinline__ void merge_tile(const ExtArgs &a, int64_t tile) {
     static_assert(!kEmit || RUN <= 16, "emitting kernels stage RUN rows per lane in LDS");
     __shared__ int32_t s_ov[kEmit ? kT * kRun : 1];
     __shared__ int32_t s_or[kEmit ? kT * kRun : 1];
-    // hits waiting to be hashed, per wave (hashing them 64 at a time keeps
-    // every lane busy even when hits are sparse across lanes)
 
     const int64_t tile0 = a.w0 + tile * kMTile;
     const int64_t tile1 = min(tile0 + (int64_t)kMTile, a.w1);
