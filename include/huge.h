@@ -82,7 +82,8 @@ typedef struct huge_plan huge_plan;
  * (and its rows per segment), a fixed strategy runs everywhere, and AUTO
  * without a table runs HUGE_STRAT_BLOCK_MERGE_LONG.  work_limit must be 0.
  * Segments are capped at 2^24 rows.  Results equal the other engines' bit for
- * bit; huge_result.launches counts graph launches. */
+ * bit; huge_result.launches counts graph launches, and profile gives no
+ * per-launch timing (kernel_ms stays 0). */
 #define HUGE_ENGINE_GRAPH 3
 #define HUGE_PERSIST_KMAX 4      /* largest query the persistent engine runs (HUGE_EINVAL above) */
 
