@@ -112,6 +112,20 @@ struct DevMem {
     }
 };
 
+// The plan as one execution sees it: the slice options of o applied to its steps.
+DevPlan exec_plan(const huge_plan *p, const huge_exec_opts &o) {
+    const int k = p->k;
+    DevPlan P = p->dev;
+    P.slice_count = o.slice_count > 1 ? o.slice_count : 1;
+    P.slice_id = o.slice_count > 1 ? o.slice_id : 0;
+    if (P.slice_count > 1 && P.slice_id >= P.slice_count) HUGE_FAIL(HUGE_EINVAL, "slice_id >= slice_count");
+    if (o.slice_vertex < -2 || o.slice_vertex >= k) HUGE_FAIL(HUGE_EINVAL, "slice_vertex out of range");
+    const int sv = o.slice_vertex == -1 ? p->order[0] : o.slice_vertex;  // -2: edge slice, no vertex
+    for (int i = 0; i < k; ++i) P.st[i].slice = p->order[i] == sv ? 1 : 0;
+    P.edge_slice = (o.slice_vertex == -2 && P.slice_count > 1) ? 1 : 0;
+    return P;
+}
+
 int64_t read_i64(const void *dev, hipStream_t st) {
     int64_t v = 0;
     HUGE_HIP(hipMemcpyAsync(&v, dev, 8, hipMemcpyDeviceToHost, st));
@@ -192,14 +206,7 @@ bool run_levels(const huge_graph *g, const huge_plan *p, const huge_exec_opts &o
     auto t0 = std::chrono::steady_clock::now();
     hipStream_t st = (hipStream_t)o.stream;
     const int k = p->k;
-    DevPlan P = p->dev;
-    P.slice_count = o.slice_count > 1 ? o.slice_count : 1;
-    P.slice_id = o.slice_count > 1 ? o.slice_id : 0;
-    if (P.slice_count > 1 && P.slice_id >= P.slice_count) HUGE_FAIL(HUGE_EINVAL, "slice_id >= slice_count");
-    if (o.slice_vertex < -2 || o.slice_vertex >= k) HUGE_FAIL(HUGE_EINVAL, "slice_vertex out of range");
-    const int sv = o.slice_vertex == -1 ? p->order[0] : o.slice_vertex;  // -2: edge slice, no vertex
-    for (int i = 0; i < k; ++i) P.st[i].slice = p->order[i] == sv ? 1 : 0;
-    P.edge_slice = (o.slice_vertex == -2 && P.slice_count > 1) ? 1 : 0;
+    const DevPlan P = exec_plan(p, o);
 
     int64_t stage_rows = 0;
     if (emit) {
@@ -497,14 +504,7 @@ void run_graph(const huge_graph *g, const huge_plan *p, const huge_exec_opts &o_
     }
     const huge_exec_opts &o = o_in;
     hipStream_t st = (hipStream_t)o.stream;
-    DevPlan P = p->dev;
-    P.slice_count = o.slice_count > 1 ? o.slice_count : 1;
-    P.slice_id = o.slice_count > 1 ? o.slice_id : 0;
-    if (P.slice_count > 1 && P.slice_id >= P.slice_count) HUGE_FAIL(HUGE_EINVAL, "slice_id >= slice_count");
-    if (o.slice_vertex < -2 || o.slice_vertex >= k) HUGE_FAIL(HUGE_EINVAL, "slice_vertex out of range");
-    const int sv = o.slice_vertex == -1 ? p->order[0] : o.slice_vertex;
-    for (int i = 0; i < k; ++i) P.st[i].slice = p->order[i] == sv ? 1 : 0;
-    P.edge_slice = (o.slice_vertex == -2 && P.slice_count > 1) ? 1 : 0;
+    const DevPlan P = exec_plan(p, o);
     const bool root_slice = P.slice_count > 1 && P.st[0].slice;
 
     Layout L = make_layout(g, p, o, 0, scan_devn_max());  // segments within the device-count scan's limit
