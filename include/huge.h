@@ -258,7 +258,8 @@ huge_status huge_plan_prefix(const huge_plan *p, int32_t size, huge_plan **out);
 huge_status huge_plan_info(const huge_plan *p, int32_t *k, int32_t *order_out, int32_t *n_sb, int32_t *sb_pairs,
                            double *est_cost);
 
-/* Device workspace needed by huge_count / huge_enumerate for these options. */
+/* Device workspace needed by huge_count / huge_enumerate for these options
+ * (engine included: the graph engine also keeps its scheduler state there). */
 huge_status huge_workspace_size(const huge_graph *g, const huge_plan *p, const huge_exec_opts *opts,
                                 uint64_t *bytes);
 
