@@ -16,6 +16,7 @@
 // launches.  So the frontier never exceeds the configured capacity.
 #include <algorithm>
 #include <chrono>
+#include <cstddef>
 #include <cstring>
 
 #include "internal.h"
@@ -28,6 +29,8 @@ namespace {
 constexpr int64_t kDefaultSeg = 1 << 22;
 constexpr int64_t kMinQueueRows = 1 << 12;
 constexpr int64_t kMaxItems = 1ll << 30;
+constexpr int kSegTotalSlot = 7;  // Ctrl::scratch slot for the segment total (0..5: bucket bounds)
+static_assert(kSegTotalSlot > HUGE_TUNE_BUCKETS, "segment total must not overlap the bucket bounds");
 constexpr uint64_t kDefaultCap = 4ull << 30;
 
 inline int ext_count(const huge_plan *p, int W) { return __builtin_popcount(p->dev.st[W].ext); }
@@ -376,17 +379,22 @@ bool run_levels(const huge_graph *g, const huge_plan *p, const huge_exec_opts &o
                     }
                     l.seg_row0 = l.next;
                     l.seg_n = cnt;
-                    int64_t hv[2 + HUGE_TUNE_BUCKETS + 1] = {};
-                    HUGE_HIP(hipMemcpyAsync(&hv[0], l.s.off + cnt, 8, hipMemcpyDeviceToHost, st));
-                    HUGE_HIP(hipMemcpyAsync(&hv[1], &ctrl->segbytes[W], 8, hipMemcpyDeviceToHost, st));
-                    if (part)
-                        HUGE_HIP(hipMemcpyAsync(&hv[2], ctrl->scratch, 8 * (HUGE_TUNE_BUCKETS + 1),
-                                                hipMemcpyDeviceToHost, st));
+                    // one read-back per segment: the segment total goes next to the
+                    // bucket bounds (a device-side copy), then segbytes[W] .. scratch[]
+                    // come back in one copy
+                    HUGE_HIP(hipMemcpyAsync(&ctrl->scratch[kSegTotalSlot], l.s.off + cnt, 8, hipMemcpyDeviceToDevice,
+                                            st));
+                    const size_t first = offsetof(Ctrl, segbytes) + sizeof(unsigned long long) * W;
+                    unsigned char hb[sizeof(Ctrl)];
+                    HUGE_HIP(hipMemcpyAsync(hb, (const unsigned char *)ctrl + first, sizeof(Ctrl) - first,
+                                            hipMemcpyDeviceToHost, st));
                     HUGE_HIP(hipStreamSynchronize(st));
-                    l.seg_total = hv[0];
-                    level_work[W - 1] += (uint64_t)hv[0];
-                    l.seg_bytes = (double)(uint64_t)hv[1];
-                    for (int c = 0; c <= HUGE_TUNE_BUCKETS; ++c) l.bw[c] = part ? hv[2 + c] : 0;
+                    Ctrl hc;
+                    memcpy((unsigned char *)&hc + first, hb, sizeof(Ctrl) - first);
+                    l.seg_total = hc.scratch[kSegTotalSlot];
+                    level_work[W - 1] += (uint64_t)l.seg_total;
+                    l.seg_bytes = (double)hc.segbytes[W];
+                    for (int c = 0; c <= HUGE_TUNE_BUCKETS; ++c) l.bw[c] = part ? hc.scratch[c] : 0;
                     l.seg_done = 0;
                     l.next += cnt;
                     if (l.seg_total == 0) continue;
