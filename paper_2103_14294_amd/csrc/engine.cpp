@@ -129,12 +129,22 @@ DevPlan exec_plan(const huge_plan *p, const huge_exec_opts &o) {
     return P;
 }
 
-int64_t read_i64(const void *dev, hipStream_t st) {
-    int64_t v = 0;
-    HUGE_HIP(hipMemcpyAsync(&v, dev, 8, hipMemcpyDeviceToHost, st));
+// Pinned host memory for the scheduler's read-backs, one block per engine call:
+// a device-to-host copy lands there directly instead of through a staging copy.
+struct PinnedBuf {
+    unsigned char *p = nullptr;
+    explicit PinnedBuf(size_t bytes) { HUGE_HIP(hipHostMalloc((void **)&p, bytes, hipHostMallocDefault)); }
+    ~PinnedBuf() {
+        if (p) (void)hipHostFree(p);
+    }
+};
+
+int64_t read_i64(const void *dev, hipStream_t st, int64_t *pinned) {
+    HUGE_HIP(hipMemcpyAsync(pinned, dev, 8, hipMemcpyDeviceToHost, st));
     HUGE_HIP(hipStreamSynchronize(st));
-    return v;
+    return *pinned;
 }
+
 
 }  // namespace
 
@@ -218,6 +228,8 @@ bool run_levels(const huge_graph *g, const huge_plan *p, const huge_exec_opts &o
         stage_rows = std::min<int64_t>(emit->buf_rows, 1 << 22);
     }
     Layout L = make_layout(g, p, o, stage_rows);
+    PinnedBuf pinned(sizeof(Ctrl) + 64);
+    int64_t *pin64 = (int64_t *)(pinned.p + sizeof(Ctrl));
     DevMem own;
     char *ws = (char *)o.workspace;
     if (ws) {
@@ -327,7 +339,7 @@ bool run_levels(const huge_graph *g, const huge_plan *p, const huge_exec_opts &o
             for (int64_t e = 0; e < nnz && !emit->stopped; e += stage_rows) {
                 launch_edge_sink(G, P, e, std::min(nnz, e + stage_rows), MODE_OUTPUT, stage, g->inv_rank, ctrl, st);
                 stats.launches++;
-                int64_t nout = read_i64(&ctrl->qcount[HUGE_KMAX], st);
+                int64_t nout = read_i64(&ctrl->qcount[HUGE_KMAX], st, pin64);
                 deliver(nout);
                 HUGE_HIP(hipMemsetAsync(&ctrl->qcount[HUGE_KMAX], 0, 8, st));
             }
@@ -385,7 +397,7 @@ bool run_levels(const huge_graph *g, const huge_plan *p, const huge_exec_opts &o
                     HUGE_HIP(hipMemcpyAsync(&ctrl->scratch[kSegTotalSlot], l.s.off + cnt, 8, hipMemcpyDeviceToDevice,
                                             st));
                     const size_t first = offsetof(Ctrl, segbytes) + sizeof(unsigned long long) * W;
-                    unsigned char hb[sizeof(Ctrl)];
+                    unsigned char *hb = pinned.p;
                     HUGE_HIP(hipMemcpyAsync(hb, (const unsigned char *)ctrl + first, sizeof(Ctrl) - first,
                                             hipMemcpyDeviceToHost, st));
                     HUGE_HIP(hipStreamSynchronize(st));
@@ -415,7 +427,7 @@ bool run_levels(const huge_graph *g, const huge_plan *p, const huge_exec_opts &o
                         int64_t chunk = std::min(remaining, stage_rows);
                         extend_range(HUGE_KC_SINK, W, MODE_OUTPUT, l, l.seg_done, l.seg_done + chunk, stage);
                         l.seg_done += chunk;
-                        int64_t nout = read_i64(&ctrl->qcount[HUGE_KMAX], st);
+                        int64_t nout = read_i64(&ctrl->qcount[HUGE_KMAX], st, pin64);
                         deliver(nout);
                         HUGE_HIP(hipMemsetAsync(&ctrl->qcount[HUGE_KMAX], 0, 8, st));
                         if (emit->stopped) {
@@ -431,7 +443,7 @@ bool run_levels(const huge_graph *g, const huge_plan *p, const huge_exec_opts &o
                     extend_range(HUGE_KC_EXTEND, W, MODE_EMIT, l, l.seg_done, l.seg_done + chunk, q.q);
                     l.seg_done += chunk;
                     work_done += chunk;
-                    int64_t nr = read_i64(&ctrl->qcount[W + 1], st);
+                    int64_t nr = read_i64(&ctrl->qcount[W + 1], st, pin64);
                     prof.bytes[HUGE_KC_EXTEND] +=
                         l.seg_bytes * (double)chunk / (double)l.seg_total + 4.0 * (W + 1) * (double)(nr - q.nrows);
                     cur_bytes += (uint64_t)(nr - q.nrows) * 4ull * (W + 1);
