@@ -14,6 +14,11 @@
 // most `free` work items and a work item (one probe element) emits at most
 // one row.  A single hub row larger than the queue is simply split across
 // launches.  So the frontier never exceeds the configured capacity.
+//
+// Two drivers of the same scheduler live here: run_levels takes every
+// decision on the host (one read-back per segment and per emitting chunk);
+// run_graph (the graph engine, at the end of this file) takes them in a
+// one-thread device kernel and replays a recorded round of launches.
 #include <algorithm>
 #include <chrono>
 #include <cstddef>
