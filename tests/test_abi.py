@@ -88,3 +88,36 @@ def test_user_order_kept_and_default_is_first_connected(H):
     assert H.plan(None, k, e).info()["order"] == [0, 1, 2, 3, 4]
     k, e = P.NAMED["4-path"]
     assert H.plan(None, k, e).info()["order"] == [0, 1, 2, 3]
+
+
+def test_ctypes_mirrors_match_the_header_layout(H, tmp_path):
+    """Sizes and field offsets of every public struct, as a C compiler lays them
+    out from include/huge.h, equal those of the binding's ctypes mirrors."""
+    import shutil
+    import subprocess
+
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    mirrors = {"huge_result": H.Result, "huge_exec_opts": H.ExecOpts, "huge_tune_table": H.TuneTable,
+               "huge_graph_info": H.GraphInfo}
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "huge.h"', "int main(void) {"]
+    for cname, py in mirrors.items():
+        lines.append('printf("%s size %%zu\\n", sizeof(%s));' % (cname, cname))
+        for fname, _ in py._fields_:
+            lines.append('printf("%s %s %%zu\\n", offsetof(%s, %s));' % (cname, fname, cname, fname))
+    lines += ["return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run([cc, "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
+    got = {}
+    for line in out:
+        if line:
+            a, b, v = line.split()
+            got[(a, b)] = int(v)
+    for cname, py in mirrors.items():
+        assert got[(cname, "size")] == ctypes.sizeof(py), cname
+        for fname, _ in py._fields_:
+            assert got[(cname, fname)] == getattr(py, fname).offset, (cname, fname)
