@@ -218,7 +218,7 @@ def main():
     args = ap.parse_args()
 
     if args.gpus != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path (see the sharding design); "
+        print("bench.py measures one GPU only: the library has no multi-GPU path (see the sharding design); "
               "run with --gpus 1", file=sys.stderr)
         sys.exit(2)
 
