@@ -84,7 +84,7 @@ MODEL_PATH = os.path.join(ROOT, "paper_2103_14294_amd", "mlp_work.npz")
 # algorithmic bytes per launch (bytes_per_launch: the profiled run's own figure).  Valid
 # for the kernel and graph-load sources (hub bitmaps change the traffic) whose digest is
 # given; null for any other sources or workload.
-TRAFFIC = {"c2": {"sources_sha256_16": "eb337fb25943d4b7", "bytes_per_launch": 3.079e9,
+TRAFFIC = {"c2": {"sources_sha256_16": "e659cd17d4841fef", "bytes_per_launch": 3.079e9,
                   "per_alg_byte": 0.3166}}
 KERNEL_SOURCES = ["paper_2103_14294_amd/csrc/extend.hip", "paper_2103_14294_amd/csrc/devfuncs.h",
                   "paper_2103_14294_amd/csrc/graph.hip"]
