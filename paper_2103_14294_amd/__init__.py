@@ -548,8 +548,9 @@ def count_batch(g: Graph, plans, **kw):
 
 
 def enumerate_matches(g: Graph, p: Plan, buf_rows=1 << 16, callback=None, **kw):
-    """huge_enumerate.  With callback None, returns all rows as an (N, k) array
-    (query-vertex order, original IDs).  Otherwise callback(rows) -> bool stop."""
+    """huge_enumerate.  Returns the result dict; with callback None it also holds
+    every match under "rows", an (N, k) int32 array (query-vertex order, original
+    IDs).  Otherwise callback(rows) is called per buffer and a true return stops."""
     lib = load_library()
     opts = exec_opts(**kw)
     buf = np.empty((int(buf_rows), p.k), dtype=np.int32)
