@@ -509,7 +509,16 @@ struct GraphRes {
     ~GraphRes() {
         if (exec) (void)hipGraphExecDestroy(exec);
         if (graph) (void)hipGraphDestroy(graph);
-        if (cs) (void)hipStreamDestroy(cs);
+        if (cs) {
+            // an error while recording leaves the stream capturing: close that first
+            hipStreamCaptureStatus status = hipStreamCaptureStatusNone;
+            if (hipStreamIsCapturing(cs, &status) == hipSuccess && status != hipStreamCaptureStatusNone) {
+                hipGraph_t partial = nullptr;
+                (void)hipStreamEndCapture(cs, &partial);
+                if (partial) (void)hipGraphDestroy(partial);
+            }
+            (void)hipStreamDestroy(cs);
+        }
     }
 };
 }  // namespace
