@@ -282,16 +282,11 @@ static void gg_rmat_body(void *arg, int64_t lo, int64_t hi) {
         uint32_t u = 0, v = 0;
         for (int l = 0; l < c->scale; ++l) {
             uint32_t x = gg_u32(&r);
-            uint32_t ub = 0, vb = 0;
-            if (x < c->ta) {
-            } else if (x < c->tab) {
-                vb = 1;
-            } else if (x < c->tabc) {
-                ub = 1;
-            } else {
-                ub = 1;
-                vb = 1;
-            }
+            /* quadrant of x: [0,a) top-left, [a,a+b) top-right, [a+b,a+b+c)
+               bottom-left, rest bottom-right; computed without branches (the
+               quadrant is unpredictable, so branches cost more than the draws) */
+            const uint32_t s1 = x >= c->ta, s2 = x >= c->tab, s3 = x >= c->tabc;
+            const uint32_t ub = s2, vb = s1 ^ s2 ^ s3;
             u = (u << 1) | ub;
             v = (v << 1) | vb;
         }

@@ -158,9 +158,9 @@ typedef struct {
     int32_t strategy;            /* HUGE_STRAT_*; HUGE_STRAT_AUTO = per the tune table, else lane merge */
     int32_t engine;              /* HUGE_ENGINE_* */
     int32_t work_stealing;       /* persistent engine: 1 = steal, 0 = static root split only */
-    int32_t deterministic;       /* reserved: results are exact and order-free either way */
+    int32_t reserved0;           /* must be 0 */
     uint32_t slice_count;        /* root slice: keep matches with mix(rank(f(s))) % slice_count == slice_id, */
-    uint32_t slice_id;           /* s = slice_vertex; slice_count 0 or 1 = everything */
+    uint32_t slice_id;           /* s = slice_vertex; slice_count 0 or 1 = everything (see slice_mode) */
     void *stream;                /* hipStream_t; NULL = the null stream */
     void *workspace;             /* caller-owned device memory, or NULL = library allocates */
     uint64_t workspace_bytes;
@@ -172,12 +172,33 @@ typedef struct {
                                     any fixed vertex, or edge slices of one plan, partition the matches,
                                     so counts add and hashes add / xor */
     uint32_t exec_flags;         /* HUGE_EXEC_* bits */
-    uint32_t reserved;
+    uint32_t slice_mode;         /* vertex slices (slice_vertex >= -1 and the second slice):
+                                    HUGE_SLICE_MIX keeps mix(rank) % count == id, HUGE_SLICE_STRIDE keeps
+                                    rank % count == id: every count-th vertex in degree order, so every
+                                    slice holds the same share of each degree class.  A strided slice of
+                                    the plan's first matched vertex (slice_vertex -1, or the vertex in
+                                    order[0]) reads only the edge-array entries of the slice's vertices:
+                                    the level engine and the graph engine gather them into the workspace
+                                    first (about 8 * (nnz / count + max degree) bytes) instead of
+                                    scanning every entry.  The persistent engine takes HUGE_SLICE_MIX
+                                    only. */
     const huge_tune_table *tune; /* per-bucket dispatch table, or NULL (read during the call only) */
     int64_t work_limit;          /* huge_count on the level engine: stop with HUGE_STOPPED once more than this
                                     many candidates were examined (the result then covers part of the work
                                     only); 0 = no limit */
+    int32_t slice2_vertex;       /* a second vertex slice, applied with the first: keep the matches whose
+                                    query vertex slice2_vertex has its image in slice slice2_id of
+                                    slice2_count (same slice_mode); slice2_count 0 or 1 = none.  Two plans
+                                    with different first vertices a and b can then run the same sample:
+                                    (a, s1 of S1) and (b, s2 of S2) in either role select the same
+                                    matches, and each plan still reads only its own slice's entries.
+                                    Not on the persistent engine. */
+    uint32_t slice2_count;
+    uint32_t slice2_id;
+    int32_t reserved1;           /* must be 0 */
 } huge_exec_opts;
+#define HUGE_SLICE_MIX 0u
+#define HUGE_SLICE_STRIDE 1u
 #define HUGE_EXEC_NO_HASH 0x1u /* count only: hash_sum / hash_xor are left 0 */
 
 /* Default options: frontier cap 4 GiB, autotuned chunk and strategy, AUTO engine, no slice. */
@@ -285,7 +306,30 @@ huge_status huge_enumerate(const huge_graph *g, const huge_plan *p, const huge_e
                            int64_t buf_rows, huge_emit_fn cb, void *user, huge_result *out);
 
 /*
- * huge_count_batch -- count np queries; outs[np], in the order of plans.
+ * huge_count_batch -- count np queries (the batching of Section 4.2, and
+ * Section 5.3's sharing of the workers between queries); outs[np], in the
+ * order of plans.  Results equal np separate huge_count calls bit for bit.
+ *
+ * engine GRAPH (batched rounds): every query keeps its own Algorithm 5 state,
+ * queues (an equal share of frontier_cap_bytes) and segment buffers on the
+ * device.  One round advances every query by one action (a one-workgroup
+ * scheduler launch, one thread per query), then runs one prepare launch, one
+ * batched bounds scan and one extend launch per (level, last level or not)
+ * for all queries together: their workgroups claim tiles in order across the
+ * queries, so many small queries fill the chip together.  Rounds are recorded
+ * once in a hipGraph and replayed on opts->stream until no query is active.
+ * Queries of 2 vertices run first on the level engine.  At most 256 queries
+ * share a round (larger batches run 256 at a time).  Strategy: a fixed
+ * lane-merge strategy (2..6; 0 and 1 give HUGE_EINVAL), or AUTO: per extend
+ * launch the lane merge the tune table gives most work to at the Ext sizes of
+ * the queries of that launch (searches count as HUGE_STRAT_MERGE_SHORT),
+ * without a table HUGE_STRAT_BLOCK_MERGE_LONG for last levels and
+ * HUGE_STRAT_BLOCK_MERGE otherwise; segments hold chunk_rows rows (default
+ * 2^20, or the table's, at most 2^20).  work_limit must be 0.  Workspace:
+ * opts->workspace when it holds huge_batch_workspace_size bytes, else
+ * allocated for the call.  Each result's query_ms is the whole batch's wall
+ * time and launches counts graph launches.
+ *
  * engine AUTO or LEVELS: a few host workers (environment variable
  * HUGE_BATCH_STREAMS, default 4), each with its own HIP stream, workspace
  * (sized for the largest query; opts->workspace is not used; kept allocated
@@ -295,12 +339,15 @@ huge_status huge_enumerate(const huge_graph *g, const huge_plan *p, const huge_e
  * batch calls on one device take turns.  engine PERSISTENT: the queries of
  * 3..HUGE_PERSIST_KMAX vertices run in one persistent launch (they share the
  * workgroups, the frontier budget and the stealing pool, Section 5.3), the
- * others on the level engine one after another on opts->stream.  engine
- * GRAPH: the queries run one after another on opts->stream, each through
- * its own recorded round.
+ * others on the level engine one after another on opts->stream.
  */
 huge_status huge_count_batch(const huge_graph *g, const huge_plan *const *plans, int32_t np,
                              const huge_exec_opts *opts, huge_result *outs);
+
+/* Device workspace huge_count_batch needs on the graph engine for these plans
+ * and options (HUGE_EINVAL for another engine). */
+huge_status huge_batch_workspace_size(const huge_graph *g, const huge_plan *const *plans, int32_t np,
+                                      const huge_exec_opts *opts, uint64_t *bytes);
 
 /* ------------------------------------------------------------------------
  * Learned cost model.  The optimiser of Section 3.3 (Algorithm 1) ranks

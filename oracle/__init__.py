@@ -67,7 +67,8 @@ def _load():
         ci = ctypes.c_int
         lib.orc_enumerate.restype = ci
         lib.orc_enumerate.argtypes = [i64, vp, vp, ci, ci, vp, ci, vp, ci, vp, ctypes.c_uint32, ctypes.c_uint32,
-                                      ci, ci, ci, ctypes.POINTER(_Result)]
+                                      ci, ci, ci, ci, ctypes.c_uint32, ctypes.c_uint32, ci,
+                                      ctypes.POINTER(_Result)]
         lib.orc_automorphisms.restype = ci
         lib.orc_automorphisms.argtypes = [ci, ci, vp, vp, ci]
         lib.orc_sb_pairs.restype = ci
@@ -88,11 +89,13 @@ def _qarr(qedges):
 
 
 def enumerate_query(row_ptr, col, k, qedges, mode=MODE_SB, order=None, sb_pairs=None, slice_count=1,
-                    slice_id=0, threads=0, slice_vertex=0, slice_pair=None):
+                    slice_id=0, threads=0, slice_vertex=0, slice_pair=None, slice_mode=0, slice2=None):
     """Run the C enumerator.  Returns a dict with count, hash_sum, hash_xor and
     level_counts (list of KMAX ints; entry d counts partial maps of the first
     d+1 vertices of the order used).  slice_pair=(a, b) slices on the ordered
-    pair of images (r(f(a)), r(f(b))) instead of one vertex."""
+    pair of images (r(f(a)), r(f(b))) instead of one vertex.  slice_mode=1
+    makes vertex slices strided (rank mod S) instead of mixed; slice2=(c, S2,
+    s2) adds a second vertex slice on query vertex c."""
     lib = _load()
     rp = np.ascontiguousarray(row_ptr, dtype=np.int64)
     cl = np.ascontiguousarray(col, dtype=np.int32)
@@ -112,7 +115,9 @@ def enumerate_query(row_ptr, col, k, qedges, mode=MODE_SB, order=None, sb_pairs=
                            e.ctypes.data, int(mode), None if o is None else o.ctypes.data, nsb,
                            None if sbp is None else sbp.ctypes.data, int(slice_count), int(slice_id),
                            int(slice_pair[0] if slice_pair else slice_vertex),
-                           int(slice_pair[1] if slice_pair else -1), int(threads), ctypes.byref(r))
+                           int(slice_pair[1] if slice_pair else -1), int(slice_mode),
+                           int(slice2[0]) if slice2 else -1, int(slice2[1]) if slice2 else 1,
+                           int(slice2[2]) if slice2 else 0, int(threads), ctypes.byref(r))
     if st != 0:
         raise ValueError("oracle rejected the query or order")
     return {"count": int(r.count), "hash_sum": int(r.hash_sum), "hash_xor": int(r.hash_xor),

@@ -57,6 +57,10 @@
  * mix(r(f(a)) * 2^32 + r(f(b))) mod S == s are kept, checked when the later
  * of a and b is matched; slices of a fixed ordered pair also partition the
  * results.
+ *
+ * Strided slices (slice_mode 1): a vertex slice keeps r(f(a)) mod S == s
+ * instead of the mix.  A second vertex slice (vertex c, count S2, id s2, same
+ * mode) can be applied on top of the first: only maps in both are kept.
  */
 #include <pthread.h>
 #include <stdint.h>
@@ -275,10 +279,20 @@ typedef struct {
     uint32_t slice_count, slice_id;
     int slice_pos;              /* position of the sliced query vertex */
     int pair_a, pair_b;         /* pair slice: positions of the two query vertices, or -1 */
+    int slice_mode;             /* vertex slices: 0 by mix of the rank, 1 by the rank itself */
+    uint32_t slice2_count, slice2_id;
+    int slice2_pos;             /* position of the second sliced query vertex, or -1 */
 } orc_plan;
 
+/* rank r in slice id of count (vertex slices) */
+static int orc_in_vslice(int32_t r, uint32_t count, uint32_t id, int mode) {
+    uint64_t x = mode ? (uint64_t)(uint32_t)r : orc_mix((uint64_t)(uint32_t)r);
+    return x % count == id;
+}
+
 static int orc_plan_init(orc_plan *P, const orc_query *q, const orc_graph *g, int mode,
-                         const int32_t *order, uint32_t sc, uint32_t sid, int slice_vertex, int slice_vertex2) {
+                         const int32_t *order, uint32_t sc, uint32_t sid, int slice_vertex, int slice_vertex2,
+                         int slice_mode, int slice2_vertex, uint32_t sc2, uint32_t sid2) {
     memset(P, 0, sizeof(*P));
     P->q = q;
     P->g = g;
@@ -336,7 +350,27 @@ static int orc_plan_init(orc_plan *P, const orc_query *q, const orc_graph *g, in
         P->pair_b = P->pos[slice_vertex2];
         P->slice_pos = -1; /* no vertex slice */
     }
+    if (slice_mode != 0 && slice_mode != 1) return -1;
+    P->slice_mode = slice_mode;
+    P->slice2_count = sc2 > 1 ? sc2 : 1;
+    P->slice2_id = sc2 > 1 ? sid2 : 0;
+    P->slice2_pos = -1;
+    if (P->slice2_count > 1) {
+        if (slice2_vertex < 0 || slice2_vertex >= k || P->slice2_id >= P->slice2_count) return -1;
+        P->slice2_pos = P->pos[slice2_vertex];
+    }
     return 0;
+}
+
+/* the vertex slices that apply at position i to the vertex of rank r */
+static int orc_slices_ok(const orc_plan *P, int i, int32_t r) {
+    if (P->slice_count > 1 && i == P->slice_pos &&
+        !orc_in_vslice(r, P->slice_count, P->slice_id, P->slice_mode))
+        return 0;
+    if (P->slice2_count > 1 && i == P->slice2_pos &&
+        !orc_in_vslice(r, P->slice2_count, P->slice2_id, P->slice_mode))
+        return 0;
+    return 1;
 }
 
 typedef struct {
@@ -387,8 +421,7 @@ static int orc_accept(orc_worker *w, int i, int32_t c) {
         if (!(g->rank[w->f[P->lt[i][t]]] < rc)) return 0;
     for (int t = 0; t < P->ngt[i]; ++t)
         if (!(rc < g->rank[w->f[P->gt[i][t]]])) return 0;
-    if (P->slice_count > 1 && i == P->slice_pos)
-        if (orc_mix((uint64_t)(uint32_t)rc) % P->slice_count != P->slice_id) return 0;
+    if (!orc_slices_ok(P, i, rc)) return 0;
     if (P->slice_count > 1 && P->pair_a >= 0 && i == (P->pair_a > P->pair_b ? P->pair_a : P->pair_b)) {
         uint32_t ra = (uint32_t)(i == P->pair_a ? rc : g->rank[w->f[P->pair_a]]);
         uint32_t rb = (uint32_t)(i == P->pair_b ? rc : g->rank[w->f[P->pair_b]]);
@@ -433,9 +466,7 @@ static void *orc_thread(void *arg) {
         if (lo >= a->n) break;
         int64_t hi = lo + a->chunk < a->n ? lo + a->chunk : a->n;
         for (int64_t u = lo; u < hi; ++u) {
-            if (P->slice_count > 1 && P->slice_pos == 0 &&
-                orc_mix((uint64_t)(uint32_t)P->g->rank[u]) % P->slice_count != P->slice_id)
-                continue;
+            if (!orc_slices_ok(P, 0, P->g->rank[u])) continue;
             w.res.level_counts[0]++;
             w.f[0] = (int32_t)u;
             orc_search(&w, 1);
@@ -456,8 +487,8 @@ static void *orc_thread(void *arg) {
 int orc_enumerate(int64_t n, const int64_t *rp, const int32_t *col, int k, int nqe,
                   const int32_t *qedges, int mode, const int32_t *order, int nsb,
                   const int32_t *sb_pairs, uint32_t slice_count, uint32_t slice_id, int slice_vertex,
-                  int slice_vertex2, int nthreads,
-                  orc_result *out) {
+                  int slice_vertex2, int slice_mode, int slice2_vertex, uint32_t slice2_count,
+                  uint32_t slice2_id, int nthreads, orc_result *out) {
     orc_query q;
     if (orc_query_init(&q, k, nqe, qedges) != 0) return -1;
     orc_query_aut(&q);
@@ -485,7 +516,8 @@ int orc_enumerate(int64_t n, const int64_t *rp, const int32_t *col, int k, int n
     g.rank = (int32_t *)malloc(sizeof(int32_t) * (size_t)(n > 0 ? n : 1));
     orc_ranks(n, rp, g.rank);
     orc_plan P;
-    if (orc_plan_init(&P, &q, &g, mode, order, slice_count, slice_id, slice_vertex, slice_vertex2) != 0) {
+    if (orc_plan_init(&P, &q, &g, mode, order, slice_count, slice_id, slice_vertex, slice_vertex2, slice_mode,
+                      slice2_vertex, slice2_count, slice2_id) != 0) {
         free(g.rank);
         free(q.aut);
         return -1;

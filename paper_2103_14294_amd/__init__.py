@@ -24,6 +24,7 @@ HOST_PTRS, DEVICE_PTRS, NO_VALIDATE, NO_HUB_BITMAP = 0x1, 0x2, 0x4, 0x8
 PLAN_COST_MODEL, PLAN_LEARNED, PLAN_VERIFY = 0x0, 0x1, 0x2
 ENGINE_AUTO, ENGINE_LEVELS, ENGINE_PERSISTENT, ENGINE_GRAPH = 0, 1, 2, 3
 EXEC_NO_HASH = 0x1
+SLICE_MIX, SLICE_STRIDE = 0, 1
 STRAT_BSEARCH, STRAT_WAVE_STAGED, STRAT_LANE_MERGE, STRAT_MERGE_SHORT, STRAT_MERGE_LONG = 0, 1, 2, 3, 4
 STRAT_BLOCK_MERGE, STRAT_BLOCK_MERGE_LONG = 5, 6
 STRAT_COUNT = 7
@@ -35,6 +36,7 @@ EXPORTED = [
     "huge_model_create", "huge_model_free", "huge_model_set", "huge_model_get", "huge_model_forward",
     "huge_model_grad", "huge_model_train", "huge_plan_features", "huge_plan_create_learned",
     "huge_autotune", "huge_graph_digest", "huge_plan_prefix", "huge_plan_create_learned2", "huge_device_name",
+    "huge_batch_workspace_size",
 ]
 MLP_F, MLP_H = 128, 256
 MLP_PARAMS = MLP_F * MLP_H + 2 * MLP_H + 1
@@ -68,10 +70,12 @@ class Result(ctypes.Structure):
 class ExecOpts(ctypes.Structure):
     _fields_ = [("frontier_cap_bytes", ctypes.c_uint64), ("chunk_rows", ctypes.c_int64),
                 ("strategy", ctypes.c_int32), ("engine", ctypes.c_int32), ("work_stealing", ctypes.c_int32),
-                ("deterministic", ctypes.c_int32), ("slice_count", ctypes.c_uint32), ("slice_id", ctypes.c_uint32),
+                ("reserved0", ctypes.c_int32), ("slice_count", ctypes.c_uint32), ("slice_id", ctypes.c_uint32),
                 ("stream", ctypes.c_void_p), ("workspace", ctypes.c_void_p), ("workspace_bytes", ctypes.c_uint64),
                 ("profile", ctypes.c_int32), ("slice_vertex", ctypes.c_int32), ("exec_flags", ctypes.c_uint32),
-                ("reserved", ctypes.c_uint32), ("tune", ctypes.c_void_p), ("work_limit", ctypes.c_int64)]
+                ("slice_mode", ctypes.c_uint32), ("tune", ctypes.c_void_p), ("work_limit", ctypes.c_int64),
+                ("slice2_vertex", ctypes.c_int32), ("slice2_count", ctypes.c_uint32), ("slice2_id", ctypes.c_uint32),
+                ("reserved1", ctypes.c_int32)]
 
 
 TUNE_BUCKETS = 5
@@ -149,6 +153,9 @@ def load_library(path: str = LIB_PATH):
         lib.huge_enumerate.argtypes = [vp, vp, ctypes.POINTER(ExecOpts), vp, i64, EMIT_FN, vp, ctypes.POINTER(Result)]
         lib.huge_count_batch.restype = st
         lib.huge_count_batch.argtypes = [vp, ctypes.POINTER(vp), i32, ctypes.POINTER(ExecOpts), ctypes.POINTER(Result)]
+        lib.huge_batch_workspace_size.restype = st
+        lib.huge_batch_workspace_size.argtypes = [vp, ctypes.POINTER(vp), i32, ctypes.POINTER(ExecOpts),
+                                                  ctypes.POINTER(ctypes.c_uint64)]
         lib.huge_last_error.restype = ctypes.c_char_p
         lib.huge_last_error.argtypes = []
         f32, f64 = ctypes.c_float, ctypes.c_double
@@ -422,7 +429,8 @@ class Model:
 
 def exec_opts(cap=None, chunk_rows=0, strategy=-1, engine=ENGINE_AUTO, work_stealing=1, slice_count=1, slice_id=0,
               stream=None, workspace=None, profile=False, slice_vertex=0, hash=True, tune=None,
-              work_limit=0) -> ExecOpts:
+              work_limit=0, slice_mode=SLICE_MIX, slice2=None) -> ExecOpts:
+    """huge_exec_opts from keywords; slice2=(query vertex, count, id) is the second vertex slice."""
     lib = load_library()
     o = ExecOpts()
     lib.huge_exec_opts_default(ctypes.byref(o))
@@ -438,6 +446,9 @@ def exec_opts(cap=None, chunk_rows=0, strategy=-1, engine=ENGINE_AUTO, work_stea
     o.slice_vertex = int(slice_vertex)
     o.exec_flags = 0 if hash else EXEC_NO_HASH
     o.work_limit = int(work_limit)
+    o.slice_mode = int(slice_mode)
+    if slice2 is not None:
+        o.slice2_vertex, o.slice2_count, o.slice2_id = int(slice2[0]), int(slice2[1]), int(slice2[2])
     if tune is not None:
         o.tune = ctypes.cast(ctypes.byref(tune), ctypes.c_void_p)
     o.stream = (stream if stream is not None else _current_stream()).value \
@@ -538,10 +549,17 @@ def autotune(g: Graph, plans, cache=None, **kw) -> TuneTable:
     return t
 
 
-def count_batch(g: Graph, plans, **kw):
+def count_batch(g: Graph, plans, workspace: Workspace | None = None, **kw):
+    """huge_count_batch; with engine=ENGINE_GRAPH a Workspace holds the batch's device memory."""
     lib = load_library()
     opts = exec_opts(**kw)
     arr = (ctypes.c_void_p * len(plans))(*[p.handle.value for p in plans])
+    if workspace is not None and opts.engine == ENGINE_GRAPH:
+        b = ctypes.c_uint64()
+        _check(lib.huge_batch_workspace_size(g.handle, arr, len(plans), ctypes.byref(opts), ctypes.byref(b)))
+        ws = workspace.get(int(b.value))
+        opts.workspace = ws.data_ptr()
+        opts.workspace_bytes = ws.numel()
     res = (Result * len(plans))()
     _check(lib.huge_count_batch(g.handle, arr, len(plans), ctypes.byref(opts), res))
     return [r.to_dict() for r in res]

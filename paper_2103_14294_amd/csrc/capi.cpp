@@ -197,8 +197,9 @@ huge_status huge_count_batch(const huge_graph *g, const huge_plan *const *plans,
             if (!plans[i]) HUGE_FAIL(HUGE_EINVAL, "plan %d is NULL", i);
         huge_exec_opts o = resolve_opts(opts);
         std::vector<huge_result> r(np);
-        if (o.engine == HUGE_ENGINE_GRAPH) {  // one query after another, each through its own graph
-            for (int i = 0; i < np; ++i) run_graph(g, plans[i], o, &r[i]);
+        if (o.engine == HUGE_ENGINE_GRAPH) {  // batched rounds, kMaxBatch queries at a time
+            for (int i = 0; i < np; i += kMaxBatch)
+                run_mgraph(g, plans + i, std::min(kMaxBatch, np - i), o, r.data() + i);
             for (int i = 0; i < np; ++i) outs[i] = r[i];
             return HUGE_OK;
         }
@@ -227,6 +228,22 @@ huge_status huge_count_batch(const huge_graph *g, const huge_plan *const *plans,
         for (int i = 0; i < np; ++i)
             if (!(plans[i]->k >= 3 && plans[i]->k <= HUGE_PERSIST_KMAX)) run_levels(g, plans[i], lo, &r[i], nullptr);
         for (int i = 0; i < np; ++i) outs[i] = r[i];
+        return HUGE_OK;
+    });
+}
+
+huge_status huge_batch_workspace_size(const huge_graph *g, const huge_plan *const *plans, int32_t np,
+                                      const huge_exec_opts *opts, uint64_t *bytes) {
+    return guard([&] {
+        if (!g || !plans || np <= 0 || !bytes) HUGE_FAIL(HUGE_EINVAL, "bad arguments");
+        for (int i = 0; i < np; ++i)
+            if (!plans[i]) HUGE_FAIL(HUGE_EINVAL, "plan %d is NULL", i);
+        huge_exec_opts o = resolve_opts(opts);
+        if (o.engine != HUGE_ENGINE_GRAPH) HUGE_FAIL(HUGE_EINVAL, "a batch workspace is for HUGE_ENGINE_GRAPH");
+        uint64_t b = 0;
+        for (int i = 0; i < np; i += kMaxBatch)
+            b = std::max(b, mgraph_workspace_bytes(g, plans + i, std::min(kMaxBatch, np - i), o));
+        *bytes = b;
         return HUGE_OK;
     });
 }

@@ -55,34 +55,45 @@ template <int W>
 __device__ __forceinline__ void load_row(const int32_t *__restrict__ rows, const GraphDev &g, int64_t r,
                                          int32_t (&f)[W]) {
     if constexpr (W == 2) {
-        f[0] = g.src[r];
-        f[1] = g.col[r];
+        const int64_t e = g.l2_idx ? g.l2_idx[r] : r;
+        f[0] = g.src[e];
+        f[1] = g.col[e];
     } else {
 #pragma unroll
         for (int p = 0; p < W; ++p) f[p] = rows[r * W + p];
     }
 }
 
+// v (a rank) in slice `id` of `count`: by its mix, or by its position in
+// degree order (every count-th vertex)
+__device__ __forceinline__ bool in_vslice(int32_t v, uint32_t count, uint32_t id, int32_t mode) {
+    if (mode) return (uint32_t)v % count == id;
+    return (uint32_t)(mix64((uint64_t)(uint32_t)v) % count) == id;
+}
 __device__ __forceinline__ bool in_slice(int32_t v, const DevPlan &P) {
-    return (uint32_t)(mix64((uint64_t)(uint32_t)v) % P.slice_count) == P.slice_id;
+    return in_vslice(v, P.slice_count, P.slice_id, P.slice_mode);
+}
+// the vertex slices marked in `bits` (DevStep::slice: bit 0 the slice, bit 1
+// the second slice) that apply to v
+__device__ __forceinline__ bool slices_ok(int32_t bits, int32_t v, const DevPlan &P) {
+    bool ok = true;
+    if ((bits & 1) && P.slice_count > 1 && !P.edge_slice) ok &= in_slice(v, P);
+    if ((bits & 2) && P.slice2_count > 1) ok &= in_vslice(v, P.slice2_count, P.slice2_id, P.slice_mode);
+    return ok;
 }
 
 // Validity of a level-2 row (the SCAN of the first query edge): the
-// constraint between positions 0 and 1, and the slice (of the row's ordered
+// constraint between positions 0 and 1, and the slices (of the row's ordered
 // pair, or of the vertex in position 0 or 1).
 __device__ __forceinline__ bool level2_ok(const int32_t (&f)[2], const DevPlan &P) {
     const DevStep &s1 = P.st[1];
     if ((s1.lo & 1u) && !(f[0] < f[1])) return false;
     if ((s1.hi & 1u) && !(f[1] < f[0])) return false;
-    if (P.slice_count > 1) {
-        if (P.edge_slice) {
-            const uint64_t key = ((uint64_t)(uint32_t)f[0] << 32) | (uint64_t)(uint32_t)f[1];
-            return (uint32_t)(mix64(key) % P.slice_count) == P.slice_id;
-        }
-        if (P.st[0].slice && !in_slice(f[0], P)) return false;
-        if (s1.slice && !in_slice(f[1], P)) return false;
+    if (P.slice_count > 1 && P.edge_slice) {
+        const uint64_t key = ((uint64_t)(uint32_t)f[0] << 32) | (uint64_t)(uint32_t)f[1];
+        if ((uint32_t)(mix64(key) % P.slice_count) != P.slice_id) return false;
     }
-    return true;
+    return slices_ok(P.st[0].slice, f[0], P) && slices_ok(s1.slice, f[1], P);
 }
 
 __device__ __forceinline__ unsigned long long wave_sum_u64(unsigned long long x) {

@@ -44,6 +44,7 @@ inline int ext_count(const huge_plan *p, int W) { return __builtin_popcount(p->d
 inline bool partitioned(const huge_exec_opts &o) { return o.tune && (o.strategy < 0 || o.strategy >= STRAT_COUNT); }
 
 struct Layout {
+    int64_t l2_rows = 0, l2_roots = 0;  // gathered level 2 (strided slice of the first vertex): bound, roots
     int64_t seg_cap[HUGE_KMAX] = {};
     int64_t q_cap[HUGE_KMAX + 1] = {};
     int64_t stage_rows = 0;
@@ -57,6 +58,12 @@ Layout make_layout(const huge_graph *g, const huge_plan *p, const huge_exec_opts
                    int64_t seg_limit = INT64_MAX) {
     Layout L;
     const int k = p->k;
+    const DevPlan P = exec_plan(p, o);
+    if (gathers_level2(P)) {
+        L.l2_roots = gathered_roots(g, P);
+        L.l2_rows = gathered_rows_bound(g, P);
+    }
+    const int64_t l2_all = L.l2_rows ? L.l2_rows : g->dev.nnz;
     int64_t seg = o.chunk_rows > 0 ? o.chunk_rows : kDefaultSeg;
     const int nq = std::max(0, k - 3);
     uint64_t cap = o.frontier_cap_bytes;
@@ -76,15 +83,16 @@ Layout make_layout(const huge_graph *g, const huge_plan *p, const huge_exec_opts
         }
         return std::min(seg, seg_limit);
     };
-    L.seg_cap[2] = std::min<int64_t>(seg_for(2), std::max<int64_t>(1, g->dev.nnz));
+    L.seg_cap[2] = std::min<int64_t>(seg_for(2), std::max<int64_t>(1, l2_all));
     for (int w = 3; w <= k - 1; ++w) L.seg_cap[w] = std::min<int64_t>(seg_for(w), L.q_cap[w]);
     L.stage_rows = stage_rows;
     int64_t maxseg = 1;
     for (int w = 2; w <= k - 1; ++w) maxseg = std::max(maxseg, L.seg_cap[w]);
     const bool part = partitioned(o);
     const int64_t maxblk = (maxseg + 255) / 256;
-    L.scan_tmp = scan_tmp_elems(std::max(maxseg + 1, HUGE_TUNE_BUCKETS * maxblk + 1));
+    L.scan_tmp = scan_tmp_elems(std::max(std::max(maxseg + 1, HUGE_TUNE_BUCKETS * maxblk + 1), L.l2_roots + 1));
     uint64_t t = align_up(sizeof(Ctrl));
+    if (L.l2_rows) t += align_up(8ull * L.l2_rows) + align_up(4ull * L.l2_roots) + align_up(8ull * (L.l2_roots + 1));
     if (k >= 3)
         for (int w = 2; w <= k - 1; ++w) {
             int64_t c = L.seg_cap[w];
@@ -120,19 +128,55 @@ struct DevMem {
     }
 };
 
+}  // namespace
+
 // The plan as one execution sees it: the slice options of o applied to its steps.
 DevPlan exec_plan(const huge_plan *p, const huge_exec_opts &o) {
     const int k = p->k;
     DevPlan P = p->dev;
+    if (o.reserved0 || o.reserved1) HUGE_FAIL(HUGE_EINVAL, "reserved option fields must be 0");
+    if (o.slice_mode > HUGE_SLICE_STRIDE) HUGE_FAIL(HUGE_EINVAL, "unknown slice_mode %u", o.slice_mode);
     P.slice_count = o.slice_count > 1 ? o.slice_count : 1;
     P.slice_id = o.slice_count > 1 ? o.slice_id : 0;
     if (P.slice_count > 1 && P.slice_id >= P.slice_count) HUGE_FAIL(HUGE_EINVAL, "slice_id >= slice_count");
     if (o.slice_vertex < -2 || o.slice_vertex >= k) HUGE_FAIL(HUGE_EINVAL, "slice_vertex out of range");
+    P.slice_mode = (int32_t)o.slice_mode;
+    P.slice2_count = o.slice2_count > 1 ? o.slice2_count : 1;
+    P.slice2_id = o.slice2_count > 1 ? o.slice2_id : 0;
+    if (P.slice2_count > 1) {
+        if (P.slice2_id >= P.slice2_count) HUGE_FAIL(HUGE_EINVAL, "slice2_id >= slice2_count");
+        if (o.slice2_vertex < 0 || o.slice2_vertex >= k) HUGE_FAIL(HUGE_EINVAL, "slice2_vertex out of range");
+    }
     const int sv = o.slice_vertex == -1 ? p->order[0] : o.slice_vertex;  // -2: edge slice, no vertex
-    for (int i = 0; i < k; ++i) P.st[i].slice = p->order[i] == sv ? 1 : 0;
+    for (int i = 0; i < k; ++i)
+        P.st[i].slice = (p->order[i] == sv ? 1 : 0) | (P.slice2_count > 1 && p->order[i] == o.slice2_vertex ? 2 : 0);
     P.edge_slice = (o.slice_vertex == -2 && P.slice_count > 1) ? 1 : 0;
+    if (P.edge_slice && o.slice_mode != HUGE_SLICE_MIX) HUGE_FAIL(HUGE_EINVAL, "edge slices are mixed slices");
     return P;
 }
+
+// level_counts[0] counts the roots in the slices that apply to position 0
+bool root_sliced(const DevPlan &P) {
+    return ((P.st[0].slice & 1) && P.slice_count > 1 && !P.edge_slice) || ((P.st[0].slice & 2) && P.slice2_count > 1);
+}
+
+// A strided slice of the first matched vertex: level 2 is gathered, not scanned.
+bool gathers_level2(const DevPlan &P) {
+    return P.slice_mode == (int32_t)HUGE_SLICE_STRIDE && P.slice_count > 1 && (P.st[0].slice & 1) && !P.edge_slice;
+}
+
+// Rows in the slice's gathered level 2: slice s of S keeps ranks s, s + S, ...,
+// and ranks ascend with degree, so every selected rank but the last has at most
+// the mean degree of the S ranks from it on: at most nnz / S + max degree entries.
+int64_t gathered_rows_bound(const huge_graph *g, const DevPlan &P) {
+    return g->dev.nnz / (int64_t)P.slice_count + g->info.max_degree + 1;
+}
+int64_t gathered_roots(const huge_graph *g, const DevPlan &P) {
+    const int64_t n = g->dev.n, s = P.slice_id, S = P.slice_count;
+    return s < n ? (n - s + S - 1) / S : 0;
+}
+
+namespace {
 
 // Pinned host memory for the scheduler's read-backs, one block per engine call:
 // a device-to-host copy lands there directly instead of through a staging copy.
@@ -288,10 +332,21 @@ bool run_levels(const huge_graph *g, const huge_plan *p, const huge_exec_opts &o
     prof.on = o.profile != 0 || probe;
     prof.probe = probe;
     prof.st = st;
-    const GraphDev &G = g->dev;
+    GraphDev G = g->dev;
+    int64_t l2_rows = G.nnz;  // level-2 rows: every edge-array entry, or the gathered slice
+    if (L.l2_rows) {
+        int64_t *idx = cv.take<int64_t>(L.l2_rows);
+        int32_t *deg = cv.take<int32_t>(L.l2_roots);
+        int64_t *off = cv.take<int64_t>(L.l2_roots + 1);
+        launch_gather_level2(G, P, L.l2_roots, deg, off, idx, L.l2_rows, scan_tmp, st);
+        stats.launches += 4;
+        l2_rows = read_i64(off + L.l2_roots, st, pin64);
+        if (l2_rows > L.l2_rows) HUGE_FAIL(HUGE_EDEVICE, "gathered level 2 exceeds its bound");
+        G.l2_idx = idx;
+    }
     const int strat = (o.strategy >= 0 && o.strategy < STRAT_COUNT) ? o.strategy : STRAT_LANE_MERGE;
     const int count_mode = (o.exec_flags & HUGE_EXEC_NO_HASH) ? MODE_COUNT_NOHASH : MODE_COUNT;
-    const bool root_slice = P.slice_count > 1 && P.st[0].slice;
+    const bool root_slice = root_sliced(P);
     bool limited = false;
     uint64_t level_work[HUGE_KMAX] = {};
     if (root_slice) {
@@ -334,7 +389,7 @@ bool run_levels(const huge_graph *g, const huge_plan *p, const huge_exec_opts &o
     };
 
     if (k == 2) {
-        const int64_t nnz = G.nnz;
+        const int64_t nnz = l2_rows;
         if (!emit) {
             for (int64_t e = 0; e < nnz; e += kMaxItems) {
                 launch_edge_sink(G, P, e, std::min(nnz, e + kMaxItems), MODE_COUNT, nullptr, g->inv_rank, ctrl, st);
@@ -351,7 +406,7 @@ bool run_levels(const huge_graph *g, const huge_plan *p, const huge_exec_opts &o
         }
     } else {
         const int lastW = k - 1;
-        lv[2].nrows = G.nnz;
+        lv[2].nrows = l2_rows;
         int64_t work_done = 0;  // candidates examined (work items launched)
         int W = 2;
         uint64_t cur_bytes = 0;
@@ -539,7 +594,7 @@ void run_graph(const huge_graph *g, const huge_plan *p, const huge_exec_opts &o_
     const huge_exec_opts &o = o_in;
     hipStream_t st = (hipStream_t)o.stream;
     const DevPlan P = exec_plan(p, o);
-    const bool root_slice = P.slice_count > 1 && P.st[0].slice;
+    const bool root_slice = root_sliced(P);
 
     Layout L = make_layout(g, p, o, 0, scan_devn_max());  // segments within the device-count scan's limit
     const uint64_t gs_off = L.total;
@@ -588,12 +643,23 @@ void run_graph(const huge_graph *g, const huge_plan *p, const huge_exec_opts &o_
         gc.off[w] = sb[w].off;
     }
     for (int w = 3; w <= k - 1; ++w) gc.q_cap[w] = L.q_cap[w];
+    GraphDev G = g->dev;
+    int64_t l2_rows = G.nnz;
+    if (L.l2_rows) {  // a strided root slice: gather its level-2 entries first
+        int64_t *idx = cv.take<int64_t>(L.l2_rows);
+        int32_t *deg = cv.take<int32_t>(L.l2_roots);
+        int64_t *off = cv.take<int64_t>(L.l2_roots + 1);
+        launch_gather_level2(G, P, L.l2_roots, deg, off, idx, L.l2_rows, scan_tmp, st);
+        HUGE_HIP(hipMemcpyAsync(&l2_rows, off + L.l2_roots, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+        HUGE_HIP(hipStreamSynchronize(st));
+        if (l2_rows > L.l2_rows) HUGE_FAIL(HUGE_EDEVICE, "gathered level 2 exceeds its bound");
+        G.l2_idx = idx;
+    }
     GState init{};
     init.W = 2;
-    init.lv[2].nrows = g->dev.nnz;
+    init.lv[2].nrows = l2_rows;
     HUGE_HIP(hipMemsetAsync(ctrl, 0, sizeof(Ctrl), st));
     HUGE_HIP(hipMemcpyAsync(gs, &init, sizeof(GState), hipMemcpyHostToDevice, st));
-    const GraphDev &G = g->dev;
     if (root_slice) launch_root_count(G, P, ctrl, st);
     const int count_mode = (o.exec_flags & HUGE_EXEC_NO_HASH) ? MODE_COUNT_NOHASH : MODE_COUNT;
 

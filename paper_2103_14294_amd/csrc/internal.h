@@ -50,6 +50,9 @@ struct GraphDev {
     int64_t hub_words;
     int32_t hub_base;        // first vertex (rank) with a bitmap; n when there is none
     int32_t pad;
+    // level-2 rows of one execution: row r is edge-array entry l2_idx[r], or
+    // entry r when l2_idx is NULL (every entry)
+    const int64_t *l2_idx = nullptr;
 };
 
 }  // namespace huge
@@ -76,7 +79,7 @@ struct DevStep {
     uint32_t lo;    // positions p with constraint f[p] < v
     uint32_t hi;    // positions p with constraint v < f[p]
     uint32_t neq;   // positions p < i not in ext (injectivity checks)
-    int32_t slice;  // 1 if position i holds query vertex 0 (root-slice filter)
+    int32_t slice;  // slice filters on position i's vertex: bit 0 the slice, bit 1 the second slice
     int32_t pad;
 };
 
@@ -85,10 +88,11 @@ struct DevPlan {
     int32_t ne;                 // query edges, as position pairs ea < eb
     uint8_t ea[32], eb[32];
     uint8_t pos[HUGE_KMAX];     // pos[v] = position of query vertex v
-    DevStep st[HUGE_KMAX];      // st[i], i = 1..k-1; st[i].slice marks the sliced vertex's position
+    DevStep st[HUGE_KMAX];      // st[i], i = 1..k-1; st[i].slice marks the sliced vertices' positions
     uint32_t slice_count, slice_id;
     int32_t edge_slice;         // 1: slice the level-2 rows (ordered pairs f[0], f[1]) instead of a vertex
-    int32_t pad;
+    int32_t slice_mode;         // vertex slices: 0 mix(v) % count, 1 v % count (v a rank)
+    uint32_t slice2_count, slice2_id;  // second vertex slice (1, 0 = none)
 };
 
 }  // namespace huge
@@ -171,6 +175,12 @@ struct EmitSink {
     uint64_t delivered = 0;
 };
 uint64_t workspace_bytes(const huge_graph *g, const huge_plan *p, const huge_exec_opts &o);
+// the plan as one execution sees it (slice options applied); HUGE_EINVAL on bad options
+DevPlan exec_plan(const huge_plan *p, const huge_exec_opts &o);
+bool root_sliced(const DevPlan &P);       // level_counts[0] is the number of roots in the slices
+bool gathers_level2(const DevPlan &P);    // level 2 is the gathered entries of a strided root slice
+int64_t gathered_rows_bound(const huge_graph *g, const DevPlan &P);
+int64_t gathered_roots(const huge_graph *g, const DevPlan &P);
 // returns true when the run stopped at o.work_limit
 bool run_levels(const huge_graph *g, const huge_plan *p, const huge_exec_opts &o, huge_result *out, EmitSink *emit,
                 TuneProbe *probe = nullptr);
@@ -183,6 +193,10 @@ void run_batch_levels(const huge_graph *g, const huge_plan *const *plans, int np
                       huge_result *outs);
 void run_persistent(const huge_graph *g, const huge_plan *const *plans, int np, const huge_exec_opts &o,
                     huge_result *outs);
+// mbatch.cpp: the batch in batched rounds (HUGE_ENGINE_GRAPH)
+void run_mgraph(const huge_graph *g, const huge_plan *const *plans, int np, const huge_exec_opts &o,
+                huge_result *outs);
+uint64_t mgraph_workspace_bytes(const huge_graph *g, const huge_plan *const *plans, int np, const huge_exec_opts &o);
 
 // ---------------------------------------------------------------------------
 // kernel launchers (extend.hip)
@@ -224,6 +238,11 @@ void launch_bucket_bounds(const SegBufs &s, int64_t nrows, Ctrl *ctrl, hipStream
 void launch_edge_sink(const GraphDev &g, const DevPlan &P, int64_t e0, int64_t e1, int mode, int32_t *out,
                       const int32_t *inv_rank, Ctrl *ctrl, hipStream_t st);
 void launch_root_count(const GraphDev &g, const DevPlan &P, Ctrl *ctrl, hipStream_t st);
+// Level 2 of a strided slice of the first matched vertex (ranks s, s + S, ...):
+// the edge-array entries of those roots, in order, into idx (at most cap
+// entries; the count lands in off[roots]).  deg int32[roots], off int64[roots + 1].
+void launch_gather_level2(const GraphDev &g, const DevPlan &P, int64_t roots, int32_t *deg, int64_t *off,
+                          int64_t *idx, int64_t cap, int64_t *scan_tmp, hipStream_t st);
 int64_t scan_tmp_elems(int64_t n);
 
 // ---------------------------------------------------------------------------
@@ -276,6 +295,48 @@ void launch_round_bucket_bounds(int width, const SegBufs &s, GState *gs, hipStre
 void launch_round_extend(int width, int mode, int strategy, const GraphDev &g, const DevPlan &P, const int32_t *rows,
                          const SegBufs &s, int32_t *out_rows, Ctrl *ctrl, const int32_t *inv_rank, GState *gs,
                          int bucket, hipStream_t st);
+
+// ---------------------------------------------------------------------------
+// batched rounds (huge_count_batch on the graph engine): every query of a
+// batch keeps its own Algorithm 5 state, queues and segment buffers; one round
+// advances each query by one action (round_sched_step, one thread per query)
+// and then runs ONE prepare launch, one batched scan and one extend launch per
+// (level, last-level-or-not) for all queries together, each workgroup claiming
+// tiles of whichever query comes next.  Recorded once in a hipGraph, replayed.
+// ---------------------------------------------------------------------------
+constexpr int kMaxBatch = 256;                 // queries in one batched round
+constexpr int kMLaunches = 2 * (HUGE_KMAX - 1);  // extend launch id (W - 2) * 2 + (W is the last level)
+struct MPat {                      // one query of the batch (fixed for the call)
+    GConst gc;                     // its scheduler constants (off[W] = sb[W].off)
+    DevPlan P;
+    GraphDev g;                    // with the batch's level-2 rows
+    Ctrl *ctrl;
+    GState *gs;
+    int32_t *q[HUGE_KMAX + 1];     // queues of levels 3..k-1
+    SegBufs sb[HUGE_KMAX + 1];     // segment buffers of levels 2..k-1
+    int64_t *scan_part;            // tile sums of its segment scan (<= 4096 tiles)
+    const int32_t *inv_rank;
+};
+struct MRound {                    // written by the round's scheduler launch
+    int64_t prep_pre[kMaxBatch + 1];            // prepare workgroups: exclusive prefix over queries
+    int64_t scan_pre[kMaxBatch + 1];            // scan tiles
+    int64_t ext_pre[kMLaunches][kMaxBatch + 1]; // extend tiles of each launch
+    unsigned long long claim[kMLaunches];       // next tile of each extend launch
+    int32_t prep_W[kMaxBatch];                  // level each query prepares (0: none)
+    int32_t active;                             // queries not done
+    int32_t error;                              // a query's scheduler found no action
+};
+struct MConst {                    // kernel argument of the scheduler
+    int32_t np;
+    int32_t tile_items[kMLaunches];  // work items per tile of each extend launch's kernel
+};
+void launch_mround_sched(MPat *mp, MRound *mr, const MConst &mc, hipStream_t st);
+void launch_mround_prepare(const MPat *mp, const MRound *mr, int np, hipStream_t st);
+void launch_mround_scan(const MPat *mp, MRound *mr, int np, int64_t max_tiles, hipStream_t st);
+// extend launch `lid` (level W = lid / 2 + 2, last level when lid is odd) with
+// `strategy` (a lane-merge strategy); returns the work items per tile of that kernel
+int mround_tile_items(int lid, int strategy);
+void launch_mround_extend(int lid, int count_mode, int strategy, const MPat *mp, MRound *mr, int np, hipStream_t st);
 
 // extend modes
 enum { MODE_EMIT = 0, MODE_COUNT = 1, MODE_OUTPUT = 2, MODE_COUNT_NOHASH = 3 };

@@ -1,0 +1,337 @@
+// A batch of queries in batched rounds (huge_count_batch, HUGE_ENGINE_GRAPH).
+//
+// Section 4.2 batches the input of an operator so that all workers share it;
+// Section 5.3 lets idle workers take over the work of busy ones.  On one GPU
+// the batch is the set of queries itself: each query runs Algorithm 5 (its own
+// device state, queues and segment buffers, an equal share of the frontier
+// budget), and every round advances all of them by one action in a fixed
+// sequence of launches whose workgroups claim tiles across the queries.  The
+// round is recorded once in a hipGraph and replayed until every query is done;
+// the host only reads one "queries still active" word per few replays.
+//
+// Queries of two vertices are a single edge-array pass each and run on the
+// level engine first.
+#include <algorithm>
+#include <chrono>
+#include <cstring>
+#include <vector>
+
+#include "internal.h"
+#include "prims.h"
+
+namespace huge {
+
+namespace {
+
+constexpr int kRounds = 4;                  // rounds recorded in the graph
+constexpr int kBatchReplays = 8;            // graph launches between reads of the active count
+constexpr int64_t kMaxRounds = 1ll << 26;
+constexpr int64_t kDefaultSegRows = 1 << 20;
+constexpr int64_t kMinQueueRows = 1 << 12;
+constexpr int64_t kScanPartElems = 4096 + 8;  // tile sums of a segment of up to 4096 tiles
+
+inline uint64_t align_up(uint64_t x) { return (x + 255) & ~uint64_t(255); }
+
+struct PatLayout {
+    int64_t seg_cap[HUGE_KMAX + 1] = {};
+    int64_t q_cap[HUGE_KMAX + 1] = {};
+    bool gathered = false;  // level 2 is the gathered strided slice
+    uint64_t bytes = 0;
+};
+
+struct BatchLayout {
+    std::vector<int> idx;        // batch positions of the queries with 3 or more vertices
+    std::vector<DevPlan> P;
+    std::vector<PatLayout> pl;
+    int64_t l2_roots = 0, l2_rows = 0, scan_tmp = 0;
+    uint64_t total = 0;
+};
+
+int64_t seg_rows_for(const huge_plan *p, int W, const huge_exec_opts &o) {
+    if (o.chunk_rows > 0) return o.chunk_rows;
+    if (o.tune) {
+        const int64_t c = o.tune->chunk_rows[__builtin_popcount(p->dev.st[W].ext)];
+        if (c > 0) return std::min<int64_t>(c, kDefaultSegRows);
+    }
+    return kDefaultSegRows;
+}
+
+BatchLayout make_batch_layout(const huge_graph *g, const huge_plan *const *plans, int np, const huge_exec_opts &o) {
+    BatchLayout B;
+    for (int i = 0; i < np; ++i)
+        if (plans[i]->k >= 3) B.idx.push_back(i);
+    const int nb = (int)B.idx.size();
+    if (nb == 0) return B;
+    uint64_t cap = o.frontier_cap_bytes;
+    if (cap == UINT64_MAX) {
+        size_t fr = 0, tot = 0;
+        HUGE_HIP(hipMemGetInfo(&fr, &tot));
+        cap = (uint64_t)(fr * 0.5);
+    }
+    const uint64_t share = cap / (uint64_t)nb;
+    uint64_t t = 0;
+    for (int b = 0; b < nb; ++b) {
+        const huge_plan *p = plans[B.idx[b]];
+        const DevPlan P = exec_plan(p, o);
+        B.P.push_back(P);
+        PatLayout L;
+        const int k = p->k, nq = std::max(0, k - 3);
+        L.gathered = gathers_level2(P);
+        if (L.gathered) {
+            B.l2_roots = gathered_roots(g, P);
+            B.l2_rows = gathered_rows_bound(g, P);
+        }
+        for (int w = 3; w <= k - 1; ++w)
+            L.q_cap[w] = std::max<int64_t>(kMinQueueRows, (int64_t)((nq ? share / nq : 0) / (4ull * w)));
+        const int64_t l2 = L.gathered ? gathered_rows_bound(g, P) : g->dev.nnz;
+        L.seg_cap[2] = std::min<int64_t>(std::min(seg_rows_for(p, 2, o), scan_devn_max()), std::max<int64_t>(1, l2));
+        for (int w = 3; w <= k - 1; ++w)
+            L.seg_cap[w] = std::min<int64_t>(std::min(seg_rows_for(p, w, o), scan_devn_max()), L.q_cap[w]);
+        uint64_t b2 = 0;
+        for (int w = 2; w <= k - 1; ++w) {
+            const int64_t c = L.seg_cap[w];
+            b2 += align_up(8ull * (c + 1)) + align_up(8ull * c) * 2 + align_up(4ull * c);
+        }
+        for (int w = 3; w <= k - 1; ++w) b2 += align_up(4ull * w * L.q_cap[w]);
+        b2 += align_up(8ull * kScanPartElems);
+        L.bytes = b2;
+        t += b2;
+        B.pl.push_back(L);
+    }
+    t += align_up(sizeof(Ctrl) * nb) + align_up(sizeof(GState) * nb) + align_up(sizeof(MPat) * nb) +
+         align_up(sizeof(MRound));
+    if (B.l2_rows) {
+        B.scan_tmp = scan_tmp_elems(B.l2_roots + 1);
+        t += align_up(8ull * B.l2_rows) + align_up(4ull * B.l2_roots) + align_up(8ull * (B.l2_roots + 1)) +
+             align_up(8ull * B.scan_tmp);
+    }
+    B.total = t;
+    return B;
+}
+
+struct Carver {
+    char *base;
+    uint64_t off = 0;
+    template <typename T>
+    T *take(uint64_t count) {
+        T *p = (T *)(base + off);
+        off += align_up(sizeof(T) * count);
+        return p;
+    }
+};
+
+struct Res {
+    void *mem = nullptr;
+    hipStream_t cs = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    ~Res() {
+        if (exec) (void)hipGraphExecDestroy(exec);
+        if (graph) (void)hipGraphDestroy(graph);
+        if (cs) {
+            hipStreamCaptureStatus status = hipStreamCaptureStatusNone;
+            if (hipStreamIsCapturing(cs, &status) == hipSuccess && status != hipStreamCaptureStatusNone) {
+                hipGraph_t partial = nullptr;
+                (void)hipStreamEndCapture(cs, &partial);
+                if (partial) (void)hipGraphDestroy(partial);
+            }
+            (void)hipStreamDestroy(cs);
+        }
+        if (mem) (void)hipFree(mem);
+    }
+};
+
+// The kernel of each extend launch: a fixed lane-merge strategy, or per launch
+// the strategy that the tune table gives most work to over the Ext sizes the
+// batch's queries extend with at that level (plain searches map to the short
+// lane merge, the nearest kernel the batched rounds have).
+int launch_strategy(int lid, const huge_exec_opts &o, const std::vector<const huge_plan *> &ps) {
+    if (o.strategy >= 0 && o.strategy < STRAT_COUNT) {
+        if (o.strategy < STRAT_LANE_MERGE) HUGE_FAIL(HUGE_EINVAL, "batched rounds run lane-merge strategies (2..6)");
+        return o.strategy;
+    }
+    const bool last = (lid & 1) != 0;
+    if (!o.tune) return last ? STRAT_BLOCK_MERGE_LONG : STRAT_BLOCK_MERGE;
+    const int W = lid / 2 + 2;
+    int64_t items[STRAT_COUNT] = {};
+    for (const huge_plan *p : ps) {
+        if (W > p->k - 1 || (W == p->k - 1) != last) continue;
+        const int j = __builtin_popcount(p->dev.st[W].ext);
+        for (int c = 0; c < HUGE_TUNE_BUCKETS; ++c) {
+            int s = o.tune->strategy[j][c];
+            if (s < 0 || s >= STRAT_COUNT) continue;
+            if (s < STRAT_LANE_MERGE) s = STRAT_MERGE_SHORT;
+            items[s] += std::max<int64_t>(1, o.tune->items[j][c]);
+        }
+    }
+    int best = last ? STRAT_BLOCK_MERGE_LONG : STRAT_BLOCK_MERGE;
+    for (int s = STRAT_LANE_MERGE; s < STRAT_COUNT; ++s)
+        if (items[s] > items[best]) best = s;
+    return best;
+}
+
+}  // namespace
+
+uint64_t mgraph_workspace_bytes(const huge_graph *g, const huge_plan *const *plans, int np, const huge_exec_opts &o) {
+    if (np > kMaxBatch) HUGE_FAIL(HUGE_EINVAL, "batched rounds take at most %d queries per call", kMaxBatch);
+    return make_batch_layout(g, plans, np, o).total;
+}
+
+void run_mgraph(const huge_graph *g, const huge_plan *const *plans, int np, const huge_exec_opts &o,
+                huge_result *outs) {
+    auto t0 = std::chrono::steady_clock::now();
+    if (np > kMaxBatch) HUGE_FAIL(HUGE_EINVAL, "batched rounds take at most %d queries per call", kMaxBatch);
+    if (o.work_limit > 0) HUGE_FAIL(HUGE_EINVAL, "batched rounds have no work limit");
+    hipStream_t st = (hipStream_t)o.stream;
+    // two-vertex queries: one edge-array pass each
+    for (int i = 0; i < np; ++i)
+        if (plans[i]->k < 3) {
+            huge_exec_opts lo = o;
+            lo.engine = HUGE_ENGINE_LEVELS;
+            lo.tune = nullptr;
+            lo.workspace = nullptr;
+            lo.workspace_bytes = 0;
+            run_levels(g, plans[i], lo, &outs[i], nullptr);
+        }
+    BatchLayout B = make_batch_layout(g, plans, np, o);
+    const int nb = (int)B.idx.size();
+    if (nb == 0) return;
+    Res res;
+    char *ws = (char *)o.workspace;
+    if (ws) {
+        if (o.workspace_bytes < B.total)
+            HUGE_FAIL(HUGE_ENOMEM, "workspace too small: %llu bytes given, %llu needed",
+                      (unsigned long long)o.workspace_bytes, (unsigned long long)B.total);
+    } else {
+        HUGE_HIP(hipMalloc(&res.mem, B.total));
+        ws = (char *)res.mem;
+    }
+    Carver cv{ws};
+    Ctrl *ctrl = cv.take<Ctrl>(nb);
+    GState *gs = cv.take<GState>(nb);
+    MPat *mp = cv.take<MPat>(nb);
+    MRound *mr = cv.take<MRound>(1);
+    GraphDev G = g->dev;
+    GraphDev Gg = g->dev;  // with the gathered level 2
+    int64_t l2_gathered = 0;
+    if (B.l2_rows) {
+        int64_t *idx = cv.take<int64_t>(B.l2_rows);
+        int32_t *deg = cv.take<int32_t>(B.l2_roots);
+        int64_t *off = cv.take<int64_t>(B.l2_roots + 1);
+        int64_t *tmp = cv.take<int64_t>(B.scan_tmp);
+        const int first = [&] {
+            for (int b = 0; b < nb; ++b)
+                if (B.pl[b].gathered) return b;
+            return 0;
+        }();
+        launch_gather_level2(G, B.P[first], B.l2_roots, deg, off, idx, B.l2_rows, tmp, st);
+        HUGE_HIP(hipMemcpyAsync(&l2_gathered, off + B.l2_roots, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+        HUGE_HIP(hipStreamSynchronize(st));
+        if (l2_gathered > B.l2_rows) HUGE_FAIL(HUGE_EDEVICE, "gathered level 2 exceeds its bound");
+        Gg.l2_idx = idx;
+    }
+    std::vector<MPat> hm(nb);
+    std::vector<GState> hs(nb);
+    std::vector<const huge_plan *> ps;
+    int64_t max_scan_tiles = 0;
+    bool use_lid[kMLaunches] = {};
+    for (int b = 0; b < nb; ++b) {
+        const huge_plan *p = plans[B.idx[b]];
+        ps.push_back(p);
+        const PatLayout &L = B.pl[b];
+        const int k = p->k;
+        MPat &m = hm[b];
+        memset((void *)&m, 0, sizeof(m));
+        m.gc.k = k;
+        m.gc.lastW = k - 1;
+        m.P = B.P[b];
+        m.g = L.gathered ? Gg : G;
+        m.ctrl = ctrl + b;
+        m.gs = gs + b;
+        m.inv_rank = g->inv_rank;
+        for (int w = 2; w <= k - 1; ++w) {
+            const int64_t c = L.seg_cap[w];
+            m.sb[w].off = cv.take<int64_t>(c + 1);
+            m.sb[w].pinfo = cv.take<uint64_t>(c);
+            m.sb[w].hpre = cv.take<uint64_t>(c);
+            m.sb[w].bound = cv.take<int32_t>(c);
+            m.sb[w].cap = c;
+            m.gc.seg_cap[w] = c;
+            m.gc.off[w] = m.sb[w].off;
+            max_scan_tiles += (c + 4095) / 4096;
+            use_lid[(w - 2) * 2 + (w == k - 1 ? 1 : 0)] = true;
+        }
+        for (int w = 3; w <= k - 1; ++w) {
+            m.q[w] = cv.take<int32_t>((uint64_t)w * L.q_cap[w]);
+            m.gc.q_cap[w] = L.q_cap[w];
+        }
+        m.scan_part = cv.take<int64_t>(kScanPartElems);
+        GState &s = hs[b];
+        memset((void *)&s, 0, sizeof(s));
+        s.W = 2;
+        s.lv[2].nrows = L.gathered ? l2_gathered : g->dev.nnz;
+    }
+    if (cv.off > B.total) HUGE_FAIL(HUGE_EDEVICE, "batched round layout overflow");
+    HUGE_HIP(hipMemsetAsync(ctrl, 0, sizeof(Ctrl) * nb, st));
+    HUGE_HIP(hipMemsetAsync(mr, 0, sizeof(MRound), st));
+    HUGE_HIP(hipMemcpyAsync(gs, hs.data(), sizeof(GState) * nb, hipMemcpyHostToDevice, st));
+    HUGE_HIP(hipMemcpyAsync(mp, hm.data(), sizeof(MPat) * nb, hipMemcpyHostToDevice, st));
+    for (int b = 0; b < nb; ++b)
+        if (root_sliced(hm[b].P)) launch_root_count(hm[b].g, hm[b].P, hm[b].ctrl, st);
+    const int count_mode = (o.exec_flags & HUGE_EXEC_NO_HASH) ? MODE_COUNT_NOHASH : MODE_COUNT;
+    MConst mc{};
+    mc.np = nb;
+    int strat[kMLaunches];
+    for (int l = 0; l < kMLaunches; ++l) {
+        strat[l] = use_lid[l] ? launch_strategy(l, o, ps) : STRAT_BLOCK_MERGE;
+        mc.tile_items[l] = mround_tile_items(l, strat[l]);
+    }
+    // the host copies above come from pageable memory: finish them before recording
+    HUGE_HIP(hipStreamSynchronize(st));
+
+    HUGE_HIP(hipStreamCreateWithFlags(&res.cs, hipStreamNonBlocking));
+    HUGE_HIP(hipStreamBeginCapture(res.cs, hipStreamCaptureModeRelaxed));  // occupancy queries run while recording
+    for (int r = 0; r < kRounds; ++r) {
+        launch_mround_sched(mp, mr, mc, res.cs);
+        launch_mround_prepare(mp, mr, nb, res.cs);
+        launch_mround_scan(mp, mr, nb, max_scan_tiles, res.cs);
+        for (int l = 0; l < kMLaunches; ++l)
+            if (use_lid[l]) launch_mround_extend(l, count_mode, strat[l], mp, mr, nb, res.cs);
+    }
+    HUGE_HIP(hipStreamEndCapture(res.cs, &res.graph));
+    HUGE_HIP(hipGraphInstantiate(&res.exec, res.graph, nullptr, nullptr, 0));
+
+    int32_t hdr[2] = {1, 0};  // active, error
+    int64_t replays = 0;
+    while (hdr[0] > 0) {
+        for (int i = 0; i < kBatchReplays; ++i) HUGE_HIP(hipGraphLaunch(res.exec, st));
+        replays += kBatchReplays;
+        HUGE_HIP(hipMemcpyAsync(hdr, &mr->active, sizeof(hdr), hipMemcpyDeviceToHost, st));
+        HUGE_HIP(hipStreamSynchronize(st));
+        if (hdr[1]) HUGE_FAIL(HUGE_EINVAL, "batched rounds: a query's scheduler found no action");
+        if (hdr[0] > 0 && replays * kRounds > kMaxRounds)
+            HUGE_FAIL(HUGE_EINVAL, "batched rounds: no end after %lld rounds", (long long)(replays * kRounds));
+    }
+    std::vector<Ctrl> hc(nb);
+    HUGE_HIP(hipMemcpyAsync(hc.data(), ctrl, sizeof(Ctrl) * nb, hipMemcpyDeviceToHost, st));
+    HUGE_HIP(hipMemcpyAsync(hs.data(), gs, sizeof(GState) * nb, hipMemcpyDeviceToHost, st));
+    HUGE_HIP(hipStreamSynchronize(st));
+    auto t1 = std::chrono::steady_clock::now();
+    const double ms = std::chrono::duration<double, std::milli>(t1 - t0).count();
+    for (int b = 0; b < nb; ++b) {
+        huge_result &out = outs[B.idx[b]];
+        memset(&out, 0, sizeof(out));
+        if (hs[b].error) HUGE_FAIL(HUGE_EINVAL, "batched rounds: the device scheduler found no action");
+        out.count = hc[b].acc[0];
+        out.hash_sum = hc[b].acc[1];
+        out.hash_xor = hc[b].acc[2];
+        for (int i = 0; i < HUGE_KMAX; ++i) out.level_counts[i] = hc[b].level[i];
+        if (!root_sliced(hm[b].P)) out.level_counts[0] = (uint64_t)g->dev.n;
+        out.peak_frontier_bytes = (uint64_t)hs[b].peak_bytes;
+        for (int i = 0; i < HUGE_KMAX; ++i) out.level_work[i] = (uint64_t)hs[b].work[i];
+        out.launches = (uint64_t)replays;
+        out.query_ms = ms;
+    }
+}
+
+}  // namespace huge

@@ -322,7 +322,7 @@ __device__ void run_tile(const PersistArgs &a, const DevPlan &P, const ChunkView
 #pragma unroll
             for (int p = 0; p < W; ++p)
                 if ((st.neq >> p) & 1u) ok &= (v != f[p]);
-            if (st.slice && P.slice_count > 1) ok &= in_slice(v, P);
+            if (st.slice) ok &= slices_ok(st.slice, v, P);
 #pragma unroll
             for (int p = 0; p < W; ++p) {
                 if (ok && ((st.ext >> p) & 1u) && p != pp) {
@@ -798,6 +798,8 @@ void run_persistent(const huge_graph *g, const huge_plan *const *plans, int np, 
     auto t0 = std::chrono::steady_clock::now();
     hipStream_t st = (hipStream_t)o.stream;
     if (np < 1 || np > 4096) HUGE_FAIL(HUGE_EINVAL, "bad number of plans %d", np);
+    if (o.slice_mode != HUGE_SLICE_MIX || o.slice2_count > 1)
+        HUGE_FAIL(HUGE_EINVAL, "the persistent engine takes mixed slices of one vertex or edge only");
     std::vector<DevPlan> dp(np);
     int kmax = 3;
     for (int i = 0; i < np; ++i) {

@@ -297,3 +297,51 @@ def test_pair_slices_partition_and_match_direct_filter():
                        if oracle.mix64((int(rank[f[pair[0]]]) << 32) | int(rank[f[pair[1]]])) % 3 == s)
             got = oracle.enumerate_query(t.row_ptr, t.col, k, e, slice_count=3, slice_id=s, slice_pair=pair)
             assert got["count"] == want, (pair, s)
+
+
+def test_strided_and_double_slices_partition_and_match_direct_filter():
+    """Strided vertex slices (rank mod S) partition the matches for any query
+    vertex; a second vertex slice on another query vertex splits each slice again,
+    so the S1 * S2 double slices also partition them, and the double slice
+    (a in s1 of S1, b in s2 of S2) is the same set whichever vertex takes the
+    first role.  On a tiny graph every slice holds exactly the SB-satisfying maps
+    picked out by the rank condition (maps enumerated with itertools)."""
+    import itertools
+
+    g = gg.chung_lu(2048, 10, 2.5, seed=12)
+    k, e = P.NAMED["house"]
+    full = oracle.enumerate_query(g.row_ptr, g.col, k, e)
+    want = (full["count"], full["hash_sum"], full["hash_xor"])
+    for sv in (0, 2, 4):
+        acc = [0, 0, 0]
+        for s in range(7):
+            r = oracle.enumerate_query(g.row_ptr, g.col, k, e, slice_count=7, slice_id=s, slice_vertex=sv,
+                                       slice_mode=1)
+            acc = [acc[0] + r["count"], (acc[1] + r["hash_sum"]) & M64, acc[2] ^ r["hash_xor"]]
+        assert tuple(acc) == want, sv
+    acc = [0, 0, 0]
+    for s1 in range(3):
+        for s2 in range(4):
+            r = oracle.enumerate_query(g.row_ptr, g.col, k, e, slice_count=3, slice_id=s1, slice_vertex=1,
+                                       slice_mode=1, slice2=(3, 4, s2))
+            swapped = oracle.enumerate_query(g.row_ptr, g.col, k, e, slice_count=4, slice_id=s2, slice_vertex=3,
+                                             slice_mode=1, slice2=(1, 3, s1))
+            assert (r["count"], r["hash_sum"], r["hash_xor"]) == \
+                (swapped["count"], swapped["hash_sum"], swapped["hash_xor"]), (s1, s2)
+            acc = [acc[0] + r["count"], (acc[1] + r["hash_sum"]) & M64, acc[2] ^ r["hash_xor"]]
+    assert tuple(acc) == want
+
+    t = gg.gnp(9, 0.55, seed=3)
+    rank = oracle.ranks(t.row_ptr)
+    adj = {(u, int(v)) for u in range(t.n) for v in t.col[t.row_ptr[u]:t.row_ptr[u + 1]]}
+    k, e = P.NAMED["diamond"]
+    sb = oracle.sb_pairs(k, e)
+    maps = [f for f in itertools.permutations(range(t.n), k)
+            if all((f[a], f[b]) in adj for a, b in e) and all(rank[f[a]] < rank[f[b]] for a, b in sb)]
+    for a, b in [(0, 3), (2, 1)]:
+        for s1 in range(2):
+            for s2 in range(3):
+                want_n = sum(1 for f in maps if rank[f[a]] % 2 == s1 and rank[f[b]] % 3 == s2)
+                got = oracle.enumerate_query(t.row_ptr, t.col, k, e, slice_count=2, slice_id=s1, slice_vertex=a,
+                                             slice_mode=1, slice2=(b, 3, s2))
+                assert got["count"] == want_n, (a, b, s1, s2)
