@@ -66,7 +66,15 @@ typedef struct huge_plan huge_plan;
 /* huge_plan flags */
 #define HUGE_PLAN_COST_MODEL 0x0u /* order from the cost model (Algorithm 1, wco plans) */
 #define HUGE_PLAN_LEARNED 0x1u    /* order from the learned cost model (huge_plan_create_learned) */
-#define HUGE_PLAN_VERIFY 0x2u     /* learned plans: measure the model's best orders on a root sample */
+#define HUGE_PLAN_VERIFY 0x2u     /* learned plans: measure the model's best orders on a small sample */
+/* Induced matching (Section 2's induced subgraphs): keep only the matches whose
+ * image is an induced subgraph, i.e. every non-edge of q maps to a non-edge of
+ * G.  Each step also tests the new vertex against the lists of the matched
+ * vertices it is NOT adjacent to in q and keeps it only when it is absent from
+ * all of them (a set difference next to Eq. 2's intersection).  Level and
+ * graph engines and batches (the persistent engine: HUGE_EINVAL).  The cost
+ * model's estimate stays the non-induced one, an upper bound. */
+#define HUGE_PLAN_INDUCED 0x4u
 
 /* huge_exec_opts.engine */
 #define HUGE_ENGINE_AUTO 0
@@ -109,6 +117,11 @@ typedef struct {
        the symmetry-breaking window) while extending the partial matches of level i
        (i+1 order vertices) by one vertex; 0 on the persistent engine */
     uint64_t level_work[HUGE_KMAX];
+    /* persistent engine: its workgroups, and the mean and standard deviation over
+       them of the time each spent in tiles and prepare passes (how evenly the
+       load was spread, Section 7.3); 0 on the other engines */
+    uint64_t workgroups;
+    double wg_busy_ms_mean, wg_busy_ms_std;
 } huge_result;
 #define HUGE_KC_PREPARE 0 /* SB window trim + probe choice */
 #define HUGE_KC_SCAN 1    /* exclusive scan of per-row bounds */
@@ -225,6 +238,16 @@ huge_status huge_load_csr(int64_t n, int64_t nnz, const int64_t *row_ptr, const 
                           void *stream, huge_graph **out);
 void huge_graph_free(huge_graph *g);
 
+/*
+ * huge_load_csr_labelled -- huge_load_csr for a vertex-labelled graph (the
+ * labelled graphs the paper's techniques extend to, Section 2): labels[u] is
+ * the label of vertex u (original IDs), in host or device memory as flags
+ * say; read, not kept.  Labelled queries (huge_plan_create_labelled) need such
+ * a graph; unlabelled queries ignore the labels.
+ */
+huge_status huge_load_csr_labelled(int64_t n, int64_t nnz, const int64_t *row_ptr, const int32_t *col,
+                                   const int32_t *labels, uint32_t flags, void *stream, huge_graph **out);
+
 typedef struct {
     int64_t n, nnz;
     int64_t max_degree;
@@ -264,6 +287,21 @@ huge_status huge_plan_create(const huge_graph *g, int32_t k, int32_t n_qedges, c
 void huge_plan_free(huge_plan *p);
 
 /*
+ * huge_plan_create_labelled -- huge_plan_create for a labelled query:
+ * qlabels[v] (k ints) is the label the image of query vertex v must carry, -1
+ * for any label.  A match is an injective map that keeps q's edges and these
+ * labels; matches are reported once per class under the automorphisms of q
+ * that also keep its labels (-1 counting as a label of its own), which is what
+ * the symmetry-breaking constraints are computed from.  Each step filters its
+ * candidates by label (next to the injectivity filter of Algorithm 4).  flags:
+ * HUGE_PLAN_INDUCED or 0 (cost model; the estimate ignores labels).  Runs on
+ * a graph from huge_load_csr_labelled (HUGE_EINVAL otherwise) on the level and
+ * graph engines and in batches (the persistent engine: HUGE_EINVAL).
+ */
+huge_status huge_plan_create_labelled(const huge_graph *g, int32_t k, int32_t n_qedges, const int32_t *qedges,
+                                      const int32_t *qlabels, const int32_t *order, uint32_t flags, huge_plan **out);
+
+/*
  * huge_plan_prefix -- the plan of the first `size` vertices (2..k) of p's
  * order: the induced prefix, numbered by order position, with p's
  * symmetry-breaking constraints restricted to it.  Its count is p's
@@ -279,8 +317,21 @@ huge_status huge_plan_prefix(const huge_plan *p, int32_t size, huge_plan **out);
 huge_status huge_plan_info(const huge_plan *p, int32_t *k, int32_t *order_out, int32_t *n_sb, int32_t *sb_pairs,
                            double *est_cost);
 
+/*
+ * The estimator behind the plan's order, per prefix of that order: est[s-1]
+ * (s = 1..k) is the estimated number of partial matches of the induced prefix
+ * of the first s order vertices that satisfy the symmetry-breaking constraints
+ * inside it (Algorithm 1's |R(q')|).  Cost model: the Chung-Lu estimate
+ * prod over prefix vertices v of M_{deg(v)} / (2m)^{edges}, M_p = sum over data
+ * vertices u of d_u^p, times the fraction of the prefix's vertex orderings that
+ * satisfy its constraints; learned plans: the model's predictions.  Entries
+ * past k are 0; all are 0 without graph statistics.  est holds HUGE_KMAX doubles.
+ */
+huge_status huge_plan_estimates(const huge_plan *p, double *est);
+
 /* Device workspace needed by huge_count / huge_enumerate for these options
- * (engine included: the graph engine also keeps its scheduler state there). */
+ * (engine included: the graph engine also keeps its scheduler state there,
+ * and the persistent engine its per-workgroup buffers, boards and counters). */
 huge_status huge_workspace_size(const huge_graph *g, const huge_plan *p, const huge_exec_opts *opts,
                                 uint64_t *bytes);
 
@@ -348,6 +399,37 @@ huge_status huge_count_batch(const huge_graph *g, const huge_plan *const *plans,
  * and options (HUGE_EINVAL for another engine). */
 huge_status huge_batch_workspace_size(const huge_graph *g, const huge_plan *const *plans, int32_t np,
                                       const huge_exec_opts *opts, uint64_t *bytes);
+
+/*
+ * huge_motif_count -- motif counting over every connected pattern of k
+ * vertices (2 <= k <= HUGE_MOTIF_KMAX): the graph-pattern-mining use of
+ * Section 6, which runs subgraph enumeration over every pattern of interest,
+ * with both readings of an occurrence from Section 2.  For each connected
+ * k-vertex graph up to isomorphism (1, 1, 2, 6, 21 and 112 of them for k = 1..6;
+ * ordered by edge count, then by the representative's edge bits), out[i] gets
+ * the representative (query vertices 0..k-1, edges), `noninduced`, the number
+ * of subgraphs of G isomorphic to it with their set-hashes (huge_count's
+ * count, hash_sum, hash_xor), and `induced`, the number of k-vertex sets X
+ * whose induced subgraph G[X] is isomorphic to it.  The induced counts follow
+ * exactly from the non-induced ones: X with G[X] isomorphic to q holds
+ * c(p, q) subgraphs isomorphic to p, c(p, q) the number of spanning subgraphs
+ * of q isomorphic to p, and the triangular system is solved from the densest
+ * pattern down.  The patterns run as one batch (huge_count_batch with the same
+ * options: engine GRAPH gives batched rounds).  No slices or work limit
+ * (HUGE_EINVAL): induced counts need every pattern's whole count.  out holds
+ * HUGE_MOTIF_MAX entries; *n_out receives the number of patterns.
+ */
+#define HUGE_MOTIF_KMAX 6
+#define HUGE_MOTIF_MAX 112
+typedef struct {
+    int32_t k, n_edges;
+    int32_t edges[30];           /* 2 * n_edges query-vertex IDs */
+    uint64_t noninduced;         /* subgraphs of G isomorphic to the pattern */
+    uint64_t induced;            /* vertex sets whose induced subgraph is isomorphic to it */
+    uint64_t hash_sum, hash_xor; /* set-hashes of the non-induced matches */
+} huge_motif;
+huge_status huge_motif_count(const huge_graph *g, int32_t k, const huge_exec_opts *opts, huge_motif *out,
+                             int32_t *n_out);
 
 /* ------------------------------------------------------------------------
  * Learned cost model.  The optimiser of Section 3.3 (Algorithm 1) ranks
@@ -423,10 +505,13 @@ huge_status huge_plan_create_learned(const huge_graph *g, const huge_model *m, i
                                      const int32_t *qedges, const int32_t *order, void *stream, huge_plan **out);
 /*
  * As huge_plan_create_learned, with flags: HUGE_PLAN_VERIFY runs the cost
- * model's order and the model's four best orders on the same edge slice of
- * about 16384 level-2 rows (halved until the cost model's order examines at
- * most 2e10 candidates; the others stop at 8 times its candidates), on
- * `stream`, and keeps the order with the least device time.
+ * model's order and the model's two best orders on a strided slice of each
+ * order's own first matched vertex (slice 0 of S: every S-th vertex in degree
+ * order, so each order reads only its own sample's entries), S the smallest
+ * power of 8 from 512 at which the cost model's order examines at most 4e7
+ * candidates; the others stop at 3 times its candidates.  The order with the
+ * least device time wins; the cost model's order keeps ties within 10%.  This
+ * costs a few milliseconds of device time per order, on `stream`.
  */
 huge_status huge_plan_create_learned2(const huge_graph *g, const huge_model *m, int32_t k, int32_t n_qedges,
                                       const int32_t *qedges, const int32_t *order, uint32_t flags, void *stream,

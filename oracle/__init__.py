@@ -67,7 +67,7 @@ def _load():
         ci = ctypes.c_int
         lib.orc_enumerate.restype = ci
         lib.orc_enumerate.argtypes = [i64, vp, vp, ci, ci, vp, ci, vp, ci, vp, ctypes.c_uint32, ctypes.c_uint32,
-                                      ci, ci, ci, ci, ctypes.c_uint32, ctypes.c_uint32, ci,
+                                      ci, ci, ci, ci, ctypes.c_uint32, ctypes.c_uint32, vp, vp, vp, ci,
                                       ctypes.POINTER(_Result)]
         lib.orc_automorphisms.restype = ci
         lib.orc_automorphisms.argtypes = [ci, ci, vp, vp, ci]
@@ -89,13 +89,18 @@ def _qarr(qedges):
 
 
 def enumerate_query(row_ptr, col, k, qedges, mode=MODE_SB, order=None, sb_pairs=None, slice_count=1,
-                    slice_id=0, threads=0, slice_vertex=0, slice_pair=None, slice_mode=0, slice2=None):
+                    slice_id=0, threads=0, slice_vertex=0, slice_pair=None, slice_mode=0, slice2=None,
+                    ranks=None, induced=False, vlabels=None, qlabels=None):
     """Run the C enumerator.  Returns a dict with count, hash_sum, hash_xor and
     level_counts (list of KMAX ints; entry d counts partial maps of the first
     d+1 vertices of the order used).  slice_pair=(a, b) slices on the ordered
     pair of images (r(f(a)), r(f(b))) instead of one vertex.  slice_mode=1
     makes vertex slices strided (rank mod S) instead of mixed; slice2=(c, S2,
-    s2) adds a second vertex slice on query vertex c."""
+    s2) adds a second vertex slice on query vertex c.  ranks: the output of
+    ranks(row_ptr) for this graph, to skip recomputing them.  induced=True
+    counts induced occurrences only (every non-edge of q maps to a non-edge).
+    vlabels (one int per data vertex) and qlabels (one per query vertex, -1 =
+    any) make it a labelled match: every query vertex's image carries its label."""
     lib = _load()
     rp = np.ascontiguousarray(row_ptr, dtype=np.int64)
     cl = np.ascontiguousarray(col, dtype=np.int32)
@@ -110,14 +115,27 @@ def enumerate_query(row_ptr, col, k, qedges, mode=MODE_SB, order=None, sb_pairs=
         nsb = int(sbp.shape[0])
         if nsb == 0:
             sbp = np.zeros((1, 2), dtype=np.int32)
+    rk = None
+    if ranks is not None:
+        rk = np.ascontiguousarray(ranks, dtype=np.int32)
+        if rk.shape != (rp.shape[0] - 1,):
+            raise ValueError("ranks must hold one entry per vertex")
+    vl = None if vlabels is None else np.ascontiguousarray(vlabels, dtype=np.int32)
+    ql = None if qlabels is None else np.ascontiguousarray(qlabels, dtype=np.int32)
+    if vl is not None and vl.shape != (rp.shape[0] - 1,):
+        raise ValueError("vlabels must hold one entry per vertex")
+    if ql is not None and ql.shape != (int(k),):
+        raise ValueError("qlabels must hold one entry per query vertex")
     r = _Result()
     st = lib.orc_enumerate(int(rp.shape[0] - 1), rp.ctypes.data, cl.ctypes.data, int(k), int(e.shape[0]),
-                           e.ctypes.data, int(mode), None if o is None else o.ctypes.data, nsb,
+                           e.ctypes.data, int(mode) | (4 if induced else 0), None if o is None else o.ctypes.data, nsb,
                            None if sbp is None else sbp.ctypes.data, int(slice_count), int(slice_id),
                            int(slice_pair[0] if slice_pair else slice_vertex),
                            int(slice_pair[1] if slice_pair else -1), int(slice_mode),
                            int(slice2[0]) if slice2 else -1, int(slice2[1]) if slice2 else 1,
-                           int(slice2[2]) if slice2 else 0, int(threads), ctypes.byref(r))
+                           int(slice2[2]) if slice2 else 0, None if rk is None else rk.ctypes.data,
+                           None if vl is None else vl.ctypes.data, None if ql is None else ql.ctypes.data,
+                           int(threads), ctypes.byref(r))
     if st != 0:
         raise ValueError("oracle rejected the query or order")
     return {"count": int(r.count), "hash_sum": int(r.hash_sum), "hash_xor": int(r.hash_xor),
@@ -221,3 +239,58 @@ def brute_force(row_ptr, col, k, qedges):
         hs = (hs + h) & _M64
         hx ^= h
     return {"count": len(images), "hash_sum": hs, "hash_xor": hx, "maps": nmaps}
+
+
+def _iso_key(k, edges):
+    """Smallest sorted edge tuple over every relabelling of vertices 0..k-1 (the
+    isomorphism class of a small graph, by brute force)."""
+    best = None
+    for p in itertools.permutations(range(k)):
+        t = tuple(sorted((min(p[a], p[b]), max(p[a], p[b])) for a, b in edges))
+        if best is None or t < best:
+            best = t
+    return best
+
+
+def _connected(k, edges):
+    adj = {v: set() for v in range(k)}
+    for a, b in edges:
+        adj[a].add(b)
+        adj[b].add(a)
+    seen, stack = {0}, [0]
+    while stack:
+        for b in adj[stack.pop()]:
+            if b not in seen:
+                seen.add(b)
+                stack.append(b)
+    return len(seen) == k
+
+
+def motif_counts(row_ptr, col, k):
+    """Motif counts by the definitions (Section 2), for tiny graphs: over every
+    k-vertex set X, the induced subgraph G[X] (if connected) adds one induced
+    occurrence of its isomorphism class, and every connected spanning subgraph of
+    G[X] adds one non-induced occurrence (a subgraph of G isomorphic to its class).
+    Returns {class key: (noninduced, induced)}, keys from _iso_key."""
+    rp = np.asarray(row_ptr, dtype=np.int64)
+    cl = np.asarray(col, dtype=np.int32)
+    n = int(rp.shape[0] - 1)
+    adj = set()
+    for u in range(n):
+        for e in range(int(rp[u]), int(rp[u + 1])):
+            adj.add((u, int(cl[e])))
+    out = {}
+    for X in itertools.combinations(range(n), k):
+        ind = [(a, b) for a in range(k) for b in range(a + 1, k) if (X[a], X[b]) in adj]
+        if not _connected(k, ind):
+            continue
+        key = _iso_key(k, ind)
+        nonind, induced = out.get(key, (0, 0))
+        out[key] = (nonind, induced + 1)
+        for r in range(k - 1, len(ind) + 1):
+            for sub in itertools.combinations(ind, r):
+                if _connected(k, sub):
+                    sk = _iso_key(k, sub)
+                    a, b = out.get(sk, (0, 0))
+                    out[sk] = (a + 1, b)
+    return out

@@ -71,6 +71,7 @@
 #define ORC_MODE_SB 0
 #define ORC_MODE_CANON 1
 #define ORC_MODE_ALL 2
+#define ORC_INDUCED 4 /* or'ed into the mode: only induced occurrences (non-edges of q absent too) */
 #define ORC_KMAX 8
 
 typedef struct {
@@ -101,6 +102,7 @@ typedef struct {
     int8_t *aut; /* naut * k */
     int nsb;
     int sba[28], sbb[28]; /* constraint sba < sbb (query vertex IDs) */
+    int label[ORC_KMAX];  /* labelled queries: the label each query vertex's image must carry, -1 any */
 } orc_query;
 
 /* Returns 0 on success, -1 on malformed query (k out of range, bad edge,
@@ -147,6 +149,8 @@ static void orc_query_aut(orc_query *q) {
         int ok = 1;
         for (int i = 0; i < q->ne && ok; ++i)
             if (!q->adj[p[q->ea[i]]][p[q->eb[i]]]) ok = 0;
+        for (int i = 0; i < k && ok; ++i) /* automorphisms of a labelled query keep labels */
+            if (q->label[p[i]] != q->label[i]) ok = 0;
         if (ok) {
             for (int i = 0; i < k; ++i) q->aut[q->naut * k + i] = (int8_t)p[i];
             q->naut++;
@@ -220,6 +224,7 @@ typedef struct {
     const int64_t *rp;
     const int32_t *col;
     int32_t *rank;
+    const int32_t *label; /* vertex labels (original IDs), or NULL */
 } orc_graph;
 
 static const int64_t *orc_sort_deg;
@@ -282,6 +287,9 @@ typedef struct {
     int slice_mode;             /* vertex slices: 0 by mix of the rank, 1 by the rank itself */
     uint32_t slice2_count, slice2_id;
     int slice2_pos;             /* position of the second sliced query vertex, or -1 */
+    int induced;                /* 1: the image of every non-edge of q must be a non-edge of G */
+    int nnon[ORC_KMAX];
+    int non[ORC_KMAX][ORC_KMAX]; /* earlier positions not adjacent to position i in q */
 } orc_plan;
 
 /* rank r in slice id of count (vertex slices) */
@@ -296,6 +304,8 @@ static int orc_plan_init(orc_plan *P, const orc_query *q, const orc_graph *g, in
     memset(P, 0, sizeof(*P));
     P->q = q;
     P->g = g;
+    P->induced = (mode & ORC_INDUCED) != 0;
+    mode &= ~ORC_INDUCED;
     P->mode = mode;
     int k = q->k;
     if (order) {
@@ -330,6 +340,9 @@ static int orc_plan_init(orc_plan *P, const orc_query *q, const orc_graph *g, in
                 else P->chk[i][P->nchk[i]++] = p;
             }
         if (P->pivot[i] < 0) return -1; /* prefix not connected */
+        P->nnon[i] = 0;
+        for (int p = 0; p < i; ++p)
+            if (!q->adj[P->order[p]][v]) P->non[i][P->nnon[i]++] = p;
     }
     if (mode == ORC_MODE_SB) {
         for (int c = 0; c < q->nsb; ++c) {
@@ -414,8 +427,12 @@ static int orc_accept(orc_worker *w, int i, int32_t c) {
     const orc_graph *g = P->g;
     for (int p = 0; p < i; ++p)
         if (w->f[p] == c) return 0; /* injectivity */
+    if (P->q->label[P->order[i]] >= 0 && (!g->label || g->label[c] != P->q->label[P->order[i]])) return 0;
     for (int t = 0; t < P->nchk[i]; ++t)
         if (!orc_adjacent(g, w->f[P->chk[i][t]], c)) return 0;
+    if (P->induced)
+        for (int t = 0; t < P->nnon[i]; ++t)
+            if (orc_adjacent(g, w->f[P->non[i][t]], c)) return 0;
     int32_t rc = g->rank[c];
     for (int t = 0; t < P->nlt[i]; ++t)
         if (!(g->rank[w->f[P->lt[i][t]]] < rc)) return 0;
@@ -467,6 +484,10 @@ static void *orc_thread(void *arg) {
         int64_t hi = lo + a->chunk < a->n ? lo + a->chunk : a->n;
         for (int64_t u = lo; u < hi; ++u) {
             if (!orc_slices_ok(P, 0, P->g->rank[u])) continue;
+            {
+                const int want = P->q->label[P->order[0]];
+                if (want >= 0 && (!P->g->label || P->g->label[u] != want)) continue;
+            }
             w.res.level_counts[0]++;
             w.f[0] = (int32_t)u;
             orc_search(&w, 1);
@@ -481,16 +502,20 @@ static void *orc_thread(void *arg) {
  * IDs; k query vertices; nqe edges as 2*nqe ints; mode; optional order
  * (k entries, every prefix connected); optional caller SB pairs (nsb pairs as
  * 2*nsb ints a<b; used by ORC_MODE_SB when nsb >= 0, nsb < 0 = compute
- * Grochow-Kellis here); root slice; thread count (0 = all online CPUs).
+ * Grochow-Kellis here); root slice; optional ranks of an earlier orc_ranks
+ * call on the same graph (NULL = computed here); thread count (0 = all
+ * online CPUs).
  * Returns 0, or -1 for a malformed query/order.
  */
 int orc_enumerate(int64_t n, const int64_t *rp, const int32_t *col, int k, int nqe,
                   const int32_t *qedges, int mode, const int32_t *order, int nsb,
                   const int32_t *sb_pairs, uint32_t slice_count, uint32_t slice_id, int slice_vertex,
                   int slice_vertex2, int slice_mode, int slice2_vertex, uint32_t slice2_count,
-                  uint32_t slice2_id, int nthreads, orc_result *out) {
+                  uint32_t slice2_id, const int32_t *rank_in, const int32_t *vlabels, const int32_t *qlabels,
+                  int nthreads, orc_result *out) {
     orc_query q;
     if (orc_query_init(&q, k, nqe, qedges) != 0) return -1;
+    for (int i = 0; i < k; ++i) q.label[i] = qlabels ? qlabels[i] : -1;
     orc_query_aut(&q);
     if (nsb >= 0) {
         if (nsb > 28) {
@@ -513,8 +538,12 @@ int orc_enumerate(int64_t n, const int64_t *rp, const int32_t *col, int k, int n
     g.n = n;
     g.rp = rp;
     g.col = col;
+    g.label = vlabels;
     g.rank = (int32_t *)malloc(sizeof(int32_t) * (size_t)(n > 0 ? n : 1));
-    orc_ranks(n, rp, g.rank);
+    if (rank_in) /* ranks from an earlier orc_ranks call on the same graph */
+        memcpy(g.rank, rank_in, sizeof(int32_t) * (size_t)n);
+    else
+        orc_ranks(n, rp, g.rank);
     orc_plan P;
     if (orc_plan_init(&P, &q, &g, mode, order, slice_count, slice_id, slice_vertex, slice_vertex2, slice_mode,
                       slice2_vertex, slice2_count, slice2_id) != 0) {

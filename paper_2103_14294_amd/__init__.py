@@ -21,7 +21,7 @@ HUGE_OK, HUGE_STOPPED = 0, 1
 STATUS = {0: "HUGE_OK", 1: "HUGE_STOPPED", -1: "HUGE_EINVAL", -2: "HUGE_ENOMEM", -3: "HUGE_EDEVICE",
           -4: "HUGE_EGRAPH", -5: "HUGE_EQUERY", -6: "HUGE_EORDER", -7: "HUGE_EOVERFLOW"}
 HOST_PTRS, DEVICE_PTRS, NO_VALIDATE, NO_HUB_BITMAP = 0x1, 0x2, 0x4, 0x8
-PLAN_COST_MODEL, PLAN_LEARNED, PLAN_VERIFY = 0x0, 0x1, 0x2
+PLAN_COST_MODEL, PLAN_LEARNED, PLAN_VERIFY, PLAN_INDUCED = 0x0, 0x1, 0x2, 0x4
 ENGINE_AUTO, ENGINE_LEVELS, ENGINE_PERSISTENT, ENGINE_GRAPH = 0, 1, 2, 3
 EXEC_NO_HASH = 0x1
 SLICE_MIX, SLICE_STRIDE = 0, 1
@@ -36,8 +36,10 @@ EXPORTED = [
     "huge_model_create", "huge_model_free", "huge_model_set", "huge_model_get", "huge_model_forward",
     "huge_model_grad", "huge_model_train", "huge_plan_features", "huge_plan_create_learned",
     "huge_autotune", "huge_graph_digest", "huge_plan_prefix", "huge_plan_create_learned2", "huge_device_name",
-    "huge_batch_workspace_size",
+    "huge_batch_workspace_size", "huge_plan_estimates",
+    "huge_motif_count", "huge_load_csr_labelled", "huge_plan_create_labelled",
 ]
+MOTIF_KMAX, MOTIF_MAX = 6, 112
 MLP_F, MLP_H = 128, 256
 MLP_PARAMS = MLP_F * MLP_H + 2 * MLP_H + 1
 
@@ -55,7 +57,8 @@ class Result(ctypes.Structure):
                 ("peak_frontier_bytes", ctypes.c_uint64), ("launches", ctypes.c_uint64),
                 ("steals", ctypes.c_uint64), ("kernel_ms", ctypes.c_double * 4),
                 ("kernel_launches", ctypes.c_uint64 * 4), ("alg_bytes", ctypes.c_double * 4),
-                ("level_work", ctypes.c_uint64 * KMAX)]
+                ("level_work", ctypes.c_uint64 * KMAX), ("workgroups", ctypes.c_uint64),
+                ("wg_busy_ms_mean", ctypes.c_double), ("wg_busy_ms_std", ctypes.c_double)]
 
     def to_dict(self):
         return {"count": int(self.count), "hash_sum": int(self.hash_sum), "hash_xor": int(self.hash_xor),
@@ -64,7 +67,14 @@ class Result(ctypes.Structure):
                 "steals": int(self.steals), "kernel_ms": [float(x) for x in self.kernel_ms],
                 "kernel_launches": [int(x) for x in self.kernel_launches],
                 "alg_bytes": [float(x) for x in self.alg_bytes],
-                "level_work": [int(x) for x in self.level_work]}
+                "level_work": [int(x) for x in self.level_work], "workgroups": int(self.workgroups),
+                "wg_busy_ms_mean": float(self.wg_busy_ms_mean), "wg_busy_ms_std": float(self.wg_busy_ms_std)}
+
+
+class Motif(ctypes.Structure):
+    _fields_ = [("k", ctypes.c_int32), ("n_edges", ctypes.c_int32), ("edges", ctypes.c_int32 * 30),
+                ("noninduced", ctypes.c_uint64), ("induced", ctypes.c_uint64), ("hash_sum", ctypes.c_uint64),
+                ("hash_xor", ctypes.c_uint64)]
 
 
 class ExecOpts(ctypes.Structure):
@@ -133,6 +143,10 @@ def load_library(path: str = LIB_PATH):
         lib.huge_exec_opts_default.argtypes = [ctypes.POINTER(ExecOpts)]
         lib.huge_load_csr.restype = st
         lib.huge_load_csr.argtypes = [i64, i64, vp, vp, u32, vp, ctypes.POINTER(vp)]
+        lib.huge_load_csr_labelled.restype = st
+        lib.huge_load_csr_labelled.argtypes = [i64, i64, vp, vp, vp, u32, vp, ctypes.POINTER(vp)]
+        lib.huge_plan_create_labelled.restype = st
+        lib.huge_plan_create_labelled.argtypes = [vp, i32, i32, vp, vp, vp, u32, ctypes.POINTER(vp)]
         lib.huge_graph_free.restype = None
         lib.huge_graph_free.argtypes = [vp]
         lib.huge_graph_get_info.restype = st
@@ -145,6 +159,11 @@ def load_library(path: str = LIB_PATH):
         lib.huge_plan_free.argtypes = [vp]
         lib.huge_plan_info.restype = st
         lib.huge_plan_info.argtypes = [vp, vp, vp, vp, vp, vp]
+        lib.huge_plan_estimates.restype = st
+        lib.huge_plan_estimates.argtypes = [vp, vp]
+        lib.huge_motif_count.restype = st
+        lib.huge_motif_count.argtypes = [vp, i32, ctypes.POINTER(ExecOpts), ctypes.POINTER(Motif),
+                                         ctypes.POINTER(i32)]
         lib.huge_workspace_size.restype = st
         lib.huge_workspace_size.argtypes = [vp, vp, ctypes.POINTER(ExecOpts), ctypes.POINTER(ctypes.c_uint64)]
         lib.huge_count.restype = st
@@ -269,6 +288,12 @@ class Plan:
                 "sb_pairs": [tuple(pairs[2 * i:2 * i + 2].tolist()) for i in range(nsb.value)],
                 "est_cost": est.value}
 
+    def estimates(self):
+        """huge_plan_estimates: estimated partial matches of each prefix size 1..k of the order."""
+        est = np.zeros(KMAX, dtype=np.float64)
+        _check(_lib.huge_plan_estimates(self._h, est.ctypes.data))
+        return est[: self.k].tolist()
+
     def free(self):
         if self._h and self._h.value and _lib is not None:
             _lib.huge_plan_free(self._h)
@@ -281,8 +306,9 @@ class Plan:
             pass
 
 
-def load(row_ptr, col, validate=True, stream=None, hub_bitmaps=True) -> Graph:
-    """huge_load_csr.  row_ptr/col: numpy arrays (host) or torch tensors on the GPU."""
+def load(row_ptr, col, validate=True, stream=None, hub_bitmaps=True, labels=None) -> Graph:
+    """huge_load_csr (or huge_load_csr_labelled with `labels`, one int per vertex).
+    row_ptr/col: numpy arrays (host) or torch tensors on the GPU."""
     lib = load_library()
     flags = (0 if validate else NO_VALIDATE) | (0 if hub_bitmaps else NO_HUB_BITMAP)
     keep = []
@@ -304,26 +330,51 @@ def load(row_ptr, col, validate=True, stream=None, hub_bitmaps=True) -> Graph:
         prp, pcl = rp.ctypes.data, (cl.ctypes.data if nnz else None)
         s = stream if stream is not None else _current_stream()
     h = ctypes.c_void_p()
-    _check(lib.huge_load_csr(int(n), int(nnz), prp, pcl, flags, s, ctypes.byref(h)))
+    if labels is None:
+        _check(lib.huge_load_csr(int(n), int(nnz), prp, pcl, flags, s, ctypes.byref(h)))
+    else:
+        if flags & DEVICE_PTRS:
+            lb = labels.to(_torch().int32).contiguous()
+            plb = lb.data_ptr()
+        else:
+            lb = np.ascontiguousarray(labels, dtype=np.int32)
+            plb = lb.ctypes.data
+        if lb.shape[0] != n:
+            raise ValueError("labels must hold one entry per vertex")
+        keep.append(lb)
+        _check(lib.huge_load_csr_labelled(int(n), int(nnz), prp, pcl, plb, flags, s, ctypes.byref(h)))
     return Graph(h.value, int(n), int(nnz))
 
 
-def plan(g: Graph, k, edges, order=None, learned=None, verify=False) -> Plan:
+def plan(g: Graph, k, edges, order=None, learned=None, verify=False, induced=False, labels=None) -> Plan:
     """huge_plan_create for query edges over vertices 0..k-1; with a Model as
     `learned`, huge_plan_create_learned2 (orders scored by the MLP on the GPU;
-    verify=True measures its best orders on a root sample)."""
+    verify=True measures its best orders on a small sample).  induced=True keeps
+    only induced matches (HUGE_PLAN_INDUCED); labels (one int per query vertex,
+    -1 any) plan a labelled query (huge_plan_create_labelled)."""
     lib = load_library()
     e = np.ascontiguousarray(np.asarray(edges, dtype=np.int32).reshape(-1, 2))
     o = None if order is None else np.ascontiguousarray(np.asarray(order, dtype=np.int32))
     h = ctypes.c_void_p()
+    ind = PLAN_INDUCED if induced else 0
+    if labels is not None:
+        if learned:
+            raise ValueError("labelled queries are planned by the cost model")
+        ql = np.ascontiguousarray(np.asarray(labels, dtype=np.int32))
+        if ql.shape != (int(k),):
+            raise ValueError("labels must hold one entry per query vertex")
+        _check(lib.huge_plan_create_labelled(None if g is None else g.handle, int(k), int(e.shape[0]), e.ctypes.data,
+                                             ql.ctypes.data, None if o is None else o.ctypes.data, ind,
+                                             ctypes.byref(h)))
+        return Plan(h.value, int(k))
     if isinstance(learned, Model):
         _check(lib.huge_plan_create_learned2(g.handle, learned.handle, int(k), int(e.shape[0]), e.ctypes.data,
-                                             None if o is None else o.ctypes.data, PLAN_VERIFY if verify else 0,
-                                             _current_stream(), ctypes.byref(h)))
+                                             None if o is None else o.ctypes.data,
+                                             (PLAN_VERIFY if verify else 0) | ind, _current_stream(), ctypes.byref(h)))
     else:
         _check(lib.huge_plan_create(None if g is None else g.handle, int(k), int(e.shape[0]), e.ctypes.data,
                                     None if o is None else o.ctypes.data,
-                                    PLAN_LEARNED if learned else PLAN_COST_MODEL, ctypes.byref(h)))
+                                    (PLAN_LEARNED if learned else PLAN_COST_MODEL) | ind, ctypes.byref(h)))
     return Plan(h.value, int(k))
 
 
@@ -495,6 +546,19 @@ def count(g: Graph, p: Plan, workspace: Workspace | None = _default_ws, **kw) ->
     d = r.to_dict()
     d["stopped"] = status == HUGE_STOPPED
     return d
+
+
+def motif_count(g: Graph, k: int, **kw) -> list:
+    """huge_motif_count: every connected k-vertex pattern with its non-induced count
+    (and set-hashes) and induced count, as dicts."""
+    lib = load_library()
+    opts = exec_opts(**kw)
+    out = (Motif * MOTIF_MAX)()
+    n = ctypes.c_int32()
+    _check(lib.huge_motif_count(g.handle, int(k), ctypes.byref(opts), out, ctypes.byref(n)))
+    return [{"k": m.k, "edges": [(m.edges[2 * i], m.edges[2 * i + 1]) for i in range(m.n_edges)],
+             "noninduced": int(m.noninduced), "induced": int(m.induced), "hash_sum": int(m.hash_sum),
+             "hash_xor": int(m.hash_xor)} for m in out[: n.value]]
 
 
 def plan_prefix(p: Plan, size: int) -> Plan:

@@ -72,6 +72,22 @@ huge_status huge_load_csr(int64_t n, int64_t nnz, const int64_t *row_ptr, const 
     });
 }
 
+huge_status huge_load_csr_labelled(int64_t n, int64_t nnz, const int64_t *row_ptr, const int32_t *col,
+                                   const int32_t *labels, uint32_t flags, void *stream, huge_graph **out) {
+    return guard([&] {
+        if (!out) HUGE_FAIL(HUGE_EINVAL, "out is NULL");
+        huge_graph *g = graph_load(n, nnz, row_ptr, col, flags, (hipStream_t)stream);
+        try {
+            graph_set_labels(g, labels, flags, (hipStream_t)stream);
+        } catch (...) {
+            graph_free(g);
+            throw;
+        }
+        *out = g;
+        return HUGE_OK;
+    });
+}
+
 void huge_graph_free(huge_graph *g) { graph_free(g); }
 
 huge_status huge_graph_get_info(const huge_graph *g, huge_graph_info *out) {
@@ -100,7 +116,25 @@ huge_status huge_plan_create(const huge_graph *g, int32_t k, int32_t n_qedges, c
         huge_plan *p = new huge_plan();
         try {
             if (flags & HUGE_PLAN_LEARNED) HUGE_FAIL(HUGE_EINVAL, "a learned plan needs a model: use huge_plan_create_learned");
+            if (flags & ~(uint32_t)HUGE_PLAN_INDUCED) HUGE_FAIL(HUGE_EINVAL, "unknown plan flags 0x%x", flags);
             plan_build(g, k, n_qedges, qedges, order, flags, nullptr, nullptr, p);
+        } catch (...) {
+            delete p;
+            throw;
+        }
+        *out = p;
+        return HUGE_OK;
+    });
+}
+
+huge_status huge_plan_create_labelled(const huge_graph *g, int32_t k, int32_t n_qedges, const int32_t *qedges,
+                                      const int32_t *qlabels, const int32_t *order, uint32_t flags, huge_plan **out) {
+    return guard([&] {
+        if (!out || !qlabels) HUGE_FAIL(HUGE_EINVAL, "NULL argument");
+        if (flags & ~(uint32_t)HUGE_PLAN_INDUCED) HUGE_FAIL(HUGE_EINVAL, "unknown plan flags 0x%x", flags);
+        huge_plan *p = new huge_plan();
+        try {
+            plan_build(g, k, n_qedges, qedges, order, flags, nullptr, nullptr, p, qlabels);
         } catch (...) {
             delete p;
             throw;
@@ -141,6 +175,14 @@ huge_status huge_plan_info(const huge_plan *p, int32_t *k, int32_t *order_out, i
     });
 }
 
+huge_status huge_plan_estimates(const huge_plan *p, double *est) {
+    return guard([&] {
+        if (!p || !est) HUGE_FAIL(HUGE_EINVAL, "NULL argument");
+        for (int i = 0; i < HUGE_KMAX; ++i) est[i] = i < p->k ? p->est_prefix[i] : 0.0;
+        return HUGE_OK;
+    });
+}
+
 huge_status huge_workspace_size(const huge_graph *g, const huge_plan *p, const huge_exec_opts *opts,
                                 uint64_t *bytes) {
     return guard([&] {
@@ -156,6 +198,7 @@ huge_status huge_count(const huge_graph *g, const huge_plan *p, const huge_exec_
         if (!g || !p || !out) HUGE_FAIL(HUGE_EINVAL, "NULL argument");
         huge_exec_opts o = resolve_opts(opts);
         if (o.work_limit < 0) HUGE_FAIL(HUGE_EINVAL, "work_limit < 0");
+        check_labels(g, p);
         huge_result r;
         bool limited = false;
         if (o.engine == HUGE_ENGINE_PERSISTENT) {
@@ -177,6 +220,7 @@ huge_status huge_enumerate(const huge_graph *g, const huge_plan *p, const huge_e
         if (!g || !p || !out) HUGE_FAIL(HUGE_EINVAL, "NULL argument");
         huge_exec_opts o = resolve_opts(opts);
         if (o.engine == HUGE_ENGINE_GRAPH) HUGE_FAIL(HUGE_EINVAL, "huge_enumerate does not run on the graph engine");
+        check_labels(g, p);
         EmitSink sink;
         sink.host_buf = host_buf;
         sink.buf_rows = buf_rows;
@@ -193,8 +237,10 @@ huge_status huge_count_batch(const huge_graph *g, const huge_plan *const *plans,
                              const huge_exec_opts *opts, huge_result *outs) {
     return guard([&] {
         if (!g || !plans || np <= 0 || !outs) HUGE_FAIL(HUGE_EINVAL, "bad arguments");
-        for (int i = 0; i < np; ++i)
+        for (int i = 0; i < np; ++i) {
             if (!plans[i]) HUGE_FAIL(HUGE_EINVAL, "plan %d is NULL", i);
+            check_labels(g, plans[i]);
+        }
         huge_exec_opts o = resolve_opts(opts);
         std::vector<huge_result> r(np);
         if (o.engine == HUGE_ENGINE_GRAPH) {  // batched rounds, kMaxBatch queries at a time
@@ -244,6 +290,19 @@ huge_status huge_batch_workspace_size(const huge_graph *g, const huge_plan *cons
         for (int i = 0; i < np; i += kMaxBatch)
             b = std::max(b, mgraph_workspace_bytes(g, plans + i, std::min(kMaxBatch, np - i), o));
         *bytes = b;
+        return HUGE_OK;
+    });
+}
+
+huge_status huge_motif_count(const huge_graph *g, int32_t k, const huge_exec_opts *opts, huge_motif *out,
+                             int32_t *n_out) {
+    return guard([&] {
+        if (!g || !out || !n_out) HUGE_FAIL(HUGE_EINVAL, "NULL argument");
+        huge_exec_opts o = resolve_opts(opts);
+        std::vector<huge_motif> r(HUGE_MOTIF_MAX);
+        const int n = motif_count(g, k, o, r.data());
+        for (int i = 0; i < n; ++i) out[i] = r[i];
+        *n_out = n;
         return HUGE_OK;
     });
 }
@@ -323,7 +382,7 @@ huge_status huge_plan_create_learned2(const huge_graph *g, const huge_model *m, 
                                       huge_plan **out) {
     return guard([&] {
         if (!g || !m || !out) HUGE_FAIL(HUGE_EINVAL, "NULL argument");
-        if (flags & ~(uint32_t)HUGE_PLAN_VERIFY) HUGE_FAIL(HUGE_EINVAL, "unknown flags 0x%x", flags);
+        if (flags & ~(uint32_t)(HUGE_PLAN_VERIFY | HUGE_PLAN_INDUCED)) HUGE_FAIL(HUGE_EINVAL, "unknown flags 0x%x", flags);
         huge_plan *p = new huge_plan();
         try {
             plan_build(g, k, n_qedges, qedges, order, HUGE_PLAN_LEARNED | flags, m, (hipStream_t)stream, p);
@@ -340,8 +399,10 @@ huge_status huge_autotune(const huge_graph *g, const huge_plan *const *plans, in
                           huge_tune_table *out) {
     return guard([&] {
         if (!g || !plans || np <= 0 || !out) HUGE_FAIL(HUGE_EINVAL, "bad arguments");
-        for (int i = 0; i < np; ++i)
+        for (int i = 0; i < np; ++i) {
             if (!plans[i]) HUGE_FAIL(HUGE_EINVAL, "plan %d is NULL", i);
+            check_labels(g, plans[i]);
+        }
         huge_exec_opts o = resolve_opts(opts);
         huge_tune_table t;
         autotune(g, plans, np, o, &t);

@@ -85,8 +85,14 @@ __device__ __forceinline__ bool slices_ok(int32_t bits, int32_t v, const DevPlan
 // Validity of a level-2 row (the SCAN of the first query edge): the
 // constraint between positions 0 and 1, and the slices (of the row's ordered
 // pair, or of the vertex in position 0 or 1).
-__device__ __forceinline__ bool level2_ok(const int32_t (&f)[2], const DevPlan &P) {
+// the label the plan asks of position i's vertex v (labelled plans)
+__device__ __forceinline__ bool label_ok(const GraphDev &g, int32_t want, int32_t v) {
+    return want < 0 || g.label[v] == want;
+}
+
+__device__ __forceinline__ bool level2_ok(const int32_t (&f)[2], const DevPlan &P, const GraphDev &g) {
     const DevStep &s1 = P.st[1];
+    if (!label_ok(g, P.st[0].label, f[0]) || !label_ok(g, s1.label, f[1])) return false;
     if ((s1.lo & 1u) && !(f[0] < f[1])) return false;
     if ((s1.hi & 1u) && !(f[1] < f[0])) return false;
     if (P.slice_count > 1 && P.edge_slice) {

@@ -23,6 +23,7 @@
 #include <chrono>
 #include <cstddef>
 #include <cstring>
+#include <mutex>
 
 #include "internal.h"
 #include "prims.h"
@@ -155,9 +156,10 @@ DevPlan exec_plan(const huge_plan *p, const huge_exec_opts &o) {
     return P;
 }
 
-// level_counts[0] counts the roots in the slices that apply to position 0
+// level_counts[0] counts the roots in the slices, and with the label, that apply to position 0
 bool root_sliced(const DevPlan &P) {
-    return ((P.st[0].slice & 1) && P.slice_count > 1 && !P.edge_slice) || ((P.st[0].slice & 2) && P.slice2_count > 1);
+    return ((P.st[0].slice & 1) && P.slice_count > 1 && !P.edge_slice) || ((P.st[0].slice & 2) && P.slice2_count > 1) ||
+           P.st[0].label >= 0;
 }
 
 // A strided slice of the first matched vertex: level 2 is gathered, not scanned.
@@ -178,13 +180,43 @@ int64_t gathered_roots(const huge_graph *g, const DevPlan &P) {
 
 namespace {
 
-// Pinned host memory for the scheduler's read-backs, one block per engine call:
-// a device-to-host copy lands there directly instead of through a staging copy.
+// Pinned host memory for the scheduler's read-backs: a device-to-host copy lands
+// there directly instead of through a staging copy.  Blocks come from a process
+// pool (a call takes one and gives it back; the pool holds as many as calls ever
+// ran at once and is never freed), so a call does not pay for an allocation;
+// callers that must not allocate hand in a host block of their own instead.
+struct PinnedPool {
+    std::mutex mu;
+    std::vector<unsigned char *> free_blocks;
+};
+PinnedPool &pinned_pool() {
+    static PinnedPool *pool = new PinnedPool();  // never destroyed: blocks outlive static teardown
+    return *pool;
+}
 struct PinnedBuf {
     unsigned char *p = nullptr;
-    explicit PinnedBuf(size_t bytes) { HUGE_HIP(hipHostMalloc((void **)&p, bytes, hipHostMallocDefault)); }
+    bool pooled = false;
+    PinnedBuf(size_t bytes, unsigned char *given) {
+        if (given) {
+            p = given;
+            return;
+        }
+        PinnedPool &pool = pinned_pool();
+        {
+            std::lock_guard<std::mutex> lock(pool.mu);
+            if (!pool.free_blocks.empty()) {
+                p = pool.free_blocks.back();
+                pool.free_blocks.pop_back();
+            }
+        }
+        if (!p) HUGE_HIP(hipHostMalloc((void **)&p, bytes, hipHostMallocDefault));
+        pooled = true;
+    }
     ~PinnedBuf() {
-        if (p) (void)hipHostFree(p);
+        if (!pooled) return;
+        PinnedPool &pool = pinned_pool();
+        std::lock_guard<std::mutex> lock(pool.mu);
+        pool.free_blocks.push_back(p);
     }
 };
 
@@ -259,12 +291,16 @@ struct Profiler {
 };
 
 uint64_t workspace_bytes(const huge_graph *g, const huge_plan *p, const huge_exec_opts &o) {
+    if (o.engine == HUGE_ENGINE_PERSISTENT) {
+        const huge_plan *pl[1] = {p};
+        return persist_workspace_bytes(pl, 1, o);
+    }
     if (o.engine == HUGE_ENGINE_GRAPH) return make_layout(g, p, o, 0, scan_devn_max()).total + align_up(sizeof(GState));
     return make_layout(g, p, o, 1 << 16).total;
 }
 
 bool run_levels(const huge_graph *g, const huge_plan *p, const huge_exec_opts &o, huge_result *out, EmitSink *emit,
-                TuneProbe *probe) {
+                TuneProbe *probe, unsigned char *host_stage) {
     auto t0 = std::chrono::steady_clock::now();
     hipStream_t st = (hipStream_t)o.stream;
     const int k = p->k;
@@ -277,7 +313,7 @@ bool run_levels(const huge_graph *g, const huge_plan *p, const huge_exec_opts &o
         stage_rows = std::min<int64_t>(emit->buf_rows, 1 << 22);
     }
     Layout L = make_layout(g, p, o, stage_rows);
-    PinnedBuf pinned(sizeof(Ctrl) + 64);
+    PinnedBuf pinned(kHostStageBytes, host_stage);
     int64_t *pin64 = (int64_t *)(pinned.p + sizeof(Ctrl));
     DevMem own;
     char *ws = (char *)o.workspace;

@@ -56,7 +56,7 @@ __global__ __launch_bounds__(kT) void k_edge_sink(GraphDev g, DevPlan P, int64_t
     int32_t f[2] = {0, 0};
     if (e < e1) {
         load_row<2>(nullptr, g, e, f);
-        ok = level2_ok(f, P);
+        ok = level2_ok(f, P, g);
     }
     const int wv = threadIdx.x >> 6;
     if (mode == MODE_COUNT) {
@@ -107,10 +107,11 @@ __global__ __launch_bounds__(kT) void k_edge_sink(GraphDev g, DevPlan P, int64_t
     }
 }
 
-__global__ __launch_bounds__(kT) void k_root_count(int64_t n, DevPlan P, Ctrl *ctrl) {
+__global__ __launch_bounds__(kT) void k_root_count(GraphDev g, DevPlan P, Ctrl *ctrl) {
     __shared__ unsigned long long s[kT / 64];
     const int64_t v = (int64_t)blockIdx.x * kT + threadIdx.x;
-    unsigned long long c = (v < n && slices_ok(P.st[0].slice, (int32_t)v, P)) ? 1 : 0;
+    unsigned long long c =
+        (v < g.n && slices_ok(P.st[0].slice, (int32_t)v, P) && label_ok(g, P.st[0].label, (int32_t)v)) ? 1 : 0;
     c = wave_sum_u64(c);
     if (__lane_id() == 0) s[threadIdx.x >> 6] = c;
     __syncthreads();
@@ -524,7 +525,7 @@ void launch_gather_level2(const GraphDev &g, const DevPlan &P, int64_t roots, in
 
 void launch_root_count(const GraphDev &g, const DevPlan &P, Ctrl *ctrl, hipStream_t st) {
     dim3 grid((unsigned)((g.n + kT - 1) / kT));
-    hipLaunchKernelGGL(k_root_count, grid, dim3(kT), 0, st, g.n, P, ctrl);
+    hipLaunchKernelGGL(k_root_count, grid, dim3(kT), 0, st, g, P, ctrl);
     HUGE_HIP(hipGetLastError());
 }
 

@@ -420,8 +420,41 @@ huge_graph *graph_load(int64_t n, int64_t nnz, const int64_t *rp_in, const int32
     return g;
 }
 
+namespace {
+// label of rank r = the label of the original vertex holding rank r
+__global__ void k_rank_labels(const int32_t *__restrict__ inv_rank, const int32_t *__restrict__ in, int64_t n,
+                              int32_t *__restrict__ out) {
+    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r < n) out[r] = in[inv_rank[r]];
+}
+}  // namespace
+
+void graph_set_labels(huge_graph *g, const int32_t *labels, uint32_t flags, hipStream_t st) {
+    const int64_t n = g->dev.n;
+    if (!labels && n > 0) HUGE_FAIL(HUGE_EINVAL, "labels is NULL");
+    HUGE_HIP(hipMalloc(&g->label, sizeof(int32_t) * (size_t)std::max<int64_t>(1, n)));
+    if (n > 0) {
+        const int32_t *in = labels;
+        int32_t *tmp = nullptr;
+        if (flags & HUGE_HOST_PTRS) {
+            HUGE_HIP(hipMalloc(&tmp, sizeof(int32_t) * (size_t)n));
+            HUGE_HIP(hipMemcpyAsync(tmp, labels, sizeof(int32_t) * (size_t)n, hipMemcpyHostToDevice, st));
+            in = tmp;
+        }
+        hipLaunchKernelGGL(k_rank_labels, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, g->inv_rank, in, n,
+                           g->label);
+        const hipError_t e = hipGetLastError();
+        HUGE_HIP(hipStreamSynchronize(st));
+        if (tmp) (void)hipFree(tmp);
+        HUGE_HIP(e);
+    }
+    g->dev.label = g->label;
+    g->info.device_bytes += 4ull * (uint64_t)n;
+}
+
 void graph_free(huge_graph *g) {
     if (!g) return;
+    if (g->label) (void)hipFree(g->label);
     if (g->rp) (void)hipFree(g->rp);
     if (g->col) (void)hipFree(g->col);
     if (g->src) (void)hipFree(g->src);

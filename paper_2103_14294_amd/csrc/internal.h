@@ -53,6 +53,7 @@ struct GraphDev {
     // level-2 rows of one execution: row r is edge-array entry l2_idx[r], or
     // entry r when l2_idx is NULL (every entry)
     const int64_t *l2_idx = nullptr;
+    const int32_t *label = nullptr;  // vertex labels by rank (labelled graphs), or NULL
 };
 
 }  // namespace huge
@@ -64,6 +65,7 @@ struct huge_graph {
     int32_t *src = nullptr;
     int32_t *inv_rank = nullptr;  // rank -> original ID
     uint32_t *hub_bm = nullptr;
+    int32_t *label = nullptr;     // vertex labels by rank, or NULL (unlabelled)
     huge_graph_info info{};
     int device = 0;
     std::string sha;  // content digest of the relabelled CSR (autotune cache key)
@@ -80,7 +82,8 @@ struct DevStep {
     uint32_t hi;    // positions p with constraint v < f[p]
     uint32_t neq;   // positions p < i not in ext (injectivity checks)
     int32_t slice;  // slice filters on position i's vertex: bit 0 the slice, bit 1 the second slice
-    int32_t pad;
+    uint32_t nadj;  // induced plans: positions p < i not adjacent to position i in q (v must not be in N(f[p]))
+    int32_t label;  // labelled plans: the label position i's vertex must carry, -1 any
 };
 
 struct DevPlan {
@@ -107,6 +110,9 @@ struct huge_plan {
     double est_cost = 0;                     // sum over prefixes of estimated partial matches
     double est_prefix[HUGE_KMAX] = {};       // estimated partial matches per prefix size
     uint32_t flags = 0;
+    bool induced = false;                    // HUGE_PLAN_INDUCED: non-edges of q must map to non-edges
+    int32_t qlabel[HUGE_KMAX] = {-1, -1, -1, -1, -1, -1, -1, -1};  // labelled queries: label per query vertex
+    bool labelled = false;
     huge::DevPlan dev{};
 };
 
@@ -126,7 +132,9 @@ namespace huge {
 
 // plan.cpp
 void plan_build(const huge_graph *g, int k, int ne, const int32_t *qe, const int32_t *order, uint32_t flags,
-                const huge_model *model, hipStream_t st, huge_plan *out);
+                const huge_model *model, hipStream_t st, huge_plan *out, const int32_t *qlabels = nullptr);
+// a labelled plan needs a labelled graph (HUGE_EINVAL otherwise)
+void check_labels(const huge_graph *g, const huge_plan *p);
 bool order_connected(const huge_plan &p, const int32_t *order);
 void plan_set_order(huge_plan &p, const int32_t *order);
 double estimate_prefix(const huge_graph_info &gi, const huge_plan &p, const int32_t *order, int size);
@@ -152,6 +160,8 @@ void model_train(huge_model *m, const float *x, const float *t, int64_t N, int e
 // graph.hip
 huge_graph *graph_load(int64_t n, int64_t nnz, const int64_t *rp, const int32_t *col, uint32_t flags,
                        hipStream_t stream);
+// labels[u] by original ID (host or device memory per flags) -> g->label by rank
+void graph_set_labels(huge_graph *g, const int32_t *labels, uint32_t flags, hipStream_t stream);
 void graph_free(huge_graph *g);
 
 // engine.cpp
@@ -181,9 +191,10 @@ bool root_sliced(const DevPlan &P);       // level_counts[0] is the number of ro
 bool gathers_level2(const DevPlan &P);    // level 2 is the gathered entries of a strided root slice
 int64_t gathered_rows_bound(const huge_graph *g, const DevPlan &P);
 int64_t gathered_roots(const huge_graph *g, const DevPlan &P);
-// returns true when the run stopped at o.work_limit
+// returns true when the run stopped at o.work_limit; host_stage: a host block of
+// kHostStageBytes for the scheduler's read-backs (NULL: pinned memory is allocated)
 bool run_levels(const huge_graph *g, const huge_plan *p, const huge_exec_opts &o, huge_result *out, EmitSink *emit,
-                TuneProbe *probe = nullptr);
+                TuneProbe *probe = nullptr, unsigned char *host_stage = nullptr);
 // counting through replays of a recorded round (HUGE_ENGINE_GRAPH)
 void run_graph(const huge_graph *g, const huge_plan *p, const huge_exec_opts &o, huge_result *out);
 void autotune(const huge_graph *g, const huge_plan *const *plans, int np, const huge_exec_opts &o,
@@ -193,6 +204,9 @@ void run_batch_levels(const huge_graph *g, const huge_plan *const *plans, int np
                       huge_result *outs);
 void run_persistent(const huge_graph *g, const huge_plan *const *plans, int np, const huge_exec_opts &o,
                     huge_result *outs);
+uint64_t persist_workspace_bytes(const huge_plan *const *plans, int np, const huge_exec_opts &o);
+// motif.cpp: every connected k-vertex pattern, non-induced and induced counts; returns the pattern count
+int motif_count(const huge_graph *g, int k, const huge_exec_opts &o, huge_motif *out);
 // mbatch.cpp: the batch in batched rounds (HUGE_ENGINE_GRAPH)
 void run_mgraph(const huge_graph *g, const huge_plan *const *plans, int np, const huge_exec_opts &o,
                 huge_result *outs);
@@ -224,6 +238,8 @@ struct Ctrl {                      // device-resident counters
     unsigned long long segbytes[HUGE_KMAX];     // algorithmic bytes of the current segment, per width
     long long scratch[8];
 };
+
+constexpr size_t kHostStageBytes = sizeof(Ctrl) + 64;  // the level engine's host read-back block
 
 void launch_prepare(int width, bool last, const GraphDev &g, const DevPlan &P, const int32_t *rows, int64_t row0,
                     int64_t nrows, const SegBufs &s, Ctrl *ctrl, hipStream_t st);

@@ -39,6 +39,7 @@
 // 3, and the kernel keeps every row in registers.
 #include <algorithm>
 #include <chrono>
+#include <cmath>
 #include <cstdlib>
 #include <cstring>
 
@@ -84,6 +85,7 @@ struct PersistArgs {
     int *busy;
     int *err;
     unsigned long long *stats;   // [0] row steals, [1] stolen rows, [2] sum of per-WG peak bytes, [3] helped tiles
+    unsigned long long *wg_busy; // [nwg] wall-clock ticks each WG spent in tiles and prepare passes
     uint64_t limit_ticks;        // longest wait, in wall-clock ticks
 };
 
@@ -216,7 +218,7 @@ __device__ void prepare_chunk(const PersistArgs &a, const DevPlan &P, bool last,
         int32_t f[W];
         load_row<W>(level_buf(a, blockIdx.x, W), g, L.row0 + t, f);
         valid = true;
-        if constexpr (W == 2) valid = level2_ok(f, P);
+        if constexpr (W == 2) valid = level2_ok(f, P, g);
         if (valid) {
             const DevStep &st = P.st[W];
             int32_t lo = 0, hi = 0x7FFFFFFF;
@@ -431,10 +433,21 @@ __device__ uint32_t dq_prepare_append(const PersistArgs &a, int W, int plan) {
     }
 }
 
+// Time thread 0 sees the workgroup spend in a piece of work (a tile or a
+// chunk's prepare pass; each ends with a workgroup barrier), for the per-WG
+// busy times that show how evenly the load is spread.
+#define HUGE_BUSY(...)                                        \
+    do {                                                      \
+        const uint64_t busy_t0_ = wall_clock64();             \
+        __VA_ARGS__;                                          \
+        if (t == 0) busy_ticks += wall_clock64() - busy_t0_;  \
+    } while (0)
+
 template <int K>
 __global__ __launch_bounds__(kT) void k_persist(PersistArgs a) {
     __shared__ Shared sh;
     const int t = threadIdx.x;
+    uint64_t busy_ticks = 0;  // thread 0: time spent in tiles and prepare passes
     unsigned long long cnt = 0, hs = 0, hx = 0;  // per lane, for query sh.plan
     const uint64_t deadline = wall_clock64() + a.limit_ticks;
     int counted = 1;  // thread 0 only: this WG is counted in *busy
@@ -491,7 +504,7 @@ __global__ __launch_bounds__(kT) void k_persist(PersistArgs a) {
                 sh.W = 2;
             }
             __syncthreads();
-            prepare_any<K>(2, a, a.plans[sh.plan], sh.k == 3, sh);
+            HUGE_BUSY(prepare_any<K>(2, a, a.plans[sh.plan], sh.k == 3, sh));
         } else {
             // ---- no fresh edges anywhere: help a big last-level chunk, steal
             // rows, or finish when nothing is left
@@ -585,7 +598,7 @@ __global__ __launch_bounds__(kT) void k_persist(PersistArgs a) {
                     cv.pinfo = b.pinfo;
                     cv.hpre = b.hpre;
                     const int64_t w0 = (int64_t)sh.tile * kPTile;
-                    tile_any<K>(W, true, a, a.plans[plan], cv, sh, w0, min(w0 + (int64_t)kPTile, b.total), cnt, hs, hx);
+                    HUGE_BUSY(tile_any<K>(W, true, a, a.plans[plan], cv, sh, w0, min(w0 + (int64_t)kPTile, b.total), cnt, hs, hx));
                     flush_counts(a, sh, plan, k, cnt, hs, hx);
                     if (t == 0) {
                         __threadfence();
@@ -651,7 +664,7 @@ __global__ __launch_bounds__(kT) void k_persist(PersistArgs a) {
                     // fused SINK: consume the whole chunk, then back to the precursor
                     const int64_t ntiles = (L.total + kPTile - 1) / kPTile;
                     if (ntiles <= 1) {
-                        tile_any<K>(W, true, a, P, cv, sh, 0, L.total, cnt, hs, hx);
+                        HUGE_BUSY(tile_any<K>(W, true, a, P, cv, sh, 0, L.total, cnt, hs, hx));
                     } else {
                         // publish the chunk so that idle WGs can take tiles of it
                         for (int i = t; i <= L.nrows; i += kT) myb.off[i] = sh.off[W][i];
@@ -682,7 +695,7 @@ __global__ __launch_bounds__(kT) void k_persist(PersistArgs a) {
                             const int tile = sh.tile;
                             if (tile < 0) break;
                             const int64_t w0 = (int64_t)tile * kPTile;
-                            tile_any<K>(W, true, a, P, cv, sh, w0, min(w0 + (int64_t)kPTile, L.total), cnt, hs, hx);
+                            HUGE_BUSY(tile_any<K>(W, true, a, P, cv, sh, w0, min(w0 + (int64_t)kPTile, L.total), cnt, hs, hx));
                             __syncthreads();
                             if (t == 0) atomicAdd(&myb.done, 1ull);
                         }
@@ -711,7 +724,7 @@ __global__ __launch_bounds__(kT) void k_persist(PersistArgs a) {
                 __syncthreads();
                 if (sh.action) {
                     const int64_t w0 = L.done, w1 = min(L.done + (int64_t)kPTile, L.total);
-                    tile_any<K>(W, false, a, P, cv, sh, w0, w1, cnt, hs, hx);
+                    HUGE_BUSY(tile_any<K>(W, false, a, P, cv, sh, w0, w1, cnt, hs, hx));
                     __threadfence();
                     __syncthreads();
                     if (t == 0) {
@@ -763,7 +776,7 @@ __global__ __launch_bounds__(kT) void k_persist(PersistArgs a) {
                 const int got = sh.action;
                 __syncthreads();  // read before thread 0 reuses sh.action
                 if (!got) break;  // this query's edges are exhausted and every deeper level is empty
-                prepare_any<K>(2, a, P, k == 3, sh);
+                HUGE_BUSY(prepare_any<K>(2, a, P, k == 3, sh));
                 continue;
             }
             if (t == 0) {
@@ -778,52 +791,51 @@ __global__ __launch_bounds__(kT) void k_persist(PersistArgs a) {
                 }
             }
             __syncthreads();
-            if (sh.action) prepare_any<K>(W, a, P, W == k - 1, sh);
+            if (sh.action) HUGE_BUSY(prepare_any<K>(W, a, P, W == k - 1, sh));
         }
         if (sh.W < 0) break;
     }
     flush_counts(a, sh, sh.plan, sh.k, cnt, hs, hx);
     if (t == 0) {
         atomicAdd(&a.stats[2], sh.peak_bytes);
+        a.wg_busy[blockIdx.x] = busy_ticks;
         if (counted) atomicSub(a.busy, 1);
     }
 }
+#undef HUGE_BUSY
 
 constexpr int kKMax = 4;  // largest query size the kernel is built for
 
 }  // namespace
 
-void run_persistent(const huge_graph *g, const huge_plan *const *plans, int np, const huge_exec_opts &o,
-                    huge_result *outs) {
-    auto t0 = std::chrono::steady_clock::now();
-    hipStream_t st = (hipStream_t)o.stream;
+namespace {
+
+// Device memory of one persistent launch, carved from one block.
+struct PersistLayout {
+    int nwg = 0, kmax = 3;
+    int64_t rows = 0, wg_ints = 0;
+    int64_t lvl_off[kLv] = {};
+    int32_t cap[kLv] = {};
+    uint64_t buf_bytes = 0, board_bytes = 0, ctl_bytes = 0, plan_bytes = 0, total = 0;
+};
+
+PersistLayout persist_layout(const huge_plan *const *plans, int np, const huge_exec_opts &o) {
+    PersistLayout L;
     if (np < 1 || np > 4096) HUGE_FAIL(HUGE_EINVAL, "bad number of plans %d", np);
-    if (o.slice_mode != HUGE_SLICE_MIX || o.slice2_count > 1)
-        HUGE_FAIL(HUGE_EINVAL, "the persistent engine takes mixed slices of one vertex or edge only");
-    std::vector<DevPlan> dp(np);
-    int kmax = 3;
     for (int i = 0; i < np; ++i) {
-        const huge_plan *p = plans[i];
-        if (p->k < 3) HUGE_FAIL(HUGE_EINVAL, "the persistent engine needs queries of 3 or more vertices");
-        dp[i] = p->dev;
-        dp[i].slice_count = o.slice_count > 1 ? o.slice_count : 1;
-        dp[i].slice_id = o.slice_count > 1 ? o.slice_id : 0;
-        if (dp[i].slice_count > 1 && dp[i].slice_id >= dp[i].slice_count) HUGE_FAIL(HUGE_EINVAL, "slice_id >= slice_count");
-        if (o.slice_vertex < -2 || o.slice_vertex >= p->k) HUGE_FAIL(HUGE_EINVAL, "slice_vertex out of range");
-        const int sv = o.slice_vertex == -1 ? p->order[0] : o.slice_vertex;  // -2: edge slice, no vertex
-        for (int j = 0; j < p->k; ++j) dp[i].st[j].slice = p->order[j] == sv ? 1 : 0;
-        dp[i].edge_slice = (o.slice_vertex == -2 && dp[i].slice_count > 1) ? 1 : 0;
-        kmax = std::max(kmax, p->k);
+        if (plans[i]->k < 3) HUGE_FAIL(HUGE_EINVAL, "the persistent engine needs queries of 3 or more vertices");
+        if (plans[i]->induced || plans[i]->labelled)
+            HUGE_FAIL(HUGE_EINVAL, "the persistent engine does not run induced or labelled plans");
+        L.kmax = std::max(L.kmax, plans[i]->k);
     }
-    if (kmax > kKMax) HUGE_FAIL(HUGE_EINVAL, "the persistent engine supports queries of 3 to %d vertices", kKMax);
+    if (L.kmax > kKMax) HUGE_FAIL(HUGE_EINVAL, "the persistent engine supports queries of 3 to %d vertices", kKMax);
     int dev = 0, cus = 0;
     HUGE_HIP(hipGetDevice(&dev));
     HUGE_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
     int per_cu = 0;
     HUGE_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void *)k_persist<kKMax>, kT, 0));
     if (per_cu < 1) HUGE_FAIL(HUGE_EDEVICE, "persistent kernel cannot be resident");
-    const int nwg = cus * per_cu;
-
+    L.nwg = cus * per_cu;
     // level capacities from the frontier budget, at least two tiles per level
     uint64_t cap = o.frontier_cap_bytes;
     if (cap == UINT64_MAX) {
@@ -832,61 +844,109 @@ void run_persistent(const huge_graph *g, const huge_plan *const *plans, int np, 
         cap = (uint64_t)(fr * 0.5);
     }
     uint64_t row_slot_bytes = 0;
-    for (int W = 3; W <= kmax - 1; ++W) row_slot_bytes += 4ull * W;
-    int64_t rows = row_slot_bytes ? (int64_t)(cap / ((uint64_t)nwg * row_slot_bytes)) : 0;
+    for (int W = 3; W <= L.kmax - 1; ++W) row_slot_bytes += 4ull * W;
+    int64_t rows = row_slot_bytes ? (int64_t)(cap / ((uint64_t)L.nwg * row_slot_bytes)) : 0;
     rows = std::max<int64_t>(rows, 2 * kPTile);
-    rows = std::min<int64_t>(rows, (1 << 24) - 1);
+    L.rows = std::min<int64_t>(rows, (1 << 24) - 1);
+    int64_t ints = 0;
+    for (int W = 0; W < kLv; ++W) {
+        L.lvl_off[W] = ints;
+        if (W >= 3 && W <= L.kmax - 1) {
+            L.cap[W] = (int32_t)L.rows;
+            ints += L.rows * W;
+        }
+    }
+    L.wg_ints = std::max<int64_t>(ints, 1);
+    auto al = [](uint64_t x) { return (x + 255) & ~255ull; };
+    L.buf_bytes = al(4ull * L.wg_ints * L.nwg);
+    L.board_bytes = al((uint64_t)sizeof(Board) * L.nwg);
+    L.ctl_bytes = al(8ull * L.nwg * kLv + 4ull * L.nwg * kLv + 8ull * np + 8ull * np * kResStride + 64 + 8ull * L.nwg);
+    L.plan_bytes = al(sizeof(DevPlan) * np);
+    L.total = L.buf_bytes + L.board_bytes + L.ctl_bytes + L.plan_bytes;
+    return L;
+}
+
+}  // namespace
+
+uint64_t persist_workspace_bytes(const huge_plan *const *plans, int np, const huge_exec_opts &o) {
+    return persist_layout(plans, np, o).total;
+}
+
+void run_persistent(const huge_graph *g, const huge_plan *const *plans, int np, const huge_exec_opts &o,
+                    huge_result *outs) {
+    auto t0 = std::chrono::steady_clock::now();
+    hipStream_t st = (hipStream_t)o.stream;
+    if (o.slice_mode != HUGE_SLICE_MIX || o.slice2_count > 1)
+        HUGE_FAIL(HUGE_EINVAL, "the persistent engine takes mixed slices of one vertex or edge only");
+    const PersistLayout L = persist_layout(plans, np, o);
+    std::vector<DevPlan> dp(np);
+    for (int i = 0; i < np; ++i) {
+        const huge_plan *p = plans[i];
+        dp[i] = p->dev;
+        dp[i].slice_count = o.slice_count > 1 ? o.slice_count : 1;
+        dp[i].slice_id = o.slice_count > 1 ? o.slice_id : 0;
+        if (dp[i].slice_count > 1 && dp[i].slice_id >= dp[i].slice_count) HUGE_FAIL(HUGE_EINVAL, "slice_id >= slice_count");
+        if (o.slice_vertex < -2 || o.slice_vertex >= p->k) HUGE_FAIL(HUGE_EINVAL, "slice_vertex out of range");
+        const int sv = o.slice_vertex == -1 ? p->order[0] : o.slice_vertex;  // -2: edge slice, no vertex
+        for (int j = 0; j < p->k; ++j) dp[i].st[j].slice = p->order[j] == sv ? 1 : 0;
+        dp[i].edge_slice = (o.slice_vertex == -2 && dp[i].slice_count > 1) ? 1 : 0;
+    }
+    const int nwg = L.nwg;
     PersistArgs a{};
     a.g = g->dev;
     a.nplans = np;
     a.steal = o.work_stealing ? 1 : 0;
-    int64_t ints = 0;
     for (int W = 0; W < kLv; ++W) {
-        a.lvl_off[W] = ints;
-        a.cap[W] = 0;
-        if (W >= 3 && W <= kmax - 1) {
-            a.cap[W] = (int32_t)rows;
-            ints += rows * W;
-        }
+        a.lvl_off[W] = L.lvl_off[W];
+        a.cap[W] = L.cap[W];
     }
-    a.wg_ints = std::max<int64_t>(ints, 1);
-    const uint64_t buf_bytes = (4ull * a.wg_ints * nwg + 255) & ~255ull;
-    const uint64_t board_bytes = ((uint64_t)sizeof(Board) * nwg + 255) & ~255ull;
-    const uint64_t ctl_bytes = 8ull * nwg * kLv + 4ull * nwg * kLv + 8ull * np + 8ull * np * kResStride + 64;
-    void *mem = nullptr;
-    HUGE_HIP(hipMalloc(&mem, buf_bytes + board_bytes + ctl_bytes + 1024));
+    a.wg_ints = L.wg_ints;
+    // the caller's workspace when it is large enough (huge_workspace_size), else one allocation
     struct Free {
-        void *p;
+        void *p = nullptr;
         ~Free() {
             if (p) (void)hipFree(p);
         }
-    } fr{mem};
-    char *c = (char *)mem;
+    } own;
+    char *mem = (char *)o.workspace;
+    if (mem) {
+        if (o.workspace_bytes < L.total)
+            HUGE_FAIL(HUGE_ENOMEM, "workspace too small: %llu bytes given, %llu needed",
+                      (unsigned long long)o.workspace_bytes, (unsigned long long)L.total);
+    } else {
+        HUGE_HIP(hipMalloc(&own.p, L.total));
+        mem = (char *)own.p;
+    }
+    char *c = mem;
     a.bufs = (int32_t *)c;
-    c += buf_bytes;
+    c += L.buf_bytes;
     a.boards = (Board *)c;
     char *zero_from = c;
-    c += board_bytes;
-    a.deq = (unsigned long long *)c;
-    c += 8ull * nwg * kLv;
-    a.pending = (int *)c;
-    c += 4ull * nwg * kLv;
-    a.cursor = (unsigned long long *)c;
-    c += 8ull * np;
-    a.res = (unsigned long long *)c;
-    c += 8ull * np * kResStride;
-    a.busy = (int *)c;
-    a.err = (int *)(c + 4);
-    a.stats = (unsigned long long *)(c + 8);
-    int wall_khz = 0;
+    c += L.board_bytes;
+    char *ctl = c;
+    a.deq = (unsigned long long *)ctl;
+    ctl += 8ull * nwg * kLv;
+    a.pending = (int *)ctl;
+    ctl += 4ull * nwg * kLv;
+    a.cursor = (unsigned long long *)ctl;
+    ctl += 8ull * np;
+    a.res = (unsigned long long *)ctl;
+    ctl += 8ull * np * kResStride;
+    a.busy = (int *)ctl;
+    a.err = (int *)(ctl + 4);
+    a.stats = (unsigned long long *)(ctl + 8);
+    a.wg_busy = (unsigned long long *)(ctl + 64);
+    c += L.ctl_bytes;
+    DevPlan *dplans = (DevPlan *)c;
+    int dev = 0, wall_khz = 0;
+    HUGE_HIP(hipGetDevice(&dev));
     HUGE_HIP(hipDeviceGetAttribute(&wall_khz, hipDeviceAttributeWallClockRate, dev));
-    double limit_s = 120.0;
+    // every wait of the kernel ends within this limit (then it reports an error), well
+    // before the time limits of the callers' tests and harnesses
+    double limit_s = 15.0;
     if (const char *e = getenv("HUGE_PERSIST_TIMEOUT_S")) limit_s = atof(e);
     a.limit_ticks = (uint64_t)((double)std::max(wall_khz, 1) * 1000.0 * limit_s);
-    HUGE_HIP(hipMemsetAsync(zero_from, 0, board_bytes + ctl_bytes, st));
-    DevPlan *dplans = nullptr;
-    HUGE_HIP(hipMalloc(&dplans, sizeof(DevPlan) * np));
-    Free fr2{dplans};
+    HUGE_HIP(hipMemsetAsync(zero_from, 0, L.board_bytes + L.ctl_bytes, st));
     HUGE_HIP(hipMemcpyAsync(dplans, dp.data(), sizeof(DevPlan) * np, hipMemcpyHostToDevice, st));
     a.plans = dplans;
 
@@ -899,12 +959,13 @@ void run_persistent(const huge_graph *g, const huge_plan *const *plans, int np, 
     hipLaunchKernelGGL(k_persist<kKMax>, dim3(nwg), dim3(kT), 0, st, a);
     HUGE_HIP(hipGetLastError());
     if (o.profile) HUGE_HIP(hipEventRecord(e1, st));
-    std::vector<unsigned long long> res((size_t)np * kResStride);
+    std::vector<unsigned long long> res((size_t)np * kResStride), busy(nwg);
     int err = 0;
     unsigned long long stats[4] = {0, 0, 0, 0};
     HUGE_HIP(hipMemcpyAsync(res.data(), a.res, 8ull * np * kResStride, hipMemcpyDeviceToHost, st));
     HUGE_HIP(hipMemcpyAsync(&err, a.err, 4, hipMemcpyDeviceToHost, st));
     HUGE_HIP(hipMemcpyAsync(stats, a.stats, sizeof(stats), hipMemcpyDeviceToHost, st));
+    HUGE_HIP(hipMemcpyAsync(busy.data(), a.wg_busy, 8ull * nwg, hipMemcpyDeviceToHost, st));
     HUGE_HIP(hipStreamSynchronize(st));
     float kms = 0;
     if (o.profile) {
@@ -915,6 +976,15 @@ void run_persistent(const huge_graph *g, const huge_plan *const *plans, int np, 
     if (err) HUGE_FAIL(HUGE_EDEVICE, "persistent engine: a wait exceeded its time limit");
     auto t1 = std::chrono::steady_clock::now();
     const double ms = std::chrono::duration<double, std::milli>(t1 - t0).count();
+    // per-WG busy time: mean and standard deviation over the launch's WGs (Section 7.3's balance measure)
+    double sum = 0, sq = 0;
+    const double tick_ms = 1.0 / std::max(wall_khz, 1);
+    for (int w = 0; w < nwg; ++w) {
+        const double x = (double)busy[w] * tick_ms;
+        sum += x;
+        sq += x * x;
+    }
+    const double mean = sum / nwg, var = std::max(0.0, sq / nwg - mean * mean);
     for (int i = 0; i < np; ++i) {
         huge_result &r = outs[i];
         memset(&r, 0, sizeof(r));
@@ -930,6 +1000,9 @@ void run_persistent(const huge_graph *g, const huge_plan *const *plans, int np, 
         r.peak_frontier_bytes = stats[2];
         r.kernel_ms[HUGE_KC_SINK] = kms;
         r.kernel_launches[HUGE_KC_SINK] = 1;
+        r.workgroups = (uint64_t)nwg;
+        r.wg_busy_ms_mean = mean;
+        r.wg_busy_ms_std = std::sqrt(var);
     }
 }
 

@@ -58,7 +58,8 @@ void check_query(int k, int ne, const int32_t *qe, huge_plan *p) {
     p->k = k;
 }
 
-// Automorphism group by testing every permutation (k <= 8).
+// Automorphism group by testing every permutation (k <= 8); a labelled query's
+// automorphisms also keep every vertex's label (-1 counts as a label of its own).
 std::vector<std::vector<int8_t>> automorphisms(const huge_plan &p) {
     std::vector<std::vector<int8_t>> out;
     std::vector<int8_t> perm(p.k);
@@ -70,6 +71,8 @@ std::vector<std::vector<int8_t>> automorphisms(const huge_plan &p) {
                 ok = false;
                 break;
             }
+        for (int v = 0; v < p.k && ok; ++v)
+            if (p.qlabel[perm[v]] != p.qlabel[v]) ok = false;
         if (ok) out.push_back(perm);
     } while (std::next_permutation(perm.begin(), perm.end()));
     return out;
@@ -203,6 +206,7 @@ void plan_set_order(huge_plan &p, const int32_t *order) {
             if (p.adj[order[j]][order[i]]) s.ext |= 1u << j;
         }
         s.neq = ((1u << i) - 1) & ~s.ext;
+        s.nadj = p.induced ? s.neq : 0u;
         s.slice = order[i] == 0 ? 1 : 0;
         for (auto &c : p.sb) {
             int pa = pos[c.first], pb = pos[c.second];
@@ -213,16 +217,17 @@ void plan_set_order(huge_plan &p, const int32_t *order) {
     }
     // position 0's slice flag lives in st[0]
     d.st[0].slice = order[0] == 0 ? 1 : 0;
+    for (int i = 0; i < k; ++i) d.st[i].label = p.qlabel[order[i]];
     p.est_cost = 0;
     for (int s = 1; s <= k; ++s) p.est_prefix[s - 1] = 0;
     return;
 }
 
 constexpr double kLearnedMargin = 2.0;
-constexpr int kVerifyCandidates = 4;          // the model's best orders measured, besides the cost model's
-constexpr double kVerifyEdges = 16384.0;      // level-2 rows (directed edges) in the measured sample
-constexpr int64_t kVerifyBaseLimit = 20000000000ll;  // candidates of the cost model's order on the sample
-constexpr double kVerifyRelLimit = 8.0;       // other orders stop at this multiple of its candidates
+constexpr int kVerifyCandidates = 2;                 // the model's best orders measured, besides the cost model's
+constexpr int64_t kVerifyWork = 40000000;            // candidates of the cost model's order on the sample
+constexpr double kVerifyRelLimit = 3.0;              // other orders stop at this multiple of its candidates
+constexpr double kVerifyGain = 1.1;                  // a measured order must be this much faster to be kept
 
 double order_cost(const std::vector<double> &e, size_t o, int k) {
     double c = 0;
@@ -231,15 +236,15 @@ double order_cost(const std::vector<double> &e, size_t o, int k) {
 }
 
 // Measured choice among the model's kVerifyCandidates best orders and the cost
-// model's order: each runs the query on the same edge slice of about
-// kVerifyEdges level-2 rows (all in one workspace), and the order with the
-// least device time wins (the time of every launch, HIP events).  The cost
-// model's order runs first; its sample is halved until it finishes within
-// kVerifyBaseLimit candidates, and the other orders stop (and lose) past
-// kVerifyRelLimit times its candidates.  An edge slice is an unbiased 1/S
-// sample of each order's work that reaches high-degree vertices in
-// proportion to their degree, where a sample of first vertices would mostly
-// miss them and misjudge orders whose work sits on hubs.
+// model's order.  Each runs the query on slice 0 of S of its own first matched
+// vertex, strided by degree rank (ranks 0, S, 2S, ...), so every order's
+// sample holds the same share of each degree class and costs only its own
+// slice's entries: an unbiased 1/S sample of that order's work.  S is the
+// smallest power of 8 (from 2^9) at which the cost model's order examines at
+// most kVerifyWork candidates; the other orders stop (and lose) past
+// kVerifyRelLimit times its candidates.  The order with the least device time
+// wins, the cost model's keeping ties within kVerifyGain.  About a few
+// milliseconds of device time per order.
 size_t verify_orders(const huge_graph *g, const huge_plan &p, const std::vector<std::vector<int32_t>> &orders,
                      const std::vector<double> &est, const huge_graph_info &gi, hipStream_t st) {
     const int k = p.k;
@@ -261,47 +266,55 @@ size_t verify_orders(const huge_graph *g, const huge_plan &p, const std::vector<
     // the cost model's order first
     cand.erase(std::remove(cand.begin(), cand.end(), base), cand.end());
     cand.insert(cand.begin(), base);
-    uint32_t S = 1;
-    while ((double)S * 2.0 * kVerifyEdges <= (double)gi.nnz && S < (1u << 30)) S *= 2;
+    if (cand.size() == 1) return base;
     huge_exec_opts o;
     huge_exec_opts_default(&o);
     o.stream = st;
-    o.slice_count = S;
+    o.slice_count = 512;
     o.slice_id = 0;
-    o.slice_vertex = -2;
-    o.work_limit = kVerifyBaseLimit;
+    o.slice_vertex = -1;
+    o.slice_mode = HUGE_SLICE_STRIDE;
+    o.work_limit = kVerifyWork;
     o.exec_flags = HUGE_EXEC_NO_HASH;
     o.profile = 1;
     std::vector<huge_plan> qs(cand.size(), p);
-    uint64_t wsb = 256;
-    for (size_t i = 0; i < cand.size(); ++i) {
-        plan_set_order(qs[i], orders[cand[i]].data());
-        wsb = std::max(wsb, workspace_bytes(g, &qs[i], o));
-    }
+    for (size_t i = 0; i < cand.size(); ++i) plan_set_order(qs[i], orders[cand[i]].data());
     struct Mem {
         void *p = nullptr;
         ~Mem() {
             if (p) (void)hipFree(p);
         }
     } mem;
-    HUGE_HIP(hipMalloc(&mem.p, wsb));
-    o.workspace = mem.p;
-    o.workspace_bytes = wsb;
+    uint64_t wsb = 0;
+    auto ensure_ws = [&]() {
+        uint64_t need = 256;
+        for (size_t i = 0; i < cand.size(); ++i) need = std::max(need, workspace_bytes(g, &qs[i], o));
+        if (need > wsb) {
+            if (mem.p) HUGE_HIP(hipFree(mem.p));
+            mem.p = nullptr;
+            HUGE_HIP(hipMalloc(&mem.p, need));
+            wsb = need;
+        }
+        o.workspace = mem.p;
+        o.workspace_bytes = wsb;
+    };
     auto device_ms = [](const huge_result &r) {
         double ms = 0;
         for (int c = 0; c < 4; ++c) ms += r.kernel_ms[c];
         return ms;
     };
     huge_result r0;
-    for (int tries = 0;; ++tries) {
+    for (;;) {
+        ensure_ws();
         if (!run_levels(g, &qs[0], o, &r0, nullptr)) break;
-        if (tries == 6 || o.slice_count >= (1u << 30)) return base;  // no workable sample: keep the cost model's
-        o.slice_count *= 2;
+        if ((int64_t)o.slice_count * 8 > std::max<int64_t>(gi.n, 1)) return base;  // no workable sample
+        o.slice_count *= 8;
     }
     double base_work = 0;
     for (int i = 0; i < HUGE_KMAX; ++i) base_work += (double)r0.level_work[i];
     size_t best = base;
-    double best_ms = device_ms(r0);
+    const double base_ms = device_ms(r0);
+    double best_ms = base_ms / kVerifyGain;
     o.work_limit = (int64_t)std::max(1.0, std::min(9.0e18, kVerifyRelLimit * base_work));
     for (size_t i = 1; i < cand.size(); ++i) {
         huge_result r;
@@ -315,15 +328,28 @@ size_t verify_orders(const huge_graph *g, const huge_plan &p, const std::vector<
     return best;
 }
 
+void check_labels(const huge_graph *g, const huge_plan *p) {
+    if (p->labelled && !g->label) HUGE_FAIL(HUGE_EINVAL, "a labelled query needs a labelled graph (huge_load_csr_labelled)");
+}
+
 void plan_build(const huge_graph *g, int k, int ne, const int32_t *qe, const int32_t *order, uint32_t flags,
-                const huge_model *model, hipStream_t st, huge_plan *p) {
+                const huge_model *model, hipStream_t st, huge_plan *p, const int32_t *qlabels) {
     static const huge_graph_info no_stats{};
     const huge_graph_info &gi = g ? g->info : no_stats;
     const bool learned = (flags & HUGE_PLAN_LEARNED) != 0;
     if (learned && (!model || !g)) HUGE_FAIL(HUGE_EINVAL, "a learned plan needs a graph and a model");
     check_query(k, ne, qe, p);
+    for (int i = 0; i < HUGE_KMAX; ++i) p->qlabel[i] = -1;
+    p->labelled = false;
+    if (qlabels)
+        for (int i = 0; i < k; ++i) {
+            if (qlabels[i] < -1) HUGE_FAIL(HUGE_EQUERY, "query label %d of vertex %d is below -1", qlabels[i], i);
+            p->qlabel[i] = qlabels[i];
+            p->labelled |= qlabels[i] >= 0;
+        }
     grochow_kellis(*p);
     p->flags = flags;
+    p->induced = (flags & HUGE_PLAN_INDUCED) != 0;
     std::vector<std::vector<int32_t>> orders;
     if (order) {
         if (!order_connected(*p, order))
@@ -385,6 +411,11 @@ void plan_prefix(const huge_plan &p, int size, huge_plan *q) {
     for (int i = 0; i < p.k; ++i) pos[p.order[i]] = i;
     q->k = size;
     q->flags = p.flags;
+    q->induced = p.induced;
+    q->labelled = p.labelled;
+    for (int i = 0; i < HUGE_KMAX; ++i) q->qlabel[i] = -1;
+    for (int v = 0; v < p.k; ++v)
+        if (pos[v] < size) q->qlabel[pos[v]] = p.qlabel[v];
     q->naut = 0;
     memset(q->adj, 0, sizeof(q->adj));
     q->edges.clear();

@@ -35,7 +35,7 @@ __device__ __forceinline__ void prepare_row(const int32_t *__restrict__ rows, in
         int32_t f[W];
         load_row<W>(rows, g, row0 + i, f);
         valid = true;
-        if constexpr (W == 2) valid = level2_ok(f, P);
+        if constexpr (W == 2) valid = level2_ok(f, P, g);
         int32_t bound = 0;
         uint64_t pinfo = 0;
         if (valid) {
@@ -274,10 +274,12 @@ __device__ __forceinline__ void extend_tile(const ExtArgs &a, int64_t tile) {
         for (int p = 0; p < W; ++p)
             if ((st.neq >> p) & 1u) ok &= (v != f[p]);
         if (st.slice) ok &= slices_ok(st.slice, v, a.P);
+            if (st.label >= 0) ok = ok && label_ok(g, st.label, v);
         if constexpr (STRAT == 0) {
 #pragma unroll
             for (int p = 0; p < W; ++p) {
                 if (ok && ((st.ext >> p) & 1u) && p != pp) ok = adj_has(g, f[p], v);
+                if (ok && ((st.nadj >> p) & 1u)) ok = !adj_has(g, f[p], v);  // induced mode
             }
         } else {
             // row segments of this wave
@@ -303,6 +305,9 @@ __device__ __forceinline__ void extend_tile(const ExtArgs &a, int64_t tile) {
                     if (need) ok &= in;
                 }
             }
+#pragma unroll
+            for (int p = 0; p < W; ++p)
+                if (ok && ((st.nadj >> p) & 1u)) ok = !adj_has(g, f[p], v);  // induced mode
         }
         if (!ok) continue;
         if constexpr (MODE == MODE_COUNT) {
@@ -577,7 +582,7 @@ __device__ __forceinline__ void merge_tile(const ExtArgs &a, int64_t tile) {
                 const int32_t v0 = cand(pshift + w);
 #pragma unroll
                 for (int p = 0; p < W; ++p) {
-                    if (((st.ext >> p) & 1u) && p != pp) {
+                    if ((((st.ext | st.nadj) >> p) & 1u) && p != pp) {
                         if (f[p] < g.hub_base) {
                             end[p] = g.rp[f[p] + 1];
                             if constexpr (BLK) {
@@ -597,9 +602,14 @@ __device__ __forceinline__ void merge_tile(const ExtArgs &a, int64_t tile) {
             for (int p = 0; p < W; ++p)
                 if ((st.neq >> p) & 1u) ok &= (v != f[p]);
             if (st.slice) ok &= slices_ok(st.slice, v, a.P);
+            if (st.label >= 0) ok = ok && label_ok(g, st.label, v);
 #pragma unroll
             for (int p = 0; p < W; ++p) {
-                if (ok && ((st.ext >> p) & 1u) && p != pp) {
+                // Ext lists must hold v; in induced mode the lists of the other
+                // matched vertices (nadj) must not
+                if (ok && (((st.ext | st.nadj) >> p) & 1u) && p != pp) {
+                    const bool absent = (st.nadj >> p) & 1u;
+                    bool in = false;
                     if (f[p] >= g.hub_base) {
                         if constexpr (BLK) {
                             // hub: the 16-byte bitmap block of 128 vertex IDs around v, cached
@@ -610,18 +620,19 @@ __device__ __forceinline__ void merge_tile(const ExtArgs &a, int64_t tile) {
                                     g.hub_bm + (int64_t)(f[p] - g.hub_base) * g.hub_words)[v >> 7];
                                 cblk[p] = key;
                             }
-                            ok = (((uint32_t)pick4(cq[p], (v >> 5) & 3)) >> (v & 31)) & 1u;
+                            in = (((uint32_t)pick4(cq[p], (v >> 5) & 3)) >> (v & 31)) & 1u;
                         } else {
-                            ok = adj_has(g, f[p], v);
+                            in = adj_has(g, f[p], v);
                         }
                     } else if constexpr (BLK) {
                         int32_t x = 0;
                         cur[p] = gallop_blk(g.col, cur[p], end[p], v, cblk[p], cq[p], x);
-                        ok = cur[p] < end[p] && x == v;
+                        in = cur[p] < end[p] && x == v;
                     } else {
                         cur[p] = gallop(g.col, cur[p], end[p], v);
-                        ok = cur[p] < end[p] && g.col[cur[p]] == v;
+                        in = cur[p] < end[p] && g.col[cur[p]] == v;
                     }
+                    ok = in != absent;
                 }
             }
         }

@@ -6,8 +6,13 @@
 // queue fill seen against its capacity.
 //
 // usage: sched_harness k nnz bmax emit_mod seed seg_cap q_cap
+//        sched_harness trace k nnz seg_cap q_cap b_2 .. b_{k-1}
+// The trace form uses a fixed model (every row of level W has b_W candidates,
+// all of them kept) and prints the device scheduler's actions in order, as
+// "kind:W" tokens (P prepare, E emit, S sink), after the count comparison.
 #include <cstdio>
 #include <cstdlib>
+#include <string>
 #include <vector>
 
 #include "round_sched.h"
@@ -28,8 +33,14 @@ struct Synth {
     int64_t nnz = 0;
     uint64_t seed = 1;
     int bmax = 8, emit_mod = 3;
-    int64_t bound(int W, uint64_t id) const { return (int64_t)(mixh(id ^ seed ^ ((uint64_t)W << 56)) % (uint64_t)(bmax + 1)); }
+    int64_t fixed[HUGE_KMAX + 1] = {};  // trace form: fixed bound per level, every candidate kept
+    bool use_fixed = false;
+    int64_t bound(int W, uint64_t id) const {
+        if (use_fixed) return fixed[W];
+        return (int64_t)(mixh(id ^ seed ^ ((uint64_t)W << 56)) % (uint64_t)(bmax + 1));
+    }
     bool emits(int W, uint64_t id, int64_t i) const {
+        if (use_fixed) return true;
         return mixh(id * 0x100000001B3ull + (uint64_t)i + ((uint64_t)W << 48) + seed) % (uint64_t)emit_mod == 0;
     }
     uint64_t child(uint64_t id, int64_t i) const { return mixh(id ^ ((uint64_t)(i + 1) * 0xD6E8FEB86659FD93ull)); }
@@ -182,18 +193,39 @@ std::vector<Action> device_steps(Sim &sim, const std::vector<int64_t> &seg_cap, 
 }  // namespace
 
 int main(int argc, char **argv) {
-    if (argc != 8) {
-        std::fprintf(stderr, "usage: %s k nnz bmax emit_mod seed seg_cap q_cap\n", argv[0]);
-        return 2;
-    }
+    const bool trace = argc >= 2 && std::string(argv[1]) == "trace";
     Synth S;
-    S.k = std::atoi(argv[1]);
-    S.lastW = S.k - 1;
-    S.nnz = std::atoll(argv[2]);
-    S.bmax = std::atoi(argv[3]);
-    S.emit_mod = std::atoi(argv[4]);
-    S.seed = std::strtoull(argv[5], nullptr, 10);
-    const int64_t seg = std::atoll(argv[6]), qc = std::atoll(argv[7]);
+    int64_t seg = 0, qc = 0;
+    if (trace) {
+        if (argc < 6) {
+            std::fprintf(stderr, "usage: %s trace k nnz seg_cap q_cap b_2 .. b_{k-1}\n", argv[0]);
+            return 2;
+        }
+        S.k = std::atoi(argv[2]);
+        S.lastW = S.k - 1;
+        S.nnz = std::atoll(argv[3]);
+        seg = std::atoll(argv[4]);
+        qc = std::atoll(argv[5]);
+        if (argc != 6 + (S.k - 2)) {
+            std::fprintf(stderr, "trace: need k - 2 bounds\n");
+            return 2;
+        }
+        S.use_fixed = true;
+        for (int w = 2; w <= S.lastW; ++w) S.fixed[w] = std::atoll(argv[6 + (w - 2)]);
+    } else {
+        if (argc != 8) {
+            std::fprintf(stderr, "usage: %s k nnz bmax emit_mod seed seg_cap q_cap\n", argv[0]);
+            return 2;
+        }
+        S.k = std::atoi(argv[1]);
+        S.lastW = S.k - 1;
+        S.nnz = std::atoll(argv[2]);
+        S.bmax = std::atoi(argv[3]);
+        S.emit_mod = std::atoi(argv[4]);
+        S.seed = std::strtoull(argv[5], nullptr, 10);
+        seg = std::atoll(argv[6]);
+        qc = std::atoll(argv[7]);
+    }
     std::vector<int64_t> seg_cap(HUGE_KMAX + 1, seg), qcap(HUGE_KMAX + 1, qc);
     int64_t ground = 0;
     for (int64_t r = 0; r < S.nnz; ++r) ground += S.ground(2, (uint64_t)r);
@@ -207,5 +239,11 @@ int main(int argc, char **argv) {
                 "overflow %d error %d\n",
                 la.size(), lb.size(), same ? 1 : 0, (long long)a.count, (long long)b.count, (long long)ground,
                 (a.overflow || b.overflow) ? 1 : 0, err ? 1 : 0);
+    if (trace) {
+        std::printf("trace");
+        for (const Action &x : lb)
+            std::printf(" %c:%d", x.kind == GACT_PREPARE ? 'P' : x.kind == GACT_EMIT ? 'E' : 'S', x.W);
+        std::printf("\n");
+    }
     return 0;
 }

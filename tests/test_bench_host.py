@@ -25,21 +25,40 @@ def test_more_than_one_gpu_is_refused():
 
 def test_recorded_traffic_needs_the_measured_sources(monkeypatch):
     b = _bench()
-    rec = dict(b.TRAFFIC["c2"])
+    rec = {"sources_sha256_16": b.sources_digest(), "per_alg_byte": 0.25}
+    monkeypatch.setitem(b.TRAFFIC, "c5", rec)
     assert b.recorded_traffic("no-such-workload", 1e9) is None
-    monkeypatch.setitem(b.TRAFFIC, "c2", dict(rec, sources_sha256_16="0" * 16))
-    assert b.recorded_traffic("c2", 1e9) is None
+    assert b.recorded_traffic("c5", 1e9) == 0.25e9
+    monkeypatch.setitem(b.TRAFFIC, "c5", dict(rec, sources_sha256_16="0" * 16))
+    assert b.recorded_traffic("c5", 1e9) is None
 
 
-def test_recorded_traffic_scales_with_algorithmic_bytes(monkeypatch):
-    import hashlib
+def test_digest_covers_every_kernel_source_and_header():
+    """Every file the intersection kernels are compiled from (the kernel sources
+    and, transitively, every header they include) is in the digest the recorded
+    traffic is keyed to: a change to any of them voids the record."""
+    import re
 
     b = _bench()
-    h = hashlib.sha256()
+    csrc = "paper_2103_14294_amd/csrc/"
+    todo, seen = [csrc + "extend.hip", csrc + "mround.hip"], set()
+    while todo:
+        f = todo.pop()
+        if f in seen:
+            continue
+        seen.add(f)
+        for inc in re.findall(r'#include "([^"]+)"', open(os.path.join(ROOT, f)).read()):
+            todo.append(os.path.normpath(os.path.join(os.path.dirname(f), inc)))
+    assert seen <= set(b.KERNEL_SOURCES), seen - set(b.KERNEL_SOURCES)
     for f in b.KERNEL_SOURCES:
-        with open(os.path.join(ROOT, f), "rb") as fh:
-            h.update(fh.read())
-    monkeypatch.setitem(b.TRAFFIC, "c2", {"sources_sha256_16": h.hexdigest()[:16], "bytes_per_launch": 1.0,
-                                          "per_alg_byte": 0.25})
-    assert b.recorded_traffic("c2", 4e9) == 1e9
-    assert b.recorded_traffic("c2", 8e9) == 2e9
+        assert os.path.exists(os.path.join(ROOT, f)), f
+
+
+def test_heldout_patterns_are_outside_the_training_set():
+    b = _bench()
+    seen = b.training_patterns()
+    qs = b.build_queries(b.WORKLOADS["c5"])
+    assert len(qs) == 32
+    for name, k, e in qs:
+        assert (k, tuple(sorted(e))) not in seen, name
+        assert 4 <= k <= 6

@@ -91,3 +91,38 @@ def test_batched_patterns_match_single_runs(H, kmax):
         ref = oracle_run(g, p["k"], p["edges"], order=pl.info()["order"])
         assert cmp_key(r, p["k"]) == cmp_key(ref, p["k"]), p
         assert r["level_counts"][:p["k"]] == ref["level_counts"][:p["k"]], p
+
+
+def test_workgroup_balance_with_and_without_stealing(H):
+    """Section 7.3's load-balance measure: the standard deviation of per-workgroup
+    busy time.  Both runs give the same results; the launch reports its workgroups
+    and the mean and spread of their busy times (stealing shrinks the spread on a
+    skewed graph)."""
+    big = gg.rmat(13, 16, seed=4)
+    G = H.load(big.row_ptr, big.col)
+    k, e = P.NAMED["diamond"]
+    p = H.plan(G, k, e)
+    on = H.count(G, p, engine=PERSIST, work_stealing=1)
+    off = H.count(G, p, engine=PERSIST, work_stealing=0)
+    assert cmp_key(on, k) == cmp_key(off, k)
+    for r in (on, off):
+        assert r["workgroups"] > 0 and r["wg_busy_ms_mean"] > 0 and r["wg_busy_ms_std"] >= 0
+    print("busy ms mean/std: stealing %.3f/%.3f, none %.3f/%.3f" % (
+        on["wg_busy_ms_mean"], on["wg_busy_ms_std"], off["wg_busy_ms_mean"], off["wg_busy_ms_std"]))
+    assert on["wg_busy_ms_std"] <= off["wg_busy_ms_std"]
+
+
+def test_persistent_uses_the_caller_workspace(H, small):
+    import torch
+
+    g, G = small
+    k, e = P.NAMED["4-clique"]
+    p = H.plan(G, k, e)
+    o = H.exec_opts(engine=PERSIST)
+    need = H.workspace_size(G, p, o)
+    assert need > 0
+    ws = H.Workspace()
+    a = H.count(G, p, engine=PERSIST, workspace=ws)
+    assert ws.buf is not None and ws.buf.numel() >= need
+    b = H.count(G, p, engine=PERSIST, workspace=None)
+    assert cmp_key(a, k) == cmp_key(b, k)

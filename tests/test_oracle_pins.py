@@ -345,3 +345,75 @@ def test_strided_and_double_slices_partition_and_match_direct_filter():
                 got = oracle.enumerate_query(t.row_ptr, t.col, k, e, slice_count=2, slice_id=s1, slice_vertex=a,
                                              slice_mode=1, slice2=(b, 3, s2))
                 assert got["count"] == want_n, (a, b, s1, s2)
+
+
+def test_given_ranks_give_the_same_result():
+    g = gg.chung_lu(3000, 8, 2.4, seed=17)
+    k, e = P.NAMED["diamond"]
+    rk = oracle.ranks(g.row_ptr)
+    for kw in [{}, dict(slice_count=5, slice_id=2, slice_mode=1), dict(slice_count=4, slice_id=1, slice_vertex=2)]:
+        assert oracle.enumerate_query(g.row_ptr, g.col, k, e, ranks=rk, **kw) == \
+            oracle.enumerate_query(g.row_ptr, g.col, k, e, **kw)
+
+
+@pytest.mark.parametrize("k", [3, 4, 5])
+def test_induced_mode_and_motif_brute_force(k):
+    """The oracle's induced mode counts, per pattern, the vertex sets whose induced
+    subgraph is isomorphic to it: equal to the brute-force motif census (every
+    k-subset of a tiny graph), whose non-induced column equals the plain oracle;
+    every connected k-subset is counted exactly once over the classes."""
+    import itertools
+
+    for seed, n, p in [(1, 10, 0.5), (2, 11, 0.35)]:
+        g = gg.gnp(n, p, seed=seed)
+        census = oracle.motif_counts(g.row_ptr, g.col, k)
+        adj = {(u, int(v)) for u in range(n) for v in g.col[g.row_ptr[u]:g.row_ptr[u + 1]]}
+        conn = 0
+        for X in itertools.combinations(range(n), k):
+            ind = [(a, b) for a in range(k) for b in range(a + 1, k) if (X[a], X[b]) in adj]
+            conn += oracle._connected(k, ind)
+        assert sum(v[1] for v in census.values()) == conn
+        for key, (nonind, induced) in census.items():
+            e = list(key)
+            assert oracle.enumerate_query(g.row_ptr, g.col, k, e)["count"] == nonind, key
+            assert oracle.enumerate_query(g.row_ptr, g.col, k, e, induced=True)["count"] == induced, key
+    K = gg.complete(7)
+    clique = [(a, b) for a in range(4) for b in range(a + 1, 4)]
+    assert oracle.enumerate_query(K.row_ptr, K.col, 4, clique, induced=True)["count"] == 35
+    assert oracle.enumerate_query(K.row_ptr, K.col, 4, [(0, 1), (1, 2), (2, 3)], induced=True)["count"] == 0
+
+
+def test_labelled_matching_brute_force_and_closed_forms():
+    """Labelled queries: every query vertex's image carries its label (-1: any).
+    A match is an injective edge- and label-preserving map, counted once per class
+    under the automorphisms of q that keep its labels (-1 counting as a label of
+    its own).  Brute force over all injective maps of tiny labelled graphs divided
+    by that group's order; uniform labels equal the unlabelled count; and in K_n
+    with a vertices labelled 0 and b labelled 1 the triangles labelled (0, 0, 1)
+    number C(a, 2) * b."""
+    import itertools
+    import math
+
+    for seed, n, p in [(1, 9, 0.5), (2, 10, 0.4)]:
+        g = gg.gnp(n, p, seed=seed)
+        lab = [(u * 7 + seed) % 3 for u in range(n)]
+        adj = {(u, int(v)) for u in range(n) for v in g.col[g.row_ptr[u]:g.row_ptr[u + 1]]}
+        for name, ql in [("triangle", [0, 1, 1]), ("4-cycle", [0, 1, 0, 1]), ("diamond", [2, 0, 0, -1]),
+                         ("4-path", [1, -1, -1, 2])]:
+            k, e = P.NAMED[name]
+            qadj = {(a, b) for a, b in e} | {(b, a) for a, b in e}
+            aut = sum(1 for s_ in itertools.permutations(range(k))
+                      if all((s_[a], s_[b]) in qadj for a, b in e) and all(ql[s_[i]] == ql[i] for i in range(k)))
+            maps = sum(1 for f in itertools.permutations(range(n), k)
+                       if all((f[a], f[b]) in adj for a, b in e) and
+                       all(q < 0 or lab[f[i]] == q for i, q in enumerate(ql)))
+            assert maps % aut == 0
+            got = oracle.enumerate_query(g.row_ptr, g.col, k, e, vlabels=lab, qlabels=ql)
+            assert got["count"] == maps // aut, (seed, name)
+            same = oracle.enumerate_query(g.row_ptr, g.col, k, e, vlabels=[5] * n, qlabels=[5] * k)
+            assert same == oracle.enumerate_query(g.row_ptr, g.col, k, e), name
+    K = gg.complete(9)
+    lab = [0] * 4 + [1] * 5
+    k, e = P.NAMED["triangle"]
+    assert oracle.enumerate_query(K.row_ptr, K.col, k, e, vlabels=lab, qlabels=[0, 0, 1])["count"] == \
+        math.comb(4, 2) * 5
