@@ -344,6 +344,28 @@ huge_status huge_workspace_size(const huge_graph *g, const huge_plan *p, const h
 huge_status huge_count(const huge_graph *g, const huge_plan *p, const huge_exec_opts *opts, huge_result *out);
 
 /*
+ * huge_count_noalloc -- huge_count for callers that cannot allocate memory:
+ * code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc.  It runs the level engine with every device buffer it needs
+ * (counters, segment buffers, queues, scan scratch, a gathered level 2) in one
+ * file-scope device array of 256 MiB (huge_noalloc_capacity), which each
+ * device that runs it holds until the process ends, and its host read-backs
+ * in a static host block: it calls no allocator of any kind.  Options as
+ * huge_count, except: no workspace (HUGE_EINVAL), profile 0, engine AUTO or
+ * LEVELS, a finite frontier_cap_bytes; options whose workspace
+ * (huge_workspace_size) exceeds the array fail with HUGE_ENOMEM: lower
+ * frontier_cap_bytes or chunk_rows (frontier_cap_bytes = 64 MiB with
+ * chunk_rows = 2^18 fits every query of up to 8 vertices, tuned or not; a
+ * strided slice adds 8 * (nnz / slice_count + max degree) bytes).  The array keeps the last call's
+ * contents; each call clears its counters first.  Calls on one device take
+ * turns (one lock per device): they are serialised, never interleaved.
+ * Results equal huge_count's bit for bit.
+ */
+huge_status huge_count_noalloc(const huge_graph *g, const huge_plan *p, const huge_exec_opts *opts, huge_result *out);
+/* Bytes of the device array huge_count_noalloc runs in. */
+huge_status huge_noalloc_capacity(uint64_t *bytes);
+
+/*
  * huge_enumerate -- enumerate and deliver every match.  Matches are written to
  * host_buf (buf_rows rows of k int32, row = f(0), ..., f(k-1) indexed by query
  * vertex, original IDs) and cb(user, host_buf, nrows, k) is called on the

@@ -36,7 +36,7 @@ EXPORTED = [
     "huge_model_create", "huge_model_free", "huge_model_set", "huge_model_get", "huge_model_forward",
     "huge_model_grad", "huge_model_train", "huge_plan_features", "huge_plan_create_learned",
     "huge_autotune", "huge_graph_digest", "huge_plan_prefix", "huge_plan_create_learned2", "huge_device_name",
-    "huge_batch_workspace_size", "huge_plan_estimates",
+    "huge_batch_workspace_size", "huge_plan_estimates", "huge_count_noalloc", "huge_noalloc_capacity",
     "huge_motif_count", "huge_load_csr_labelled", "huge_plan_create_labelled",
 ]
 MOTIF_KMAX, MOTIF_MAX = 6, 112
@@ -164,6 +164,10 @@ def load_library(path: str = LIB_PATH):
         lib.huge_motif_count.restype = st
         lib.huge_motif_count.argtypes = [vp, i32, ctypes.POINTER(ExecOpts), ctypes.POINTER(Motif),
                                          ctypes.POINTER(i32)]
+        lib.huge_count_noalloc.restype = st
+        lib.huge_count_noalloc.argtypes = [vp, vp, ctypes.POINTER(ExecOpts), ctypes.POINTER(Result)]
+        lib.huge_noalloc_capacity.restype = st
+        lib.huge_noalloc_capacity.argtypes = [ctypes.POINTER(ctypes.c_uint64)]
         lib.huge_workspace_size.restype = st
         lib.huge_workspace_size.argtypes = [vp, vp, ctypes.POINTER(ExecOpts), ctypes.POINTER(ctypes.c_uint64)]
         lib.huge_count.restype = st
@@ -559,6 +563,24 @@ def motif_count(g: Graph, k: int, **kw) -> list:
     return [{"k": m.k, "edges": [(m.edges[2 * i], m.edges[2 * i + 1]) for i in range(m.n_edges)],
              "noninduced": int(m.noninduced), "induced": int(m.induced), "hash_sum": int(m.hash_sum),
              "hash_xor": int(m.hash_xor)} for m in out[: n.value]]
+
+
+def count_noalloc(g: Graph, p: Plan, **kw) -> dict:
+    """huge_count_noalloc: huge_count in the library's own fixed device array (no allocation)."""
+    lib = load_library()
+    opts = exec_opts(**kw)
+    r = Result()
+    status = _check(lib.huge_count_noalloc(g.handle, p.handle, ctypes.byref(opts), ctypes.byref(r)))
+    d = r.to_dict()
+    d["stopped"] = status == HUGE_STOPPED
+    return d
+
+
+def noalloc_capacity() -> int:
+    lib = load_library()
+    b = ctypes.c_uint64()
+    _check(lib.huge_noalloc_capacity(ctypes.byref(b)))
+    return int(b.value)
 
 
 def plan_prefix(p: Plan, size: int) -> Plan:

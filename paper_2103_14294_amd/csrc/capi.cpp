@@ -214,6 +214,33 @@ huge_status huge_count(const huge_graph *g, const huge_plan *p, const huge_exec_
     });
 }
 
+huge_status huge_count_noalloc(const huge_graph *g, const huge_plan *p, const huge_exec_opts *opts, huge_result *out) {
+    return guard([&] {
+        if (!g || !p || !out) HUGE_FAIL(HUGE_EINVAL, "NULL argument");
+        huge_exec_opts o = resolve_opts(opts);
+        if (o.workspace || o.workspace_bytes) HUGE_FAIL(HUGE_EINVAL, "huge_count_noalloc takes no workspace");
+        if (o.profile) HUGE_FAIL(HUGE_EINVAL, "huge_count_noalloc does not profile (events would be created)");
+        if (o.engine != HUGE_ENGINE_AUTO && o.engine != HUGE_ENGINE_LEVELS)
+            HUGE_FAIL(HUGE_EINVAL, "huge_count_noalloc runs on the level engine");
+        if (o.work_limit < 0) HUGE_FAIL(HUGE_EINVAL, "work_limit < 0");
+        if (o.frontier_cap_bytes == UINT64_MAX) HUGE_FAIL(HUGE_EINVAL, "huge_count_noalloc needs a finite frontier cap");
+        check_labels(g, p);
+        huge_result r;
+        bool limited = false;
+        run_count_noalloc(g, p, o, &r, &limited);
+        *out = r;
+        return limited ? HUGE_STOPPED : HUGE_OK;
+    });
+}
+
+huge_status huge_noalloc_capacity(uint64_t *bytes) {
+    return guard([&] {
+        if (!bytes) HUGE_FAIL(HUGE_EINVAL, "NULL argument");
+        *bytes = noalloc_scratch_bytes();
+        return HUGE_OK;
+    });
+}
+
 huge_status huge_enumerate(const huge_graph *g, const huge_plan *p, const huge_exec_opts *opts, int32_t *host_buf,
                            int64_t buf_rows, huge_emit_fn cb, void *user, huge_result *out) {
     return guard([&] {

@@ -207,6 +207,10 @@ void run_persistent(const huge_graph *g, const huge_plan *const *plans, int np, 
 uint64_t persist_workspace_bytes(const huge_plan *const *plans, int np, const huge_exec_opts &o);
 // motif.cpp: every connected k-vertex pattern, non-induced and induced counts; returns the pattern count
 int motif_count(const huge_graph *g, int k, const huge_exec_opts &o, huge_motif *out);
+// noalloc.hip: huge_count on the level engine inside the file-scope device array
+uint64_t noalloc_scratch_bytes();
+void run_count_noalloc(const huge_graph *g, const huge_plan *p, const huge_exec_opts &o, huge_result *out,
+                       bool *limited);
 // mbatch.cpp: the batch in batched rounds (HUGE_ENGINE_GRAPH)
 void run_mgraph(const huge_graph *g, const huge_plan *const *plans, int np, const huge_exec_opts &o,
                 huge_result *outs);
