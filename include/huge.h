@@ -181,11 +181,15 @@ typedef struct {
     int32_t slice_vertex;        /* query vertex whose image is sliced (default 0; -1 = the plan's first
                                     matched vertex, order[0]; -2 = edge slice: keep the matches whose
                                     first two matched vertices (x, y) = (f(order[0]), f(order[1])), as
-                                    ranks, have mix(x << 32 | y) % slice_count == slice_id); slices of
-                                    any fixed vertex, or edge slices of one plan, partition the matches,
+                                    ranks, have mix(x << 32 | y) % slice_count == slice_id, or with
+                                    HUGE_SLICE_STRIDE whose entry index e (x's row, y's place in it) in
+                                    the relabelled CSR has e % slice_count == slice_id: the engines then
+                                    read only entries slice_id, slice_id + slice_count, ..., a sample of
+                                    every vertex's list in proportion to its degree); slices of any
+                                    fixed vertex, or edge slices of one plan, partition the matches,
                                     so counts add and hashes add / xor */
     uint32_t exec_flags;         /* HUGE_EXEC_* bits */
-    uint32_t slice_mode;         /* vertex slices (slice_vertex >= -1 and the second slice):
+    uint32_t slice_mode;         /* how every slice selects (edge slices: see slice_vertex -2):
                                     HUGE_SLICE_MIX keeps mix(rank) % count == id, HUGE_SLICE_STRIDE keeps
                                     rank % count == id: every count-th vertex in degree order, so every
                                     slice holds the same share of each degree class.  A strided slice of
@@ -205,14 +209,22 @@ typedef struct {
                                     with different first vertices a and b can then run the same sample:
                                     (a, s1 of S1) and (b, s2 of S2) in either role select the same
                                     matches, and each plan still reads only its own slice's entries.
+                                    With HUGE_EXEC_SLICE2_PAIR the second slice is on a pair of
+                                    adjacent query vertices (slice2_vertex, slice2_vertex2), read as an
+                                    edge slice of that pair, so two plans with different first pairs
+                                    can share an edge-slice sample the same way.
                                     Not on the persistent engine. */
     uint32_t slice2_count;
     uint32_t slice2_id;
-    int32_t reserved1;           /* must be 0 */
+    int32_t slice2_vertex2;      /* the pair's other query vertex (with HUGE_EXEC_SLICE2_PAIR), else unused */
 } huge_exec_opts;
 #define HUGE_SLICE_MIX 0u
 #define HUGE_SLICE_STRIDE 1u
 #define HUGE_EXEC_NO_HASH 0x1u /* count only: hash_sum / hash_xor are left 0 */
+/* the second slice is on the pair (slice2_vertex, slice2_vertex2) of adjacent
+   query vertices, read like an edge slice of that pair (its mix, or with
+   HUGE_SLICE_STRIDE its entry index in the relabelled CSR) */
+#define HUGE_EXEC_SLICE2_PAIR 0x2u
 
 /* Default options: frontier cap 4 GiB, autotuned chunk and strategy, AUTO engine, no slice. */
 huge_status huge_exec_opts_default(huge_exec_opts *opts);
@@ -527,11 +539,11 @@ huge_status huge_plan_create_learned(const huge_graph *g, const huge_model *m, i
                                      const int32_t *qedges, const int32_t *order, void *stream, huge_plan **out);
 /*
  * As huge_plan_create_learned, with flags: HUGE_PLAN_VERIFY runs the cost
- * model's order and the model's two best orders on a strided slice of each
- * order's own first matched vertex (slice 0 of S: every S-th vertex in degree
- * order, so each order reads only its own sample's entries), S the smallest
- * power of 8 from 512 at which the cost model's order examines at most 4e7
- * candidates; the others stop at 3 times its candidates.  The order with the
+ * model's order and the model's two best orders on a strided edge slice of
+ * each order's own first matched pair (slice 0 of S: every S-th entry of the
+ * relabelled CSR, so each order reads only its own sample's entries), S the
+ * smallest power of 8 from 512 at which the cost model's order examines at
+ * most 4e7 candidates; the others stop at 3 times its candidates.  The order with the
  * least device time wins; the cost model's order keeps ties within 10%.  This
  * costs a few milliseconds of device time per order, on `stream`.
  */

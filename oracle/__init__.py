@@ -67,7 +67,7 @@ def _load():
         ci = ctypes.c_int
         lib.orc_enumerate.restype = ci
         lib.orc_enumerate.argtypes = [i64, vp, vp, ci, ci, vp, ci, vp, ci, vp, ctypes.c_uint32, ctypes.c_uint32,
-                                      ci, ci, ci, ci, ctypes.c_uint32, ctypes.c_uint32, vp, vp, vp, ci,
+                                      ci, ci, ci, ci, ci, ctypes.c_uint32, ctypes.c_uint32, vp, vp, vp, ci,
                                       ctypes.POINTER(_Result)]
         lib.orc_automorphisms.restype = ci
         lib.orc_automorphisms.argtypes = [ci, ci, vp, vp, ci]
@@ -95,8 +95,10 @@ def enumerate_query(row_ptr, col, k, qedges, mode=MODE_SB, order=None, sb_pairs=
     level_counts (list of KMAX ints; entry d counts partial maps of the first
     d+1 vertices of the order used).  slice_pair=(a, b) slices on the ordered
     pair of images (r(f(a)), r(f(b))) instead of one vertex.  slice_mode=1
-    makes vertex slices strided (rank mod S) instead of mixed; slice2=(c, S2,
-    s2) adds a second vertex slice on query vertex c.  ranks: the output of
+    makes vertex slices strided (rank mod S) instead of mixed, and pair slices
+    strided by the pair's entry in the rank-relabelled CSR; slice2=(c, S2, s2)
+    adds a second vertex slice on query vertex c, slice2=(c, d, S2, s2) a second
+    pair slice on (c, d).  ranks: the output of
     ranks(row_ptr) for this graph, to skip recomputing them.  induced=True
     counts induced occurrences only (every non-edge of q maps to a non-edge).
     vlabels (one int per data vertex) and qlabels (one per query vertex, -1 =
@@ -132,8 +134,9 @@ def enumerate_query(row_ptr, col, k, qedges, mode=MODE_SB, order=None, sb_pairs=
                            None if sbp is None else sbp.ctypes.data, int(slice_count), int(slice_id),
                            int(slice_pair[0] if slice_pair else slice_vertex),
                            int(slice_pair[1] if slice_pair else -1), int(slice_mode),
-                           int(slice2[0]) if slice2 else -1, int(slice2[1]) if slice2 else 1,
-                           int(slice2[2]) if slice2 else 0, None if rk is None else rk.ctypes.data,
+                           int(slice2[0]) if slice2 else -1, int(slice2[1]) if slice2 and len(slice2) == 4 else -1,
+                           int(slice2[-2]) if slice2 else 1, int(slice2[-1]) if slice2 else 0,
+                           None if rk is None else rk.ctypes.data,
                            None if vl is None else vl.ctypes.data, None if ql is None else ql.ctypes.data,
                            int(threads), ctypes.byref(r))
     if st != 0:

@@ -59,8 +59,12 @@
  * results.
  *
  * Strided slices (slice_mode 1): a vertex slice keeps r(f(a)) mod S == s
- * instead of the mix.  A second vertex slice (vertex c, count S2, id s2, same
- * mode) can be applied on top of the first: only maps in both are kept.
+ * instead of the mix; a pair slice keeps the maps whose pair (f(a), f(b)) (a, b
+ * adjacent in q) sits at an entry e of the rank-relabelled CSR with
+ * e mod S == s, where e(x, y) = (sum of the degrees of the vertices ranked below
+ * x) + #{z in N(x) : r(z) < r(y)}.  A second slice (vertex c, or pair (c, d);
+ * count S2, id s2, same mode) can be applied on top of the first: only maps in
+ * both are kept.
  */
 #include <pthread.h>
 #include <stdint.h>
@@ -287,10 +291,19 @@ typedef struct {
     int slice_mode;             /* vertex slices: 0 by mix of the rank, 1 by the rank itself */
     uint32_t slice2_count, slice2_id;
     int slice2_pos;             /* position of the second sliced query vertex, or -1 */
+    int pair2_a, pair2_b;       /* second slice on a pair of positions (or -1) */
+    const int64_t *roff;        /* strided pair slices: first entry of each rank's row in the relabelled CSR */
     int induced;                /* 1: the image of every non-edge of q must be a non-edge of G */
     int nnon[ORC_KMAX];
     int non[ORC_KMAX][ORC_KMAX]; /* earlier positions not adjacent to position i in q */
 } orc_plan;
+
+struct orc_worker_s {
+    const orc_plan *P;
+    orc_result res;
+    int32_t f[ORC_KMAX];
+};
+typedef struct orc_worker_s orc_worker;
 
 /* rank r in slice id of count (vertex slices) */
 static int orc_in_vslice(int32_t r, uint32_t count, uint32_t id, int mode) {
@@ -300,7 +313,7 @@ static int orc_in_vslice(int32_t r, uint32_t count, uint32_t id, int mode) {
 
 static int orc_plan_init(orc_plan *P, const orc_query *q, const orc_graph *g, int mode,
                          const int32_t *order, uint32_t sc, uint32_t sid, int slice_vertex, int slice_vertex2,
-                         int slice_mode, int slice2_vertex, uint32_t sc2, uint32_t sid2) {
+                         int slice_mode, int slice2_vertex, int slice2_vertex2, uint32_t sc2, uint32_t sid2) {
     memset(P, 0, sizeof(*P));
     P->q = q;
     P->g = g;
@@ -368,11 +381,41 @@ static int orc_plan_init(orc_plan *P, const orc_query *q, const orc_graph *g, in
     P->slice2_count = sc2 > 1 ? sc2 : 1;
     P->slice2_id = sc2 > 1 ? sid2 : 0;
     P->slice2_pos = -1;
+    P->pair2_a = P->pair2_b = -1;
     if (P->slice2_count > 1) {
         if (slice2_vertex < 0 || slice2_vertex >= k || P->slice2_id >= P->slice2_count) return -1;
-        P->slice2_pos = P->pos[slice2_vertex];
+        if (slice2_vertex2 >= 0) {
+            if (slice2_vertex2 >= k || slice2_vertex2 == slice2_vertex) return -1;
+            P->pair2_a = P->pos[slice2_vertex];
+            P->pair2_b = P->pos[slice2_vertex2];
+        } else {
+            P->slice2_pos = P->pos[slice2_vertex];
+        }
     }
+    /* strided pair slices need adjacent ends (their pair is an edge of G) */
+    if (slice_mode == 1 && P->pair_a >= 0 && !q->adj[slice_vertex][slice_vertex2]) return -1;
+    if (slice_mode == 1 && P->pair2_a >= 0 && !q->adj[slice2_vertex][slice2_vertex2]) return -1;
     return 0;
+}
+
+/* e(x, y) of a strided pair slice: x's first entry in the relabelled CSR plus
+ * the number of x's neighbours ranked below y */
+static int64_t orc_entry(const orc_plan *P, int32_t x, int32_t y) {
+    const orc_graph *g = P->g;
+    int64_t e = P->roff[g->rank[x]];
+    const int32_t ry = g->rank[y];
+    for (int64_t t = g->rp[x]; t < g->rp[x + 1]; ++t) e += g->rank[g->col[t]] < ry;
+    return e;
+}
+
+/* the pair slice (positions a, b; count, id; mode) at position i with candidate c */
+static int orc_pair_ok(const struct orc_worker_s *w, int i, int32_t c, int a, int b, uint32_t count, uint32_t id) {
+    const orc_plan *P = w->P;
+    if (count <= 1 || a < 0 || i != (a > b ? a : b)) return 1;
+    const int32_t x = i == a ? c : w->f[a], y = i == b ? c : w->f[b];
+    if (P->slice_mode == 1) return (uint64_t)orc_entry(P, x, y) % count == id;
+    const uint32_t ra = (uint32_t)P->g->rank[x], rb = (uint32_t)P->g->rank[y];
+    return orc_mix(((uint64_t)ra << 32) | rb) % count == id;
 }
 
 /* the vertex slices that apply at position i to the vertex of rank r */
@@ -386,11 +429,6 @@ static int orc_slices_ok(const orc_plan *P, int i, int32_t r) {
     return 1;
 }
 
-typedef struct {
-    const orc_plan *P;
-    orc_result res;
-    int32_t f[ORC_KMAX];
-} orc_worker;
 
 static void orc_emit(orc_worker *w) {
     const orc_plan *P = w->P;
@@ -439,12 +477,44 @@ static int orc_accept(orc_worker *w, int i, int32_t c) {
     for (int t = 0; t < P->ngt[i]; ++t)
         if (!(rc < g->rank[w->f[P->gt[i][t]]])) return 0;
     if (!orc_slices_ok(P, i, rc)) return 0;
-    if (P->slice_count > 1 && P->pair_a >= 0 && i == (P->pair_a > P->pair_b ? P->pair_a : P->pair_b)) {
-        uint32_t ra = (uint32_t)(i == P->pair_a ? rc : g->rank[w->f[P->pair_a]]);
-        uint32_t rb = (uint32_t)(i == P->pair_b ? rc : g->rank[w->f[P->pair_b]]);
-        if (orc_mix(((uint64_t)ra << 32) | rb) % P->slice_count != P->slice_id) return 0;
-    }
+    if (!orc_pair_ok(w, i, c, P->pair_a, P->pair_b, P->slice_count, P->slice_id)) return 0;
+    if (!orc_pair_ok(w, i, c, P->pair2_a, P->pair2_b, P->slice2_count, P->slice2_id)) return 0;
     return 1;
+}
+
+static int orc_cmp_u64(const void *a, const void *b) {
+    uint64_t x = *(const uint64_t *)a, y = *(const uint64_t *)b;
+    return (x > y) - (x < y);
+}
+
+static void orc_search(orc_worker *w, int i);
+
+/* Position 1 under a strided pair slice on positions (0, 1): only the entries
+ * e = base + j of f[0]'s row in the relabelled CSR with e mod S == s, j being
+ * the rank order of the neighbour in N(f[0]). */
+static void orc_search_pair_slice(orc_worker *w) {
+    const orc_plan *P = w->P;
+    const orc_graph *g = P->g;
+    const int32_t x = w->f[0];
+    const int64_t d = g->rp[x + 1] - g->rp[x];
+    const int64_t base = P->roff[g->rank[x]];
+    const int64_t S = P->slice_count;
+    const int64_t j0 = ((int64_t)P->slice_id - base % S + S) % S;
+    if (j0 >= d) return;
+    uint64_t *nb = (uint64_t *)malloc(sizeof(uint64_t) * (size_t)d);
+    for (int64_t t = 0; t < d; ++t) {
+        const int32_t z = g->col[g->rp[x] + t];
+        nb[t] = ((uint64_t)(uint32_t)g->rank[z] << 32) | (uint32_t)z;
+    }
+    qsort(nb, (size_t)d, sizeof(uint64_t), orc_cmp_u64);
+    for (int64_t j = j0; j < d; j += S) {
+        const int32_t c = (int32_t)(uint32_t)nb[j];
+        if (!orc_accept(w, 1, c)) continue;
+        w->res.level_counts[1]++;
+        w->f[1] = c;
+        orc_search(w, 2);
+    }
+    free(nb);
 }
 
 static void orc_search(orc_worker *w, int i) {
@@ -452,6 +522,10 @@ static void orc_search(orc_worker *w, int i) {
     int k = P->q->k;
     if (i == k) {
         orc_emit(w);
+        return;
+    }
+    if (i == 1 && P->slice_mode == 1 && P->slice_count > 1 && P->pair_a == 0 && P->pair_b == 1) {
+        orc_search_pair_slice(w);
         return;
     }
     const orc_graph *g = P->g;
@@ -510,7 +584,7 @@ static void *orc_thread(void *arg) {
 int orc_enumerate(int64_t n, const int64_t *rp, const int32_t *col, int k, int nqe,
                   const int32_t *qedges, int mode, const int32_t *order, int nsb,
                   const int32_t *sb_pairs, uint32_t slice_count, uint32_t slice_id, int slice_vertex,
-                  int slice_vertex2, int slice_mode, int slice2_vertex, uint32_t slice2_count,
+                  int slice_vertex2, int slice_mode, int slice2_vertex, int slice2_vertex2, uint32_t slice2_count,
                   uint32_t slice2_id, const int32_t *rank_in, const int32_t *vlabels, const int32_t *qlabels,
                   int nthreads, orc_result *out) {
     orc_query q;
@@ -546,10 +620,19 @@ int orc_enumerate(int64_t n, const int64_t *rp, const int32_t *col, int k, int n
         orc_ranks(n, rp, g.rank);
     orc_plan P;
     if (orc_plan_init(&P, &q, &g, mode, order, slice_count, slice_id, slice_vertex, slice_vertex2, slice_mode,
-                      slice2_vertex, slice2_count, slice2_id) != 0) {
+                      slice2_vertex, slice2_vertex2, slice2_count, slice2_id) != 0) {
         free(g.rank);
         free(q.aut);
         return -1;
+    }
+    int64_t *roff = NULL;
+    if (slice_mode == 1 && (P.pair_a >= 0 || P.pair2_a >= 0)) {
+        /* first entry of each rank's row in the relabelled CSR */
+        roff = (int64_t *)malloc(sizeof(int64_t) * (size_t)(n + 1));
+        for (int64_t u = 0; u < n; ++u) roff[g.rank[u] + 1] = rp[u + 1] - rp[u];
+        roff[0] = 0;
+        for (int64_t r = 0; r < n; ++r) roff[r + 1] += roff[r];
+        P.roff = roff;
     }
     if (nthreads <= 0) {
         long c = sysconf(_SC_NPROCESSORS_ONLN);
@@ -579,6 +662,7 @@ int orc_enumerate(int64_t n, const int64_t *rp, const int32_t *col, int k, int n
     *out = r;
     free(args);
     free(th);
+    free(roff);
     free(g.rank);
     free(q.aut);
     return 0;

@@ -23,7 +23,7 @@ STATUS = {0: "HUGE_OK", 1: "HUGE_STOPPED", -1: "HUGE_EINVAL", -2: "HUGE_ENOMEM",
 HOST_PTRS, DEVICE_PTRS, NO_VALIDATE, NO_HUB_BITMAP = 0x1, 0x2, 0x4, 0x8
 PLAN_COST_MODEL, PLAN_LEARNED, PLAN_VERIFY, PLAN_INDUCED = 0x0, 0x1, 0x2, 0x4
 ENGINE_AUTO, ENGINE_LEVELS, ENGINE_PERSISTENT, ENGINE_GRAPH = 0, 1, 2, 3
-EXEC_NO_HASH = 0x1
+EXEC_NO_HASH, EXEC_SLICE2_PAIR = 0x1, 0x2
 SLICE_MIX, SLICE_STRIDE = 0, 1
 STRAT_BSEARCH, STRAT_WAVE_STAGED, STRAT_LANE_MERGE, STRAT_MERGE_SHORT, STRAT_MERGE_LONG = 0, 1, 2, 3, 4
 STRAT_BLOCK_MERGE, STRAT_BLOCK_MERGE_LONG = 5, 6
@@ -85,7 +85,7 @@ class ExecOpts(ctypes.Structure):
                 ("profile", ctypes.c_int32), ("slice_vertex", ctypes.c_int32), ("exec_flags", ctypes.c_uint32),
                 ("slice_mode", ctypes.c_uint32), ("tune", ctypes.c_void_p), ("work_limit", ctypes.c_int64),
                 ("slice2_vertex", ctypes.c_int32), ("slice2_count", ctypes.c_uint32), ("slice2_id", ctypes.c_uint32),
-                ("reserved1", ctypes.c_int32)]
+                ("slice2_vertex2", ctypes.c_int32)]
 
 
 TUNE_BUCKETS = 5
@@ -485,7 +485,8 @@ class Model:
 def exec_opts(cap=None, chunk_rows=0, strategy=-1, engine=ENGINE_AUTO, work_stealing=1, slice_count=1, slice_id=0,
               stream=None, workspace=None, profile=False, slice_vertex=0, hash=True, tune=None,
               work_limit=0, slice_mode=SLICE_MIX, slice2=None) -> ExecOpts:
-    """huge_exec_opts from keywords; slice2=(query vertex, count, id) is the second vertex slice."""
+    """huge_exec_opts from keywords; slice2=(query vertex, count, id) is the second vertex slice,
+    slice2=(a, b, count, id) a second slice on the pair of adjacent query vertices (a, b)."""
     lib = load_library()
     o = ExecOpts()
     lib.huge_exec_opts_default(ctypes.byref(o))
@@ -503,7 +504,12 @@ def exec_opts(cap=None, chunk_rows=0, strategy=-1, engine=ENGINE_AUTO, work_stea
     o.work_limit = int(work_limit)
     o.slice_mode = int(slice_mode)
     if slice2 is not None:
-        o.slice2_vertex, o.slice2_count, o.slice2_id = int(slice2[0]), int(slice2[1]), int(slice2[2])
+        if len(slice2) == 4:
+            o.slice2_vertex, o.slice2_vertex2 = int(slice2[0]), int(slice2[1])
+            o.exec_flags |= EXEC_SLICE2_PAIR
+        else:
+            o.slice2_vertex = int(slice2[0])
+        o.slice2_count, o.slice2_id = int(slice2[-2]), int(slice2[-1])
     if tune is not None:
         o.tune = ctypes.cast(ctypes.byref(tune), ctypes.c_void_p)
     o.stream = (stream if stream is not None else _current_stream()).value \

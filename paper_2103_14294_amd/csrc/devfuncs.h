@@ -55,7 +55,7 @@ template <int W>
 __device__ __forceinline__ void load_row(const int32_t *__restrict__ rows, const GraphDev &g, int64_t r,
                                          int32_t (&f)[W]) {
     if constexpr (W == 2) {
-        const int64_t e = g.l2_idx ? g.l2_idx[r] : r;
+        const int64_t e = g.l2_idx ? g.l2_idx[r] : g.l2_first + r * g.l2_stride;
         f[0] = g.src[e];
         f[1] = g.col[e];
     } else {
@@ -78,13 +78,37 @@ __device__ __forceinline__ bool in_slice(int32_t v, const DevPlan &P) {
 __device__ __forceinline__ bool slices_ok(int32_t bits, int32_t v, const DevPlan &P) {
     bool ok = true;
     if ((bits & 1) && P.slice_count > 1 && !P.edge_slice) ok &= in_slice(v, P);
-    if ((bits & 2) && P.slice2_count > 1) ok &= in_vslice(v, P.slice2_count, P.slice2_id, P.slice_mode);
+    if ((bits & 2) && P.slice2_count > 1 && P.p2a < 0) ok &= in_vslice(v, P.slice2_count, P.slice2_id, P.slice_mode);
     return ok;
 }
 
 // Validity of a level-2 row (the SCAN of the first query edge): the
 // constraint between positions 0 and 1, and the slices (of the row's ordered
 // pair, or of the vertex in position 0 or 1).
+// The second slice on a pair of positions (p2a, p2b), checked at the step that
+// places the later of them (W is that step's position, v its candidate): the
+// pair (x, y) of their images sits at entry e of the relabelled CSR (x's row,
+// y's place in it), kept when e % count == id (strided), or by the pair's mix.
+template <int W>
+__device__ __forceinline__ bool pair2_ok(const GraphDev &g, const DevPlan &P, const int32_t (&f)[W], int32_t v) {
+    int32_t x = v, y = v;
+#pragma unroll
+    for (int p = 0; p < W; ++p) {
+        if (p == P.p2a) x = f[p];
+        if (p == P.p2b) y = f[p];
+    }
+    if (P.slice_mode) {
+        int64_t lo = g.rp[x], hi = g.rp[x + 1];
+        while (lo < hi) {
+            const int64_t mid = lo + ((hi - lo) >> 1);
+            if (g.col[mid] < y) lo = mid + 1; else hi = mid;
+        }
+        return (uint64_t)lo % P.slice2_count == P.slice2_id;
+    }
+    const uint64_t key = ((uint64_t)(uint32_t)x << 32) | (uint64_t)(uint32_t)y;
+    return (uint32_t)(mix64(key) % P.slice2_count) == P.slice2_id;
+}
+
 // the label the plan asks of position i's vertex v (labelled plans)
 __device__ __forceinline__ bool label_ok(const GraphDev &g, int32_t want, int32_t v) {
     return want < 0 || g.label[v] == want;
@@ -95,10 +119,11 @@ __device__ __forceinline__ bool level2_ok(const int32_t (&f)[2], const DevPlan &
     if (!label_ok(g, P.st[0].label, f[0]) || !label_ok(g, s1.label, f[1])) return false;
     if ((s1.lo & 1u) && !(f[0] < f[1])) return false;
     if ((s1.hi & 1u) && !(f[1] < f[0])) return false;
-    if (P.slice_count > 1 && P.edge_slice) {
+    if (P.slice_count > 1 && P.edge_slice == 1) {
         const uint64_t key = ((uint64_t)(uint32_t)f[0] << 32) | (uint64_t)(uint32_t)f[1];
         if ((uint32_t)(mix64(key) % P.slice_count) != P.slice_id) return false;
     }
+    if ((s1.slice & 4) && !pair2_ok<1>(g, P, {f[0]}, f[1])) return false;
     return slices_ok(P.st[0].slice, f[0], P) && slices_ok(s1.slice, f[1], P);
 }
 

@@ -64,7 +64,7 @@ Layout make_layout(const huge_graph *g, const huge_plan *p, const huge_exec_opts
         L.l2_roots = gathered_roots(g, P);
         L.l2_rows = gathered_rows_bound(g, P);
     }
-    const int64_t l2_all = L.l2_rows ? L.l2_rows : g->dev.nnz;
+    const int64_t l2_all = L.l2_rows ? L.l2_rows : P.edge_slice == 2 ? strided_l2_rows(g, P) : g->dev.nnz;
     int64_t seg = o.chunk_rows > 0 ? o.chunk_rows : kDefaultSeg;
     const int nq = std::max(0, k - 3);
     uint64_t cap = o.frontier_cap_bytes;
@@ -135,7 +135,7 @@ struct DevMem {
 DevPlan exec_plan(const huge_plan *p, const huge_exec_opts &o) {
     const int k = p->k;
     DevPlan P = p->dev;
-    if (o.reserved0 || o.reserved1) HUGE_FAIL(HUGE_EINVAL, "reserved option fields must be 0");
+    if (o.reserved0) HUGE_FAIL(HUGE_EINVAL, "reserved option fields must be 0");
     if (o.slice_mode > HUGE_SLICE_STRIDE) HUGE_FAIL(HUGE_EINVAL, "unknown slice_mode %u", o.slice_mode);
     P.slice_count = o.slice_count > 1 ? o.slice_count : 1;
     P.slice_id = o.slice_count > 1 ? o.slice_id : 0;
@@ -144,16 +144,34 @@ DevPlan exec_plan(const huge_plan *p, const huge_exec_opts &o) {
     P.slice_mode = (int32_t)o.slice_mode;
     P.slice2_count = o.slice2_count > 1 ? o.slice2_count : 1;
     P.slice2_id = o.slice2_count > 1 ? o.slice2_id : 0;
+    P.p2a = P.p2b = -1;
+    const bool pair2 = (o.exec_flags & HUGE_EXEC_SLICE2_PAIR) != 0;
+    int pos[HUGE_KMAX];
+    for (int i = 0; i < k; ++i) pos[p->order[i]] = i;
     if (P.slice2_count > 1) {
         if (P.slice2_id >= P.slice2_count) HUGE_FAIL(HUGE_EINVAL, "slice2_id >= slice2_count");
         if (o.slice2_vertex < 0 || o.slice2_vertex >= k) HUGE_FAIL(HUGE_EINVAL, "slice2_vertex out of range");
+        if (pair2) {
+            const int b = o.slice2_vertex2;
+            if (b < 0 || b >= k || b == o.slice2_vertex) HUGE_FAIL(HUGE_EINVAL, "slice2_vertex2 out of range");
+            if (!p->adj[o.slice2_vertex][b]) HUGE_FAIL(HUGE_EINVAL, "a pair slice needs adjacent query vertices");
+            P.p2a = pos[o.slice2_vertex];
+            P.p2b = pos[b];
+        }
     }
     const int sv = o.slice_vertex == -1 ? p->order[0] : o.slice_vertex;  // -2: edge slice, no vertex
     for (int i = 0; i < k; ++i)
-        P.st[i].slice = (p->order[i] == sv ? 1 : 0) | (P.slice2_count > 1 && p->order[i] == o.slice2_vertex ? 2 : 0);
-    P.edge_slice = (o.slice_vertex == -2 && P.slice_count > 1) ? 1 : 0;
-    if (P.edge_slice && o.slice_mode != HUGE_SLICE_MIX) HUGE_FAIL(HUGE_EINVAL, "edge slices are mixed slices");
+        P.st[i].slice = (p->order[i] == sv ? 1 : 0) |
+                        (P.slice2_count > 1 && !pair2 && p->order[i] == o.slice2_vertex ? 2 : 0) |
+                        (P.p2a >= 0 && i == std::max(P.p2a, P.p2b) ? 4 : 0);
+    P.edge_slice = (o.slice_vertex == -2 && P.slice_count > 1) ? (o.slice_mode == HUGE_SLICE_STRIDE ? 2 : 1) : 0;
     return P;
+}
+
+// Level-2 rows of a strided edge slice: entries slice_id, slice_id + S, ...
+int64_t strided_l2_rows(const huge_graph *g, const DevPlan &P) {
+    const int64_t nnz = g->dev.nnz, s = P.slice_id, S = P.slice_count;
+    return nnz > s ? (nnz - s + S - 1) / S : 0;
 }
 
 // level_counts[0] counts the roots in the slices, and with the label, that apply to position 0
@@ -369,7 +387,12 @@ bool run_levels(const huge_graph *g, const huge_plan *p, const huge_exec_opts &o
     prof.probe = probe;
     prof.st = st;
     GraphDev G = g->dev;
-    int64_t l2_rows = G.nnz;  // level-2 rows: every edge-array entry, or the gathered slice
+    int64_t l2_rows = G.nnz;  // level-2 rows: every edge-array entry, a strided edge slice, or the gathered slice
+    if (P.edge_slice == 2) {
+        G.l2_first = P.slice_id;
+        G.l2_stride = P.slice_count;
+        l2_rows = strided_l2_rows(g, P);
+    }
     if (L.l2_rows) {
         int64_t *idx = cv.take<int64_t>(L.l2_rows);
         int32_t *deg = cv.take<int32_t>(L.l2_roots);
@@ -681,6 +704,11 @@ void run_graph(const huge_graph *g, const huge_plan *p, const huge_exec_opts &o_
     for (int w = 3; w <= k - 1; ++w) gc.q_cap[w] = L.q_cap[w];
     GraphDev G = g->dev;
     int64_t l2_rows = G.nnz;
+    if (P.edge_slice == 2) {
+        G.l2_first = P.slice_id;
+        G.l2_stride = P.slice_count;
+        l2_rows = strided_l2_rows(g, P);
+    }
     if (L.l2_rows) {  // a strided root slice: gather its level-2 entries first
         int64_t *idx = cv.take<int64_t>(L.l2_rows);
         int32_t *deg = cv.take<int32_t>(L.l2_roots);

@@ -53,6 +53,7 @@ struct GraphDev {
     // level-2 rows of one execution: row r is edge-array entry l2_idx[r], or
     // entry r when l2_idx is NULL (every entry)
     const int64_t *l2_idx = nullptr;
+    int64_t l2_first = 0, l2_stride = 1;  // without l2_idx: row r is entry l2_first + r * l2_stride
     const int32_t *label = nullptr;  // vertex labels by rank (labelled graphs), or NULL
 };
 
@@ -93,9 +94,11 @@ struct DevPlan {
     uint8_t pos[HUGE_KMAX];     // pos[v] = position of query vertex v
     DevStep st[HUGE_KMAX];      // st[i], i = 1..k-1; st[i].slice marks the sliced vertices' positions
     uint32_t slice_count, slice_id;
-    int32_t edge_slice;         // 1: slice the level-2 rows (ordered pairs f[0], f[1]) instead of a vertex
+    int32_t edge_slice;         // slice the level-2 rows (ordered pairs f[0], f[1]) instead of a vertex:
+                                // 1 by the pair's mix, 2 by its entry index (rows pre-selected by stride)
     int32_t slice_mode;         // vertex slices: 0 mix(v) % count, 1 v % count (v a rank)
-    uint32_t slice2_count, slice2_id;  // second vertex slice (1, 0 = none)
+    uint32_t slice2_count, slice2_id;  // second slice (1, 0 = none)
+    int32_t p2a, p2b;           // second slice on the pair of these positions (-1: a vertex slice)
 };
 
 }  // namespace huge
@@ -191,6 +194,7 @@ bool root_sliced(const DevPlan &P);       // level_counts[0] is the number of ro
 bool gathers_level2(const DevPlan &P);    // level 2 is the gathered entries of a strided root slice
 int64_t gathered_rows_bound(const huge_graph *g, const DevPlan &P);
 int64_t gathered_roots(const huge_graph *g, const DevPlan &P);
+int64_t strided_l2_rows(const huge_graph *g, const DevPlan &P);  // rows of a strided edge slice
 // returns true when the run stopped at o.work_limit; host_stage: a host block of
 // kHostStageBytes for the scheduler's read-backs (NULL: pinned memory is allocated)
 bool run_levels(const huge_graph *g, const huge_plan *p, const huge_exec_opts &o, huge_result *out, EmitSink *emit,

@@ -83,7 +83,8 @@ BatchLayout make_batch_layout(const huge_graph *g, const huge_plan *const *plans
         }
         for (int w = 3; w <= k - 1; ++w)
             L.q_cap[w] = std::max<int64_t>(kMinQueueRows, (int64_t)((nq ? share / nq : 0) / (4ull * w)));
-        const int64_t l2 = L.gathered ? gathered_rows_bound(g, P) : g->dev.nnz;
+        const int64_t l2 = L.gathered ? gathered_rows_bound(g, P) : P.edge_slice == 2 ? strided_l2_rows(g, P)
+                                                                                      : g->dev.nnz;
         L.seg_cap[2] = std::min<int64_t>(std::min(seg_rows_for(p, 2, o), scan_devn_max()), std::max<int64_t>(1, l2));
         for (int w = 3; w <= k - 1; ++w)
             L.seg_cap[w] = std::min<int64_t>(std::min(seg_rows_for(p, w, o), scan_devn_max()), L.q_cap[w]);
@@ -246,6 +247,10 @@ void run_mgraph(const huge_graph *g, const huge_plan *const *plans, int np, cons
         m.gc.lastW = k - 1;
         m.P = B.P[b];
         m.g = L.gathered ? Gg : G;
+        if (m.P.edge_slice == 2) {
+            m.g.l2_first = m.P.slice_id;
+            m.g.l2_stride = m.P.slice_count;
+        }
         m.ctrl = ctrl + b;
         m.gs = gs + b;
         m.inv_rank = g->inv_rank;
@@ -269,7 +274,7 @@ void run_mgraph(const huge_graph *g, const huge_plan *const *plans, int np, cons
         GState &s = hs[b];
         memset((void *)&s, 0, sizeof(s));
         s.W = 2;
-        s.lv[2].nrows = L.gathered ? l2_gathered : g->dev.nnz;
+        s.lv[2].nrows = L.gathered ? l2_gathered : m.P.edge_slice == 2 ? strided_l2_rows(g, m.P) : g->dev.nnz;
     }
     if (cv.off > B.total) HUGE_FAIL(HUGE_EDEVICE, "batched round layout overflow");
     HUGE_HIP(hipMemsetAsync(ctrl, 0, sizeof(Ctrl) * nb, st));

@@ -236,15 +236,16 @@ double order_cost(const std::vector<double> &e, size_t o, int k) {
 }
 
 // Measured choice among the model's kVerifyCandidates best orders and the cost
-// model's order.  Each runs the query on slice 0 of S of its own first matched
-// vertex, strided by degree rank (ranks 0, S, 2S, ...), so every order's
-// sample holds the same share of each degree class and costs only its own
-// slice's entries: an unbiased 1/S sample of that order's work.  S is the
-// smallest power of 8 (from 2^9) at which the cost model's order examines at
-// most kVerifyWork candidates; the other orders stop (and lose) past
-// kVerifyRelLimit times its candidates.  The order with the least device time
-// wins, the cost model's keeping ties within kVerifyGain.  About a few
-// milliseconds of device time per order.
+// model's order.  Each runs the query on edge slice 0 of S of its own first
+// matched pair: the matches whose first two vertices sit at an entry e of the
+// relabelled CSR with e % S == 0.  That is every S-th entry of every adjacency
+// list, so hubs are sampled in proportion to their degree, the engines read
+// only those entries, and the sample is an unbiased 1/S share of that order's
+// work.  S is the smallest power of 8 (from 2^9) at which the cost model's
+// order examines at most kVerifyWork candidates; the other orders stop (and
+// lose) past kVerifyRelLimit times its candidates.  The order with the least
+// device time wins, the cost model's keeping ties within kVerifyGain.  About a
+// few milliseconds of device time per order.
 size_t verify_orders(const huge_graph *g, const huge_plan &p, const std::vector<std::vector<int32_t>> &orders,
                      const std::vector<double> &est, const huge_graph_info &gi, hipStream_t st) {
     const int k = p.k;
@@ -272,7 +273,7 @@ size_t verify_orders(const huge_graph *g, const huge_plan &p, const std::vector<
     o.stream = st;
     o.slice_count = 512;
     o.slice_id = 0;
-    o.slice_vertex = -1;
+    o.slice_vertex = -2;
     o.slice_mode = HUGE_SLICE_STRIDE;
     o.work_limit = kVerifyWork;
     o.exec_flags = HUGE_EXEC_NO_HASH;
@@ -307,7 +308,7 @@ size_t verify_orders(const huge_graph *g, const huge_plan &p, const std::vector<
     for (;;) {
         ensure_ws();
         if (!run_levels(g, &qs[0], o, &r0, nullptr)) break;
-        if ((int64_t)o.slice_count * 8 > std::max<int64_t>(gi.n, 1)) return base;  // no workable sample
+        if ((int64_t)o.slice_count * 8 > std::max<int64_t>(g->dev.nnz, 1)) return base;  // no workable sample
         o.slice_count *= 8;
     }
     double base_work = 0;

@@ -417,3 +417,64 @@ def test_labelled_matching_brute_force_and_closed_forms():
     k, e = P.NAMED["triangle"]
     assert oracle.enumerate_query(K.row_ptr, K.col, k, e, vlabels=lab, qlabels=[0, 0, 1])["count"] == \
         math.comb(4, 2) * 5
+
+
+def _relabelled_entry_index(g):
+    """entry[(x, y)] = position of the pair in the CSR relabelled by degree rank
+    (rows in rank order, each list sorted by rank), built directly."""
+    rank = oracle.ranks(g.row_ptr)
+    order = sorted(range(g.n), key=lambda u: int(rank[u]))
+    entry, e = {}, 0
+    for u in order:
+        for v in sorted((int(x) for x in g.col[g.row_ptr[u]:g.row_ptr[u + 1]]), key=lambda z: int(rank[z])):
+            entry[(u, v)] = e
+            e += 1
+    return rank, entry
+
+
+def test_strided_pair_slices_partition_and_match_the_relabelled_csr():
+    """A strided pair slice keeps the maps whose pair (f(a), f(b)) sits at an entry
+    e of the rank-relabelled CSR with e mod S == s: on a tiny graph each slice is
+    exactly those SB-satisfying maps (entries computed from an explicitly built
+    relabelled CSR); the slices partition the matches, for the order's first
+    pair and for a later pair; a second pair slice splits them again."""
+    import itertools
+
+    t = gg.gnp(10, 0.5, seed=7)
+    rank, entry = _relabelled_entry_index(t)
+    adj = {(u, int(v)) for u in range(t.n) for v in t.col[t.row_ptr[u]:t.row_ptr[u + 1]]}
+    k, e = P.NAMED["diamond"]
+    sb = oracle.sb_pairs(k, e)
+    maps = [f for f in itertools.permutations(range(t.n), k)
+            if all((f[a], f[b]) in adj for a, b in e) and all(rank[f[a]] < rank[f[b]] for a, b in sb)]
+    for order, pair in [([1, 2, 0, 3], (1, 2)), ([0, 1, 2, 3], (2, 3)), ([3, 1, 2, 0], (2, 0))]:
+        for s in range(5):
+            want = sum(1 for f in maps if entry[(f[pair[0]], f[pair[1]])] % 5 == s)
+            got = oracle.enumerate_query(t.row_ptr, t.col, k, e, order=order, slice_count=5, slice_id=s,
+                                         slice_pair=pair, slice_mode=1)
+            assert got["count"] == want, (order, pair, s)
+    g = gg.chung_lu(2000, 9, 2.4, seed=12)
+    for name, order in [("house", None), ("4-cycle", [1, 2, 3, 0]), ("tailed-triangle", [2, 3, 0, 1])]:
+        k, e = P.NAMED[name]
+        full = oracle.enumerate_query(g.row_ptr, g.col, k, e)
+        o = order or [0, 1, 2, 3, 4][:k]
+        acc = [0, 0, 0]
+        for s in range(7):
+            r = oracle.enumerate_query(g.row_ptr, g.col, k, e, order=o, slice_count=7, slice_id=s,
+                                       slice_pair=(o[0], o[1]), slice_mode=1)
+            acc = [acc[0] + r["count"], (acc[1] + r["hash_sum"]) & M64, acc[2] ^ r["hash_xor"]]
+        assert tuple(acc) == (full["count"], full["hash_sum"], full["hash_xor"]), name
+    # double: first pair of one order and first pair of another, in either role
+    k, e = P.NAMED["house"]
+    oa, ob = [0, 1, 2, 3, 4], [3, 2, 1, 0, 4]
+    full = oracle.enumerate_query(g.row_ptr, g.col, k, e)
+    acc = [0, 0, 0]
+    for s1 in range(3):
+        for s2 in range(2):
+            a = oracle.enumerate_query(g.row_ptr, g.col, k, e, order=oa, slice_count=3, slice_id=s1,
+                                       slice_pair=(0, 1), slice_mode=1, slice2=(3, 2, 2, s2))
+            b = oracle.enumerate_query(g.row_ptr, g.col, k, e, order=ob, slice_count=2, slice_id=s2,
+                                       slice_pair=(3, 2), slice_mode=1, slice2=(0, 1, 3, s1))
+            assert (a["count"], a["hash_sum"], a["hash_xor"]) == (b["count"], b["hash_sum"], b["hash_xor"])
+            acc = [acc[0] + a["count"], (acc[1] + a["hash_sum"]) & M64, acc[2] ^ a["hash_xor"]]
+    assert tuple(acc) == (full["count"], full["hash_sum"], full["hash_xor"])
