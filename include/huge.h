@@ -106,10 +106,12 @@ typedef struct {
     uint64_t steals;                   /* successful steals (persistent engine) */
     /* filled when huge_exec_opts.profile != 0 (HIP events on the exec stream),
        per kernel class HUGE_KC_*: summed device time, launches, and the
-       algorithmic bytes of the work those launches did: a merge intersection
-       over symmetry-breaking-trimmed lists moves 4i + 16j + 4 * (sum of the
-       trimmed list lengths) bytes per input row of width i with j
-       intersected lists, plus 4(i+1) bytes per emitted row */
+       algorithmic bytes of the work those launches did: an intersection of
+       symmetry-breaking-trimmed lists must read, per input row of width i with
+       j intersected lists, 4i + 16j bytes, the shortest window P whole and of
+       every other window W at least 4 * min(|W|, |P|) bytes (one element per
+       candidate, or the whole window if shorter), plus 4(i+1) bytes per
+       emitted row */
     double kernel_ms[4];
     uint64_t kernel_launches[4];
     double alg_bytes[4];
@@ -341,6 +343,75 @@ huge_status huge_plan_info(const huge_plan *p, int32_t *k, int32_t *order_out, i
  */
 huge_status huge_plan_estimates(const huge_plan *p, double *est);
 
+/*
+ * Bushy plans: Algorithm 1 (OptimalExecutionPlan, Section 3.3) over the
+ * join-based framework of Section 3.1 (Eq. 1), stars as the join unit, with
+ * each join's physical setting from the settings equation of Section 3.3.
+ * A sub-query is a connected set of query edges; a star (every edge at one
+ * centre) is a join unit, costed at its estimated result size; any other
+ * sub-query q' is a two-way join (q', l, r) of two connected edge-disjoint
+ * parts, costed M(l) + M(r) + |R(q')| plus its communication:
+ *   machines * |E_G| when it pulls (r a star (c; L) with L inside V(l) --
+ *   a complete star join -- or with c inside V(l)), else |R(l)| + |R(r)|.
+ * |R| is the Chung-Lu estimate of huge_plan_estimates over the part's edges
+ * and vertices, with the symmetry-breaking constraints inside it.  Kinds:
+ */
+#define HUGE_BUSHY_UNIT 0      /* a star join unit: SCAN of one edge, EXTENDs from the centre (Section 5.1) */
+#define HUGE_BUSHY_EXTEND 1    /* complete star join, right = star (c; L), c new, L in V(left): one PULL-EXTEND
+                                  of c intersecting the lists of L (Eq. 2) */
+#define HUGE_BUSHY_PULL_HASH 2 /* pulled hash join, right = star (c; L) with c in V(left): the edges from c to
+                                  L inside V(left) verified by lookup (the verify-only EXTEND with its hint),
+                                  then one EXTEND from c per other leaf (Section 5.1) */
+#define HUGE_BUSHY_PUSH 3      /* PUSH-JOIN (Section 4.3): both parts materialised, hash-joined on their shared
+                                  vertices */
+#define HUGE_BUSHY_MAX_EDGES 15
+#define HUGE_BUSHY_MAX_NODES 29 /* 2 * HUGE_BUSHY_MAX_EDGES - 1 */
+
+typedef struct {
+    uint32_t edge_mask;   /* bit e: query edge e, in the order given at creation */
+    uint32_t vertex_mask; /* its query vertices */
+    int32_t kind;         /* HUGE_BUSHY_* */
+    int32_t left, right;  /* children (node indices), -1 for units; pulled joins keep the star on the right */
+    int32_t star_root;    /* units and pulled joins: the star's centre; PUSH-JOIN: -1 */
+    int32_t reserved;
+    double est_rows;      /* estimated |R(q')| */
+    double cost;          /* Algorithm 1's M_cost[q'] */
+} huge_bushy_node;
+
+/*
+ * huge_plan_create_bushy -- a bushy plan by Algorithm 1.  stats: the degree
+ * statistics the estimates use (NULL: g's; g may be NULL when stats is given,
+ * for planning only); machines: Algorithm 1's k (1 for one GPU; 0 makes every
+ * pull free, large values make pulling dear); qlabels: as
+ * huge_plan_create_labelled, or NULL.  At most HUGE_BUSHY_MAX_EDGES query
+ * edges (HUGE_EQUERY).  Symmetry breaking is q's, as for every plan, and
+ * each part of the tree applies the constraints inside it.  The plan runs
+ * through huge_count (level engine; HUGE_EINVAL for other engines, for edge
+ * slices, second slices, work limits and induced matching): chains of pulled
+ * joins over a SCAN run on the level engine with a bounded frontier; the
+ * parts below and around a PUSH-JOIN are materialised in device memory that
+ * the call allocates (sized exactly by a counting pass) and frees.
+ */
+huge_status huge_plan_create_bushy(const huge_graph *g, const huge_graph_info *stats, int32_t k, int32_t n_qedges,
+                                   const int32_t *qedges, const int32_t *qlabels, double machines, huge_plan **out);
+/*
+ * huge_plan_create_bushy_tree -- a bushy plan from a logical plan the caller
+ * gives (Remark 3.2: existing logical plans plug into the optimiser, which
+ * only configures each join's physical setting).  joins: n_joins pairs of edge
+ * masks (left, right) over the query edges in the order given; the pairs must
+ * form one tree whose root splits the whole query: each part connected, the
+ * two parts of a join disjoint and non-empty, every part that no join splits
+ * a star.  Each join's setting follows the settings equation (a star side is
+ * read as the right part); costs are computed as Algorithm 1's for the report.
+ * Errors: HUGE_EORDER for a malformed tree, otherwise as huge_plan_create_bushy.
+ */
+huge_status huge_plan_create_bushy_tree(const huge_graph *g, const huge_graph_info *stats, int32_t k,
+                                        int32_t n_qedges, const int32_t *qedges, const int32_t *qlabels,
+                                        const uint32_t *joins, int32_t n_joins, double machines, huge_plan **out);
+/* The join tree of a bushy plan, children before parents, the root last
+   (HUGE_EINVAL for other plans).  nodes may be NULL to read the count. */
+huge_status huge_plan_bushy_nodes(const huge_plan *p, huge_bushy_node *nodes, int32_t max_nodes, int32_t *n_nodes);
+
 /* Device workspace needed by huge_count / huge_enumerate for these options
  * (engine included: the graph engine also keeps its scheduler state there,
  * and the persistent engine its per-workgroup buffers, boards and counters). */
@@ -354,6 +425,11 @@ huge_status huge_workspace_size(const huge_graph *g, const huge_plan *p, const h
  * Returns HUGE_STOPPED (out filled, partial) when opts->work_limit ended the run.
  */
 huge_status huge_count(const huge_graph *g, const huge_plan *p, const huge_exec_opts *opts, huge_result *out);
+/* huge_count of a bushy plan that also reports, per tree node, the rows its
+   part produced (node_rows[i] for node i < max_nodes; the root's is the
+   count). */
+huge_status huge_count_bushy(const huge_graph *g, const huge_plan *p, const huge_exec_opts *opts, huge_result *out,
+                             int64_t *node_rows, int32_t max_nodes);
 
 /*
  * huge_count_noalloc -- huge_count for callers that cannot allocate memory:
@@ -543,7 +619,9 @@ huge_status huge_plan_create_learned(const huge_graph *g, const huge_model *m, i
  * each order's own first matched pair (slice 0 of S: every S-th entry of the
  * relabelled CSR, so each order reads only its own sample's entries), S the
  * smallest power of 8 from 512 at which the cost model's order examines at
- * most 4e7 candidates; the others stop at 3 times its candidates.  The order with the
+ * most 4e7 candidates (when no edge sample of 64 entries or more fits, strided
+ * root slices of the first matched vertex, at least 4 roots); the others stop
+ * at 3 times its candidates.  The order with the
  * least device time wins; the cost model's order keeps ties within 10%.  This
  * costs a few milliseconds of device time per order, on `stream`.
  */

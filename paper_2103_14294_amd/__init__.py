@@ -38,6 +38,7 @@ EXPORTED = [
     "huge_autotune", "huge_graph_digest", "huge_plan_prefix", "huge_plan_create_learned2", "huge_device_name",
     "huge_batch_workspace_size", "huge_plan_estimates", "huge_count_noalloc", "huge_noalloc_capacity",
     "huge_motif_count", "huge_load_csr_labelled", "huge_plan_create_labelled",
+    "huge_plan_create_bushy", "huge_plan_bushy_nodes", "huge_count_bushy", "huge_plan_create_bushy_tree",
 ]
 MOTIF_KMAX, MOTIF_MAX = 6, 112
 MLP_F, MLP_H = 128, 256
@@ -120,6 +121,17 @@ class GraphInfo(ctypes.Structure):
                 ("hub_min_degree", ctypes.c_int64)]
 
 
+BUSHY_UNIT, BUSHY_EXTEND, BUSHY_PULL_HASH, BUSHY_PUSH = 0, 1, 2, 3
+BUSHY_KINDS = {0: "unit", 1: "extend", 2: "pull_hash", 3: "push"}
+BUSHY_MAX_EDGES, BUSHY_MAX_NODES = 15, 29
+
+
+class BushyNode(ctypes.Structure):
+    _fields_ = [("edge_mask", ctypes.c_uint32), ("vertex_mask", ctypes.c_uint32), ("kind", ctypes.c_int32),
+                ("left", ctypes.c_int32), ("right", ctypes.c_int32), ("star_root", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("est_rows", ctypes.c_double), ("cost", ctypes.c_double)]
+
+
 EMIT_FN = ctypes.CFUNCTYPE(ctypes.c_int, ctypes.c_void_p, ctypes.POINTER(ctypes.c_int32), ctypes.c_int64,
                            ctypes.c_int32)
 
@@ -164,6 +176,16 @@ def load_library(path: str = LIB_PATH):
         lib.huge_motif_count.restype = st
         lib.huge_motif_count.argtypes = [vp, i32, ctypes.POINTER(ExecOpts), ctypes.POINTER(Motif),
                                          ctypes.POINTER(i32)]
+        lib.huge_plan_create_bushy.restype = st
+        lib.huge_plan_create_bushy.argtypes = [vp, ctypes.POINTER(GraphInfo), i32, i32, vp, vp, ctypes.c_double,
+                                               ctypes.POINTER(ctypes.c_void_p)]
+        lib.huge_plan_create_bushy_tree.restype = st
+        lib.huge_plan_create_bushy_tree.argtypes = [vp, ctypes.POINTER(GraphInfo), i32, i32, vp, vp, vp, i32,
+                                                    ctypes.c_double, ctypes.POINTER(ctypes.c_void_p)]
+        lib.huge_plan_bushy_nodes.restype = st
+        lib.huge_plan_bushy_nodes.argtypes = [vp, ctypes.POINTER(BushyNode), i32, ctypes.POINTER(i32)]
+        lib.huge_count_bushy.restype = st
+        lib.huge_count_bushy.argtypes = [vp, vp, ctypes.POINTER(ExecOpts), ctypes.POINTER(Result), vp, i32]
         lib.huge_count_noalloc.restype = st
         lib.huge_count_noalloc.argtypes = [vp, vp, ctypes.POINTER(ExecOpts), ctypes.POINTER(Result)]
         lib.huge_noalloc_capacity.restype = st
@@ -272,9 +294,19 @@ class Graph:
 
 
 class Plan:
-    def __init__(self, handle, k):
+    def __init__(self, handle, k, bushy=False):
         self._h = ctypes.c_void_p(handle)
         self.k = k
+        self.bushy = bushy
+
+    def bushy_nodes(self):
+        """huge_plan_bushy_nodes: the join tree, children before parents, the root last."""
+        n = ctypes.c_int32()
+        out = (BushyNode * BUSHY_MAX_NODES)()
+        _check(_lib.huge_plan_bushy_nodes(self._h, out, BUSHY_MAX_NODES, ctypes.byref(n)))
+        return [{"edge_mask": int(x.edge_mask), "vertex_mask": int(x.vertex_mask), "kind": BUSHY_KINDS[x.kind],
+                 "left": int(x.left), "right": int(x.right), "star_root": int(x.star_root),
+                 "est_rows": float(x.est_rows), "cost": float(x.cost)} for x in out[: n.value]]
 
     @property
     def handle(self):
@@ -380,6 +412,51 @@ def plan(g: Graph, k, edges, order=None, learned=None, verify=False, induced=Fal
                                     None if o is None else o.ctypes.data,
                                     (PLAN_LEARNED if learned else PLAN_COST_MODEL) | ind, ctypes.byref(h)))
     return Plan(h.value, int(k))
+
+
+def graph_info_struct(stats: dict) -> GraphInfo:
+    """A huge_graph_info holding n, nnz and degree_moments from a dict (planning without a graph)."""
+    gi = GraphInfo()
+    gi.n, gi.nnz = int(stats["n"]), int(stats["nnz"])
+    for i, m in enumerate(stats["degree_moments"]):
+        gi.degree_moments[i] = float(m)
+    return gi
+
+
+def plan_bushy(g: Graph | None, k, edges, machines=1.0, stats: dict | None = None, labels=None,
+               joins=None) -> Plan:
+    """huge_plan_create_bushy: Algorithm 1's bushy plan; `machines` is its k (the
+    pull cost k |E_G|); stats (n, nnz, degree_moments) plan without a graph.
+    joins=[(left_mask, right_mask), ...] gives the tree instead
+    (huge_plan_create_bushy_tree): masks over the query edges as listed."""
+    lib = load_library()
+    e = np.ascontiguousarray(np.asarray(edges, dtype=np.int32).reshape(-1, 2))
+    ql = None if labels is None else np.ascontiguousarray(np.asarray(labels, dtype=np.int32))
+    gi = None if stats is None else graph_info_struct(stats)
+    h = ctypes.c_void_p()
+    gh, gip = None if g is None else g.handle, None if gi is None else ctypes.byref(gi)
+    qp = None if ql is None else ql.ctypes.data
+    if joins is None:
+        _check(lib.huge_plan_create_bushy(gh, gip, int(k), int(e.shape[0]), e.ctypes.data, qp, float(machines),
+                                          ctypes.byref(h)))
+    else:
+        js = np.ascontiguousarray(np.asarray(joins, dtype=np.uint32).reshape(-1, 2))
+        _check(lib.huge_plan_create_bushy_tree(gh, gip, int(k), int(e.shape[0]), e.ctypes.data, qp,
+                                               js.ctypes.data if js.size else None, int(js.shape[0]),
+                                               float(machines), ctypes.byref(h)))
+    return Plan(h.value, int(k), bushy=True)
+
+
+def count_bushy(g: Graph, p: Plan, **kw):
+    """huge_count_bushy: the result dict and the rows each tree node produced (-1
+    for nodes inside a chain of pulled joins)."""
+    lib = load_library()
+    opts = exec_opts(**kw)
+    r = Result()
+    rows = np.full(BUSHY_MAX_NODES, -2, dtype=np.int64)
+    _check(lib.huge_count_bushy(g.handle, p.handle, ctypes.byref(opts), ctypes.byref(r), rows.ctypes.data,
+                                BUSHY_MAX_NODES))
+    return r.to_dict(), rows.tolist()
 
 
 def plan_features(g: Graph, p: Plan, size: int, order=None) -> np.ndarray:
@@ -547,7 +624,7 @@ def count(g: Graph, p: Plan, workspace: Workspace | None = _default_ws, **kw) ->
     """huge_count: count matches; returns count, hash_sum, hash_xor, level_counts, query_ms, ..."""
     lib = load_library()
     opts = exec_opts(**kw)
-    if workspace is not None:
+    if workspace is not None and not getattr(p, "bushy", False):  # bushy plans allocate their own tables
         ws = workspace.get(workspace_size(g, p, opts))
         opts.workspace = ws.data_ptr()
         opts.workspace_bytes = ws.numel()

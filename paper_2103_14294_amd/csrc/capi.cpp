@@ -201,7 +201,9 @@ huge_status huge_count(const huge_graph *g, const huge_plan *p, const huge_exec_
         check_labels(g, p);
         huge_result r;
         bool limited = false;
-        if (o.engine == HUGE_ENGINE_PERSISTENT) {
+        if (!p->bushy.empty()) {
+            run_bushy(g, p, o, &r, nullptr, 0);
+        } else if (o.engine == HUGE_ENGINE_PERSISTENT) {
             const huge_plan *pl[1] = {p};
             run_persistent(g, pl, 1, o, &r);
         } else if (o.engine == HUGE_ENGINE_GRAPH) {
@@ -211,6 +213,69 @@ huge_status huge_count(const huge_graph *g, const huge_plan *p, const huge_exec_
         }
         *out = r;
         return limited ? HUGE_STOPPED : HUGE_OK;
+    });
+}
+
+huge_status huge_count_bushy(const huge_graph *g, const huge_plan *p, const huge_exec_opts *opts, huge_result *out,
+                             int64_t *node_rows, int32_t max_nodes) {
+    return guard([&] {
+        if (!g || !p || !out) HUGE_FAIL(HUGE_EINVAL, "NULL argument");
+        if (max_nodes < 0 || (max_nodes > 0 && !node_rows)) HUGE_FAIL(HUGE_EINVAL, "bad node_rows");
+        huge_exec_opts o = resolve_opts(opts);
+        check_labels(g, p);
+        huge_result r;
+        run_bushy(g, p, o, &r, node_rows, max_nodes);
+        *out = r;
+        return HUGE_OK;
+    });
+}
+
+huge_status huge_plan_create_bushy(const huge_graph *g, const huge_graph_info *stats, int32_t k, int32_t n_qedges,
+                                   const int32_t *qedges, const int32_t *qlabels, double machines, huge_plan **out) {
+    return guard([&] {
+        if (!out) HUGE_FAIL(HUGE_EINVAL, "NULL argument");
+        if (!g && !stats) HUGE_FAIL(HUGE_EINVAL, "a bushy plan needs a graph or its statistics");
+        huge_plan *p = new huge_plan();
+        try {
+            plan_build(g, k, n_qedges, qedges, nullptr, 0, nullptr, nullptr, p, qlabels);
+            plan_bushy(stats ? *stats : g->info, *p, machines);
+        } catch (...) {
+            delete p;
+            throw;
+        }
+        *out = p;
+        return HUGE_OK;
+    });
+}
+
+huge_status huge_plan_create_bushy_tree(const huge_graph *g, const huge_graph_info *stats, int32_t k,
+                                        int32_t n_qedges, const int32_t *qedges, const int32_t *qlabels,
+                                        const uint32_t *joins, int32_t n_joins, double machines, huge_plan **out) {
+    return guard([&] {
+        if (!out) HUGE_FAIL(HUGE_EINVAL, "NULL argument");
+        if (!g && !stats) HUGE_FAIL(HUGE_EINVAL, "a bushy plan needs a graph or its statistics");
+        if (n_joins < 0 || (n_joins > 0 && !joins)) HUGE_FAIL(HUGE_EINVAL, "bad joins");
+        huge_plan *p = new huge_plan();
+        try {
+            plan_build(g, k, n_qedges, qedges, nullptr, 0, nullptr, nullptr, p, qlabels);
+            plan_bushy_tree(stats ? *stats : g->info, *p, joins, n_joins, machines);
+        } catch (...) {
+            delete p;
+            throw;
+        }
+        *out = p;
+        return HUGE_OK;
+    });
+}
+
+huge_status huge_plan_bushy_nodes(const huge_plan *p, huge_bushy_node *nodes, int32_t max_nodes, int32_t *n_nodes) {
+    return guard([&] {
+        if (!p || !n_nodes) HUGE_FAIL(HUGE_EINVAL, "NULL argument");
+        if (p->bushy.empty()) HUGE_FAIL(HUGE_EINVAL, "not a bushy plan");
+        *n_nodes = (int32_t)p->bushy.size();
+        if (nodes)
+            for (int i = 0; i < max_nodes && i < (int)p->bushy.size(); ++i) nodes[i] = p->bushy[(size_t)i];
+        return HUGE_OK;
     });
 }
 

@@ -136,6 +136,7 @@ DevPlan exec_plan(const huge_plan *p, const huge_exec_opts &o) {
     const int k = p->k;
     DevPlan P = p->dev;
     if (o.reserved0) HUGE_FAIL(HUGE_EINVAL, "reserved option fields must be 0");
+    if (!p->bushy.empty()) HUGE_FAIL(HUGE_EINVAL, "a bushy plan runs through huge_count / huge_count_bushy only");
     if (o.slice_mode > HUGE_SLICE_STRIDE) HUGE_FAIL(HUGE_EINVAL, "unknown slice_mode %u", o.slice_mode);
     P.slice_count = o.slice_count > 1 ? o.slice_count : 1;
     P.slice_id = o.slice_count > 1 ? o.slice_id : 0;
@@ -326,10 +327,17 @@ bool run_levels(const huge_graph *g, const huge_plan *p, const huge_exec_opts &o
 
     int64_t stage_rows = 0;
     if (emit) {
-        if (!emit->host_buf || emit->buf_rows <= 0 || !emit->cb)
+        if ((!emit->dev_out && (!emit->host_buf || !emit->cb)) || emit->buf_rows <= 0)
             HUGE_FAIL(HUGE_EINVAL, "huge_enumerate: host_buf, buf_rows and cb are required");
         stage_rows = std::min<int64_t>(emit->buf_rows, 1 << 22);
     }
+    // rows for a device table are written in place, as ranks; for the host, staged and mapped to original IDs
+    const int32_t *inv_rank = (emit && emit->dev_out) ? nullptr : g->inv_rank;
+    auto out_rows = [&](int32_t *stage_buf, int64_t chunk) -> int32_t * {
+        if (!emit->dev_out) return stage_buf;
+        if ((int64_t)emit->delivered + chunk > emit->dev_cap) HUGE_FAIL(HUGE_EDEVICE, "device table overflow");
+        return emit->dev_out + (int64_t)emit->delivered * k;
+    };
     Layout L = make_layout(g, p, o, stage_rows);
     PinnedBuf pinned(kHostStageBytes, host_stage);
     int64_t *pin64 = (int64_t *)(pinned.p + sizeof(Ctrl));
@@ -415,6 +423,10 @@ bool run_levels(const huge_graph *g, const huge_plan *p, const huge_exec_opts &o
 
     auto deliver = [&](int64_t nout) {
         if (nout <= 0) return;
+        if (emit->dev_out) {  // already in place
+            emit->delivered += (uint64_t)nout;
+            return;
+        }
         HUGE_HIP(hipMemcpyAsync(emit->host_buf, stage, sizeof(int32_t) * k * nout, hipMemcpyDeviceToHost, st));
         HUGE_HIP(hipStreamSynchronize(st));
         emit->delivered += (uint64_t)nout;
@@ -427,7 +439,7 @@ bool run_levels(const huge_graph *g, const huge_plan *p, const huge_exec_opts &o
         const int jW = ext_count(p, W);
         if (!part) {
             prof.run(cls, [&] {
-                launch_extend(W, mode, strat, G, P, l.q, l.seg_row0, l.s, l.seg_n, w0, w1, outp, ctrl, g->inv_rank,
+                launch_extend(W, mode, strat, G, P, l.q, l.seg_row0, l.s, l.seg_n, w0, w1, outp, ctrl, inv_rank,
                               st, false);
             });
             stats.launches++;
@@ -439,7 +451,7 @@ bool run_levels(const huge_graph *g, const huge_plan *p, const huge_exec_opts &o
             int sc = o.tune->strategy[jW][c];
             if (sc < 0 || sc >= STRAT_COUNT) sc = STRAT_LANE_MERGE;
             prof.run(cls, [&] {
-                launch_extend(W, mode, sc, G, P, l.q, l.seg_row0, l.s, l.seg_n, a, b, outp, ctrl, g->inv_rank, st,
+                launch_extend(W, mode, sc, G, P, l.q, l.seg_row0, l.s, l.seg_n, a, b, outp, ctrl, inv_rank, st,
                               true);
             }, jW * 8 + c);
             if (probe) probe->items[jW][c] += b - a;
@@ -456,7 +468,8 @@ bool run_levels(const huge_graph *g, const huge_plan *p, const huge_exec_opts &o
             }
         } else {
             for (int64_t e = 0; e < nnz && !emit->stopped; e += stage_rows) {
-                launch_edge_sink(G, P, e, std::min(nnz, e + stage_rows), MODE_OUTPUT, stage, g->inv_rank, ctrl, st);
+                const int64_t e1 = std::min(nnz, e + stage_rows);
+                launch_edge_sink(G, P, e, e1, MODE_OUTPUT, out_rows(stage, e1 - e), inv_rank, ctrl, st);
                 stats.launches++;
                 int64_t nout = read_i64(&ctrl->qcount[HUGE_KMAX], st, pin64);
                 deliver(nout);
@@ -534,6 +547,9 @@ bool run_levels(const huge_graph *g, const huge_plan *p, const huge_exec_opts &o
                 if (W == lastW) {
                     if (!emit) {
                         int64_t chunk = std::min(remaining, kMaxItems);
+                        // under a work limit, stop soon after crossing it
+                        if (o.work_limit > 0)
+                            chunk = std::min(chunk, std::max<int64_t>(1 << 20, o.work_limit - work_done + 1));
                         extend_range(HUGE_KC_SINK, W, count_mode, l, l.seg_done, l.seg_done + chunk, nullptr);
                         prof.bytes[HUGE_KC_SINK] += l.seg_bytes * (double)chunk / (double)l.seg_total;
                         l.seg_done += chunk;
@@ -544,7 +560,8 @@ bool run_levels(const huge_graph *g, const huge_plan *p, const huge_exec_opts &o
                         }
                     } else {
                         int64_t chunk = std::min(remaining, stage_rows);
-                        extend_range(HUGE_KC_SINK, W, MODE_OUTPUT, l, l.seg_done, l.seg_done + chunk, stage);
+                        extend_range(HUGE_KC_SINK, W, MODE_OUTPUT, l, l.seg_done, l.seg_done + chunk,
+                                     out_rows(stage, chunk));
                         l.seg_done += chunk;
                         int64_t nout = read_i64(&ctrl->qcount[HUGE_KMAX], st, pin64);
                         deliver(nout);

@@ -101,8 +101,8 @@ __global__ __launch_bounds__(kT) void k_edge_sink(GraphDev g, DevPlan P, int64_t
             // row indexed by query vertex: vertex q sits at position pos[q]
             const int32_t a0 = P.pos[0] == 0 ? f[0] : f[1];
             const int32_t a1 = P.pos[1] == 0 ? f[0] : f[1];
-            out[o * 2 + 0] = inv_rank[a0];
-            out[o * 2 + 1] = inv_rank[a1];
+            out[o * 2 + 0] = inv_rank ? inv_rank[a0] : a0;
+            out[o * 2 + 1] = inv_rank ? inv_rank[a1] : a1;
         }
     }
 }

@@ -85,6 +85,8 @@ struct DevStep {
     int32_t slice;  // slice filters on position i's vertex: bit 0 the slice, bit 1 the second slice
     uint32_t nadj;  // induced plans: positions p < i not adjacent to position i in q (v must not be in N(f[p]))
     int32_t label;  // labelled plans: the label position i's vertex must carry, -1 any
+    uint32_t vadj;  // positions p < i whose lists must hold position i's vertex, looked up only (never the
+                    // probe): the verify-only edges of a bushy plan's pulled hash joins
 };
 
 struct DevPlan {
@@ -117,6 +119,7 @@ struct huge_plan {
     int32_t qlabel[HUGE_KMAX] = {-1, -1, -1, -1, -1, -1, -1, -1};  // labelled queries: label per query vertex
     bool labelled = false;
     huge::DevPlan dev{};
+    std::vector<huge_bushy_node> bushy;      // bushy plans (Algorithm 1): the join tree, root last; else empty
 };
 
 // learned cardinality model (mlp.hip): FP32 master weights, BF16 copies used
@@ -180,6 +183,8 @@ struct ExecStats {
     uint64_t peak_frontier_bytes = 0;
 };
 struct EmitSink {
+    int32_t *dev_out = nullptr;  // rows go to this device table (ranks, no callback) instead of host_buf
+    int64_t dev_cap = 0;         // its capacity in rows
     int32_t *host_buf = nullptr;
     int64_t buf_rows = 0;
     huge_emit_fn cb = nullptr;
@@ -211,6 +216,13 @@ void run_persistent(const huge_graph *g, const huge_plan *const *plans, int np, 
 uint64_t persist_workspace_bytes(const huge_plan *const *plans, int np, const huge_exec_opts &o);
 // motif.cpp: every connected k-vertex pattern, non-induced and induced counts; returns the pattern count
 int motif_count(const huge_graph *g, int k, const huge_exec_opts &o, huge_motif *out);
+// bushy_plan.cpp: Algorithm 1 over connected edge sets (p.bushy); machines = the k of k |E_G|
+void plan_bushy(const huge_graph_info &gi, huge_plan &p, double machines);
+// the same tables for a given tree: splits[2i], splits[2i+1] = the parts of join i
+void plan_bushy_tree(const huge_graph_info &gi, huge_plan &p, const uint32_t *splits, int nsplits, double machines);
+// bushy.cpp: run a bushy plan (level engine for chains from a SCAN, join.hip for the rest)
+void run_bushy(const huge_graph *g, const huge_plan *p, const huge_exec_opts &o, huge_result *out,
+               int64_t *node_rows, int max_nodes);
 // noalloc.hip: huge_count on the level engine inside the file-scope device array
 uint64_t noalloc_scratch_bytes();
 void run_count_noalloc(const huge_graph *g, const huge_plan *p, const huge_exec_opts &o, huge_result *out,

@@ -242,10 +242,13 @@ double order_cost(const std::vector<double> &e, size_t o, int k) {
 // list, so hubs are sampled in proportion to their degree, the engines read
 // only those entries, and the sample is an unbiased 1/S share of that order's
 // work.  S is the smallest power of 8 (from 2^9) at which the cost model's
-// order examines at most kVerifyWork candidates; the other orders stop (and
-// lose) past kVerifyRelLimit times its candidates.  The order with the least
-// device time wins, the cost model's keeping ties within kVerifyGain.  About a
-// few milliseconds of device time per order.
+// order examines at most kVerifyWork candidates.  When no edge sample with at
+// least 64 entries fits (single hub entries of the query hold more), the
+// samples are strided root slices instead (slice 0 of S of the first matched
+// vertex by degree rank, at least 4 roots).  The other orders stop (and lose)
+// past kVerifyRelLimit times the cost model's candidates.  The order with the
+// least device time wins, the cost model's keeping ties within kVerifyGain.
+// About a few milliseconds of device time per order.
 size_t verify_orders(const huge_graph *g, const huge_plan &p, const std::vector<std::vector<int32_t>> &orders,
                      const std::vector<double> &est, const huge_graph_info &gi, hipStream_t st) {
     const int k = p.k;
@@ -308,7 +311,13 @@ size_t verify_orders(const huge_graph *g, const huge_plan &p, const std::vector<
     for (;;) {
         ensure_ws();
         if (!run_levels(g, &qs[0], o, &r0, nullptr)) break;
-        if ((int64_t)o.slice_count * 8 > std::max<int64_t>(g->dev.nnz, 1)) return base;  // no workable sample
+        if (o.slice_vertex == -2 && (int64_t)o.slice_count * 8 > g->dev.nnz / 64) {
+            // single entries hold more than the budget: strided root slices instead
+            o.slice_vertex = -1;
+            o.slice_count = 512;
+            continue;
+        }
+        if (o.slice_vertex == -1 && (int64_t)o.slice_count * 8 > std::max<int64_t>(gi.n / 4, 1)) return base;
         o.slice_count *= 8;
     }
     double base_work = 0;

@@ -29,7 +29,12 @@ __device__ __forceinline__ void prepare_row(const int32_t *__restrict__ rows, in
     __shared__ unsigned long long s_valid[kT / 64];
     __shared__ unsigned long long s_bytes[kT / 64];
     bool valid = false;
-    unsigned long long abytes = 0;  // algorithmic bytes of a merge intersection for this row
+    // Algorithmic bytes of this row's intersection: the row, 16 bytes of list
+    // bounds per Ext list, the probe window, and of every other window at
+    // least one element per probe candidate unless the window is shorter (a
+    // membership needs one element of it; a merge reads it whole): the fewest
+    // list bytes any intersection of these windows must read.
+    unsigned long long abytes = 0;
     if (i < nrows) {
         abytes = 4ull * W;
         int32_t f[W];
@@ -49,14 +54,16 @@ __device__ __forceinline__ void prepare_row(const int32_t *__restrict__ rows, in
             if (lo < hi) {
                 int64_t best = -1, bb = 0;
                 int bp = 0;
+                int64_t len[W];
 #pragma unroll
                 for (int p = 0; p < W; ++p) {
+                    len[p] = 0;
                     if ((st.ext >> p) & 1u) {
                         int32_t x = f[p];
                         int64_t b = g.rp[x], e = g.rp[x + 1];
                         int64_t a = lo > 0 ? lower_bound(g.col, b, e, lo) : b;
                         int64_t z = hi < 0x7FFFFFFF ? lower_bound(g.col, a, e, hi) : e;
-                        abytes += 16ull + 4ull * (unsigned long long)(z - a);
+                        len[p] = z - a;
                         if (best < 0 || z - a < best) {
                             best = z - a;
                             bb = a;
@@ -64,6 +71,10 @@ __device__ __forceinline__ void prepare_row(const int32_t *__restrict__ rows, in
                         }
                     }
                 }
+#pragma unroll
+                for (int p = 0; p < W; ++p)
+                    if ((st.ext >> p) & 1u)
+                        abytes += 16ull + 4ull * (unsigned long long)(len[p] < best ? len[p] : best);
                 bound = (int32_t)best;
                 pinfo = (uint64_t)bb | ((uint64_t)bp << 56);
             }
@@ -279,7 +290,7 @@ __device__ __forceinline__ void extend_tile(const ExtArgs &a, int64_t tile) {
         if constexpr (STRAT == 0) {
 #pragma unroll
             for (int p = 0; p < W; ++p) {
-                if (ok && ((st.ext >> p) & 1u) && p != pp) ok = adj_has(g, f[p], v);
+                if (ok && (((st.ext | st.vadj) >> p) & 1u) && p != pp) ok = adj_has(g, f[p], v);
                 if (ok && ((st.nadj >> p) & 1u)) ok = !adj_has(g, f[p], v);  // induced mode
             }
         } else {
@@ -307,15 +318,17 @@ __device__ __forceinline__ void extend_tile(const ExtArgs &a, int64_t tile) {
                 }
             }
 #pragma unroll
-            for (int p = 0; p < W; ++p)
+            for (int p = 0; p < W; ++p) {
                 if (ok && ((st.nadj >> p) & 1u)) ok = !adj_has(g, f[p], v);  // induced mode
+                if (ok && ((st.vadj >> p) & 1u)) ok = adj_has(g, f[p], v);   // verify-only edges
+            }
         }
         if (!ok) continue;
         if constexpr (MODE == MODE_COUNT) {
             uint64_t h = a.hpre[r];
 #pragma unroll
             for (int p = 0; p < W; ++p)
-                if ((st.ext >> p) & 1u) h += mix64(edge_key(f[p], v));
+                if (((st.ext | st.vadj) >> p) & 1u) h += mix64(edge_key(f[p], v));
             h = mix64(h);
             cnt += 1;
             hs += h;
@@ -395,7 +408,7 @@ __device__ __forceinline__ void extend_tile(const ExtArgs &a, int64_t tile) {
                 for (int p = 0; p < W; ++p) dst[p] = f[p];
                 dst[W] = vv[j];
             } else {
-                // final match, indexed by query vertex, original IDs
+                // final match, indexed by query vertex, original IDs (ranks without inv_rank)
                 int32_t *dst = a.out + o * (W + 1);
 #pragma unroll
                 for (int q = 0; q < W + 1; ++q) {
@@ -404,7 +417,7 @@ __device__ __forceinline__ void extend_tile(const ExtArgs &a, int64_t tile) {
 #pragma unroll
                     for (int t = 0; t < W; ++t)
                         if (t == p) x = f[t];
-                    dst[q] = a.inv_rank[x];
+                    dst[q] = a.inv_rank ? a.inv_rank[x] : x;
                 }
             }
             ++o;
@@ -583,7 +596,7 @@ __device__ __forceinline__ void merge_tile(const ExtArgs &a, int64_t tile) {
                 const int32_t v0 = cand(pshift + w);
 #pragma unroll
                 for (int p = 0; p < W; ++p) {
-                    if ((((st.ext | st.nadj) >> p) & 1u) && p != pp) {
+                    if ((((st.ext | st.nadj | st.vadj) >> p) & 1u) && p != pp) {
                         if (f[p] < g.hub_base) {
                             end[p] = g.rp[f[p] + 1];
                             if constexpr (BLK) {
@@ -607,9 +620,9 @@ __device__ __forceinline__ void merge_tile(const ExtArgs &a, int64_t tile) {
             if (st.slice & 4) ok = ok && pair2_ok<W>(g, a.P, f, v);
 #pragma unroll
             for (int p = 0; p < W; ++p) {
-                // Ext lists must hold v; in induced mode the lists of the other
-                // matched vertices (nadj) must not
-                if (ok && (((st.ext | st.nadj) >> p) & 1u) && p != pp) {
+                // Ext lists (and verify-only lists) must hold v; in induced mode
+                // the lists of the other matched vertices (nadj) must not
+                if (ok && (((st.ext | st.nadj | st.vadj) >> p) & 1u) && p != pp) {
                     const bool absent = (st.nadj >> p) & 1u;
                     bool in = false;
                     if (f[p] >= g.hub_base) {
@@ -643,7 +656,7 @@ __device__ __forceinline__ void merge_tile(const ExtArgs &a, int64_t tile) {
                 uint64_t h = hrow;
 #pragma unroll
                 for (int p = 0; p < W; ++p)
-                    if ((st.ext >> p) & 1u) h += mix64(edge_key(f[p], v));
+                    if (((st.ext | st.vadj) >> p) & 1u) h += mix64(edge_key(f[p], v));
                 h = mix64(h);
                 cnt += 1;
                 hs += h;
@@ -729,7 +742,7 @@ __device__ __forceinline__ void merge_tile(const ExtArgs &a, int64_t tile) {
 #pragma unroll
                     for (int t = 0; t < W; ++t)
                         if (t == p) x = ff[t];
-                    dst[qq] = a.inv_rank[x];
+                    dst[qq] = a.inv_rank ? a.inv_rank[x] : x;
                 }
             }
         }

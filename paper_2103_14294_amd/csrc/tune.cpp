@@ -10,6 +10,7 @@
 // sample and per j the fastest total (intersections plus the segment's
 // prepare, partition and scan launches) wins.  Because every run counts the
 // same matches, the tuner also checks that all runs agree.
+#include <algorithm>
 #include <cstring>
 
 #include "internal.h"
@@ -46,8 +47,35 @@ void run_sample(const huge_graph *g, const huge_plan *const *plans, int np, cons
 
 }  // namespace
 
-void autotune(const huge_graph *g, const huge_plan *const *plans, int np, const huge_exec_opts &o,
+void autotune(const huge_graph *g, const huge_plan *const *plans, int np, const huge_exec_opts &opts,
               huge_tune_table *out) {
+    const int64_t cands[3] = {1 << 18, 1 << 20, 1 << 22};  // segment rows tried in pass 2
+    // one workspace for every run: the largest any plan needs under any table tried
+    struct Mem {
+        void *p = nullptr;
+        ~Mem() {
+            if (p) (void)hipFree(p);
+        }
+    } mem;
+    huge_exec_opts o = opts;
+    if (!o.workspace) {
+        huge_tune_table t;
+        blank(t);
+        huge_exec_opts oo = o;
+        oo.tune = &t;
+        oo.strategy = HUGE_STRAT_AUTO;
+        oo.engine = HUGE_ENGINE_LEVELS;
+        uint64_t need = 256;
+        for (int i = 0; i < np; ++i) need = std::max(need, workspace_bytes(g, plans[i], oo));
+        oo.chunk_rows = 0;
+        for (int64_t c : cands) {
+            for (int j = 0; j <= HUGE_KMAX; ++j) t.chunk_rows[j] = c;
+            for (int i = 0; i < np; ++i) need = std::max(need, workspace_bytes(g, plans[i], oo));
+        }
+        HUGE_HIP(hipMalloc(&mem.p, need));
+        o.workspace = mem.p;
+        o.workspace_bytes = need;
+    }
     huge_tune_table best;
     blank(best);
     std::vector<Key> ref, keys;
@@ -74,7 +102,6 @@ void autotune(const huge_graph *g, const huge_plan *const *plans, int np, const 
             best.items[j][c] = pr[b].items[j][c];
         }
     // 2. segment rows per j, with the chosen strategies
-    const int64_t cands[3] = {1 << 18, 1 << 20, 1 << 22};
     TuneProbe pc[3];
     for (int i = 0; i < 3; ++i) {
         huge_tune_table t = best;

@@ -57,8 +57,10 @@ def test_digest_covers_every_kernel_source_and_header():
 def test_heldout_patterns_are_outside_the_training_set():
     b = _bench()
     seen = b.training_patterns()
-    qs = b.build_queries(b.WORKLOADS["c5"])
-    assert len(qs) == 32
+    qs = b.candidate_patterns(b.WORKLOADS["c5"])
+    # every held-out class of 4-6 vertices is a candidate (fewer than the draw allows)
+    assert b.WORKLOADS["c5"]["queries"][1]["count"] <= len(qs) <= b.WORKLOADS["c5"]["queries"][1]["draw"]
+    assert len({(k, tuple(sorted(e))) for _, k, e in qs}) == len(qs)
     for name, k, e in qs:
         assert (k, tuple(sorted(e))) not in seen, name
         assert 4 <= k <= 6
