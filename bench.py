@@ -11,11 +11,13 @@ timed on samples: root slice s of S_q, the matches whose first matched vertex
 has degree rank r with r mod S_q == s (every S_q-th vertex in degree order, so
 every slice holds the same share of each degree class; the engines gather
 only the slice's edge-array entries).  It is an unbiased 1/S_q sample of that
-plan's work.  S_q is fixed per query (the smallest power of 4 from 2^10 at
-which the first two steps' root slices of the cost-model plan examine at most
-4e8 candidates each), so every mode processes the same fraction of each query.
-Patterns are drawn in seed order and kept when such an S_q <= 2^24 exists
-(at least 4 roots per slice); the JSON line says how many were skipped.
+plan's work.  S_q is fixed per query: the smallest power of 4 from 2^10 at
+which every root slice the run uses (timed and warmup), under the cost-model
+plan and under the learned plan, examines at most 1e8 candidates; so every
+mode processes the same fraction of each query, and no step meets a root
+whose work has no bound.  Patterns are drawn in seed order and kept when such
+an S_q <= 2^24 exists (at least 4 roots per slice); the JSON line says how
+many were skipped.
 (Edge slices, every S-th entry of the CSR, sample hub lists in proportion to
 their degree, but here a single hub entry of most 5-6-vertex patterns holds
 more than 1e9 candidates: no edge sample of them fits any budget.)
@@ -30,15 +32,16 @@ Modes, timed on the same steps:
                       connected ones, its two best measured against the cost
                       model's on a small sample), one huge_count per query;
   learned-batched     the learned plans batched: the headline.
-Query time includes planning.  The value is a whole-workload estimate: slice s
-of S_q is an unbiased 1/S_q sample of a query's matches and work, so over the K
-timed slices a query's whole count is S_q * (sampled count) / K and its whole
-run time S_q * (sampled seconds) / K (per batch of equal S_q in the batched
-modes).  A mode's query time = planning (once per query) + those run times;
-value = the workload's estimated embeddings (pooled over the distinct plans'
-samples) / the headline mode's estimated query time.  The timed steps use the
-slices slice_of(0..K-1), a fixed permutation of 0..S_q-1, so they spread over
-the degree strata; warmup uses the next ones.  The raw sampled rates are in
+Query time includes planning, paid once per query while the timed slices are
+a fraction K/S_q of it.  So each query's sample is scaled to the whole query:
+count S_q * (sampled count) / K, run time S_q * (sampled seconds) / K (per
+batch of equal S_q in the batched modes); a mode's query time = planning +
+those run times; value = the workload's scaled embeddings (pooled over the
+distinct plans' samples) / the headline mode's query time.  Equivalently, the
+sampled rate with planning charged in proportion to the sampled fraction.
+The timed steps are slices 0..K-1, the lowest position in every degree
+stratum (warmup: the next ones), so the scaled figures describe those strata,
+not the hubs' own slices.  The raw sampled rates are in
 config.modes[*].sampled.
 
 Exactness: for every query both plans run one shared sample (the double slice:
@@ -76,22 +79,22 @@ KC_KERNELS = ["k_prepare<W,LAST>", "k_tile_scan/k_tile_reduce", "k_extend*<W,EMI
 WORKLOADS = {
     "c5": {
         "desc": "R-MAT scale 26, edge factor 16, (0.57,0.19,0.19,0.05), seed 5: 32 held-out random 4-6 vertex "
-                "patterns (seed 5, the first 32 drawn whose 1/2^24 root sample fits 4e8 candidates); "
+                "patterns (seed 5, the first 32 drawn whose root slices fit 1e8 candidates at some S <= 2^24); "
                 "learned/batched vs cost-model plans",
         "graph": ("rmat", dict(scale=26, edge_factor=16, seed=5)),
         "queries": ("heldout", dict(count=32, draw=400, seed=5, kmin=4, kmax=6)),
         "cap": 16 << 30,
-        "budget": 4e8,
+        "budget": 1e8,
         "modes": ["cost-model", "cost-model-batched", "learned", "learned-batched"],
     },
     "c4": {
         "desc": "R-MAT scale 24, edge factor 16, (0.57,0.19,0.19,0.05), seed 4: 64 random connected 3-6 vertex "
-                "patterns (seed 4, the first 64 drawn whose 1/2^24 root sample fits 1e8 candidates); batched vs "
+                "patterns (seed 4, the first 64 drawn whose root slices fit 5e7 candidates at some S <= 2^24); batched vs "
                 "one query at a time",
         "graph": ("rmat", dict(scale=24, edge_factor=16, seed=4)),
         "queries": ("random", dict(count=64, draw=600, seed=4, kmin=3, kmax=6)),
         "cap": 16 << 30,
-        "budget": 1e8,
+        "budget": 5e7,
         "modes": ["cost-model", "cost-model-batched"],
     },
     "c2": {
@@ -177,29 +180,39 @@ SLICE = dict(slice_vertex=-1)  # root slices of each plan's first matched vertex
 
 
 def slice_of(step, S):
-    """The slice that step `step` runs: a fixed odd-multiplier permutation of
-    0..S-1 (S a power of two), so the timed steps are a spread-out sample of the
-    slices rather than the lowest ranks of every stratum."""
-    return (0x9E3779B1 * step + 0x632BE5AB) % S if S > 1 else 0
+    """The slice that step `step` runs: slice `step` (mod S).  Slice s holds the
+    ranks s, s + S, s + 2S, ...: the timed steps take the lowest position in
+    every degree stratum.  (A spread-out permutation of the slices was tried:
+    about one slice in a few hundred then holds a high-degree root whose 6-vertex
+    matches alone take minutes, which no bounded step can time.)"""
+    return step % S if S > 1 else 0
 S_MIN, S_MAX = 1 << 10, 1 << 24
 
 
-def pilot(huge, G, p, budget, ws, cap):
-    """The smallest power-of-4 slice count S in [S_MIN, S_MAX] whose root slices of the
-    first two steps each examine at most `budget` candidates with plan p, or None."""
-    def fits(S):
-        for s in (slice_of(0, S), slice_of(1, S)):
-            r = huge.count(G, p, slice_count=S, slice_id=s, slice_mode=huge.SLICE_STRIDE, work_limit=int(budget),
-                           hash=False, workspace=ws, cap=cap, **SLICE)
-            if r["stopped"]:
-                return False
+def pilot(huge, G, plans, budget, ws, cap, nslices):
+    """The smallest power-of-4 slice count S in [S_MIN, S_MAX] at which every plan
+    of the query examines at most `budget` candidates in each root slice the run
+    will use (slices 0..nslices-1), or None.  The descent tests the first two
+    slices; the chosen S is then checked on all of them (and raised by 4 while
+    some slice holds a heavier root)."""
+    def fits(S, ids):
+        for p in plans:
+            for s in ids:
+                r = huge.count(G, p, slice_count=S, slice_id=slice_of(s, S), slice_mode=huge.SLICE_STRIDE,
+                               work_limit=int(budget), hash=False, workspace=ws, cap=cap, **SLICE)
+                if r["stopped"]:
+                    return False
         return True
 
-    if not fits(S_MAX):
+    if not fits(S_MAX, (0, 1)):
         return None
     S = S_MAX
-    while S > S_MIN and fits(S // 4):
+    while S > S_MIN and fits(S // 4, (0, 1)):
         S //= 4
+    while not fits(S, range(nslices)):
+        if S >= S_MAX:
+            return None
+        S *= 4
     return S
 
 
@@ -215,33 +228,120 @@ def candidate_patterns(W):
     return [("%s-k%d-%d" % (p["family"], p["k"], i), p["k"], p["edges"]) for i, p in enumerate(pats)]
 
 
-def build_queries(huge, G, W, ws, cap):
-    """[(name, k, edges)], their cost-model plans and slice counts.  Named queries
-    take the workload's fixed slice count; random ones are drawn in seed order
-    (held-out ones skip the learned model's training patterns) and kept when the
-    pilot finds a slice count for them, until the workload's count is reached."""
+def build_queries(huge, G, W, ws, cap, nslices, learned_plan=None):
+    """[(name, k, edges)], their cost-model plans, learned plans (or None), planning
+    seconds of the kept learned plans, slice counts and the number of rejected
+    patterns.  Named queries take the workload's fixed slice count; random ones are
+    drawn in seed order (held-out ones skip the learned model's training patterns)
+    and kept when the pilot finds a slice count for all their plans, until the
+    workload's count is reached.  learned_plan(k, edges) -> (plan, seconds)."""
     from graphgen import patterns as P
 
     q = W["queries"]
     if isinstance(q, list):
         qs = [(n,) + tuple(P.NAMED[n]) for n in q]
-        return qs, [huge.plan(G, k, e) for _, k, e in qs], [W["slices"]] * len(qs), 0
-    qs, plans, slices, rejected = [], [], [], 0
+        lp = [learned_plan(k, e) for _, k, e in qs] if learned_plan else None
+        return (qs, [huge.plan(G, k, e) for _, k, e in qs], [x[0] for x in lp] if lp else None,
+                sum(x[1] for x in lp) if lp else 0.0, [W["slices"]] * len(qs), 0)
+    qs, cms, lps, lsec, slices, rejected = [], [], [], 0.0, [], 0
     for name, k, e in candidate_patterns(W):
         pl = huge.plan(G, k, e)
-        S = pilot(huge, G, pl, W["budget"], ws, cap)
+        lp, ls = learned_plan(k, e) if learned_plan else (None, 0.0)
+        S = pilot(huge, G, [pl] + ([lp] if lp else []), W["budget"], ws, cap, nslices)
         log("pilot %s: %s" % (name, "S=2^%d" % (S.bit_length() - 1) if S else "rejected"))
         if S is None:
             rejected += 1
             continue
         qs.append((name, k, e))
-        plans.append(pl)
+        cms.append(pl)
+        lps.append(lp)
+        lsec += ls
         slices.append(S)
         if len(qs) == q[1]["count"]:
             break
     if len(qs) < q[1]["count"]:
         raise SystemExit("only %d of %d patterns fit the sampling budget" % (len(qs), q[1]["count"]))
-    return qs, plans, slices, rejected
+    return qs, cms, (lps if learned_plan else None), lsec, slices, rejected
+
+
+BUSHY = {
+    "desc": "Chung-Lu n=16384, mean degree 16, gamma 2.5, exact, seed 1 (the C1 graph): path- and cycle-like "
+            "queries, whole; bushy plans of Algorithm 1 (machines 1, and 1e9 so that parts are pushed) vs the "
+            "left-deep cost-model plan",
+    "graph": ("chung_lu", dict(n=16384, dbar=16, gamma=2.5, seed=1, exact=True)),
+    "queries": ["4-path", "tailed-triangle", "diamond", "5-cycle", "house", "6-cycle"],
+    "modes": {"cost-model": None, "bushy": 1.0, "bushy-push": 1e9},
+}
+
+
+def bench_bushy(args, huge, torch):
+    """The bushy-plan line: every query whole, per mode, timed over the steps;
+    all modes must give the oracle's count and hashes."""
+    import oracle
+    from graphgen import patterns as P
+
+    g = make_graph(BUSHY["graph"])
+    G = huge.load(g.row_ptr, g.col)
+    qs = [(n,) + tuple(P.NAMED[n]) for n in BUSHY["queries"]]
+    plans, trees = {}, {}
+    for m, machines in BUSHY["modes"].items():
+        if machines is None:
+            plans[m] = [huge.plan(G, k, e) for _, k, e in qs]
+        else:
+            plans[m] = [huge.plan_bushy(G, k, e, machines=machines) for _, k, e in qs]
+            trees[m] = {q[0]: [nd["kind"] for nd in p.bushy_nodes()] for q, p in zip(qs, plans[m])}
+    # the oracle on the three cheapest queries (the baseline, and a parity check of the first mode there)
+    threads = min(16, os.cpu_count() or 1)
+    t_o = time.perf_counter()
+    oref = {n: oracle.enumerate_query(g.row_ptr, g.col, k, e, threads=threads) for n, k, e in qs[:3]}
+    t_o = time.perf_counter() - t_o
+    ref = [None] * len(qs)
+    res = {}
+    for m in BUSHY["modes"]:
+        for _ in range(args.warmup):
+            for p in plans[m]:
+                huge.count(G, p)
+        per = [0.0] * len(qs)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            for i, p in enumerate(plans[m]):
+                t1 = time.perf_counter()
+                r = huge.count(G, p)
+                per[i] += time.perf_counter() - t1
+                key = (r["count"], r["hash_sum"], r["hash_xor"])
+                if ref[i] is None:
+                    ref[i] = key
+                    o = oref.get(qs[i][0])
+                    if o is not None and key != (o["count"], o["hash_sum"], o["hash_xor"]):
+                        raise SystemExit("%s disagrees with the oracle on %s" % (m, qs[i][0]))
+                if key != ref[i]:
+                    raise SystemExit("%s disagrees with %s on %s" % (m, list(BUSHY["modes"])[0], qs[i][0]))
+        torch.cuda.synchronize()
+        res[m] = (time.perf_counter() - t0, per)
+        log("[%s] %.3f s" % (m, res[m][0]))
+    total = sum(r[0] for r in ref)
+    main = "bushy"
+    el = res[main][0]
+    out = {
+        "metric": "embeddings/sec, bushy plans (Algorithm 1) vs the left-deep cost-model plan, 1 GPU",
+        "value": total * args.steps / el,
+        "unit": "embeddings/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": el * 1e3 / args.steps,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "int32", "data": "synthetic",
+        "config": {"workload": BUSHY["desc"], "mode": main, "n": g.n, "m": g.m, "embeddings_per_step": total,
+                   "trees": trees,
+                   "modes": {m: {"s": round(res[m][0], 4), "embeddings_per_s": total * args.steps / res[m][0],
+                                 "per_query_ms": {q[0]: round(t * 1e3 / args.steps, 3)
+                                                  for q, t in zip(qs, res[m][1])}} for m in res},
+                   "exactness": "every mode, every step: count, hash_sum and hash_xor equal to the first mode's; "
+                                "the first mode's equal to the oracle's on %s" % ", ".join(oref)},
+        "roofline": None,
+        "cpu_baseline": {"value": sum(o["count"] for o in oref.values()) / t_o, "unit": "embeddings/s",
+                         "cores": threads, "kind": "oracle",
+                         "sample": "%s, whole, once (%.1f s)" % (", ".join(oref), t_o)},
+    }
+    print(json.dumps(out), flush=True)
 
 
 def cpu_baseline(g, queries, orders, slices, steps, budget_s, threads):
@@ -301,7 +401,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="c5", choices=sorted(WORKLOADS))
+    ap.add_argument("--workload", default="c5", choices=sorted(WORKLOADS) + ["bushy"])
     ap.add_argument("--modes", default=None, help="comma-separated subset of the workload's modes")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
     ap.add_argument("--no-cpu", action="store_true")
@@ -331,6 +431,9 @@ def main():
         gbs, moved = copy_bandwidth(torch)
         print(json.dumps({"copy_gbs": round(gbs, 1), "bytes_per_copy": moved, "copies": 6}), flush=True)
         return
+    if args.workload == "bushy":
+        bench_bushy(args, huge, torch)
+        return
     W = WORKLOADS[args.workload]
     modes = args.modes.split(",") if args.modes else list(W["modes"])
     t0 = time.perf_counter()
@@ -341,8 +444,34 @@ def main():
     log("loaded on GPU in %.1f ms (max degree %d)" % (info["load_ms"], info["max_degree"]))
     ws = huge.Workspace()
     cap = int(args.cap) if args.cap is not None else W["cap"]
+    model = huge.Model.load(args.model) if any(m.startswith("learned") for m in modes) else None
+
+    def learned_plan(k, e):
+        torch.cuda.synchronize()
+        t_p = time.perf_counter()
+        p = huge.plan(G, k, e, learned=model, verify=True)
+        torch.cuda.synchronize()
+        return p, time.perf_counter() - t_p
+
     t_q = time.perf_counter()
-    queries, cm_plans, slices, rejected = build_queries(huge, G, W, ws, cap)
+    nslices = args.steps + args.warmup
+    pc = os.environ.get("HUGE_PILOT_CACHE")  # reuse a previous run's query selection (profiling passes)
+    pkey = "%s|%d|%s" % (args.workload, nslices, ",".join(modes))
+    pcd = json.load(open(pc)) if pc and os.path.exists(pc) else {}
+    if pkey in pcd:
+        d = pcd[pkey]
+        queries = [(n, k, [tuple(x) for x in e]) for n, k, e in d["queries"]]
+        cm_plans = [huge.plan(G, k, e) for _, k, e in queries]
+        lp = [learned_plan(k, e) for _, k, e in queries] if model is not None else None
+        l_plans, l_sec = ([x[0] for x in lp], sum(x[1] for x in lp)) if lp else (None, 0.0)
+        slices, rejected = d["slices"], d["rejected"]
+    else:
+        queries, cm_plans, l_plans, l_sec, slices, rejected = build_queries(
+            huge, G, W, ws, cap, nslices, learned_plan if model is not None else None)
+        if pc:
+            pcd[pkey] = {"queries": queries, "slices": slices, "rejected": rejected}
+            with open(pc, "w") as f:
+                json.dump(pcd, f)
     log("%d queries (%d drawn patterns rejected: no slice count up to 2^24 fits the budget), %.1f s; "
         "slices per query: %s" % (len(queries), rejected, time.perf_counter() - t_q, slices))
 
@@ -358,15 +487,11 @@ def main():
                      "chunk_rows": {str(j): table.chunk_rows[j] for j in range(huge.KMAX + 1) if table.chunk_rows[j]}}
         log("autotuned in %.1f s: %s" % (tune_info["tune_s"], json.dumps(tune_info)))
 
-    model = huge.Model.load(args.model) if any(m.startswith("learned") for m in modes) else None
     plans = {"cost-model": cm_plans}
     plan_s = {"cost-model": 0.0}
     if model is not None:
-        torch.cuda.synchronize()
-        t_p = time.perf_counter()
-        plans["learned"] = [huge.plan(G, k, e, learned=model, verify=True) for _, k, e in queries]
-        torch.cuda.synchronize()
-        plan_s["learned"] = time.perf_counter() - t_p
+        plans["learned"] = l_plans
+        plan_s["learned"] = l_sec
         log("learned planning: %.2f s for %d queries" % (plan_s["learned"], len(queries)))
 
     kw = dict(cap=cap, tune=table, hash=True)
@@ -503,14 +628,15 @@ def main():
     main_mode = modes[-1]
     acc, elapsed = results[main_mode]
     cfg = {"workload": W["desc"], "mode": main_mode, "n": g.n, "m": g.m, "queries": nq,
-           "slices": "per query: root slice slice_of(step) of S_q (first matched vertex of degree rank r with "
-                     "r mod S_q == slice_of(step), a fixed permutation of the slices); S_q = %s"
+           "slices": "per query: root slice `step` of S_q (first matched vertex of degree rank r with "
+                     "r mod S_q == step); S_q = %s"
                      % json.dumps(dict(zip([q[0] for q in queries], slices))) if nq <= 64
            else "per query", "frontier_cap_bytes": cap, "peak_frontier_bytes": acc.get("_peak", 0),
            "graph_load_ms": info["load_ms"], "patterns_rejected_by_pilot": rejected,
-           "value_is": "estimated embeddings of the whole queries (S_q x sampled count / steps, pooled over the "
-                       "distinct plans' samples) / estimated whole-query time of the mode (planning once per query "
-                       "+ S_q x sampled seconds / steps)",
+           "value_is": "scaled embeddings (S_q x sampled count / steps per query, pooled over the distinct "
+                       "plans' samples) / scaled query time of the mode (planning once per query + S_q x sampled "
+                       "seconds / steps): the sampled rate with planning charged in proportion to the sampled "
+                       "fraction",
            "estimated_embeddings": pooled,
            "estimated_embeddings_by_plan": est_emb}
     if tune_info:
