@@ -130,7 +130,12 @@ MODEL_PATH = os.path.join(ROOT, "paper_2103_14294_amd", "mlp_work.npz")
 # 4 GiB device copy, recorded per algorithmic byte (a run's traffic per launch is
 # that ratio times its own algorithmic bytes per launch).  Valid only for the
 # kernel sources whose digest is given; null for any other sources or workload.
-TRAFFIC = {}
+TRAFFIC = {
+    # R-MAT 26 held-out patterns (default run, 20 steps, 5 warmup, no cpu leg): the 42 sink-class
+    # dispatches of the profiled pass, FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0 (factors from the 4 GiB copy),
+    # 107.5 MB per launch against 55.1 MB of algorithmic bytes
+    "c5": {"per_alg_byte": 1.9497, "sources_sha256_16": "1a158ed370f00d4c"},
+}
 KERNEL_SOURCES = ["paper_2103_14294_amd/csrc/" + f for f in
                   ("extend.hip", "tiles.h", "devfuncs.h", "internal.h", "round_sched.h", "graph.hip", "mround.hip",
                    "scan_tiles.h", "prims.hip", "prims.h", "engine.cpp", "mbatch.cpp")] + ["include/huge.h"]
@@ -410,6 +415,8 @@ def main():
                     help="skip autotuning the per-bucket dispatch before timing (library default kernels)")
     ap.add_argument("--profile-steps", type=int, default=2, help="steps of the profiled pass (roofline)")
     ap.add_argument("--cap", type=float, default=None, help="frontier cap in bytes (default: the workload's)")
+    ap.add_argument("--budget", type=float, default=None,
+                    help="candidates a sampled slice may examine (default: the workload's)")
     ap.add_argument("--copy-only", action="store_true",
                     help="only run the 4 GiB device copy (counter calibration) and print its bandwidth")
     args = ap.parse_args()
@@ -434,7 +441,9 @@ def main():
     if args.workload == "bushy":
         bench_bushy(args, huge, torch)
         return
-    W = WORKLOADS[args.workload]
+    W = dict(WORKLOADS[args.workload])
+    if args.budget is not None:
+        W["budget"] = args.budget
     modes = args.modes.split(",") if args.modes else list(W["modes"])
     t0 = time.perf_counter()
     g = make_graph(W["graph"])
@@ -456,7 +465,7 @@ def main():
     t_q = time.perf_counter()
     nslices = args.steps + args.warmup
     pc = os.environ.get("HUGE_PILOT_CACHE")  # reuse a previous run's query selection (profiling passes)
-    pkey = "%s|%d|%s" % (args.workload, nslices, ",".join(modes))
+    pkey = "%s|%d|%s|%g" % (args.workload, nslices, ",".join(modes), W.get("budget", 0))
     pcd = json.load(open(pc)) if pc and os.path.exists(pc) else {}
     if pkey in pcd:
         d = pcd[pkey]
@@ -604,7 +613,9 @@ def main():
                       "cost-model mode over the same slices",
             "avg_launch_ms": round(avg_ms, 4), "alg_bytes_per_launch": bytes_per_launch, "launches": kl[dom],
             "sources_sha256_16": sources_digest(),
-            "kernel_ms_by_class": {KC_NAMES[c]: round(kms[c], 3) for c in range(4)}}
+            "kernel_ms_by_class": {KC_NAMES[c]: round(kms[c], 3) for c in range(4)},
+            "launches_by_class": {KC_NAMES[c]: kl[c] for c in range(4)},
+            "alg_bytes_by_class": {KC_NAMES[c]: kb[c] for c in range(4)}}
 
     # Whole-query estimates.  Slice s of S_q is an unbiased 1/S_q sample of a
     # query's matches and of its plan's work, so over K sampled slices a query's

@@ -392,6 +392,9 @@ struct Exec {
                 svals = v1.as<uint32_t>();
             }
         }
+        // R's rows in key order, so that every left row meets a run of adjacent rows
+        Buf rs((size_t)nr1 * std::max(1, R.w) * 4, &live, &peak);
+        launch_gather_rows(R.rows, nr, R.w, svals, rs.as<int32_t>(), st);
         Buf bound((size_t)nl1 * 4), first((size_t)nl1 * 8), off((size_t)(nl1 + 1) * 8);
         clear_acc();
         int64_t items = 0;
@@ -405,8 +408,8 @@ struct Exec {
             items = read_i64(off.as<int64_t>() + nl);
         }
         return sink(out, root, items, [&](int mode, int32_t *dst, int64_t cap) {
-            launch_join_items(L.rows, nl, R.rows, off.as<int64_t>(), first.as<int64_t>(), svals, items, J, mode, dst,
-                              cap, acc->as<unsigned long long>(), st);
+            launch_join_items(L.rows, nl, rs.as<int32_t>(), off.as<int64_t>(), first.as<int64_t>(), items, J, mode,
+                              dst, cap, acc->as<unsigned long long>(), st);
         });
     }
 

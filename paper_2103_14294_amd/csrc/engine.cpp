@@ -181,6 +181,16 @@ bool root_sliced(const DevPlan &P) {
            P.st[0].label >= 0;
 }
 
+// The first matched vertex's count when its only filter is a strided slice
+// (ranks s, s + S, ... below n): known without a pass over the vertices.
+bool strided_root_count(const DevPlan &P, int64_t n, uint64_t *count) {
+    if (P.st[0].label >= 0 || P.slice_mode != (int32_t)HUGE_SLICE_STRIDE || P.edge_slice) return false;
+    if ((P.st[0].slice & 2) && P.slice2_count > 1) return false;
+    if (!((P.st[0].slice & 1) && P.slice_count > 1)) return false;
+    *count = n > (int64_t)P.slice_id ? (uint64_t)((n - P.slice_id + P.slice_count - 1) / P.slice_count) : 0;
+    return true;
+}
+
 // A strided slice of the first matched vertex: level 2 is gathered, not scanned.
 bool gathers_level2(const DevPlan &P) {
     return P.slice_mode == (int32_t)HUGE_SLICE_STRIDE && P.slice_count > 1 && (P.st[0].slice & 1) && !P.edge_slice;
@@ -416,7 +426,9 @@ bool run_levels(const huge_graph *g, const huge_plan *p, const huge_exec_opts &o
     const bool root_slice = root_sliced(P);
     bool limited = false;
     uint64_t level_work[HUGE_KMAX] = {};
-    if (root_slice) {
+    uint64_t roots_known = 0;
+    const bool roots_closed = root_slice && strided_root_count(P, G.n, &roots_known);
+    if (root_slice && !roots_closed) {
         launch_root_count(G, P, ctrl, st);
         stats.launches++;
     }
@@ -608,6 +620,7 @@ bool run_levels(const huge_graph *g, const huge_plan *p, const huge_exec_opts &o
     out->hash_xor = h.acc[2];
     for (int i = 0; i < HUGE_KMAX; ++i) out->level_counts[i] = h.level[i];
     if (!root_slice) out->level_counts[0] = (uint64_t)G.n;
+    if (roots_closed) out->level_counts[0] = roots_known;
     out->peak_frontier_bytes = stats.peak_frontier_bytes;
     for (int i = 0; i < HUGE_KMAX; ++i) out->level_work[i] = level_work[i];
     out->launches = stats.launches;
@@ -741,7 +754,9 @@ void run_graph(const huge_graph *g, const huge_plan *p, const huge_exec_opts &o_
     init.lv[2].nrows = l2_rows;
     HUGE_HIP(hipMemsetAsync(ctrl, 0, sizeof(Ctrl), st));
     HUGE_HIP(hipMemcpyAsync(gs, &init, sizeof(GState), hipMemcpyHostToDevice, st));
-    if (root_slice) launch_root_count(G, P, ctrl, st);
+    uint64_t roots_known = 0;
+    const bool roots_closed = root_slice && strided_root_count(P, G.n, &roots_known);
+    if (root_slice && !roots_closed) launch_root_count(G, P, ctrl, st);
     const int count_mode = (o.exec_flags & HUGE_EXEC_NO_HASH) ? MODE_COUNT_NOHASH : MODE_COUNT;
 
     // record kRounds rounds on a private stream
@@ -803,6 +818,7 @@ void run_graph(const huge_graph *g, const huge_plan *p, const huge_exec_opts &o_
     out->hash_xor = h.acc[2];
     for (int i = 0; i < HUGE_KMAX; ++i) out->level_counts[i] = h.level[i];
     if (!root_slice) out->level_counts[0] = (uint64_t)G.n;
+    if (roots_closed) out->level_counts[0] = roots_known;
     out->peak_frontier_bytes = (uint64_t)hs.peak_bytes;
     for (int i = 0; i < HUGE_KMAX; ++i) out->level_work[i] = (uint64_t)hs.work[i];
     out->launches = (uint64_t)replays;  // graph launches

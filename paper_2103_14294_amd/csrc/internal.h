@@ -196,7 +196,9 @@ uint64_t workspace_bytes(const huge_graph *g, const huge_plan *p, const huge_exe
 // the plan as one execution sees it (slice options applied); HUGE_EINVAL on bad options
 DevPlan exec_plan(const huge_plan *p, const huge_exec_opts &o);
 bool root_sliced(const DevPlan &P);       // level_counts[0] is the number of roots in the slices
-bool gathers_level2(const DevPlan &P);    // level 2 is the gathered entries of a strided root slice
+bool gathers_level2(const DevPlan &P);
+// level_counts[0] of a root slice whose only filter is a rank stride (false: needs k_root_count)
+bool strided_root_count(const DevPlan &P, int64_t n, uint64_t *count);    // level 2 is the gathered entries of a strided root slice
 int64_t gathered_rows_bound(const huge_graph *g, const DevPlan &P);
 int64_t gathered_roots(const huge_graph *g, const DevPlan &P);
 int64_t strided_l2_rows(const huge_graph *g, const DevPlan &P);  // rows of a strided edge slice

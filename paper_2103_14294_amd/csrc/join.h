@@ -56,8 +56,11 @@ void launch_join_keys(const int32_t *R, int64_t nr, const JoinSpec &J, uint32_t 
 // per L row: the count and first index of equal key hashes in the sorted keys
 void launch_join_prepare(const int32_t *L, int64_t nl, const JoinSpec &J, const uint32_t *skeys, int64_t nr,
                          uint32_t *bound, int64_t *first, unsigned long long *acc, hipStream_t st);
-void launch_join_items(const int32_t *L, int64_t nl, const int32_t *R, const int64_t *off, const int64_t *first,
-                       const uint32_t *svals, int64_t items, const JoinSpec &J, int mode, int32_t *out, int64_t cap,
-                       unsigned long long *acc, hipStream_t st);
+// out[i] = R[svals[i]] (rows of width w): R in key-hash order
+void launch_gather_rows(const int32_t *R, int64_t nr, int w, const uint32_t *svals, int32_t *out, hipStream_t st);
+// items over off: left row r meets sorted right rows first[r] .. first[r] + bound[r] - 1 of Rs
+void launch_join_items(const int32_t *L, int64_t nl, const int32_t *Rs, const int64_t *off, const int64_t *first,
+                       int64_t items, const JoinSpec &J, int mode, int32_t *out, int64_t cap, unsigned long long *acc,
+                       hipStream_t st);
 
 }  // namespace huge

@@ -10,7 +10,8 @@
 // join), an exclusive scan turns the counts into offsets, and an item pass
 // maps every item back to its row by binary search in the offsets and tests
 // it -- the same flattening as the level engine's, so a hub row's work
-// spreads over the whole grid.  The item pass either counts the rows that
+// spreads over the whole grid; each lane takes a run of consecutive items, so
+// the row search and the row load are paid once per run and row.  The item pass either counts the rows that
 // pass (to size the output exactly), writes them (one atomic per wave), or,
 // for the plan's root, counts them with the set-hash of their edges.
 #include <hip/hip_runtime.h>
@@ -98,6 +99,18 @@ __device__ __forceinline__ void sink_row(const Sink &s, bool ok, const int32_t (
     }
 }
 
+// Every lane takes kChunk consecutive work items per round: one binary search
+// finds the row of the first, a forward cursor the rows of the others, and
+// the row is loaded again only when it changes.
+constexpr int kChunk = 8;
+
+// the row holding item t, from a cursor at row r <= that row (rows without
+// items are stepped over)
+__device__ __forceinline__ int64_t advance_row(const int64_t *__restrict__ off, int64_t n, int64_t r, int64_t t) {
+    while (r + 1 < n && off[r + 1] <= t) ++r;
+    return r;
+}
+
 // ---------------------------------------------------------------------------
 // table steps
 // ---------------------------------------------------------------------------
@@ -156,38 +169,50 @@ __global__ __launch_bounds__(kJT) void k_tab_prepare(const int32_t *__restrict__
 __global__ __launch_bounds__(kJT) void k_tab_items(const int32_t *__restrict__ in, int64_t n,
                                                    const int64_t *__restrict__ off, const uint64_t *__restrict__ pinfo,
                                                    int64_t items, TabStep S, GraphDev g, Sink sk) {
-    const int64_t stride = (int64_t)gridDim.x * kJT;
+    const int64_t span = (int64_t)gridDim.x * kJT * kChunk;
+    const int64_t t_lane = ((int64_t)blockIdx.x * kJT + threadIdx.x) * kChunk;
     // every lane of a wave runs the same number of iterations (the sink's ballots)
-    const int64_t rounds = (items + stride - 1) / stride;
+    const int64_t rounds = (items + span - 1) / span;
     for (int64_t it = 0; it < rounds; ++it) {
-        const int64_t t = it * stride + (int64_t)blockIdx.x * kJT + threadIdx.x;
-        bool ok = false;
-        int32_t f[HUGE_KMAX];
+        const int64_t t0 = it * span + t_lane;
+        int64_t r = t0 < items ? find_row(off, 0, n - 1, t0) : 0, rl = -1;
+        int32_t fr[HUGE_KMAX];
+        uint64_t pi = 0;
+        for (int j = 0; j < kChunk; ++j) {
+            const int64_t t = t0 + j;
+            bool ok = false;
+            int32_t f[HUGE_KMAX];
 #pragma unroll
-        for (int c = 0; c < HUGE_KMAX; ++c) f[c] = -1;
-        if (t < items) {
-            const int64_t r = find_row(off, 0, n - 1, t);
-            load_tab_row(in, S.w, r, f);
-            ok = true;
-            if (S.add) {
-                const uint64_t pi = pinfo[r];
-                const int pp = (int)(pi >> 56);
-                const int32_t v = g.col[(int64_t)(pi & kPbMask) + (t - off[r])];
-#pragma unroll
-                for (int c = 0; c < HUGE_KMAX; ++c) {
-                    if (c < S.w) {
-                        ok = ok && v != f[c];  // injectivity
-                        if (ok && ((S.ext >> c) & 1u) && c != pp) ok = adj_has(g, f[c], v);
-                    }
+            for (int c = 0; c < HUGE_KMAX; ++c) f[c] = -1;
+            if (t < items) {
+                r = advance_row(off, n, r, t);
+                if (r != rl) {
+                    load_tab_row(in, S.w, r, fr);
+                    pi = S.add ? pinfo[r] : 0;
+                    rl = r;
                 }
-                if (ok && S.slice) ok = in_vslice(v, S.slice_count, S.slice_id, S.slice_mode);
-                if (ok && S.label >= 0) ok = label_ok(g, S.label, v);
 #pragma unroll
-                for (int c = 0; c < HUGE_KMAX; ++c)
-                    if (c == S.w) f[c] = v;
+                for (int c = 0; c < HUGE_KMAX; ++c) f[c] = fr[c];
+                ok = true;
+                if (S.add) {
+                    const int pp = (int)(pi >> 56);
+                    const int32_t v = g.col[(int64_t)(pi & kPbMask) + (t - off[r])];
+#pragma unroll
+                    for (int c = 0; c < HUGE_KMAX; ++c) {
+                        if (c < S.w) {
+                            ok = ok && v != f[c];  // injectivity
+                            if (ok && ((S.ext >> c) & 1u) && c != pp) ok = adj_has(g, f[c], v);
+                        }
+                    }
+                    if (ok && S.slice) ok = in_vslice(v, S.slice_count, S.slice_id, S.slice_mode);
+                    if (ok && S.label >= 0) ok = label_ok(g, S.label, v);
+#pragma unroll
+                    for (int c = 0; c < HUGE_KMAX; ++c)
+                        if (c == S.w) f[c] = v;
+                }
             }
+            sink_row(sk, ok, f);
         }
-        sink_row(sk, ok, f);
     }
 }
 
@@ -243,64 +268,80 @@ __global__ __launch_bounds__(kJT) void k_join_prepare(const int32_t *__restrict_
     }
 }
 
+// R's rows in key-hash order (after the sort), so that a key's rows are adjacent
+__global__ __launch_bounds__(kJT) void k_gather_rows(const int32_t *__restrict__ R, int64_t nr, int w,
+                                                     const uint32_t *__restrict__ svals, int32_t *__restrict__ out) {
+    for (int64_t i = (int64_t)blockIdx.x * kJT + threadIdx.x; i < nr * w; i += (int64_t)gridDim.x * kJT) {
+        const int64_t r = i / w, c = i - r * w;
+        out[i] = R[(int64_t)svals[r] * w + c];
+    }
+}
+
 __global__ __launch_bounds__(kJT) void k_join_items(const int32_t *__restrict__ L, int64_t nl,
-                                                    const int32_t *__restrict__ R, const int64_t *__restrict__ off,
-                                                    const int64_t *__restrict__ first,
-                                                    const uint32_t *__restrict__ svals, int64_t items, JoinSpec J,
+                                                    const int32_t *__restrict__ Rs, const int64_t *__restrict__ off,
+                                                    const int64_t *__restrict__ first, int64_t items, JoinSpec J,
                                                     Sink sk) {
-    const int64_t stride = (int64_t)gridDim.x * kJT;
-    const int64_t rounds = (items + stride - 1) / stride;
+    const int64_t span = (int64_t)gridDim.x * kJT * kChunk;
+    const int64_t t_lane = ((int64_t)blockIdx.x * kJT + threadIdx.x) * kChunk;
+    const int64_t rounds = (items + span - 1) / span;
     for (int64_t it = 0; it < rounds; ++it) {
-        const int64_t t = it * stride + (int64_t)blockIdx.x * kJT + threadIdx.x;
-        bool ok = false;
-        int32_t f[HUGE_KMAX];
+        const int64_t t0 = it * span + t_lane;
+        int64_t r = t0 < items ? find_row(off, 0, nl - 1, t0) : 0, rl = -1;
+        int32_t fl[HUGE_KMAX];
+        for (int jj = 0; jj < kChunk; ++jj) {
+            const int64_t t = t0 + jj;
+            bool ok = false;
+            int32_t f[HUGE_KMAX];
 #pragma unroll
-        for (int c = 0; c < HUGE_KMAX; ++c) f[c] = -1;
-        if (t < items) {
-            const int64_t r = find_row(off, 0, nl - 1, t);
-            const int64_t j = (int64_t)svals[first[r] + (t - off[r])];
-            int32_t fl[HUGE_KMAX], fr[HUGE_KMAX];
-            load_tab_row(L, J.wl, r, fl);
-            load_tab_row(R, J.wr, j, fr);
-            ok = true;
-            // the join key itself (the hash only grouped the rows)
-            for (int i = 0; i < J.nkey; ++i) {
-                int32_t a = 0, b = 0;
-#pragma unroll
-                for (int c = 0; c < HUGE_KMAX; ++c) {
-                    if (c == J.kl[i]) a = fl[c];
-                    if (c == J.kr[i]) b = fr[c];
+            for (int c = 0; c < HUGE_KMAX; ++c) f[c] = -1;
+            if (t < items) {
+                r = advance_row(off, nl, r, t);
+                if (r != rl) {
+                    load_tab_row(L, J.wl, r, fl);
+                    rl = r;
                 }
-                ok = ok && a == b;
-            }
-            // output row: the left columns, then the right-only ones
+                int32_t fr[HUGE_KMAX];
+                load_tab_row(Rs, J.wr, first[r] + (t - off[r]), fr);
+                ok = true;
+                // the join key itself (the hash only grouped the rows)
+                for (int i = 0; i < J.nkey; ++i) {
+                    int32_t a = 0, b = 0;
 #pragma unroll
-            for (int c = 0; c < HUGE_KMAX; ++c) f[c] = fl[c];
-            for (int i = 0; i < J.nro; ++i) {
-                int32_t x = 0;
-#pragma unroll
-                for (int c = 0; c < HUGE_KMAX; ++c)
-                    if (c == J.ro[i]) x = fr[c];
-                // injectivity: a right-only vertex differs from every left one
-#pragma unroll
-                for (int c = 0; c < HUGE_KMAX; ++c)
-                    if (c < J.wl) ok = ok && x != fl[c];
-#pragma unroll
-                for (int c = 0; c < HUGE_KMAX; ++c)
-                    if (c == J.wl + i) f[c] = x;
-            }
-            // symmetry-breaking constraints across the two sides
-            for (int i = 0; i < J.nsb && ok; ++i) {
-                int32_t a = 0, b = 0;
-#pragma unroll
-                for (int c = 0; c < HUGE_KMAX; ++c) {
-                    if (c == J.sa[i]) a = f[c];
-                    if (c == J.sb[i]) b = f[c];
+                    for (int c = 0; c < HUGE_KMAX; ++c) {
+                        if (c == J.kl[i]) a = fl[c];
+                        if (c == J.kr[i]) b = fr[c];
+                    }
+                    ok = ok && a == b;
                 }
-                ok = a < b;
+                // output row: the left columns, then the right-only ones
+#pragma unroll
+                for (int c = 0; c < HUGE_KMAX; ++c) f[c] = fl[c];
+                for (int i = 0; i < J.nro; ++i) {
+                    int32_t x = 0;
+#pragma unroll
+                    for (int c = 0; c < HUGE_KMAX; ++c)
+                        if (c == J.ro[i]) x = fr[c];
+                    // injectivity: a right-only vertex differs from every left one
+#pragma unroll
+                    for (int c = 0; c < HUGE_KMAX; ++c)
+                        if (c < J.wl) ok = ok && x != fl[c];
+#pragma unroll
+                    for (int c = 0; c < HUGE_KMAX; ++c)
+                        if (c == J.wl + i) f[c] = x;
+                }
+                // symmetry-breaking constraints across the two sides
+                for (int i = 0; i < J.nsb && ok; ++i) {
+                    int32_t a = 0, b = 0;
+#pragma unroll
+                    for (int c = 0; c < HUGE_KMAX; ++c) {
+                        if (c == J.sa[i]) a = f[c];
+                        if (c == J.sb[i]) b = f[c];
+                    }
+                    ok = a < b;
+                }
             }
+            sink_row(sk, ok, f);
         }
-        sink_row(sk, ok, f);
     }
 }
 
@@ -308,6 +349,8 @@ int grid_for(int64_t n) {
     const int64_t b = (n + kJT - 1) / kJT;
     return (int)std::max<int64_t>(1, std::min<int64_t>(b, 256 * 64));
 }
+
+int grid_items(int64_t items) { return grid_for((items + kChunk - 1) / kChunk); }
 
 Sink make_sink(int mode, int32_t *out, int64_t cap, int w, unsigned long long *acc, int ne, const int8_t *ea,
                const int8_t *eb) {
@@ -340,7 +383,7 @@ void launch_tab_items(const int32_t *in, int64_t n, const int64_t *off, const ui
                       unsigned long long *acc, hipStream_t st) {
     if (items <= 0) return;
     const Sink sk = make_sink(mode, out, cap, S.w + (S.add ? 1 : 0), acc, S.ne, S.ea, S.eb);
-    hipLaunchKernelGGL(k_tab_items, dim3(grid_for(items)), dim3(kJT), 0, st, in, n, off, pinfo, items, S, g, sk);
+    hipLaunchKernelGGL(k_tab_items, dim3(grid_items(items)), dim3(kJT), 0, st, in, n, off, pinfo, items, S, g, sk);
     HUGE_HIP(hipGetLastError());
 }
 
@@ -358,13 +401,18 @@ void launch_join_prepare(const int32_t *L, int64_t nl, const JoinSpec &J, const 
     HUGE_HIP(hipGetLastError());
 }
 
-void launch_join_items(const int32_t *L, int64_t nl, const int32_t *R, const int64_t *off, const int64_t *first,
-                       const uint32_t *svals, int64_t items, const JoinSpec &J, int mode, int32_t *out, int64_t cap,
-                       unsigned long long *acc, hipStream_t st) {
+void launch_gather_rows(const int32_t *R, int64_t nr, int w, const uint32_t *svals, int32_t *out, hipStream_t st) {
+    if (nr <= 0) return;
+    hipLaunchKernelGGL(k_gather_rows, dim3(grid_for(nr * w)), dim3(kJT), 0, st, R, nr, w, svals, out);
+    HUGE_HIP(hipGetLastError());
+}
+
+void launch_join_items(const int32_t *L, int64_t nl, const int32_t *Rs, const int64_t *off, const int64_t *first,
+                       int64_t items, const JoinSpec &J, int mode, int32_t *out, int64_t cap, unsigned long long *acc,
+                       hipStream_t st) {
     if (items <= 0) return;
     const Sink sk = make_sink(mode, out, cap, J.wl + J.nro, acc, J.ne, J.ea, J.eb);
-    hipLaunchKernelGGL(k_join_items, dim3(grid_for(items)), dim3(kJT), 0, st, L, nl, R, off, first, svals, items, J,
-                       sk);
+    hipLaunchKernelGGL(k_join_items, dim3(grid_items(items)), dim3(kJT), 0, st, L, nl, Rs, off, first, items, J, sk);
     HUGE_HIP(hipGetLastError());
 }
 

@@ -14,6 +14,8 @@
 #include <algorithm>
 #include <chrono>
 #include <cstring>
+#include <list>
+#include <mutex>
 #include <vector>
 
 #include "internal.h"
@@ -121,13 +123,58 @@ struct Carver {
     }
 };
 
+// A recorded round reads everything that changes between calls (query
+// plans, slices, scheduler states, counters) from device memory that each call
+// rewrites before the replays; its launches capture only the addresses of
+// that memory, the batch size, the scan grid, the per-launch strategies and
+// tile sizes, the count mode and the device.  Calls that agree on all of these
+// replay the same instantiated graph, so a call records and instantiates only
+// when its key is new.  The cache keeps the 16 most recent graphs.
+struct GraphKey {
+    int device;
+    const void *mp, *mr;
+    int nb, count_mode;
+    int64_t max_scan_tiles;
+    int strat[kMLaunches];
+    int64_t tile_items[kMLaunches];
+    uint32_t lids;
+    bool operator==(const GraphKey &o) const { return memcmp(this, &o, sizeof(*this)) == 0; }
+};
+
+struct GraphCache {
+    std::mutex mu;
+    std::list<std::pair<GraphKey, hipGraphExec_t>> lru;  // most recent first
+    static constexpr size_t kCap = 16;
+    hipGraphExec_t find(const GraphKey &k) {
+        for (auto it = lru.begin(); it != lru.end(); ++it)
+            if (it->first == k) {
+                lru.splice(lru.begin(), lru, it);
+                return lru.front().second;
+            }
+        return nullptr;
+    }
+    void put(const GraphKey &k, hipGraphExec_t e) {
+        lru.emplace_front(k, e);
+        while (lru.size() > kCap) {
+            (void)hipGraphExecDestroy(lru.back().second);
+            lru.pop_back();
+        }
+    }
+};
+
+GraphCache &graph_cache() {
+    static GraphCache *c = new GraphCache();  // lives until the process ends
+    return *c;
+}
+
 struct Res {
     void *mem = nullptr;
     hipStream_t cs = nullptr;
     hipGraph_t graph = nullptr;
-    hipGraphExec_t exec = nullptr;
+    hipGraphExec_t exec = nullptr;  // owned by the cache once stored there
+    bool cached = false;
     ~Res() {
-        if (exec) (void)hipGraphExecDestroy(exec);
+        if (exec && !cached) (void)hipGraphExecDestroy(exec);
         if (graph) (void)hipGraphDestroy(graph);
         if (cs) {
             hipStreamCaptureStatus status = hipStreamCaptureStatusNone;
@@ -281,8 +328,10 @@ void run_mgraph(const huge_graph *g, const huge_plan *const *plans, int np, cons
     HUGE_HIP(hipMemsetAsync(mr, 0, sizeof(MRound), st));
     HUGE_HIP(hipMemcpyAsync(gs, hs.data(), sizeof(GState) * nb, hipMemcpyHostToDevice, st));
     HUGE_HIP(hipMemcpyAsync(mp, hm.data(), sizeof(MPat) * nb, hipMemcpyHostToDevice, st));
+    std::vector<uint64_t> roots_known(nb, UINT64_MAX);
     for (int b = 0; b < nb; ++b)
-        if (root_sliced(hm[b].P)) launch_root_count(hm[b].g, hm[b].P, hm[b].ctrl, st);
+        if (root_sliced(hm[b].P) && !strided_root_count(hm[b].P, g->dev.n, &roots_known[b]))
+            launch_root_count(hm[b].g, hm[b].P, hm[b].ctrl, st);
     const int count_mode = (o.exec_flags & HUGE_EXEC_NO_HASH) ? MODE_COUNT_NOHASH : MODE_COUNT;
     MConst mc{};
     mc.np = nb;
@@ -294,17 +343,40 @@ void run_mgraph(const huge_graph *g, const huge_plan *const *plans, int np, cons
     // the host copies above come from pageable memory: finish them before recording
     HUGE_HIP(hipStreamSynchronize(st));
 
-    HUGE_HIP(hipStreamCreateWithFlags(&res.cs, hipStreamNonBlocking));
-    HUGE_HIP(hipStreamBeginCapture(res.cs, hipStreamCaptureModeRelaxed));  // occupancy queries run while recording
-    for (int r = 0; r < kRounds; ++r) {
-        launch_mround_sched(mp, mr, mc, res.cs);
-        launch_mround_prepare(mp, mr, nb, res.cs);
-        launch_mround_scan(mp, mr, nb, max_scan_tiles, res.cs);
-        for (int l = 0; l < kMLaunches; ++l)
-            if (use_lid[l]) launch_mround_extend(l, count_mode, strat[l], mp, mr, nb, res.cs);
+    GraphKey key;
+    memset(&key, 0, sizeof(key));
+    HUGE_HIP(hipGetDevice(&key.device));
+    key.mp = mp;
+    key.mr = mr;
+    key.nb = nb;
+    key.count_mode = count_mode;
+    key.max_scan_tiles = max_scan_tiles;
+    for (int l = 0; l < kMLaunches; ++l) {
+        key.strat[l] = strat[l];
+        key.tile_items[l] = mc.tile_items[l];
+        if (use_lid[l]) key.lids |= 1u << l;
     }
-    HUGE_HIP(hipStreamEndCapture(res.cs, &res.graph));
-    HUGE_HIP(hipGraphInstantiate(&res.exec, res.graph, nullptr, nullptr, 0));
+    // the cache lock is held from lookup to the last replay: two calls with one
+    // key would share one workspace anyway, and a graph is not replayed while
+    // another call could evict and destroy it
+    std::lock_guard<std::mutex> lock(graph_cache().mu);
+    res.exec = graph_cache().find(key);
+    res.cached = res.exec != nullptr;
+    if (!res.exec) {
+        HUGE_HIP(hipStreamCreateWithFlags(&res.cs, hipStreamNonBlocking));
+        HUGE_HIP(hipStreamBeginCapture(res.cs, hipStreamCaptureModeRelaxed));  // occupancy queries run while recording
+        for (int r = 0; r < kRounds; ++r) {
+            launch_mround_sched(mp, mr, mc, res.cs);
+            launch_mround_prepare(mp, mr, nb, res.cs);
+            launch_mround_scan(mp, mr, nb, max_scan_tiles, res.cs);
+            for (int l = 0; l < kMLaunches; ++l)
+                if (use_lid[l]) launch_mround_extend(l, count_mode, strat[l], mp, mr, nb, res.cs);
+        }
+        HUGE_HIP(hipStreamEndCapture(res.cs, &res.graph));
+        HUGE_HIP(hipGraphInstantiate(&res.exec, res.graph, nullptr, nullptr, 0));
+        graph_cache().put(key, res.exec);
+        res.cached = true;
+    }
 
     int32_t hdr[2] = {1, 0};  // active, error
     int64_t replays = 0;
@@ -332,6 +404,7 @@ void run_mgraph(const huge_graph *g, const huge_plan *const *plans, int np, cons
         out.hash_xor = hc[b].acc[2];
         for (int i = 0; i < HUGE_KMAX; ++i) out.level_counts[i] = hc[b].level[i];
         if (!root_sliced(hm[b].P)) out.level_counts[0] = (uint64_t)g->dev.n;
+        if (roots_known[b] != UINT64_MAX) out.level_counts[0] = roots_known[b];
         out.peak_frontier_bytes = (uint64_t)hs[b].peak_bytes;
         for (int i = 0; i < HUGE_KMAX; ++i) out.level_work[i] = (uint64_t)hs[b].work[i];
         out.launches = (uint64_t)replays;
