@@ -13,7 +13,7 @@ every slice holds the same share of each degree class; the engines gather
 only the slice's edge-array entries).  It is an unbiased 1/S_q sample of that
 plan's work.  S_q is fixed per query: the smallest power of 4 from 2^10 at
 which every root slice the run uses (timed and warmup), under the cost-model
-plan and under the learned plan, examines at most 1e8 candidates; so every
+plan and under the learned plan, examines at most 1e9 candidates; so every
 mode processes the same fraction of each query, and no step meets a root
 whose work has no bound.  Patterns are drawn in seed order and kept when such
 an S_q <= 2^24 exists (at least 4 roots per slice); the JSON line says how
@@ -79,12 +79,12 @@ KC_KERNELS = ["k_prepare<W,LAST>", "k_tile_scan/k_tile_reduce", "k_extend*<W,EMI
 WORKLOADS = {
     "c5": {
         "desc": "R-MAT scale 26, edge factor 16, (0.57,0.19,0.19,0.05), seed 5: 32 held-out random 4-6 vertex "
-                "patterns (seed 5, the first 32 drawn whose root slices fit 1e8 candidates at some S <= 2^24); "
+                "patterns (seed 5, the first 32 drawn whose root slices fit 1e9 candidates at some S <= 2^24); "
                 "learned/batched vs cost-model plans",
         "graph": ("rmat", dict(scale=26, edge_factor=16, seed=5)),
         "queries": ("heldout", dict(count=32, draw=400, seed=5, kmin=4, kmax=6)),
         "cap": 16 << 30,
-        "budget": 1e8,
+        "budget": 1e9,
         "modes": ["cost-model", "cost-model-batched", "learned", "learned-batched"],
     },
     "c4": {
@@ -675,7 +675,8 @@ def main():
                 oc, ol = plans["cost-model"][i].info()["order"], plans["learned"][i].info()["order"]
                 changed += oc != ol
                 per[name] = {"order_cost_model": oc, "order_learned": ol, "S": slices[i],
-                             "est_s_cost_model": round(t_c, 2), "est_s_learned": round(t_l, 2)}
+                             "est_s_cost_model": round(t_c, 2), "est_s_learned": round(t_l, 2),
+                             "segment_rows_learned": huge.segment_rows(G, plans["learned"][i], cap=cap, tune=table)[2:k]}
             cmpd["learned_vs_cost_model_per_query_geomean"] = round(math.exp(sum(math.log(r) for r in ratios) /
                                                                              len(ratios)), 4)
             cmpd["orders_changed"] = changed

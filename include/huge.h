@@ -425,6 +425,15 @@ huge_status huge_workspace_size(const huge_graph *g, const huge_plan *p, const h
  * Returns HUGE_STOPPED (out filled, partial) when opts->work_limit ended the run.
  */
 huge_status huge_count(const huge_graph *g, const huge_plan *p, const huge_exec_opts *opts, huge_result *out);
+/* The rows of one scheduling segment (the batch of input rows a level's operator
+   takes per scheduling, Sections 5.2 and 7.3) that the level engine uses at each
+   level w = 2..k-1 under these options: rows[w], HUGE_KMAX entries, 0 elsewhere.
+   Precedence: opts->chunk_rows; for learned plans the model's choice -- enough
+   rows that one segment's predicted output (the model's estimate of the step's
+   fan-out) fills the next level's queue once, 2^12..2^22, the last level excepted;
+   the tune table's choice per |Ext|; 2^22.  Each is capped by the level's queue
+   (and level 2 by its rows). */
+huge_status huge_segment_rows(const huge_graph *g, const huge_plan *p, const huge_exec_opts *opts, int64_t *rows);
 /* huge_count of a bushy plan that also reports, per tree node, the rows its
    part produced (node_rows[i] for node i < max_nodes; the root's is the
    count). */

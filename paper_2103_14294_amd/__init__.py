@@ -39,6 +39,7 @@ EXPORTED = [
     "huge_batch_workspace_size", "huge_plan_estimates", "huge_count_noalloc", "huge_noalloc_capacity",
     "huge_motif_count", "huge_load_csr_labelled", "huge_plan_create_labelled",
     "huge_plan_create_bushy", "huge_plan_bushy_nodes", "huge_count_bushy", "huge_plan_create_bushy_tree",
+    "huge_segment_rows",
 ]
 MOTIF_KMAX, MOTIF_MAX = 6, 112
 MLP_F, MLP_H = 128, 256
@@ -182,6 +183,8 @@ def load_library(path: str = LIB_PATH):
         lib.huge_plan_create_bushy_tree.restype = st
         lib.huge_plan_create_bushy_tree.argtypes = [vp, ctypes.POINTER(GraphInfo), i32, i32, vp, vp, vp, i32,
                                                     ctypes.c_double, ctypes.POINTER(ctypes.c_void_p)]
+        lib.huge_segment_rows.restype = st
+        lib.huge_segment_rows.argtypes = [vp, vp, ctypes.POINTER(ExecOpts), vp]
         lib.huge_plan_bushy_nodes.restype = st
         lib.huge_plan_bushy_nodes.argtypes = [vp, ctypes.POINTER(BushyNode), i32, ctypes.POINTER(i32)]
         lib.huge_count_bushy.restype = st
@@ -445,6 +448,15 @@ def plan_bushy(g: Graph | None, k, edges, machines=1.0, stats: dict | None = Non
                                                js.ctypes.data if js.size else None, int(js.shape[0]),
                                                float(machines), ctypes.byref(h)))
     return Plan(h.value, int(k), bushy=True)
+
+
+def segment_rows(g: Graph, p: Plan, **kw) -> list:
+    """huge_segment_rows: the level engine's rows per scheduling segment, per level."""
+    lib = load_library()
+    opts = exec_opts(**kw)
+    rows = np.zeros(KMAX, dtype=np.int64)
+    _check(lib.huge_segment_rows(g.handle, p.handle, ctypes.byref(opts), rows.ctypes.data))
+    return rows.tolist()
 
 
 def count_bushy(g: Graph, p: Plan, **kw):

@@ -193,6 +193,15 @@ huge_status huge_workspace_size(const huge_graph *g, const huge_plan *p, const h
     });
 }
 
+huge_status huge_segment_rows(const huge_graph *g, const huge_plan *p, const huge_exec_opts *opts, int64_t *rows) {
+    return guard([&] {
+        if (!g || !p || !rows) HUGE_FAIL(HUGE_EINVAL, "NULL argument");
+        huge_exec_opts o = resolve_opts(opts);
+        segment_rows(g, p, o, rows);
+        return HUGE_OK;
+    });
+}
+
 huge_status huge_count(const huge_graph *g, const huge_plan *p, const huge_exec_opts *opts, huge_result *out) {
     return guard([&] {
         if (!g || !p || !out) HUGE_FAIL(HUGE_EINVAL, "NULL argument");

@@ -78,6 +78,10 @@ Layout make_layout(const huge_graph *g, const huge_plan *p, const huge_exec_opts
         L.q_cap[w] = std::max<int64_t>(kMinQueueRows, (int64_t)(share / (4ull * w)));
     }
     auto seg_for = [&](int w) {
+        if (o.chunk_rows <= 0 && w + 1 <= k - 1) {
+            const int64_t m = model_segment_rows(p, w, L.q_cap[w + 1]);
+            if (m > 0) return std::min(m, seg_limit);
+        }
         if (o.chunk_rows <= 0 && o.tune) {
             const int64_t c = o.tune->chunk_rows[ext_count(p, w)];
             if (c > 0) return std::min(c, seg_limit);
@@ -326,6 +330,11 @@ uint64_t workspace_bytes(const huge_graph *g, const huge_plan *p, const huge_exe
     }
     if (o.engine == HUGE_ENGINE_GRAPH) return make_layout(g, p, o, 0, scan_devn_max()).total + align_up(sizeof(GState));
     return make_layout(g, p, o, 1 << 16).total;
+}
+
+void segment_rows(const huge_graph *g, const huge_plan *p, const huge_exec_opts &o, int64_t *rows) {
+    const Layout L = make_layout(g, p, o, 0);
+    for (int w = 0; w < HUGE_KMAX; ++w) rows[w] = (w >= 2 && w <= p->k - 1) ? L.seg_cap[w] : 0;
 }
 
 bool run_levels(const huge_graph *g, const huge_plan *p, const huge_exec_opts &o, huge_result *out, EmitSink *emit,

@@ -120,7 +120,23 @@ struct huge_plan {
     bool labelled = false;
     huge::DevPlan dev{};
     std::vector<huge_bushy_node> bushy;      // bushy plans (Algorithm 1): the join tree, root last; else empty
+    bool model_batch = false;                // learned plans: segment rows from the predicted fan-outs
 };
+
+namespace huge {
+// Learned plans choose the input rows of each scheduling segment (the batch
+// size of Section 7.3) from the model's predicted fan-out of the step: enough
+// rows that one segment's predicted output fills the next level's queue once,
+// between 2^12 and 2^22.  0: no choice (other plans, the last level, no
+// prediction).  est_prefix[s - 1] predicts the partial matches of s vertices.
+inline int64_t model_segment_rows(const huge_plan *p, int W, int64_t out_queue_rows) {
+    if (!p->model_batch || W < 2 || W >= p->k - 1) return 0;
+    const double a = p->est_prefix[W - 1], b = p->est_prefix[W];
+    if (!(a > 0) || !(b > 0)) return 0;
+    const double rows = (double)out_queue_rows * a / b;
+    return (int64_t)(rows < 4096.0 ? 4096.0 : rows > 4194304.0 ? 4194304.0 : rows);
+}
+}  // namespace huge
 
 // learned cardinality model (mlp.hip): FP32 master weights, BF16 copies used
 // by the kernels, Adam moments and the feature / target standardisation
@@ -193,6 +209,8 @@ struct EmitSink {
     uint64_t delivered = 0;
 };
 uint64_t workspace_bytes(const huge_graph *g, const huge_plan *p, const huge_exec_opts &o);
+// the level engine's rows per scheduling segment of every level w = 2..k-1 (rows[w])
+void segment_rows(const huge_graph *g, const huge_plan *p, const huge_exec_opts &o, int64_t *rows);
 // the plan as one execution sees it (slice options applied); HUGE_EINVAL on bad options
 DevPlan exec_plan(const huge_plan *p, const huge_exec_opts &o);
 bool root_sliced(const DevPlan &P);       // level_counts[0] is the number of roots in the slices

@@ -26,7 +26,7 @@ namespace huge {
 namespace {
 
 constexpr int kRounds = 4;                  // rounds recorded in the graph
-constexpr int kBatchReplays = 8;            // graph launches between reads of the active count
+constexpr int kBatchReplays = 8;            // most graph launches between reads of the active count
 constexpr int64_t kMaxRounds = 1ll << 26;
 constexpr int64_t kDefaultSegRows = 1 << 20;
 constexpr int64_t kMinQueueRows = 1 << 12;
@@ -49,8 +49,10 @@ struct BatchLayout {
     uint64_t total = 0;
 };
 
-int64_t seg_rows_for(const huge_plan *p, int W, const huge_exec_opts &o) {
+int64_t seg_rows_for(const huge_plan *p, int W, const huge_exec_opts &o, int64_t out_queue_rows) {
     if (o.chunk_rows > 0) return o.chunk_rows;
+    const int64_t m = model_segment_rows(p, W, out_queue_rows);
+    if (m > 0) return m;
     if (o.tune) {
         const int64_t c = o.tune->chunk_rows[__builtin_popcount(p->dev.st[W].ext)];
         if (c > 0) return std::min<int64_t>(c, kDefaultSegRows);
@@ -87,9 +89,11 @@ BatchLayout make_batch_layout(const huge_graph *g, const huge_plan *const *plans
             L.q_cap[w] = std::max<int64_t>(kMinQueueRows, (int64_t)((nq ? share / nq : 0) / (4ull * w)));
         const int64_t l2 = L.gathered ? gathered_rows_bound(g, P) : P.edge_slice == 2 ? strided_l2_rows(g, P)
                                                                                       : g->dev.nnz;
-        L.seg_cap[2] = std::min<int64_t>(std::min(seg_rows_for(p, 2, o), scan_devn_max()), std::max<int64_t>(1, l2));
+        L.seg_cap[2] = std::min<int64_t>(std::min(seg_rows_for(p, 2, o, L.q_cap[3]), scan_devn_max()),
+                                         std::max<int64_t>(1, l2));
         for (int w = 3; w <= k - 1; ++w)
-            L.seg_cap[w] = std::min<int64_t>(std::min(seg_rows_for(p, w, o), scan_devn_max()), L.q_cap[w]);
+            L.seg_cap[w] = std::min<int64_t>(std::min(seg_rows_for(p, w, o, L.q_cap[w + 1]), scan_devn_max()),
+                                             L.q_cap[w]);
         uint64_t b2 = 0;
         for (int w = 2; w <= k - 1; ++w) {
             const int64_t c = L.seg_cap[w];
@@ -380,9 +384,13 @@ void run_mgraph(const huge_graph *g, const huge_plan *const *plans, int np, cons
 
     int32_t hdr[2] = {1, 0};  // active, error
     int64_t replays = 0;
+    // replays between reads of the active count: 1, 2, 4, ... up to kBatchReplays,
+    // so that a batch of light queries does not run rounds after it is done
+    int burst = 1;
     while (hdr[0] > 0) {
-        for (int i = 0; i < kBatchReplays; ++i) HUGE_HIP(hipGraphLaunch(res.exec, st));
-        replays += kBatchReplays;
+        for (int i = 0; i < burst; ++i) HUGE_HIP(hipGraphLaunch(res.exec, st));
+        replays += burst;
+        burst = std::min(2 * burst, kBatchReplays);
         HUGE_HIP(hipMemcpyAsync(hdr, &mr->active, sizeof(hdr), hipMemcpyDeviceToHost, st));
         HUGE_HIP(hipStreamSynchronize(st));
         if (hdr[1]) HUGE_FAIL(HUGE_EINVAL, "batched rounds: a query's scheduler found no action");

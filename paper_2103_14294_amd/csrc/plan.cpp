@@ -414,6 +414,7 @@ void plan_build(const huge_graph *g, int k, int ne, const int32_t *qe, const int
         p->est_prefix[s - 1] = est[chosen * k + s - 1];
         if (s >= 2) p->est_cost += p->est_prefix[s - 1];
     }
+    p->model_batch = learned;  // est holds the model's predictions for every candidate order
 }
 
 void plan_prefix(const huge_plan &p, int size, huge_plan *q) {

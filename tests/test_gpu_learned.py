@@ -87,3 +87,43 @@ def test_learned_plans_are_exact(H, name):
     for verify in (False, True):
         order = H.plan(G, k, e, learned=m, verify=verify).info()["order"]
         assert_parity(H, G, g, k, e, order=order)
+
+
+@pytest.mark.parametrize("cap", [1 << 20, 1 << 26])
+def test_learned_plans_choose_segment_rows(H, cap):
+    """A learned plan sizes each level's scheduling segment from its model's
+    predicted fan-out (enough rows that one segment's predicted output fills the
+    next queue once, 2^12..2^22, capped by the level's own queue); an explicit
+    chunk_rows overrides it, cost-model plans keep 2^22; every choice counts the
+    oracle's matches."""
+    from tests.gpu_common import cmp_key, oracle_run
+
+    m = H.Model.load(os.path.join(PKG, "mlp_work.npz"))
+    g = gg.chung_lu(3000, 10, 2.3, seed=21)
+    G = H.load(g.row_ptr, g.col)
+    for name in ["house", "5-clique", "6-cycle", "tailed-triangle"]:
+        k, e = P.NAMED[name]
+        p = H.plan(G, k, e, learned=m)
+        est = p.estimates()
+        rows = H.segment_rows(G, p, cap=cap)
+        nq = max(0, k - 3)
+        qcap = [0] * (H.KMAX + 2)
+        for w in range(3, k):
+            qcap[w] = max(4096, (cap // nq) // (4 * w))
+        for w in range(2, k):
+            if w < k - 1 and est[w - 1] > 0 and est[w] > 0:
+                want = min(max(4096, int(qcap[w + 1] * est[w - 1] / est[w])), 1 << 22)
+            else:
+                want = 1 << 22
+            if w >= 3:
+                want = min(want, qcap[w])
+            else:
+                want = min(want, g.nnz)
+            assert rows[w] == want, (name, cap, w, rows, want)
+        assert H.segment_rows(G, p, cap=cap, chunk_rows=5000)[2] == 5000
+        cm = H.plan(G, k, e, order=p.info()["order"])
+        assert H.segment_rows(G, cm, cap=cap)[2] == min(1 << 22, g.nnz)
+        ref = oracle_run(g, k, e)
+        for eng in (H.ENGINE_LEVELS, H.ENGINE_GRAPH):
+            assert cmp_key(H.count(G, p, cap=cap, engine=eng), k) == cmp_key(ref, k), (name, cap, eng)
+        assert cmp_key(H.count_batch(G, [p, cm], cap=cap, engine=H.ENGINE_GRAPH)[0], k) == cmp_key(ref, k)
