@@ -144,6 +144,42 @@ def from_edges(n: int, edges, permute: bool = False, seed: int = 0, name: str = 
     return _take(ptr, name or "edges_n%d" % n)
 
 
+class DiCSR(CSR):
+    """A directed graph: its undirected skeleton (row_ptr, col: every adjacent pair,
+    both ways) and its out-lists (out_rp, out_col), original IDs, lists ascending."""
+
+    def __init__(self, row_ptr, col, out_rp, out_col, name: str = ""):
+        super().__init__(row_ptr, col, name)
+        self.out_rp = np.ascontiguousarray(out_rp, dtype=np.int64)
+        self.out_col = np.ascontiguousarray(out_col, dtype=np.int32)
+
+    @property
+    def arcs(self) -> int:
+        return int(self.out_col.shape[0])
+
+
+def orient(g: CSR, p_both: float, seed: int) -> DiCSR:
+    """Directions for every edge {u, v} of g: both with probability p_both, else
+    one of the two, each with probability 1/2 (numpy's Philox generator, seeded).
+    The skeleton of the result is g itself."""
+    rng = np.random.Generator(np.random.Philox(int(seed)))
+    u = np.repeat(np.arange(g.n, dtype=np.int64), np.diff(g.row_ptr))
+    v = g.col.astype(np.int64)
+    keep = u < v
+    eu, ev = u[keep], v[keep]
+    both = rng.random(eu.shape[0]) < p_both
+    pick = rng.integers(0, 2, eu.shape[0])
+    fwd = both | (pick == 0)
+    bwd = both | (pick == 1)
+    src = np.concatenate([eu[fwd], ev[bwd]])
+    dst = np.concatenate([ev[fwd], eu[bwd]])
+    order = np.lexsort((dst, src))
+    src, dst = src[order], dst[order]
+    out_rp = np.zeros(g.n + 1, dtype=np.int64)
+    np.cumsum(np.bincount(src, minlength=g.n), out=out_rp[1:])
+    return DiCSR(g.row_ptr, g.col, out_rp, dst.astype(np.int32), g.name + "_dir%g_s%d" % (p_both, seed))
+
+
 def philox4x32_10(ctr, key):
     """One Philox4x32-10 block (exposed for the generator's known-answer test)."""
     lib = _load()

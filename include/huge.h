@@ -75,6 +75,10 @@ typedef struct huge_plan huge_plan;
  * graph engines and batches (the persistent engine: HUGE_EINVAL).  The cost
  * model's estimate stays the non-induced one, an upper bound. */
 #define HUGE_PLAN_INDUCED 0x4u
+/* Every injective map counted: no symmetry breaking, so each subgraph is
+ * reported once per automorphism of q (Section 2's matches before the
+ * automorphism classes are taken; used for queries with pinned vertices). */
+#define HUGE_PLAN_ALL_MAPS 0x8u
 
 /* huge_exec_opts.engine */
 #define HUGE_ENGINE_AUTO 0
@@ -250,6 +254,19 @@ huge_status huge_exec_opts_default(huge_exec_opts *opts);
  */
 huge_status huge_load_csr(int64_t n, int64_t nnz, const int64_t *row_ptr, const int32_t *col, uint32_t flags,
                           void *stream, huge_graph **out);
+/*
+ * huge_load_csr_directed -- a directed graph (Section 2: the techniques carry
+ * over to directed graphs) from out-lists: row_ptr int64[n+1], col int32[n_arcs]
+ * in host memory (HUGE_HOST_PTRS; copied), each list strictly ascending, no
+ * self-loops.  The graph the engines search is the undirected skeleton (every
+ * pair joined by an arc in either direction, relabelled by degree rank as by
+ * huge_load_csr); the out-lists are kept beside it in rank IDs, and a directed
+ * query's edges are checked in their direction by lookups in them.  Undirected
+ * queries on a directed graph match its skeleton.  Errors: HUGE_EGRAPH,
+ * HUGE_EINVAL, HUGE_ENOMEM, HUGE_EDEVICE.
+ */
+huge_status huge_load_csr_directed(int64_t n, int64_t n_arcs, const int64_t *row_ptr, const int32_t *col,
+                                   uint32_t flags, void *stream, huge_graph **out);
 void huge_graph_free(huge_graph *g);
 
 /*
@@ -314,6 +331,23 @@ void huge_plan_free(huge_plan *p);
  */
 huge_status huge_plan_create_labelled(const huge_graph *g, int32_t k, int32_t n_qedges, const int32_t *qedges,
                                       const int32_t *qlabels, const int32_t *order, uint32_t flags, huge_plan **out);
+
+/*
+ * huge_plan_create_directed -- a directed query: arcs holds n_arcs directed
+ * edges a -> b over vertices 0..k-1 (both directions of a pair may be given);
+ * its undirected skeleton must be connected.  A match is an injective map
+ * that keeps every edge's direction (and labels, with qlabels as in
+ * huge_plan_create_labelled, or NULL), counted once per class of the
+ * automorphisms of q that keep directions (and labels), from which the
+ * symmetry-breaking constraints come.  The order (or the cost model's, on the
+ * skeleton) and Eq. 2's intersections run on the skeleton; each step then
+ * looks up its directed edges to matched vertices in the out-lists.  The
+ * set-hash hashes the image's skeleton edges.  Needs a graph from
+ * huge_load_csr_directed (HUGE_EINVAL otherwise).  Level and graph engines and
+ * batches (the persistent engine and bushy plans: HUGE_EINVAL).
+ */
+huge_status huge_plan_create_directed(const huge_graph *g, int32_t k, int32_t n_arcs, const int32_t *arcs,
+                                      const int32_t *qlabels, const int32_t *order, huge_plan **out);
 
 /*
  * huge_plan_prefix -- the plan of the first `size` vertices (2..k) of p's
@@ -434,6 +468,18 @@ huge_status huge_count(const huge_graph *g, const huge_plan *p, const huge_exec_
    the tune table's choice per |Ext|; 2^22.  Each is capped by the level's queue
    (and level 2 by its rows). */
 huge_status huge_segment_rows(const huge_graph *g, const huge_plan *p, const huge_exec_opts *opts, int64_t *rows);
+/*
+ * huge_count_paths -- hop-constrained path queries (Section 6 lists them among
+ * the applications): counts[L] (L = 1..max_hops, max_hops <= 7; counts[0] = 0)
+ * is the number of simple paths of exactly L edges from s to t (original IDs,
+ * s != t).  Each length runs as the path query 0 - 1 - ... - L in that order,
+ * every map counted (HUGE_PLAN_ALL_MAPS), with query vertex 0 pinned to s by a
+ * strided root slice of count n (one root: s's rank) and vertex L pinned to t
+ * by a second strided slice; the options' engine, cap and tune table apply
+ * (slice options must be unset).  counts holds max_hops + 1 entries.
+ */
+huge_status huge_count_paths(const huge_graph *g, int32_t s, int32_t t, int32_t max_hops,
+                             const huge_exec_opts *opts, uint64_t *counts);
 /* huge_count of a bushy plan that also reports, per tree node, the rows its
    part produced (node_rows[i] for node i < max_nodes; the root's is the
    count). */

@@ -69,6 +69,11 @@ def _load():
         lib.orc_enumerate.argtypes = [i64, vp, vp, ci, ci, vp, ci, vp, ci, vp, ctypes.c_uint32, ctypes.c_uint32,
                                       ci, ci, ci, ci, ci, ctypes.c_uint32, ctypes.c_uint32, vp, vp, vp, ci,
                                       ctypes.POINTER(_Result)]
+        lib.orc_enumerate_directed.restype = ci
+        lib.orc_enumerate_directed.argtypes = [i64, vp, vp, vp, vp, ci, ci, vp, ci, vp, ctypes.c_uint32,
+                                               ctypes.c_uint32, ci, ci, vp, vp, ci, ctypes.POINTER(_Result)]
+        lib.orc_automorphisms_directed.restype = ci
+        lib.orc_automorphisms_directed.argtypes = [ci, ci, vp]
         lib.orc_automorphisms.restype = ci
         lib.orc_automorphisms.argtypes = [ci, ci, vp, vp, ci]
         lib.orc_sb_pairs.restype = ci
@@ -143,6 +148,47 @@ def enumerate_query(row_ptr, col, k, qedges, mode=MODE_SB, order=None, sb_pairs=
         raise ValueError("oracle rejected the query or order")
     return {"count": int(r.count), "hash_sum": int(r.hash_sum), "hash_xor": int(r.hash_xor),
             "level_counts": [int(x) for x in r.level_counts]}
+
+
+def enumerate_directed(row_ptr, col, out_rp, out_col, k, qedges, mode=MODE_SB, order=None, slice_count=1,
+                       slice_id=0, slice_vertex=0, slice_mode=0, threads=0, vlabels=None, qlabels=None):
+    """A directed query on a directed graph: row_ptr/col is the graph's undirected
+    skeleton, out_rp/out_col its out-lists (original IDs, ascending), qedges the
+    query's directed edges a -> b.  Matches keep every edge's direction and are
+    counted once per class of the direction-keeping automorphisms; the set-hash
+    hashes the image's skeleton edges."""
+    lib = _load()
+    rp = np.ascontiguousarray(row_ptr, dtype=np.int64)
+    cl = np.ascontiguousarray(col, dtype=np.int32)
+    drp = np.ascontiguousarray(out_rp, dtype=np.int64)
+    dcl = np.ascontiguousarray(out_col, dtype=np.int32)
+    if cl.size == 0:
+        cl = np.zeros(1, dtype=np.int32)
+    if dcl.size == 0:
+        dcl = np.zeros(1, dtype=np.int32)
+    e = _qarr(qedges)
+    o = None if order is None else np.ascontiguousarray(np.asarray(order, dtype=np.int32))
+    vl = None if vlabels is None else np.ascontiguousarray(vlabels, dtype=np.int32)
+    ql = None if qlabels is None else np.ascontiguousarray(qlabels, dtype=np.int32)
+    r = _Result()
+    st = lib.orc_enumerate_directed(int(rp.shape[0] - 1), rp.ctypes.data, cl.ctypes.data, drp.ctypes.data,
+                                    dcl.ctypes.data, int(k), int(e.shape[0]), e.ctypes.data, int(mode),
+                                    None if o is None else o.ctypes.data, int(slice_count), int(slice_id),
+                                    int(slice_vertex), int(slice_mode), None if vl is None else vl.ctypes.data,
+                                    None if ql is None else ql.ctypes.data, int(threads), ctypes.byref(r))
+    if st != 0:
+        raise ValueError("oracle rejected the query or order")
+    return {"count": int(r.count), "hash_sum": int(r.hash_sum), "hash_xor": int(r.hash_xor),
+            "level_counts": [int(x) for x in r.level_counts]}
+
+
+def automorphisms_directed(k, qedges):
+    """|Aut(q)| of a directed query: the permutations keeping every edge's direction."""
+    e = _qarr(qedges)
+    n = _load().orc_automorphisms_directed(int(k), int(e.shape[0]), e.ctypes.data)
+    if n < 0:
+        raise ValueError("malformed query")
+    return n
 
 
 def automorphisms(k, qedges):

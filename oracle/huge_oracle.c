@@ -107,6 +107,8 @@ typedef struct {
     int nsb;
     int sba[28], sbb[28]; /* constraint sba < sbb (query vertex IDs) */
     int label[ORC_KMAX];  /* labelled queries: the label each query vertex's image must carry, -1 any */
+    int directed;         /* directed queries: dadj[a][b] = 1 for every query edge a -> b */
+    int dadj[ORC_KMAX][ORC_KMAX];
 } orc_query;
 
 /* Returns 0 on success, -1 on malformed query (k out of range, bad edge,
@@ -140,6 +142,32 @@ static int orc_query_init(orc_query *q, int k, int ne, const int32_t *e) {
     return 0;
 }
 
+/* A directed query: edges a -> b (a pair may hold both directions).  Its
+ * undirected skeleton (one edge per adjacent pair) must be connected; the
+ * skeleton drives the search, the directions filter it. */
+static int orc_query_init_directed(orc_query *q, int k, int ne, const int32_t *e) {
+    memset(q, 0, sizeof(*q));
+    if (k < 2 || k > ORC_KMAX || ne < 1 || ne > 56) return -1;
+    int32_t sk[2 * 28];
+    int nsk = 0;
+    int dadj[ORC_KMAX][ORC_KMAX];
+    memset(dadj, 0, sizeof(dadj));
+    for (int i = 0; i < ne; ++i) {
+        int a = e[2 * i], b = e[2 * i + 1];
+        if (a < 0 || b < 0 || a >= k || b >= k || a == b || dadj[a][b]) return -1;
+        dadj[a][b] = 1;
+        if (!dadj[b][a]) {
+            sk[2 * nsk] = a;
+            sk[2 * nsk + 1] = b;
+            ++nsk;
+        }
+    }
+    if (orc_query_init(q, k, nsk, sk) != 0) return -1;
+    q->directed = 1;
+    memcpy(q->dadj, dadj, sizeof(dadj));
+    return 0;
+}
+
 /* All automorphisms by trying every permutation (k <= 8: at most 40320). */
 static void orc_query_aut(orc_query *q) {
     int k = q->k;
@@ -155,6 +183,9 @@ static void orc_query_aut(orc_query *q) {
             if (!q->adj[p[q->ea[i]]][p[q->eb[i]]]) ok = 0;
         for (int i = 0; i < k && ok; ++i) /* automorphisms of a labelled query keep labels */
             if (q->label[p[i]] != q->label[i]) ok = 0;
+        for (int a = 0; a < k && ok && q->directed; ++a) /* ... and of a directed one, directions */
+            for (int b = 0; b < k && ok; ++b)
+                if (q->dadj[p[a]][p[b]] != q->dadj[a][b]) ok = 0;
         if (ok) {
             for (int i = 0; i < k; ++i) q->aut[q->naut * k + i] = (int8_t)p[i];
             q->naut++;
@@ -229,6 +260,8 @@ typedef struct {
     const int32_t *col;
     int32_t *rank;
     const int32_t *label; /* vertex labels (original IDs), or NULL */
+    const int64_t *drp;   /* directed graphs: out-lists (original IDs, ascending), or NULL */
+    const int32_t *dcol;
 } orc_graph;
 
 static const int64_t *orc_sort_deg;
@@ -264,6 +297,18 @@ static int orc_adjacent(const orc_graph *g, int32_t a, int32_t b) {
     while (lo < hi) {
         int64_t mid = lo + ((hi - lo) >> 1);
         int32_t x = g->col[mid];
+        if (x == b) return 1;
+        if (x < b) lo = mid + 1; else hi = mid;
+    }
+    return 0;
+}
+
+/* a -> b in a directed graph's out-lists */
+static int orc_arc(const orc_graph *g, int32_t a, int32_t b) {
+    int64_t lo = g->drp[a], hi = g->drp[a + 1];
+    while (lo < hi) {
+        int64_t mid = lo + ((hi - lo) >> 1);
+        int32_t x = g->dcol[mid];
         if (x == b) return 1;
         if (x < b) lo = mid + 1; else hi = mid;
     }
@@ -471,6 +516,12 @@ static int orc_accept(orc_worker *w, int i, int32_t c) {
     if (P->induced)
         for (int t = 0; t < P->nnon[i]; ++t)
             if (orc_adjacent(g, w->f[P->non[i][t]], c)) return 0;
+    if (P->q->directed) /* every query edge between an earlier vertex and this one, in its direction */
+        for (int p = 0; p < i; ++p) {
+            const int u = P->order[p], v = P->order[i];
+            if (P->q->dadj[u][v] && !orc_arc(g, w->f[p], c)) return 0;
+            if (P->q->dadj[v][u] && !orc_arc(g, c, w->f[p])) return 0;
+        }
     int32_t rc = g->rank[c];
     for (int t = 0; t < P->nlt[i]; ++t)
         if (!(g->rank[w->f[P->lt[i][t]]] < rc)) return 0;
@@ -581,14 +632,15 @@ static void *orc_thread(void *arg) {
  * online CPUs).
  * Returns 0, or -1 for a malformed query/order.
  */
-int orc_enumerate(int64_t n, const int64_t *rp, const int32_t *col, int k, int nqe,
-                  const int32_t *qedges, int mode, const int32_t *order, int nsb,
-                  const int32_t *sb_pairs, uint32_t slice_count, uint32_t slice_id, int slice_vertex,
-                  int slice_vertex2, int slice_mode, int slice2_vertex, int slice2_vertex2, uint32_t slice2_count,
-                  uint32_t slice2_id, const int32_t *rank_in, const int32_t *vlabels, const int32_t *qlabels,
-                  int nthreads, orc_result *out) {
+static int orc_enumerate_impl(int64_t n, const int64_t *rp, const int32_t *col, int k, int nqe,
+                              const int32_t *qedges, int mode, const int32_t *order, int nsb,
+                              const int32_t *sb_pairs, uint32_t slice_count, uint32_t slice_id, int slice_vertex,
+                              int slice_vertex2, int slice_mode, int slice2_vertex, int slice2_vertex2,
+                              uint32_t slice2_count, uint32_t slice2_id, const int32_t *rank_in,
+                              const int32_t *vlabels, const int32_t *qlabels, int nthreads, orc_result *out,
+                              const int64_t *drp, const int32_t *dcol) {
     orc_query q;
-    if (orc_query_init(&q, k, nqe, qedges) != 0) return -1;
+    if ((drp ? orc_query_init_directed(&q, k, nqe, qedges) : orc_query_init(&q, k, nqe, qedges)) != 0) return -1;
     for (int i = 0; i < k; ++i) q.label[i] = qlabels ? qlabels[i] : -1;
     orc_query_aut(&q);
     if (nsb >= 0) {
@@ -613,6 +665,8 @@ int orc_enumerate(int64_t n, const int64_t *rp, const int32_t *col, int k, int n
     g.rp = rp;
     g.col = col;
     g.label = vlabels;
+    g.drp = drp;
+    g.dcol = dcol;
     g.rank = (int32_t *)malloc(sizeof(int32_t) * (size_t)(n > 0 ? n : 1));
     if (rank_in) /* ranks from an earlier orc_ranks call on the same graph */
         memcpy(g.rank, rank_in, sizeof(int32_t) * (size_t)n);
@@ -666,6 +720,45 @@ int orc_enumerate(int64_t n, const int64_t *rp, const int32_t *col, int k, int n
     free(g.rank);
     free(q.aut);
     return 0;
+}
+
+int orc_enumerate(int64_t n, const int64_t *rp, const int32_t *col, int k, int nqe,
+                  const int32_t *qedges, int mode, const int32_t *order, int nsb,
+                  const int32_t *sb_pairs, uint32_t slice_count, uint32_t slice_id, int slice_vertex,
+                  int slice_vertex2, int slice_mode, int slice2_vertex, int slice2_vertex2, uint32_t slice2_count,
+                  uint32_t slice2_id, const int32_t *rank_in, const int32_t *vlabels, const int32_t *qlabels,
+                  int nthreads, orc_result *out) {
+    return orc_enumerate_impl(n, rp, col, k, nqe, qedges, mode, order, nsb, sb_pairs, slice_count, slice_id,
+                              slice_vertex, slice_vertex2, slice_mode, slice2_vertex, slice2_vertex2, slice2_count,
+                              slice2_id, rank_in, vlabels, qlabels, nthreads, out, NULL, NULL);
+}
+
+/*
+ * The same for a directed graph and a directed query: rp/col is the graph's
+ * undirected skeleton (every adjacent pair both ways), drp/dcol its out-lists
+ * (original IDs, ascending); qedges are the query's directed edges a -> b.  A
+ * match is an injective map keeping every query edge's direction, reported
+ * once per class of the automorphisms that keep directions (and labels).
+ */
+int orc_enumerate_directed(int64_t n, const int64_t *rp, const int32_t *col, const int64_t *drp,
+                           const int32_t *dcol, int k, int nqe, const int32_t *qedges, int mode,
+                           const int32_t *order, uint32_t slice_count, uint32_t slice_id, int slice_vertex,
+                           int slice_mode, const int32_t *vlabels, const int32_t *qlabels, int nthreads,
+                           orc_result *out) {
+    if (!drp || !dcol) return -1;
+    return orc_enumerate_impl(n, rp, col, k, nqe, qedges, mode, order, -1, NULL, slice_count, slice_id,
+                              slice_vertex, -1, slice_mode, -1, -1, 1, 0, NULL, vlabels, qlabels, nthreads, out,
+                              drp, dcol);
+}
+
+/* |Aut(q)| of a directed query (automorphisms keep directions), or -1. */
+int orc_automorphisms_directed(int k, int nqe, const int32_t *qedges) {
+    orc_query q;
+    if (orc_query_init_directed(&q, k, nqe, qedges) != 0) return -1;
+    orc_query_aut(&q);
+    int n = q.naut;
+    free(q.aut);
+    return n;
 }
 
 /* |Aut(q)|, or -1 for a malformed query; perms (if not NULL) receives naut*k entries. */

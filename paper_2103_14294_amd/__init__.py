@@ -21,7 +21,7 @@ HUGE_OK, HUGE_STOPPED = 0, 1
 STATUS = {0: "HUGE_OK", 1: "HUGE_STOPPED", -1: "HUGE_EINVAL", -2: "HUGE_ENOMEM", -3: "HUGE_EDEVICE",
           -4: "HUGE_EGRAPH", -5: "HUGE_EQUERY", -6: "HUGE_EORDER", -7: "HUGE_EOVERFLOW"}
 HOST_PTRS, DEVICE_PTRS, NO_VALIDATE, NO_HUB_BITMAP = 0x1, 0x2, 0x4, 0x8
-PLAN_COST_MODEL, PLAN_LEARNED, PLAN_VERIFY, PLAN_INDUCED = 0x0, 0x1, 0x2, 0x4
+PLAN_COST_MODEL, PLAN_LEARNED, PLAN_VERIFY, PLAN_INDUCED, PLAN_ALL_MAPS = 0x0, 0x1, 0x2, 0x4, 0x8
 ENGINE_AUTO, ENGINE_LEVELS, ENGINE_PERSISTENT, ENGINE_GRAPH = 0, 1, 2, 3
 EXEC_NO_HASH, EXEC_SLICE2_PAIR = 0x1, 0x2
 SLICE_MIX, SLICE_STRIDE = 0, 1
@@ -39,7 +39,7 @@ EXPORTED = [
     "huge_batch_workspace_size", "huge_plan_estimates", "huge_count_noalloc", "huge_noalloc_capacity",
     "huge_motif_count", "huge_load_csr_labelled", "huge_plan_create_labelled",
     "huge_plan_create_bushy", "huge_plan_bushy_nodes", "huge_count_bushy", "huge_plan_create_bushy_tree",
-    "huge_segment_rows",
+    "huge_segment_rows", "huge_load_csr_directed", "huge_plan_create_directed", "huge_count_paths",
 ]
 MOTIF_KMAX, MOTIF_MAX = 6, 112
 MLP_F, MLP_H = 128, 256
@@ -183,6 +183,12 @@ def load_library(path: str = LIB_PATH):
         lib.huge_plan_create_bushy_tree.restype = st
         lib.huge_plan_create_bushy_tree.argtypes = [vp, ctypes.POINTER(GraphInfo), i32, i32, vp, vp, vp, i32,
                                                     ctypes.c_double, ctypes.POINTER(ctypes.c_void_p)]
+        lib.huge_load_csr_directed.restype = st
+        lib.huge_load_csr_directed.argtypes = [i64, i64, vp, vp, ctypes.c_uint32, vp, ctypes.POINTER(ctypes.c_void_p)]
+        lib.huge_plan_create_directed.restype = st
+        lib.huge_plan_create_directed.argtypes = [vp, i32, i32, vp, vp, vp, ctypes.POINTER(ctypes.c_void_p)]
+        lib.huge_count_paths.restype = st
+        lib.huge_count_paths.argtypes = [vp, i32, i32, i32, ctypes.POINTER(ExecOpts), vp]
         lib.huge_segment_rows.restype = st
         lib.huge_segment_rows.argtypes = [vp, vp, ctypes.POINTER(ExecOpts), vp]
         lib.huge_plan_bushy_nodes.restype = st
@@ -385,7 +391,8 @@ def load(row_ptr, col, validate=True, stream=None, hub_bitmaps=True, labels=None
     return Graph(h.value, int(n), int(nnz))
 
 
-def plan(g: Graph, k, edges, order=None, learned=None, verify=False, induced=False, labels=None) -> Plan:
+def plan(g: Graph, k, edges, order=None, learned=None, verify=False, induced=False, labels=None,
+         all_maps=False) -> Plan:
     """huge_plan_create for query edges over vertices 0..k-1; with a Model as
     `learned`, huge_plan_create_learned2 (orders scored by the MLP on the GPU;
     verify=True measures its best orders on a small sample).  induced=True keeps
@@ -395,7 +402,7 @@ def plan(g: Graph, k, edges, order=None, learned=None, verify=False, induced=Fal
     e = np.ascontiguousarray(np.asarray(edges, dtype=np.int32).reshape(-1, 2))
     o = None if order is None else np.ascontiguousarray(np.asarray(order, dtype=np.int32))
     h = ctypes.c_void_p()
-    ind = PLAN_INDUCED if induced else 0
+    ind = (PLAN_INDUCED if induced else 0) | (PLAN_ALL_MAPS if all_maps else 0)  # all_maps: no symmetry breaking
     if labels is not None:
         if learned:
             raise ValueError("labelled queries are planned by the cost model")
@@ -448,6 +455,43 @@ def plan_bushy(g: Graph | None, k, edges, machines=1.0, stats: dict | None = Non
                                                js.ctypes.data if js.size else None, int(js.shape[0]),
                                                float(machines), ctypes.byref(h)))
     return Plan(h.value, int(k), bushy=True)
+
+
+def load_directed(out_rp, out_col, hub_bitmaps=True, stream=None) -> Graph:
+    """huge_load_csr_directed: a directed graph from its out-lists (host numpy arrays)."""
+    lib = load_library()
+    rp = np.ascontiguousarray(out_rp, dtype=np.int64)
+    cl = np.ascontiguousarray(out_col, dtype=np.int32)
+    n = int(rp.shape[0] - 1)
+    h = ctypes.c_void_p()
+    flags = HOST_PTRS | (0 if hub_bitmaps else NO_HUB_BITMAP)
+    _check(lib.huge_load_csr_directed(n, int(cl.shape[0]), rp.ctypes.data, cl.ctypes.data if cl.size else None,
+                                      flags, stream if stream is not None else _current_stream(), ctypes.byref(h)))
+    gi = GraphInfo()
+    _check(lib.huge_graph_get_info(h, ctypes.byref(gi)))
+    return Graph(h.value, n, int(gi.nnz))
+
+
+def plan_directed(g: Graph, k, arcs, order=None, labels=None) -> Plan:
+    """huge_plan_create_directed: a directed query, arcs = [(a, b), ...] meaning a -> b."""
+    lib = load_library()
+    a = np.ascontiguousarray(np.asarray(arcs, dtype=np.int32).reshape(-1, 2))
+    o = None if order is None else np.ascontiguousarray(np.asarray(order, dtype=np.int32))
+    ql = None if labels is None else np.ascontiguousarray(np.asarray(labels, dtype=np.int32))
+    h = ctypes.c_void_p()
+    _check(lib.huge_plan_create_directed(None if g is None else g.handle, int(k), int(a.shape[0]), a.ctypes.data,
+                                         None if ql is None else ql.ctypes.data, None if o is None else o.ctypes.data,
+                                         ctypes.byref(h)))
+    return Plan(h.value, int(k))
+
+
+def count_paths(g: Graph, s: int, t: int, max_hops: int, **kw) -> list:
+    """huge_count_paths: counts[L] = simple s-t paths of exactly L edges, L = 0..max_hops."""
+    lib = load_library()
+    opts = exec_opts(**kw)
+    out = np.zeros(int(max_hops) + 1, dtype=np.uint64)
+    _check(lib.huge_count_paths(g.handle, int(s), int(t), int(max_hops), ctypes.byref(opts), out.ctypes.data))
+    return [int(x) for x in out]
 
 
 def segment_rows(g: Graph, p: Plan, **kw) -> list:

@@ -455,6 +455,7 @@ void run_bushy(const huge_graph *g, const huge_plan *p, const huge_exec_opts &o,
     if (o.slice_count > 1 && o.slice_id >= o.slice_count) HUGE_FAIL(HUGE_EINVAL, "slice_id >= slice_count");
     if (o.slice_mode > HUGE_SLICE_STRIDE) HUGE_FAIL(HUGE_EINVAL, "unknown slice_mode %u", o.slice_mode);
     if (p->induced) HUGE_FAIL(HUGE_EINVAL, "bushy plans do not run induced matching");
+    if (p->directed) HUGE_FAIL(HUGE_EINVAL, "bushy plans take undirected queries");
     const auto t0 = std::chrono::steady_clock::now();
     Exec ex{g, p, o, (hipStream_t)o.stream};
     ex.rows.assign(p->bushy.size(), -1);

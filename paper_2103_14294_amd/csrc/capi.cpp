@@ -4,6 +4,8 @@
 #include <cstdarg>
 #include <cstring>
 
+#include <vector>
+
 #include "internal.h"
 
 namespace huge {
@@ -88,6 +90,96 @@ huge_status huge_load_csr_labelled(int64_t n, int64_t nnz, const int64_t *row_pt
     });
 }
 
+huge_status huge_load_csr_directed(int64_t n, int64_t narcs, const int64_t *row_ptr, const int32_t *col,
+                                   uint32_t flags, void *stream, huge_graph **out) {
+    return guard([&] {
+        if (!out) HUGE_FAIL(HUGE_EINVAL, "out is NULL");
+        *out = graph_load_directed(n, narcs, row_ptr, col, flags, (hipStream_t)stream);
+        return HUGE_OK;
+    });
+}
+
+huge_status huge_plan_create_directed(const huge_graph *g, int32_t k, int32_t n_arcs, const int32_t *arcs,
+                                      const int32_t *qlabels, const int32_t *order, huge_plan **out) {
+    return guard([&] {
+        if (!out || !arcs) HUGE_FAIL(HUGE_EINVAL, "NULL argument");
+        if (n_arcs < 1 || n_arcs > 56) HUGE_FAIL(HUGE_EQUERY, "bad number of directed edges (%d)", n_arcs);
+        // the undirected skeleton: one edge per pair joined in either direction
+        std::vector<int32_t> sk;
+        for (int i = 0; i < n_arcs; ++i) {
+            const int a = arcs[2 * i], b = arcs[2 * i + 1];
+            bool seen = false;
+            for (size_t j = 0; j < sk.size(); j += 2)
+                seen |= (sk[j] == a && sk[j + 1] == b) || (sk[j] == b && sk[j + 1] == a);
+            if (!seen) {
+                sk.push_back(a);
+                sk.push_back(b);
+            }
+        }
+        huge_plan *p = new huge_plan();
+        try {
+            plan_build(g, k, (int)sk.size() / 2, sk.data(), order, 0, nullptr, nullptr, p, qlabels, n_arcs, arcs);
+        } catch (...) {
+            delete p;
+            throw;
+        }
+        *out = p;
+        return HUGE_OK;
+    });
+}
+
+huge_status huge_count_paths(const huge_graph *g, int32_t s, int32_t t, int32_t max_hops,
+                             const huge_exec_opts *opts, uint64_t *counts) {
+    return guard([&] {
+        if (!g || !counts) HUGE_FAIL(HUGE_EINVAL, "NULL argument");
+        const int64_t n = g->dev.n;
+        if (s < 0 || t < 0 || s >= n || t >= n || s == t) HUGE_FAIL(HUGE_EINVAL, "s and t must be distinct vertices");
+        if (max_hops < 1 || max_hops > HUGE_KMAX - 1) HUGE_FAIL(HUGE_EINVAL, "max_hops must be 1..%d", HUGE_KMAX - 1);
+        huge_exec_opts o = resolve_opts(opts);
+        if (o.slice_count > 1 || o.slice2_count > 1) HUGE_FAIL(HUGE_EINVAL, "huge_count_paths sets the slices itself");
+        if (o.engine == HUGE_ENGINE_PERSISTENT) HUGE_FAIL(HUGE_EINVAL, "huge_count_paths runs on the level or graph engine");
+        o.workspace = nullptr;  // each length sizes its own
+        o.workspace_bytes = 0;
+        // the ranks of s and t
+        std::vector<int32_t> inv((size_t)n);
+        HUGE_HIP(hipMemcpy(inv.data(), g->inv_rank, sizeof(int32_t) * (size_t)n, hipMemcpyDeviceToHost));
+        int32_t rs = -1, rt = -1;
+        for (int64_t r = 0; r < n; ++r) {
+            if (inv[(size_t)r] == s) rs = (int32_t)r;
+            if (inv[(size_t)r] == t) rt = (int32_t)r;
+        }
+        o.slice_count = (uint32_t)n;
+        o.slice_id = (uint32_t)rs;
+        o.slice_vertex = 0;
+        o.slice_mode = HUGE_SLICE_STRIDE;
+        o.slice2_count = (uint32_t)n;
+        o.slice2_id = (uint32_t)rt;
+        o.exec_flags &= ~(uint32_t)HUGE_EXEC_SLICE2_PAIR;
+        counts[0] = 0;
+        for (int L = 1; L <= max_hops; ++L) {
+            int32_t qe[2 * (HUGE_KMAX - 1)], order[HUGE_KMAX];
+            for (int i = 0; i < L; ++i) {
+                qe[2 * i] = i;
+                qe[2 * i + 1] = i + 1;
+            }
+            for (int i = 0; i <= L; ++i) order[i] = i;
+            huge_plan p;
+            plan_build(g, L + 1, L, qe, order, HUGE_PLAN_ALL_MAPS, nullptr, nullptr, &p);
+            huge_exec_opts ol = o;
+            ol.slice2_vertex = L;
+            huge_result r;
+            if (ol.engine == HUGE_ENGINE_GRAPH && L + 1 >= 3) {
+                run_graph(g, &p, ol, &r);
+            } else {
+                ol.engine = HUGE_ENGINE_LEVELS;
+                run_levels(g, &p, ol, &r, nullptr);
+            }
+            counts[L] = r.count;
+        }
+        return HUGE_OK;
+    });
+}
+
 void huge_graph_free(huge_graph *g) { graph_free(g); }
 
 huge_status huge_graph_get_info(const huge_graph *g, huge_graph_info *out) {
@@ -116,7 +208,8 @@ huge_status huge_plan_create(const huge_graph *g, int32_t k, int32_t n_qedges, c
         huge_plan *p = new huge_plan();
         try {
             if (flags & HUGE_PLAN_LEARNED) HUGE_FAIL(HUGE_EINVAL, "a learned plan needs a model: use huge_plan_create_learned");
-            if (flags & ~(uint32_t)HUGE_PLAN_INDUCED) HUGE_FAIL(HUGE_EINVAL, "unknown plan flags 0x%x", flags);
+            if (flags & ~(uint32_t)(HUGE_PLAN_INDUCED | HUGE_PLAN_ALL_MAPS))
+                HUGE_FAIL(HUGE_EINVAL, "unknown plan flags 0x%x", flags);
             plan_build(g, k, n_qedges, qedges, order, flags, nullptr, nullptr, p);
         } catch (...) {
             delete p;
@@ -131,7 +224,8 @@ huge_status huge_plan_create_labelled(const huge_graph *g, int32_t k, int32_t n_
                                       const int32_t *qlabels, const int32_t *order, uint32_t flags, huge_plan **out) {
     return guard([&] {
         if (!out || !qlabels) HUGE_FAIL(HUGE_EINVAL, "NULL argument");
-        if (flags & ~(uint32_t)HUGE_PLAN_INDUCED) HUGE_FAIL(HUGE_EINVAL, "unknown plan flags 0x%x", flags);
+        if (flags & ~(uint32_t)(HUGE_PLAN_INDUCED | HUGE_PLAN_ALL_MAPS))
+            HUGE_FAIL(HUGE_EINVAL, "unknown plan flags 0x%x", flags);
         huge_plan *p = new huge_plan();
         try {
             plan_build(g, k, n_qedges, qedges, order, flags, nullptr, nullptr, p, qlabels);

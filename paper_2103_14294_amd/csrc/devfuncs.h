@@ -109,6 +109,24 @@ __device__ __forceinline__ bool pair2_ok(const GraphDev &g, const DevPlan &P, co
     return (uint32_t)(mix64(key) % P.slice2_count) == P.slice2_id;
 }
 
+// a -> b is an arc of a directed graph
+__device__ __forceinline__ bool arc(const GraphDev &g, int32_t a, int32_t b) {
+    return contains(g.dcol, g.drp[a], g.drp[a + 1], b);
+}
+
+// directed plans: every query edge between the new vertex v and a matched
+// position keeps its direction
+template <int W>
+__device__ __forceinline__ bool dirs_ok(const GraphDev &g, const DevStep &st, const int32_t (&f)[W], int32_t v) {
+    bool ok = true;
+#pragma unroll
+    for (int p = 0; p < W; ++p) {
+        if (ok && ((st.dout >> p) & 1u)) ok = arc(g, f[p], v);
+        if (ok && ((st.din >> p) & 1u)) ok = arc(g, v, f[p]);
+    }
+    return ok;
+}
+
 // the label the plan asks of position i's vertex v (labelled plans)
 __device__ __forceinline__ bool label_ok(const GraphDev &g, int32_t want, int32_t v) {
     return want < 0 || g.label[v] == want;
@@ -124,6 +142,7 @@ __device__ __forceinline__ bool level2_ok(const int32_t (&f)[2], const DevPlan &
         if ((uint32_t)(mix64(key) % P.slice_count) != P.slice_id) return false;
     }
     if ((s1.slice & 4) && !pair2_ok<1>(g, P, {f[0]}, f[1])) return false;
+    if ((s1.dout | s1.din) && !dirs_ok<1>(g, s1, {f[0]}, f[1])) return false;
     return slices_ok(P.st[0].slice, f[0], P) && slices_ok(s1.slice, f[1], P);
 }
 

@@ -460,6 +460,8 @@ void graph_free(huge_graph *g) {
     if (g->src) (void)hipFree(g->src);
     if (g->inv_rank) (void)hipFree(g->inv_rank);
     if (g->hub_bm) (void)hipFree(g->hub_bm);
+    if (g->drp) (void)hipFree(g->drp);
+    if (g->dcol) (void)hipFree(g->dcol);
     delete g;
 }
 

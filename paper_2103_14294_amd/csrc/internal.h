@@ -55,6 +55,10 @@ struct GraphDev {
     const int64_t *l2_idx = nullptr;
     int64_t l2_first = 0, l2_stride = 1;  // without l2_idx: row r is entry l2_first + r * l2_stride
     const int32_t *label = nullptr;  // vertex labels by rank (labelled graphs), or NULL
+    // directed graphs: out-lists by rank, each ascending (the lists above are the
+    // undirected skeleton); NULL for undirected graphs
+    const int64_t *drp = nullptr;
+    const int32_t *dcol = nullptr;
 };
 
 }  // namespace huge
@@ -67,6 +71,9 @@ struct huge_graph {
     int32_t *inv_rank = nullptr;  // rank -> original ID
     uint32_t *hub_bm = nullptr;
     int32_t *label = nullptr;     // vertex labels by rank, or NULL (unlabelled)
+    int64_t *drp = nullptr;       // directed graphs: out-lists by rank (dev.drp / dev.dcol)
+    int32_t *dcol = nullptr;
+    bool directed = false;
     huge_graph_info info{};
     int device = 0;
     std::string sha;  // content digest of the relabelled CSR (autotune cache key)
@@ -87,6 +94,8 @@ struct DevStep {
     int32_t label;  // labelled plans: the label position i's vertex must carry, -1 any
     uint32_t vadj;  // positions p < i whose lists must hold position i's vertex, looked up only (never the
                     // probe): the verify-only edges of a bushy plan's pulled hash joins
+    uint32_t dout;  // directed plans: positions p < i with a query edge p -> i (f[p] -> v must be an arc)
+    uint32_t din;   // ... and with an edge i -> p (v -> f[p] must be an arc)
 };
 
 struct DevPlan {
@@ -121,6 +130,8 @@ struct huge_plan {
     huge::DevPlan dev{};
     std::vector<huge_bushy_node> bushy;      // bushy plans (Algorithm 1): the join tree, root last; else empty
     bool model_batch = false;                // learned plans: segment rows from the predicted fan-outs
+    bool directed = false;                   // directed query: dadj[a][b] for every edge a -> b; `edges` is
+    int dadj[HUGE_KMAX][HUGE_KMAX] = {};     // its undirected skeleton
 };
 
 namespace huge {
@@ -154,8 +165,13 @@ namespace huge {
 
 // plan.cpp
 void plan_build(const huge_graph *g, int k, int ne, const int32_t *qe, const int32_t *order, uint32_t flags,
-                const huge_model *model, hipStream_t st, huge_plan *out, const int32_t *qlabels = nullptr);
-// a labelled plan needs a labelled graph (HUGE_EINVAL otherwise)
+                const huge_model *model, hipStream_t st, huge_plan *out, const int32_t *qlabels = nullptr,
+                int narcs = 0, const int32_t *arcs = nullptr);
+// graph.hip: a directed graph from out-lists (host memory): the skeleton loaded as usual,
+// the out-lists relabelled by rank beside it
+huge_graph *graph_load_directed(int64_t n, int64_t narcs, const int64_t *rp, const int32_t *col, uint32_t flags,
+                                hipStream_t stream);
+// a labelled plan needs a labelled graph, a directed plan a directed graph (HUGE_EINVAL otherwise)
 void check_labels(const huge_graph *g, const huge_plan *p);
 bool order_connected(const huge_plan &p, const int32_t *order);
 void plan_set_order(huge_plan &p, const int32_t *order);

@@ -883,6 +883,7 @@ void run_persistent(const huge_graph *g, const huge_plan *const *plans, int np, 
     for (int i = 0; i < np; ++i) {
         const huge_plan *p = plans[i];
         if (!p->bushy.empty()) HUGE_FAIL(HUGE_EINVAL, "a bushy plan runs through huge_count / huge_count_bushy only");
+        if (p->directed) HUGE_FAIL(HUGE_EINVAL, "the persistent engine takes undirected queries only");
         dp[i] = p->dev;
         dp[i].slice_count = o.slice_count > 1 ? o.slice_count : 1;
         dp[i].slice_id = o.slice_count > 1 ? o.slice_id : 0;

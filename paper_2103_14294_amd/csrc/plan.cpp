@@ -59,7 +59,8 @@ void check_query(int k, int ne, const int32_t *qe, huge_plan *p) {
 }
 
 // Automorphism group by testing every permutation (k <= 8); a labelled query's
-// automorphisms also keep every vertex's label (-1 counts as a label of its own).
+// automorphisms also keep every vertex's label (-1 counts as a label of its own),
+// a directed query's every edge's direction.
 std::vector<std::vector<int8_t>> automorphisms(const huge_plan &p) {
     std::vector<std::vector<int8_t>> out;
     std::vector<int8_t> perm(p.k);
@@ -73,6 +74,9 @@ std::vector<std::vector<int8_t>> automorphisms(const huge_plan &p) {
             }
         for (int v = 0; v < p.k && ok; ++v)
             if (p.qlabel[perm[v]] != p.qlabel[v]) ok = false;
+        for (int a = 0; a < p.k && ok && p.directed; ++a)  // a directed query's keep directions
+            for (int b = 0; b < p.k && ok; ++b)
+                if (p.dadj[perm[a]][perm[b]] != p.dadj[a][b]) ok = false;
         if (ok) out.push_back(perm);
     } while (std::next_permutation(perm.begin(), perm.end()));
     return out;
@@ -207,6 +211,11 @@ void plan_set_order(huge_plan &p, const int32_t *order) {
         }
         s.neq = ((1u << i) - 1) & ~s.ext;
         s.nadj = p.induced ? s.neq : 0u;
+        if (p.directed)
+            for (int j = 0; j < i; ++j) {
+                if (p.dadj[order[j]][order[i]]) s.dout |= 1u << j;
+                if (p.dadj[order[i]][order[j]]) s.din |= 1u << j;
+            }
         s.slice = order[i] == 0 ? 1 : 0;
         for (auto &c : p.sb) {
             int pa = pos[c.first], pb = pos[c.second];
@@ -340,10 +349,13 @@ size_t verify_orders(const huge_graph *g, const huge_plan &p, const std::vector<
 
 void check_labels(const huge_graph *g, const huge_plan *p) {
     if (p->labelled && !g->label) HUGE_FAIL(HUGE_EINVAL, "a labelled query needs a labelled graph (huge_load_csr_labelled)");
+    if (p->directed && !g->directed)
+        HUGE_FAIL(HUGE_EINVAL, "a directed query needs a directed graph (huge_load_csr_directed)");
 }
 
 void plan_build(const huge_graph *g, int k, int ne, const int32_t *qe, const int32_t *order, uint32_t flags,
-                const huge_model *model, hipStream_t st, huge_plan *p, const int32_t *qlabels) {
+                const huge_model *model, hipStream_t st, huge_plan *p, const int32_t *qlabels, int narcs,
+                const int32_t *arcs) {
     static const huge_graph_info no_stats{};
     const huge_graph_info &gi = g ? g->info : no_stats;
     const bool learned = (flags & HUGE_PLAN_LEARNED) != 0;
@@ -357,7 +369,17 @@ void plan_build(const huge_graph *g, int k, int ne, const int32_t *qe, const int
             p->qlabel[i] = qlabels[i];
             p->labelled |= qlabels[i] >= 0;
         }
+    p->directed = arcs != nullptr;
+    memset(p->dadj, 0, sizeof(p->dadj));
+    for (int i = 0; i < narcs && arcs; ++i) {
+        const int a = arcs[2 * i], b = arcs[2 * i + 1];
+        if (a < 0 || b < 0 || a >= k || b >= k || !p->adj[a][b])
+            HUGE_FAIL(HUGE_EQUERY, "directed edge %d is not an edge of the skeleton", i);
+        if (p->dadj[a][b]) HUGE_FAIL(HUGE_EQUERY, "directed edge %d is a duplicate", i);
+        p->dadj[a][b] = 1;
+    }
     grochow_kellis(*p);
+    if (flags & HUGE_PLAN_ALL_MAPS) p->sb.clear();  // every injective map
     p->flags = flags;
     p->induced = (flags & HUGE_PLAN_INDUCED) != 0;
     std::vector<std::vector<int32_t>> orders;
@@ -429,6 +451,11 @@ void plan_prefix(const huge_plan &p, int size, huge_plan *q) {
         if (pos[v] < size) q->qlabel[pos[v]] = p.qlabel[v];
     q->naut = 0;
     memset(q->adj, 0, sizeof(q->adj));
+    q->directed = p.directed;
+    memset(q->dadj, 0, sizeof(q->dadj));
+    for (int a = 0; a < p.k; ++a)
+        for (int b = 0; b < p.k; ++b)
+            if (p.dadj[a][b] && pos[a] < size && pos[b] < size) q->dadj[pos[a]][pos[b]] = 1;
     q->edges.clear();
     for (auto &e : p.edges) {
         const int a = pos[e.first], b = pos[e.second];

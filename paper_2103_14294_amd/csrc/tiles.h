@@ -287,6 +287,7 @@ __device__ __forceinline__ void extend_tile(const ExtArgs &a, int64_t tile) {
         if (st.slice) ok &= slices_ok(st.slice, v, a.P);
             if (st.label >= 0) ok = ok && label_ok(g, st.label, v);
             if (st.slice & 4) ok = ok && pair2_ok<W>(g, a.P, f, v);
+            if (st.dout | st.din) ok = ok && dirs_ok<W>(g, st, f, v);
         if constexpr (STRAT == 0) {
 #pragma unroll
             for (int p = 0; p < W; ++p) {
@@ -618,6 +619,7 @@ __device__ __forceinline__ void merge_tile(const ExtArgs &a, int64_t tile) {
             if (st.slice) ok &= slices_ok(st.slice, v, a.P);
             if (st.label >= 0) ok = ok && label_ok(g, st.label, v);
             if (st.slice & 4) ok = ok && pair2_ok<W>(g, a.P, f, v);
+            if (st.dout | st.din) ok = ok && dirs_ok<W>(g, st, f, v);
 #pragma unroll
             for (int p = 0; p < W; ++p) {
                 // Ext lists (and verify-only lists) must hold v; in induced mode

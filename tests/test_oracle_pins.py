@@ -478,3 +478,106 @@ def test_strided_pair_slices_partition_and_match_the_relabelled_csr():
             assert (a["count"], a["hash_sum"], a["hash_xor"]) == (b["count"], b["hash_sum"], b["hash_xor"])
             acc = [acc[0] + a["count"], (acc[1] + a["hash_sum"]) & M64, acc[2] ^ a["hash_xor"]]
     assert tuple(acc) == (full["count"], full["hash_sum"], full["hash_xor"])
+
+
+DIRECTED = {
+    "cycle3": (3, [(0, 1), (1, 2), (2, 0)]),
+    "transitive3": (3, [(0, 1), (1, 2), (0, 2)]),
+    "path2": (3, [(0, 1), (1, 2)]),
+    "in-star": (4, [(1, 0), (2, 0), (3, 0)]),
+    "recip-tail": (3, [(0, 1), (1, 0), (1, 2)]),
+    "bifan": (4, [(0, 2), (0, 3), (1, 2), (1, 3)]),
+    "cycle4": (4, [(0, 1), (1, 2), (2, 3), (3, 0)]),
+}
+
+
+def _arcs(d):
+    return {(u, int(v)) for u in range(d.n) for v in d.out_col[d.out_rp[u]:d.out_rp[u + 1]]}
+
+
+def test_directed_matching_brute_force_and_closed_forms():
+    """Directed queries on directed graphs: a match is an injective map keeping
+    every query edge's direction, counted once per class of the automorphisms
+    that keep directions.  Brute force over all injective maps of tiny digraphs
+    divided by that group's order; closed forms on larger ones: directed 3-cycles
+    number tr(A^3)/3, transitive triangles sum over arcs a->c of (A^2)_ac, and
+    directed 2-paths a->b->c (a != c) sum over b of in(b)*out(b) minus the
+    reciprocated pairs at b; with every edge reciprocated, a fully reciprocated
+    query counts what the undirected query counts."""
+    import itertools
+
+    for seed, n, p, pb in [(1, 8, 0.5, 0.3), (2, 9, 0.45, 0.0), (3, 8, 0.6, 0.6)]:
+        d = gg.orient(gg.gnp(n, p, seed=seed), pb, seed=seed + 10)
+        arcs = _arcs(d)
+        for name, (k, e) in DIRECTED.items():
+            aut = sum(1 for s_ in itertools.permutations(range(k))
+                      if {(s_[a], s_[b]) for a, b in e} == set(e))
+            assert oracle.automorphisms_directed(k, e) == aut, name
+            maps = sum(1 for f in itertools.permutations(range(n), k) if all((f[a], f[b]) in arcs for a, b in e))
+            assert maps % aut == 0
+            got = oracle.enumerate_directed(d.row_ptr, d.col, d.out_rp, d.out_col, k, e)
+            assert got["count"] == maps // aut, (seed, name, got["count"], maps // aut)
+    import scipy.sparse as sp
+
+    d = gg.orient(gg.chung_lu(2000, 10, 2.4, seed=7), 0.25, seed=8)
+    A = sp.csr_matrix((np.ones(d.arcs, dtype=np.int64), d.out_col, d.out_rp), shape=(d.n, d.n))
+    A2 = A @ A
+    run = lambda name: oracle.enumerate_directed(d.row_ptr, d.col, d.out_rp, d.out_col, *DIRECTED[name])["count"]
+    assert run("cycle3") == int((A2 @ A).diagonal().sum()) // 3
+    assert run("transitive3") == int(A.multiply(A2).sum())
+    recip = int(A.multiply(A.T).sum())
+    indeg, outdeg = np.asarray(A.sum(axis=0)).ravel(), np.asarray(A.sum(axis=1)).ravel()
+    assert run("path2") == int((indeg * outdeg).sum()) - recip
+    u = gg.chung_lu(600, 8, 2.4, seed=9)
+    full = gg.orient(u, 1.0, seed=1)
+    for name in ["triangle", "4-cycle", "diamond"]:
+        k, e = P.NAMED[name]
+        both = [x for a, b in e for x in ((a, b), (b, a))]
+        assert oracle.enumerate_directed(full.row_ptr, full.col, full.out_rp, full.out_col, k, both) == \
+            oracle.enumerate_query(u.row_ptr, u.col, k, e), name
+
+
+def _dfs_paths(g, s, t, L):
+    """Simple s-t paths of exactly L edges, by depth-first search."""
+    adj = [list(map(int, g.col[g.row_ptr[u]:g.row_ptr[u + 1]])) for u in range(g.n)]
+    cnt = 0
+    stack = [(s, (s,))]
+    while stack:
+        u, path = stack.pop()
+        if len(path) == L + 1:
+            cnt += u == t
+            continue
+        for v in adj[u]:
+            if v not in path and (v != t or len(path) == L):
+                stack.append((v, path + (v,)))
+    return cnt
+
+
+def pinned_path_counts(g, s, t, max_hops, ranks=None):
+    """The oracle's count of the path query 0 - ... - L, every map (no symmetry
+    breaking), vertex 0 pinned to s and vertex L to t by strided slices of
+    count n (one rank each): the hop-constrained path counts."""
+    rk = oracle.ranks(g.row_ptr) if ranks is None else ranks
+    out = [0]
+    for L in range(1, max_hops + 1):
+        e = [(i, i + 1) for i in range(L)]
+        r = oracle.enumerate_query(g.row_ptr, g.col, L + 1, e, mode=oracle.MODE_ALL, order=list(range(L + 1)),
+                                   slice_count=g.n, slice_id=int(rk[s]), slice_vertex=0, slice_mode=1,
+                                   slice2=(L, g.n, int(rk[t])), ranks=rk)
+        out.append(r["count"])
+    return out
+
+
+def test_pinned_path_counts():
+    """Hop-constrained s-t paths: the pinned all-maps path queries equal a
+    depth-first search on random graphs, and on K_n the paths of L edges number
+    (n-2)! / (n-1-L)! (the ordered choice of the L-1 inner vertices)."""
+    import math
+
+    for seed, n, p in [(1, 12, 0.35), (2, 14, 0.3)]:
+        g = gg.gnp(n, p, seed=seed)
+        for s, t in [(0, 1), (3, 7)]:
+            got = pinned_path_counts(g, s, t, 5)
+            assert got == [0] + [_dfs_paths(g, s, t, L) for L in range(1, 6)], (seed, s, t)
+    K = gg.complete(8)
+    assert pinned_path_counts(K, 2, 5, 7) == [0] + [math.factorial(6) // math.factorial(7 - L) for L in range(1, 8)]
