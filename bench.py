@@ -453,7 +453,10 @@ def main():
     log("loaded on GPU in %.1f ms (max degree %d)" % (info["load_ms"], info["max_degree"]))
     ws = huge.Workspace()
     cap = int(args.cap) if args.cap is not None else W["cap"]
-    model = huge.Model.load(args.model) if any(m.startswith("learned") for m in modes) else None
+    # the query selection checks every plan the workload compares, whichever modes this run times, so
+    # a run of a subset of the modes (a profiling pass) times the same queries on the same slices
+    model = huge.Model.load(args.model) if any(m.startswith("learned") for m in list(W["modes"]) + modes) \
+        else None
 
     def learned_plan(k, e):
         torch.cuda.synchronize()
@@ -465,7 +468,7 @@ def main():
     t_q = time.perf_counter()
     nslices = args.steps + args.warmup
     pc = os.environ.get("HUGE_PILOT_CACHE")  # reuse a previous run's query selection (profiling passes)
-    pkey = "%s|%d|%s|%g" % (args.workload, nslices, ",".join(modes), W.get("budget", 0))
+    pkey = "%s|%d|%s|%g" % (args.workload, nslices, ",".join(W["modes"]), W.get("budget", 0))
     pcd = json.load(open(pc)) if pc and os.path.exists(pc) else {}
     if pkey in pcd:
         d = pcd[pkey]

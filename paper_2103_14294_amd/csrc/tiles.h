@@ -232,6 +232,113 @@ __device__ __forceinline__ bool wave_member(const GraphDev &g, bool need_any, in
     return found;
 }
 
+// The binary-search strategy's items of one lane: the kIPT work items
+// w = tile0 + j * kT + threadIdx.x.  Their searches run in lockstep -- the
+// row of each item in the tile's offsets, then for every Ext list the
+// membership of each candidate by a branch-free binary search (Khuong and
+// Morin's form: halve the range on one comparison per round, test the one
+// element left) -- so a round issues one load per item and the kIPT chains
+// of dependent loads overlap instead of following one another.  ok[j] says
+// whether item j passes every test; v[j], r[j] and f[j] are its candidate,
+// segment row and row.
+template <int W>
+__device__ __forceinline__ void bsearch_items(const ExtArgs &a, const DevStep &st, int64_t tile0, int64_t tile1,
+                                              int64_t rlo, int64_t rhi, bool (&ok)[kIPT], int32_t (&v)[kIPT],
+                                              int64_t (&r)[kIPT], int32_t (&f)[kIPT][W]) {
+    const GraphDev &g = a.g;
+    int64_t w[kIPT], lo[kIPT], hi[kIPT];
+#pragma unroll
+    for (int j = 0; j < kIPT; ++j) {
+        w[j] = tile0 + j * kT + threadIdx.x;
+        ok[j] = w[j] < tile1;
+        lo[j] = rlo;
+        hi[j] = ok[j] ? rhi : rlo;
+    }
+    // rows: the last r in [rlo, rhi] with off[r] <= w (every probe inside the tile's rows)
+    for (;;) {
+        bool more = false;
+        int64_t x[kIPT];
+#pragma unroll
+        for (int j = 0; j < kIPT; ++j) x[j] = a.off[lo[j] < hi[j] ? (lo[j] + hi[j] + 1) >> 1 : lo[j]];
+#pragma unroll
+        for (int j = 0; j < kIPT; ++j) {
+            if (lo[j] < hi[j]) {
+                const int64_t mid = (lo[j] + hi[j] + 1) >> 1;
+                if (x[j] <= w[j]) lo[j] = mid; else hi[j] = mid - 1;
+                more |= lo[j] < hi[j];
+            }
+        }
+        if (!more) break;
+    }
+    int pp[kIPT];
+#pragma unroll
+    for (int j = 0; j < kIPT; ++j) {
+        r[j] = lo[j];
+        const uint64_t pi = a.pinfo[r[j]];
+        pp[j] = (int)(pi >> 56);
+        v[j] = g.col[(int64_t)(pi & kPbMask) + (ok[j] ? w[j] - a.off[r[j]] : 0)];
+        load_row<W>(a.rows, g, row_at(a, r[j]), f[j]);
+    }
+#pragma unroll
+    for (int j = 0; j < kIPT; ++j) {
+        bool o = ok[j];
+#pragma unroll
+        for (int p = 0; p < W; ++p)
+            if ((st.neq >> p) & 1u) o &= (v[j] != f[j][p]);
+        if (st.slice) o &= slices_ok(st.slice, v[j], a.P);
+        if (st.label >= 0) o = o && label_ok(g, st.label, v[j]);
+        if (st.slice & 4) o = o && pair2_ok<W>(g, a.P, f[j], v[j]);
+        if (st.dout | st.din) o = o && dirs_ok<W>(g, st, f[j], v[j]);
+        ok[j] = o;
+    }
+#pragma unroll
+    for (int p = 0; p < W; ++p) {
+        if (!(((st.ext | st.vadj) >> p) & 1u)) continue;
+        int64_t b[kIPT];
+        int32_t n[kIPT];
+        bool found[kIPT];
+#pragma unroll
+        for (int j = 0; j < kIPT; ++j) {
+            const int32_t x = f[j][p];
+            const bool need = ok[j] && p != pp[j];
+            const bool hub = need && x >= g.hub_base;
+            found[j] = !need;
+            if (hub) {
+                const uint32_t word = g.hub_bm[(int64_t)(x - g.hub_base) * g.hub_words + (v[j] >> 5)];
+                found[j] = (word >> (v[j] & 31)) & 1u;
+            }
+            const int32_t xx = (need && !hub) ? x : 0;
+            b[j] = g.rp[xx];
+            n[j] = (need && !hub) ? (int32_t)(g.rp[xx + 1] - b[j]) : 0;
+        }
+        // found[j] for a non-hub list: the last element <= v[j] stays in [b, b + n) until n = 1
+        for (;;) {
+            bool more = false;
+            int32_t y[kIPT];
+#pragma unroll
+            for (int j = 0; j < kIPT; ++j) y[j] = g.col[n[j] > 0 ? b[j] + (n[j] >> 1) : 0];
+#pragma unroll
+            for (int j = 0; j < kIPT; ++j) {
+                const int32_t half = n[j] >> 1;
+                found[j] = n[j] == 1 ? y[j] == v[j] : found[j];
+                b[j] += (n[j] > 1 && y[j] <= v[j]) ? half : 0;
+                n[j] = n[j] > 1 ? n[j] - half : 0;
+                more |= n[j] > 0;
+            }
+            if (!more) break;
+        }
+#pragma unroll
+        for (int j = 0; j < kIPT; ++j) ok[j] = ok[j] && found[j];
+    }
+    if (st.nadj) {  // induced mode
+#pragma unroll
+        for (int j = 0; j < kIPT; ++j)
+#pragma unroll
+            for (int p = 0; p < W; ++p)
+                if (ok[j] && ((st.nadj >> p) & 1u)) ok[j] = !adj_has(g, f[j][p], v[j]);
+    }
+}
+
 // One tile of kTile work items (every thread of the workgroup calls it).
 template <int W, int MODE, int STRAT>
 __device__ __forceinline__ void extend_tile(const ExtArgs &a, int64_t tile) {
@@ -260,13 +367,44 @@ __device__ __forceinline__ void extend_tile(const ExtArgs &a, int64_t tile) {
     uint32_t okmask = 0;
     int32_t vv[kIPT];
     int32_t rr[kIPT];
+    // a passing item: folded into the counting SINK, or kept for the output pass
+    auto accept = [&](int j, int64_t r, int32_t v, const int32_t(&f)[W]) {
+        if constexpr (MODE == MODE_COUNT) {
+            uint64_t h = a.hpre[r];
+#pragma unroll
+            for (int p = 0; p < W; ++p)
+                if (((st.ext | st.vadj) >> p) & 1u) h += mix64(edge_key(f[p], v));
+            h = mix64(h);
+            cnt += 1;
+            hs += h;
+            hx ^= h;
+        } else if constexpr (MODE == MODE_COUNT_NOHASH) {
+            cnt += 1;
+        } else {
+            okmask |= 1u << j;
+            vv[j] = v;
+            rr[j] = (int32_t)r;
+        }
+    };
 #pragma unroll
     for (int j = 0; j < kIPT; ++j) {
         vv[j] = 0;
         rr[j] = 0;
+    }
+    if constexpr (STRAT == 0) {
+        bool okb[kIPT];
+        int32_t vb[kIPT];
+        int64_t rb[kIPT];
+        int32_t fb[kIPT][W];
+        bsearch_items<W>(a, st, tile0, tile1, rlo, rhi, okb, vb, rb, fb);
+#pragma unroll
+        for (int j = 0; j < kIPT; ++j)
+            if (okb[j]) accept(j, rb[j], vb[j], fb[j]);
+    } else {
+#pragma unroll
+    for (int j = 0; j < kIPT; ++j) {
         const int64_t w = tile0 + j * kT + threadIdx.x;
         const bool active = w < tile1;
-        if (STRAT == 0 && !active) continue;
         int64_t r = rlo;
         int32_t v = 0;
         int pp = 0;
@@ -285,64 +423,40 @@ __device__ __forceinline__ void extend_tile(const ExtArgs &a, int64_t tile) {
         for (int p = 0; p < W; ++p)
             if ((st.neq >> p) & 1u) ok &= (v != f[p]);
         if (st.slice) ok &= slices_ok(st.slice, v, a.P);
-            if (st.label >= 0) ok = ok && label_ok(g, st.label, v);
-            if (st.slice & 4) ok = ok && pair2_ok<W>(g, a.P, f, v);
-            if (st.dout | st.din) ok = ok && dirs_ok<W>(g, st, f, v);
-        if constexpr (STRAT == 0) {
+        if (st.label >= 0) ok = ok && label_ok(g, st.label, v);
+        if (st.slice & 4) ok = ok && pair2_ok<W>(g, a.P, f, v);
+        if (st.dout | st.din) ok = ok && dirs_ok<W>(g, st, f, v);
+        // row segments of this wave
+        const int64_t rprev = __shfl_up(r, 1, 64);
+        const bool head = active && (lane == 0 || rprev != r);
+        const uint64_t hmask = __ballot(head);
+        const uint64_t amask = __ballot(active);
+        const uint64_t le = (lane == 63) ? ~0ull : ((2ull << lane) - 1);
+        WaveSeg sg;
+        const uint64_t hle = hmask & le;
+        sg.head = hle ? 63 - __clzll(hle) : 0;
+        const uint64_t after = hmask & ~le;
+        const int last_active = amask ? 63 - __clzll(amask) : 0;
+        sg.tail = after ? __ffsll((long long)after) - 2 : last_active;
+        sg.ord = __popcll(hle) - 1;
+        sg.nseg = __popcll(hmask);
+        sg.big = (sg.tail - sg.head) >= 2;
 #pragma unroll
-            for (int p = 0; p < W; ++p) {
-                if (ok && (((st.ext | st.vadj) >> p) & 1u) && p != pp) ok = adj_has(g, f[p], v);
-                if (ok && ((st.nadj >> p) & 1u)) ok = !adj_has(g, f[p], v);  // induced mode
-            }
-        } else {
-            // row segments of this wave
-            const int64_t rprev = __shfl_up(r, 1, 64);
-            const bool head = active && (lane == 0 || rprev != r);
-            const uint64_t hmask = __ballot(head);
-            const uint64_t amask = __ballot(active);
-            const uint64_t le = (lane == 63) ? ~0ull : ((2ull << lane) - 1);
-            WaveSeg sg;
-            const uint64_t hle = hmask & le;
-            sg.head = hle ? 63 - __clzll(hle) : 0;
-            const uint64_t after = hmask & ~le;
-            const int last_active = amask ? 63 - __clzll(amask) : 0;
-            sg.tail = after ? __ffsll((long long)after) - 2 : last_active;
-            sg.ord = __popcll(hle) - 1;
-            sg.nseg = __popcll(hmask);
-            sg.big = (sg.tail - sg.head) >= 2;
-#pragma unroll
-            for (int p = 0; p < W; ++p) {
-                if ((st.ext >> p) & 1u) {
-                    const bool need = active && p != pp;
-                    const bool in = wave_member(g, need, f[p], v, lane, sg, s_stage[wvi], s_pref[wvi], s_lb[wvi]);
-                    if (need) ok &= in;
-                }
-            }
-#pragma unroll
-            for (int p = 0; p < W; ++p) {
-                if (ok && ((st.nadj >> p) & 1u)) ok = !adj_has(g, f[p], v);  // induced mode
-                if (ok && ((st.vadj >> p) & 1u)) ok = adj_has(g, f[p], v);   // verify-only edges
+        for (int p = 0; p < W; ++p) {
+            if ((st.ext >> p) & 1u) {
+                const bool need = active && p != pp;
+                const bool in = wave_member(g, need, f[p], v, lane, sg, s_stage[wvi], s_pref[wvi], s_lb[wvi]);
+                if (need) ok &= in;
             }
         }
-        if (!ok) continue;
-        if constexpr (MODE == MODE_COUNT) {
-            uint64_t h = a.hpre[r];
 #pragma unroll
-            for (int p = 0; p < W; ++p)
-                if (((st.ext | st.vadj) >> p) & 1u) h += mix64(edge_key(f[p], v));
-            h = mix64(h);
-            cnt += 1;
-            hs += h;
-            hx ^= h;
-        } else if constexpr (MODE == MODE_COUNT_NOHASH) {
-            cnt += 1;
-        } else {
-            okmask |= 1u << j;
-            vv[j] = v;
-            rr[j] = (int32_t)r;
+        for (int p = 0; p < W; ++p) {
+            if (ok && ((st.nadj >> p) & 1u)) ok = !adj_has(g, f[p], v);  // induced mode
+            if (ok && ((st.vadj >> p) & 1u)) ok = adj_has(g, f[p], v);   // verify-only edges
         }
+        if (ok) accept(j, r, v, f);
     }
-
+    }
     const int wv = wvi;
     if constexpr (MODE == MODE_COUNT || MODE == MODE_COUNT_NOHASH) {
         cnt = wave_sum_u64(cnt);
