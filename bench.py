@@ -131,10 +131,10 @@ MODEL_PATH = os.path.join(ROOT, "paper_2103_14294_amd", "mlp_work.npz")
 # that ratio times its own algorithmic bytes per launch).  Valid only for the
 # kernel sources whose digest is given; null for any other sources or workload.
 TRAFFIC = {
-    # R-MAT 26 held-out patterns (default run, 20 steps, 5 warmup, no cpu leg): the 42 sink-class
-    # dispatches of the profiled pass, FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0 (factors from the 4 GiB copy),
-    # 107.5 MB per launch against 55.1 MB of algorithmic bytes
-    "c5": {"per_alg_byte": 1.9497, "sources_sha256_16": "1a158ed370f00d4c"},
+    # R-MAT 26 held-out patterns (the default run's queries and slices, 20 steps, 5 warmup, the cost-model
+    # mode timed): the 153 sink-class dispatches of the profiled pass, FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0
+    # (factors from the 4 GiB copy), 146.2 MB per launch against 140.2 MB of algorithmic bytes
+    "c5": {"per_alg_byte": 1.0425, "sources_sha256_16": "0dcba225d19b6352"},
 }
 KERNEL_SOURCES = ["paper_2103_14294_amd/csrc/" + f for f in
                   ("extend.hip", "tiles.h", "devfuncs.h", "internal.h", "round_sched.h", "graph.hip", "mround.hip",
