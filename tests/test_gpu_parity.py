@@ -248,6 +248,16 @@ def test_strategies_agree(H, small, strategy):
     for name in ["4-clique", "diamond", "4-cycle"]:
         k, e = P.NAMED[name]
         assert_parity(H, G3, g3, k, e, strategy=strategy)
+    # a graph whose 12 vertices of degree >= 256 answer membership from their bitmaps,
+    # next to lists searched in memory
+    g4 = gg.rmat(11, 16, seed=9)
+    G4 = H.load(g4.row_ptr, g4.col)
+    assert G4.info()["hub_count"] > 0
+    for name in ["4-clique", "diamond"]:
+        k, e = P.NAMED[name]
+        assert_parity(H, G4, g4, k, e, strategy=strategy)
+    k, e = P.NAMED["5-clique"]
+    assert_parity(H, G4, g4, k, e, strategy=strategy, slice_count=16, slice_id=3, slice_vertex=0)
 
 
 @pytest.mark.parametrize("sv", [1, 3, 4])
