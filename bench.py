@@ -349,6 +349,182 @@ def bench_bushy(args, huge, torch):
     print(json.dumps(out), flush=True)
 
 
+VARIANTS = {
+    "desc": "Chung-Lu n=131072, mean degree 12, gamma 2.6, seed 8, whole: motif counts (every connected 3- and "
+            "4-vertex pattern, non-induced and induced), labelled queries (4 labels, numpy Philox seed 8), induced "
+            "queries, directed queries (the graph oriented, 20% of pairs both ways, seed 8) and hop-constrained "
+            "s-t path counts (up to 5 hops)",
+    "graph": ("chung_lu", dict(n=131072, dbar=12, gamma=2.6, seed=8)),
+    "labels": 4,
+    "motif_k": [3, 4],
+    "labelled": [("triangle", [0, 1, 2]), ("4-cycle", [0, 1, 0, 1]), ("diamond", [0, 1, 2, 1]),
+                 ("house", [0, 1, 2, 3, -1])],
+    "induced": ["4-cycle", "4-path", "diamond", "house"],
+    "directed": {"cycle3": (3, [(0, 1), (1, 2), (2, 0)]), "transitive3": (3, [(0, 1), (1, 2), (0, 2)]),
+                 "bifan": (4, [(0, 2), (0, 3), (1, 2), (1, 3)]), "cycle4": (4, [(0, 1), (1, 2), (2, 3), (3, 0)]),
+                 "ffl-diamond": (4, [(0, 1), (0, 2), (1, 3), (2, 3), (1, 2)])},
+    "path_hops": 5,
+    "path_pairs": 3,
+    # the oracle on the items it finishes in seconds (the CPU baseline, and the exactness check there)
+    "oracle_motifs": ["triangle", "4-clique", "diamond", "4-cycle", "tailed-triangle"],
+}
+
+
+def bench_variants(args, huge, torch):
+    """The line of the paper's variants on the same kernels: every item whole,
+    timed over the steps, each step's results equal to the first step's; the
+    oracle checks the items it finishes in seconds (and is their CPU baseline);
+    the roofline is the dominant kernel class of a profiled pass over the
+    level-engine items (labelled, induced and directed queries)."""
+    import numpy as np
+
+    import graphgen as gg
+    import oracle
+    from graphgen import patterns as P
+
+    V = VARIANTS
+    g = make_graph(V["graph"])
+    rng = np.random.Generator(np.random.Philox(V["graph"][1]["seed"]))
+    labels = rng.integers(0, V["labels"], g.n).astype(np.int32)
+    d = gg.orient(g, 0.2, seed=V["graph"][1]["seed"])
+    G = huge.load(g.row_ptr, g.col)
+    GL = huge.load(g.row_ptr, g.col, labels=labels)
+    GD = huge.load_directed(d.out_rp, d.out_col)
+    deg = np.diff(g.row_ptr)
+    # s-t pairs: vertices of middle degree, seeded
+    mid = np.flatnonzero((deg >= 8) & (deg <= 16))
+    pairs = [tuple(int(x) for x in rng.choice(mid, 2, replace=False)) for _ in range(V["path_pairs"])]
+
+    items = []  # (name, kind, run() -> (embeddings, key), oracle() -> key or None)
+    for k in V["motif_k"]:
+        def run_m(k=k):
+            out = huge.motif_count(G, k)
+            return sum(m["noninduced"] for m in out), tuple((m["noninduced"], m["induced"], m["hash_sum"],
+                                                             m["hash_xor"]) for m in out)
+        items.append(("motifs-k%d" % k, "motif", run_m))
+    lvl = []
+    for name, ql in V["labelled"]:
+        k, e = P.NAMED[name]
+        lvl.append(("labelled-" + name, GL, huge.plan(GL, k, e, labels=ql),
+                    dict(vlabels=labels, qlabels=np.asarray(ql, dtype=np.int32)), k, e, False))
+    for name in V["induced"]:
+        k, e = P.NAMED[name]
+        lvl.append(("induced-" + name, G, huge.plan(G, k, e, induced=True), dict(induced=True), k, e, False))
+    for name, (k, e) in V["directed"].items():
+        lvl.append(("directed-" + name, GD, huge.plan_directed(GD, k, e), None, k, e, True))
+    for name, GG, pl, okw, k, e, directed in lvl:
+        def run_q(GG=GG, pl=pl):
+            r = huge.count(GG, pl)
+            return r["count"], (r["count"], r["hash_sum"], r["hash_xor"])
+        items.append((name, "query", run_q))
+    for s_, t_ in pairs:
+        def run_p(s_=s_, t_=t_):
+            c = huge.count_paths(G, s_, t_, V["path_hops"])
+            return sum(c), tuple(c)
+        items.append(("paths-%d-%d" % (s_, t_), "paths", run_p))
+
+    ref, per = {}, {}
+    for _ in range(args.warmup):
+        for name, _, run in items:
+            run()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    emb = 0
+    for _ in range(args.steps):
+        for name, _, run in items:
+            t1 = time.perf_counter()
+            n, key = run()
+            per[name] = per.get(name, 0.0) + time.perf_counter() - t1
+            emb += n
+            if ref.setdefault(name, key) != key:
+                raise SystemExit("%s changed between steps" % name)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    log("[variants] %.3f s for %d steps" % (el, args.steps))
+
+    # the oracle: the cheap motif patterns (non-induced, whole), every labelled and directed query, the
+    # induced 4-cycle and diamond, and the path counts (each length a pinned all-maps path query)
+    threads = min(16, os.cpu_count() or 1)
+    checked, o_emb, t_o = [], 0, time.perf_counter()
+    motifs = {k: huge.motif_count(G, k) for k in V["motif_k"]}
+    for name in V["oracle_motifs"]:
+        k, e = P.NAMED[name]
+        r = oracle.enumerate_query(g.row_ptr, g.col, k, e, threads=threads)
+        key = oracle._iso_key(k, [tuple(x) for x in e])
+        hit = [m for m in motifs[k] if oracle._iso_key(k, [tuple(x) for x in m["edges"]]) == key]
+        if len(hit) != 1 or (hit[0]["noninduced"], hit[0]["hash_sum"], hit[0]["hash_xor"]) != \
+                (r["count"], r["hash_sum"], r["hash_xor"]):
+            raise SystemExit("motif %s disagrees with the oracle" % name)
+        checked.append("motif " + name)
+        o_emb += r["count"]
+    for name, GG, pl, okw, k, e, directed in lvl:
+        if name.startswith("induced-") and name not in ("induced-4-cycle", "induced-diamond"):
+            continue
+        if directed:
+            r = oracle.enumerate_directed(d.row_ptr, d.col, d.out_rp, d.out_col, k, e, threads=threads)
+        else:
+            r = oracle.enumerate_query(g.row_ptr, g.col, k, e, threads=threads, **okw)
+        if ref[name] != (r["count"], r["hash_sum"], r["hash_xor"]):
+            raise SystemExit("%s disagrees with the oracle: %s vs %s" % (name, ref[name], r["count"]))
+        checked.append(name)
+        o_emb += r["count"]
+    rk = oracle.ranks(g.row_ptr)
+    for s_, t_ in pairs:
+        want = [0]
+        for L in range(1, V["path_hops"] + 1):
+            e = [(i, i + 1) for i in range(L)]
+            r = oracle.enumerate_query(g.row_ptr, g.col, L + 1, e, mode=oracle.MODE_ALL, order=list(range(L + 1)),
+                                       slice_count=g.n, slice_id=int(rk[s_]), slice_vertex=0, slice_mode=1,
+                                       slice2=(L, g.n, int(rk[t_])), ranks=rk, threads=threads)
+            want.append(r["count"])
+        if tuple(want) != ref["paths-%d-%d" % (s_, t_)]:
+            raise SystemExit("paths %d-%d disagree with the oracle: %s vs %s" % (s_, t_, ref["paths-%d-%d" % (s_, t_)], want))
+        checked.append("paths-%d-%d" % (s_, t_))
+        o_emb += sum(want)
+    t_o = time.perf_counter() - t_o
+
+    # profiled pass over the level-engine items: the dominant kernel class against the HBM roof
+    kms, kl, kb = [0.0] * 4, [0] * 4, [0.0] * 4
+    for name, GG, pl, okw, k, e, directed in lvl:
+        r = huge.count(GG, pl, profile=True)
+        for c in range(4):
+            kms[c] += r["kernel_ms"][c]
+            kl[c] += r["kernel_launches"][c]
+            kb[c] += r["alg_bytes"][c]
+    dom = max(range(4), key=lambda c: kms[c])
+    avg_ms = kms[dom] / max(1, kl[dom])
+    bpl = kb[dom] / max(1, kl[dom])
+    ach = (bpl / (avg_ms * 1e-3)) / 1e9 if avg_ms > 0 else 0.0
+    roof = {"bound": "hbm", "achieved": round(ach, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None,
+            "kernel": KC_KERNELS[dom] + ", level engine; profiled pass over the labelled, induced and directed "
+                      "queries", "avg_launch_ms": round(avg_ms, 4), "alg_bytes_per_launch": bpl, "launches": kl[dom],
+            "kernel_ms_by_class": {KC_NAMES[c]: round(kms[c], 3) for c in range(4)},
+            "launches_by_class": {KC_NAMES[c]: kl[c] for c in range(4)}}
+    out = {
+        "metric": "embeddings/sec, the paper's variants (motifs, labelled, induced, directed, s-t paths), 1 GPU",
+        "value": emb / el,
+        "unit": "embeddings/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": el * 1e3 / args.steps,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "int32", "data": "synthetic",
+        "config": {"workload": V["desc"], "n": g.n, "m": g.m, "arcs": int(d.out_rp[-1]), "path_pairs": pairs,
+                   "embeddings_per_step": emb // args.steps,
+                   "per_item_ms": {name: round(per[name] * 1e3 / args.steps, 3) for name, _, _ in items},
+                   "per_item_embeddings": {name: (ref[name][0] if kind == "query" else
+                                                  sum(ref[name]) if kind == "paths" else
+                                                  sum(x[0] for x in ref[name])) for name, kind, _ in items},
+                   "motifs": {"k%d" % k: [{"edges": m["edges"], "noninduced": m["noninduced"],
+                                           "induced": m["induced"]} for m in motifs[k]] for k in motifs},
+                   "path_counts": {"%d-%d" % pq: list(ref["paths-%d-%d" % pq]) for pq in pairs},
+                   "exactness": "every item, every step: equal to the first step; equal to the oracle on " +
+                                ", ".join(checked)},
+        "roofline": roof,
+        "cpu_baseline": {"value": o_emb / t_o if t_o > 0 else 0.0, "unit": "embeddings/s", "cores": threads,
+                         "kind": "oracle", "sample": "the checked items above, whole, once (%.1f s)" % t_o},
+    }
+    print(json.dumps(out), flush=True)
+
+
 def cpu_baseline(g, queries, orders, slices, steps, budget_s, threads):
     """The oracle, as it stands, on the slices the GPU times (each query's cost-model
     order and strided slice s of S_q, s = 0, 1, ...), until the time budget."""
@@ -406,7 +582,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="c5", choices=sorted(WORKLOADS) + ["bushy"])
+    ap.add_argument("--workload", default="c5", choices=sorted(WORKLOADS) + ["bushy", "variants"])
     ap.add_argument("--modes", default=None, help="comma-separated subset of the workload's modes")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
     ap.add_argument("--no-cpu", action="store_true")
@@ -440,6 +616,9 @@ def main():
         return
     if args.workload == "bushy":
         bench_bushy(args, huge, torch)
+        return
+    if args.workload == "variants":
+        bench_variants(args, huge, torch)
         return
     W = dict(WORKLOADS[args.workload])
     if args.budget is not None:

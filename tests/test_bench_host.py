@@ -64,3 +64,25 @@ def test_heldout_patterns_are_outside_the_training_set():
     for name, k, e in qs:
         assert (k, tuple(sorted(e))) not in seen, name
         assert 4 <= k <= 6
+
+
+def test_variants_workload_is_well_formed():
+    """The variants line's items name patterns that exist, with one label per
+    query vertex, and directed queries whose arcs join distinct query vertices
+    of a connected skeleton."""
+    from graphgen import patterns as P
+
+    V = _bench().VARIANTS
+    for name, ql in V["labelled"]:
+        assert name in P.NAMED and len(ql) == P.NAMED[name][0], name
+    for name in V["induced"] + V["oracle_motifs"]:
+        assert name in P.NAMED, name
+    for name in V["oracle_motifs"]:
+        assert P.NAMED[name][0] in V["motif_k"], name
+    for name, (k, arcs) in V["directed"].items():
+        seen = {0}
+        und = {tuple(sorted(a)) for a in arcs}
+        assert all(a != b and 0 <= a < k and 0 <= b < k for a, b in arcs), name
+        for _ in range(k):
+            seen |= {b for a, b in und if a in seen} | {a for a, b in und if b in seen}
+        assert seen == set(range(k)), name
