@@ -536,12 +536,16 @@ huge_status huge_enumerate(const huge_graph *g, const huge_plan *p, const huge_e
  * once in a hipGraph and replayed on opts->stream until no query is active.
  * Queries of 2 vertices run first on the level engine.  At most 256 queries
  * share a round (larger batches run 256 at a time).  Strategy: a fixed
- * lane-merge strategy (2..6; 0 and 1 give HUGE_EINVAL), or AUTO: per extend
- * launch the lane merge the tune table gives most work to at the Ext sizes of
- * the queries of that launch (searches count as HUGE_STRAT_MERGE_SHORT),
- * without a table HUGE_STRAT_BLOCK_MERGE_LONG for last levels and
- * HUGE_STRAT_BLOCK_MERGE otherwise; segments hold chunk_rows rows (default
- * 2^20, or the table's, at most 2^20).  work_limit must be 0.  Workspace:
+ * strategy for every query (2..6 a lane merge; 0 and 1 binary-search tiles),
+ * or AUTO: with a tune table, a query's level runs binary-search tiles when the
+ * table's buckets at its Ext size give more work items to strategies 0 and 1
+ * than to the lane merges, and lane merges otherwise, in the same extend launch
+ * (each tile belongs to one query); the launch's lane merge is the one the
+ * table gives most work to over the merging queries (searches count as
+ * HUGE_STRAT_MERGE_SHORT); without a table every level merges,
+ * HUGE_STRAT_BLOCK_MERGE_LONG for last levels and HUGE_STRAT_BLOCK_MERGE
+ * otherwise; segments hold chunk_rows rows (default 2^20, or a learned plan's
+ * choice; a tune table's segment rows apply to the level engine only).  work_limit must be 0.  Workspace:
  * opts->workspace when it holds huge_batch_workspace_size bytes, else
  * allocated for the call.  Each result's query_ms is the whole batch's wall
  * time and launches counts graph launches.

@@ -388,6 +388,7 @@ struct MPat {                      // one query of the batch (fixed for the call
     SegBufs sb[HUGE_KMAX + 1];     // segment buffers of levels 2..k-1
     int64_t *scan_part;            // tile sums of its segment scan (<= 4096 tiles)
     const int32_t *inv_rank;
+    int32_t search[HUGE_KMAX + 1]; // 1: level W runs binary-search tiles (kTile items), 0: lane merges
 };
 struct MRound {                    // written by the round's scheduler launch
     int64_t prep_pre[kMaxBatch + 1];            // prepare workgroups: exclusive prefix over queries
@@ -400,15 +401,19 @@ struct MRound {                    // written by the round's scheduler launch
 };
 struct MConst {                    // kernel argument of the scheduler
     int32_t np;
-    int32_t tile_items[kMLaunches];  // work items per tile of each extend launch's kernel
+    uint32_t lids;                   // the extend launches the batch uses
+    int32_t tile_items[kMLaunches];  // work items per lane-merge tile of each extend launch's kernel
 };
 void launch_mround_sched(MPat *mp, MRound *mr, const MConst &mc, hipStream_t st);
 void launch_mround_prepare(const MPat *mp, const MRound *mr, int np, hipStream_t st);
 void launch_mround_scan(const MPat *mp, MRound *mr, int np, int64_t max_tiles, hipStream_t st);
 // extend launch `lid` (level W = lid / 2 + 2, last level when lid is odd) with
-// `strategy` (a lane-merge strategy); returns the work items per tile of that kernel
+// `strategy` (a lane-merge strategy) for the queries whose level W merges, and,
+// with `search`, binary-search tiles for those whose level W searches
+// (MPat::search); mround_tile_items gives the work items per lane-merge tile
 int mround_tile_items(int lid, int strategy);
-void launch_mround_extend(int lid, int count_mode, int strategy, const MPat *mp, MRound *mr, int np, hipStream_t st);
+void launch_mround_extend(int lid, int count_mode, int strategy, bool search, const MPat *mp, MRound *mr, int np,
+                          hipStream_t st);
 
 // extend modes
 enum { MODE_EMIT = 0, MODE_COUNT = 1, MODE_OUTPUT = 2, MODE_COUNT_NOHASH = 3 };

@@ -49,14 +49,14 @@ struct BatchLayout {
     uint64_t total = 0;
 };
 
+// Rows per segment of a query's level W: the caller's, the learned model's, or
+// kDefaultSegRows.  A tune table's segment rows are left to the level engine:
+// they are measured there, while a batched round pays its fixed launches once
+// per segment, so smaller segments only add rounds.
 int64_t seg_rows_for(const huge_plan *p, int W, const huge_exec_opts &o, int64_t out_queue_rows) {
     if (o.chunk_rows > 0) return o.chunk_rows;
     const int64_t m = model_segment_rows(p, W, out_queue_rows);
     if (m > 0) return m;
-    if (o.tune) {
-        const int64_t c = o.tune->chunk_rows[__builtin_popcount(p->dev.st[W].ext)];
-        if (c > 0) return std::min<int64_t>(c, kDefaultSegRows);
-    }
     return kDefaultSegRows;
 }
 
@@ -141,7 +141,7 @@ struct GraphKey {
     int64_t max_scan_tiles;
     int strat[kMLaunches];
     int64_t tile_items[kMLaunches];
-    uint32_t lids;
+    uint32_t lids, search_lids;
     bool operator==(const GraphKey &o) const { return memcmp(this, &o, sizeof(*this)) == 0; }
 };
 
@@ -193,21 +193,38 @@ struct Res {
     }
 };
 
-// The kernel of each extend launch: a fixed lane-merge strategy, or per launch
-// the strategy that the tune table gives most work to over the Ext sizes the
-// batch's queries extend with at that level (plain searches map to the short
-// lane merge, the nearest kernel the batched rounds have).
-int launch_strategy(int lid, const huge_exec_opts &o, const std::vector<const huge_plan *> &ps) {
-    if (o.strategy >= 0 && o.strategy < STRAT_COUNT) {
-        if (o.strategy < STRAT_LANE_MERGE) HUGE_FAIL(HUGE_EINVAL, "batched rounds run lane-merge strategies (2..6)");
-        return o.strategy;
+// Whether a query's level W runs binary-search tiles rather than lane merges:
+// a forced strategy decides for every query (0 and 1 search); a tune table by
+// the work items its buckets at the level's Ext count give to each kind;
+// without either, lane merges.
+bool level_searches(const huge_plan *p, int W, const huge_exec_opts &o) {
+    if (o.strategy >= 0 && o.strategy < STRAT_COUNT) return o.strategy < STRAT_LANE_MERGE;
+    if (!o.tune) return false;
+    const int j = __builtin_popcount(p->dev.st[W].ext);
+    int64_t search = 0, merge = 0;
+    for (int c = 0; c < HUGE_TUNE_BUCKETS; ++c) {
+        const int s = o.tune->strategy[j][c];
+        if (s < 0 || s >= STRAT_COUNT) continue;
+        (s < STRAT_LANE_MERGE ? search : merge) += std::max<int64_t>(1, o.tune->items[j][c]);
     }
+    return search > merge;
+}
+
+// The lane merge of each extend launch, for the queries whose level merges: a
+// forced lane-merge strategy, or the one the tune table gives most work to at
+// the Ext sizes of those queries (searches count as the short lane merge, the
+// nearest of its kernels), or without a table the block-cached merges.
+int launch_strategy(int lid, const huge_exec_opts &o, const std::vector<const huge_plan *> &ps,
+                    const std::vector<MPat> &hm) {
     const bool last = (lid & 1) != 0;
-    if (!o.tune) return last ? STRAT_BLOCK_MERGE_LONG : STRAT_BLOCK_MERGE;
+    const int dflt = last ? STRAT_BLOCK_MERGE_LONG : STRAT_BLOCK_MERGE;
+    if (o.strategy >= STRAT_LANE_MERGE && o.strategy < STRAT_COUNT) return o.strategy;
+    if (!o.tune) return dflt;
     const int W = lid / 2 + 2;
     int64_t items[STRAT_COUNT] = {};
-    for (const huge_plan *p : ps) {
-        if (W > p->k - 1 || (W == p->k - 1) != last) continue;
+    for (size_t b = 0; b < ps.size(); ++b) {
+        const huge_plan *p = ps[b];
+        if (W > p->k - 1 || (W == p->k - 1) != last || hm[b].search[W]) continue;
         const int j = __builtin_popcount(p->dev.st[W].ext);
         for (int c = 0; c < HUGE_TUNE_BUCKETS; ++c) {
             int s = o.tune->strategy[j][c];
@@ -216,7 +233,7 @@ int launch_strategy(int lid, const huge_exec_opts &o, const std::vector<const hu
             items[s] += std::max<int64_t>(1, o.tune->items[j][c]);
         }
     }
-    int best = last ? STRAT_BLOCK_MERGE_LONG : STRAT_BLOCK_MERGE;
+    int best = dflt;
     for (int s = STRAT_LANE_MERGE; s < STRAT_COUNT; ++s)
         if (items[s] > items[best]) best = s;
     return best;
@@ -286,7 +303,7 @@ void run_mgraph(const huge_graph *g, const huge_plan *const *plans, int np, cons
     std::vector<GState> hs(nb);
     std::vector<const huge_plan *> ps;
     int64_t max_scan_tiles = 0;
-    bool use_lid[kMLaunches] = {};
+    bool use_lid[kMLaunches] = {}, search_lid[kMLaunches] = {};
     for (int b = 0; b < nb; ++b) {
         const huge_plan *p = plans[B.idx[b]];
         ps.push_back(p);
@@ -315,7 +332,10 @@ void run_mgraph(const huge_graph *g, const huge_plan *const *plans, int np, cons
             m.gc.seg_cap[w] = c;
             m.gc.off[w] = m.sb[w].off;
             max_scan_tiles += (c + 4095) / 4096;
-            use_lid[(w - 2) * 2 + (w == k - 1 ? 1 : 0)] = true;
+            const int lid = (w - 2) * 2 + (w == k - 1 ? 1 : 0);
+            m.search[w] = level_searches(p, w, o) ? 1 : 0;
+            use_lid[lid] = true;
+            search_lid[lid] |= m.search[w] != 0;
         }
         for (int w = 3; w <= k - 1; ++w) {
             m.q[w] = cv.take<int32_t>((uint64_t)w * L.q_cap[w]);
@@ -341,8 +361,9 @@ void run_mgraph(const huge_graph *g, const huge_plan *const *plans, int np, cons
     mc.np = nb;
     int strat[kMLaunches];
     for (int l = 0; l < kMLaunches; ++l) {
-        strat[l] = use_lid[l] ? launch_strategy(l, o, ps) : STRAT_BLOCK_MERGE;
+        strat[l] = use_lid[l] ? launch_strategy(l, o, ps, hm) : STRAT_BLOCK_MERGE;
         mc.tile_items[l] = mround_tile_items(l, strat[l]);
+        if (use_lid[l]) mc.lids |= 1u << l;
     }
     // the host copies above come from pageable memory: finish them before recording
     HUGE_HIP(hipStreamSynchronize(st));
@@ -359,6 +380,7 @@ void run_mgraph(const huge_graph *g, const huge_plan *const *plans, int np, cons
         key.strat[l] = strat[l];
         key.tile_items[l] = mc.tile_items[l];
         if (use_lid[l]) key.lids |= 1u << l;
+        if (search_lid[l]) key.search_lids |= 1u << l;
     }
     // the cache lock is held from lookup to the last replay: two calls with one
     // key would share one workspace anyway, and a graph is not replayed while
@@ -374,7 +396,7 @@ void run_mgraph(const huge_graph *g, const huge_plan *const *plans, int np, cons
             launch_mround_prepare(mp, mr, nb, res.cs);
             launch_mround_scan(mp, mr, nb, max_scan_tiles, res.cs);
             for (int l = 0; l < kMLaunches; ++l)
-                if (use_lid[l]) launch_mround_extend(l, count_mode, strat[l], mp, mr, nb, res.cs);
+                if (use_lid[l]) launch_mround_extend(l, count_mode, strat[l], search_lid[l], mp, mr, nb, res.cs);
         }
         HUGE_HIP(hipStreamEndCapture(res.cs, &res.graph));
         HUGE_HIP(hipGraphInstantiate(&res.exec, res.graph, nullptr, nullptr, 0));

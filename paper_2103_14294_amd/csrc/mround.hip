@@ -16,7 +16,9 @@
 //   k_mround_extend   one launch per (level W, last level or not): its
 //                     workgroups claim tiles in order across the queries
 //                     extending at W, so small queries fill the chip together
-//                     and a hub row of one query spreads over every CU.
+//                     and a hub row of one query spreads over every CU; each
+//                     query's tiles are lane merges or binary searches, as
+//                     its tuned buckets at that level favour.
 // The round holds no memset or copy, so it can be recorded once in a graph
 // and replayed until every query is done.
 #include <algorithm>
@@ -80,7 +82,7 @@ __global__ __launch_bounds__(kMaxBatch) void k_mround_sched(MPat *mp, MRound *mr
             }
             if (s.ext_w1[W] > s.ext_w0[W]) {
                 lid = (W - 2) * 2 + (W == m.gc.lastW ? 1 : 0);
-                const int64_t ti = mc.tile_items[lid];
+                const int64_t ti = m.search[W] ? (int64_t)kTile : (int64_t)mc.tile_items[lid];
                 ext_tiles = (s.ext_w1[W] - s.ext_w0[W] + ti - 1) / ti;
             }
         }
@@ -88,7 +90,8 @@ __global__ __launch_bounds__(kMaxBatch) void k_mround_sched(MPat *mp, MRound *mr
     }
     sched_scan(prep_blocks, np, mr->prep_pre, s_w);
     sched_scan(scan_tiles, np, mr->scan_pre, s_w);
-    for (int l = 0; l < kMLaunches; ++l) sched_scan(lid == l ? ext_tiles : 0, np, mr->ext_pre[l], s_w);
+    for (int l = 0; l < kMLaunches; ++l)
+        if ((mc.lids >> l) & 1u) sched_scan(lid == l ? ext_tiles : 0, np, mr->ext_pre[l], s_w);
     if (p < kMLaunches) mr->claim[p] = 0;
     {
         const uint64_t m = __ballot(alive != 0);
@@ -189,7 +192,9 @@ __global__ __launch_bounds__(scan::kScanThreads) void k_mscan_tiles(const MPat *
     }
 }
 
-template <int W, int MODE, int RUN, bool BLK>
+// SEARCH: the launch also serves queries whose level W runs binary-search
+// tiles (a branch that is uniform over the workgroup, by the tile's query)
+template <int W, int MODE, int RUN, bool BLK, bool SEARCH = false>
 __global__ __launch_bounds__(kT) void k_mround_extend(const MPat *__restrict__ mp, MRound *__restrict__ mr, int np,
                                                       int lid) {
     __shared__ int64_t s_t;
@@ -224,7 +229,14 @@ __global__ __launch_bounds__(kT) void k_mround_extend(const MPat *__restrict__ m
         a.inv_rank = m.inv_rank;
         a.g = m.g;
         a.P = m.P;
-        merge_tile<W, MODE, RUN, BLK>(a, t - pre[p]);
+        if constexpr (SEARCH) {
+            if (m.search[W])
+                extend_tile<W, MODE, STRAT_BSEARCH>(a, t - pre[p]);
+            else
+                merge_tile<W, MODE, RUN, BLK>(a, t - pre[p]);
+        } else {
+            merge_tile<W, MODE, RUN, BLK>(a, t - pre[p]);
+        }
         __syncthreads();
     }
 }
@@ -240,9 +252,14 @@ unsigned resident(F f) {
 }
 
 template <int W, int MODE, int RUN, bool BLK>
-void mextend(const MPat *mp, MRound *mr, int np, int lid, hipStream_t st) {
-    auto f = k_mround_extend<W, MODE, RUN, BLK>;
-    hipLaunchKernelGGL(f, dim3(resident(f)), dim3(kT), 0, st, mp, mr, np, lid);
+void mextend(bool search, const MPat *mp, MRound *mr, int np, int lid, hipStream_t st) {
+    if (search) {
+        auto f = k_mround_extend<W, MODE, RUN, BLK, true>;
+        hipLaunchKernelGGL(f, dim3(resident(f)), dim3(kT), 0, st, mp, mr, np, lid);
+    } else {
+        auto f = k_mround_extend<W, MODE, RUN, BLK, false>;
+        hipLaunchKernelGGL(f, dim3(resident(f)), dim3(kT), 0, st, mp, mr, np, lid);
+    }
 }
 
 // RUN and BLK of a lane-merge strategy; emitting kernels stage at most 16 rows per lane
@@ -259,26 +276,26 @@ void merge_shape(int strategy, bool emit, int &run, bool &blk) {
 }
 
 template <int W, int MODE>
-void mextend_mode(int run, bool blk, const MPat *mp, MRound *mr, int np, int lid, hipStream_t st) {
+void mextend_mode(int run, bool blk, bool search, const MPat *mp, MRound *mr, int np, int lid, hipStream_t st) {
     if (blk) {
-        if (run == 16) mextend<W, MODE, 16, true>(mp, mr, np, lid, st);
-        else if (MODE != MODE_EMIT) mextend<W, MODE, (MODE == MODE_EMIT ? 16 : 64), true>(mp, mr, np, lid, st);
+        if (run == 16) mextend<W, MODE, 16, true>(search, mp, mr, np, lid, st);
+        else if (MODE != MODE_EMIT) mextend<W, MODE, (MODE == MODE_EMIT ? 16 : 64), true>(search, mp, mr, np, lid, st);
     } else {
-        if (run == 4) mextend<W, MODE, 4, false>(mp, mr, np, lid, st);
-        else if (run == 16) mextend<W, MODE, 16, false>(mp, mr, np, lid, st);
-        else if (MODE != MODE_EMIT) mextend<W, MODE, (MODE == MODE_EMIT ? 16 : 64), false>(mp, mr, np, lid, st);
+        if (run == 4) mextend<W, MODE, 4, false>(search, mp, mr, np, lid, st);
+        else if (run == 16) mextend<W, MODE, 16, false>(search, mp, mr, np, lid, st);
+        else if (MODE != MODE_EMIT) mextend<W, MODE, (MODE == MODE_EMIT ? 16 : 64), false>(search, mp, mr, np, lid, st);
     }
 }
 
 template <int W>
-void mextend_w(bool last, int count_mode, int run, bool blk, const MPat *mp, MRound *mr, int np, int lid,
-               hipStream_t st) {
+void mextend_w(bool last, int count_mode, int run, bool blk, bool search, const MPat *mp, MRound *mr, int np,
+               int lid, hipStream_t st) {
     if (!last)
-        mextend_mode<W, MODE_EMIT>(run, blk, mp, mr, np, lid, st);
+        mextend_mode<W, MODE_EMIT>(run, blk, search, mp, mr, np, lid, st);
     else if (count_mode == MODE_COUNT_NOHASH)
-        mextend_mode<W, MODE_COUNT_NOHASH>(run, blk, mp, mr, np, lid, st);
+        mextend_mode<W, MODE_COUNT_NOHASH>(run, blk, search, mp, mr, np, lid, st);
     else
-        mextend_mode<W, MODE_COUNT>(run, blk, mp, mr, np, lid, st);
+        mextend_mode<W, MODE_COUNT>(run, blk, search, mp, mr, np, lid, st);
 }
 
 }  // namespace
@@ -309,19 +326,20 @@ int mround_tile_items(int lid, int strategy) {
     return kT * run;
 }
 
-void launch_mround_extend(int lid, int count_mode, int strategy, const MPat *mp, MRound *mr, int np, hipStream_t st) {
+void launch_mround_extend(int lid, int count_mode, int strategy, bool search, const MPat *mp, MRound *mr, int np,
+                          hipStream_t st) {
     const int W = lid / 2 + 2;
     const bool last = (lid & 1) != 0;
     int run = 16;
     bool blk = false;
     merge_shape(strategy, !last, run, blk);
     switch (W) {
-        case 2: mextend_w<2>(last, count_mode, run, blk, mp, mr, np, lid, st); break;
-        case 3: mextend_w<3>(last, count_mode, run, blk, mp, mr, np, lid, st); break;
-        case 4: mextend_w<4>(last, count_mode, run, blk, mp, mr, np, lid, st); break;
-        case 5: mextend_w<5>(last, count_mode, run, blk, mp, mr, np, lid, st); break;
-        case 6: mextend_w<6>(last, count_mode, run, blk, mp, mr, np, lid, st); break;
-        case 7: mextend_w<7>(last, count_mode, run, blk, mp, mr, np, lid, st); break;
+        case 2: mextend_w<2>(last, count_mode, run, blk, search, mp, mr, np, lid, st); break;
+        case 3: mextend_w<3>(last, count_mode, run, blk, search, mp, mr, np, lid, st); break;
+        case 4: mextend_w<4>(last, count_mode, run, blk, search, mp, mr, np, lid, st); break;
+        case 5: mextend_w<5>(last, count_mode, run, blk, search, mp, mr, np, lid, st); break;
+        case 6: mextend_w<6>(last, count_mode, run, blk, search, mp, mr, np, lid, st); break;
+        case 7: mextend_w<7>(last, count_mode, run, blk, search, mp, mr, np, lid, st); break;
         default: HUGE_FAIL(HUGE_EINVAL, "bad extend launch %d", lid);
     }
     HUGE_HIP(hipGetLastError());

@@ -255,8 +255,10 @@ double order_cost(const std::vector<double> &e, size_t o, int k) {
 // least 64 entries fits (single hub entries of the query hold more), the
 // samples are strided root slices instead (slice 0 of S of the first matched
 // vertex by degree rank, at least 4 roots).  The other orders stop (and lose)
-// past kVerifyRelLimit times the cost model's candidates.  The order with the
-// least device time wins, the cost model's keeping ties within kVerifyGain.
+// past kVerifyRelLimit times the cost model's candidates.  An order must beat
+// the cost model's device time by kVerifyGain; among those within kVerifyGain of
+// the fastest (a tie on one sample), the one sharing the longest prefix with the
+// cost model's order wins, then the faster.
 // About a few milliseconds of device time per order.
 size_t verify_orders(const huge_graph *g, const huge_plan &p, const std::vector<std::vector<int32_t>> &orders,
                      const std::vector<double> &est, const huge_graph_info &gi, hipStream_t st) {
@@ -331,17 +333,34 @@ size_t verify_orders(const huge_graph *g, const huge_plan &p, const std::vector<
     }
     double base_work = 0;
     for (int i = 0; i < HUGE_KMAX; ++i) base_work += (double)r0.level_work[i];
-    size_t best = base;
     const double base_ms = device_ms(r0);
-    double best_ms = base_ms / kVerifyGain;
     o.work_limit = (int64_t)std::max(1.0, std::min(9.0e18, kVerifyRelLimit * base_work));
+    // the orders that beat the cost model's by kVerifyGain, with their times
+    std::vector<std::pair<size_t, double>> won;
+    double best_ms = INFINITY;
     for (size_t i = 1; i < cand.size(); ++i) {
         huge_result r;
         if (run_levels(g, &qs[i], o, &r, nullptr)) continue;
         const double ms = device_ms(r);
-        if (ms < best_ms) {
-            best_ms = ms;
-            best = cand[i];
+        if (ms * kVerifyGain < base_ms) {
+            won.push_back({cand[i], ms});
+            best_ms = std::min(best_ms, ms);
+        }
+    }
+    // orders within kVerifyGain of the fastest are a tie on this sample: the one
+    // sharing the longest prefix with the cost model's order wins it (the least
+    // departure from the baseline), then the faster
+    size_t best = base;
+    int best_pre = -1;
+    double best_t = INFINITY;
+    for (const auto &w : won) {
+        if (w.second > best_ms * kVerifyGain) continue;
+        int pre = 0;
+        while (pre < k && orders[w.first][pre] == orders[base][pre]) ++pre;
+        if (pre > best_pre || (pre == best_pre && w.second < best_t)) {
+            best = w.first;
+            best_pre = pre;
+            best_t = w.second;
         }
     }
     return best;

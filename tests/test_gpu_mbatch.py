@@ -46,10 +46,12 @@ def test_batched_rounds_match_oracle(H, graph):
 
 
 @pytest.mark.parametrize("cap,chunk,strategy", [(0, 0, -1), (1 << 20, 300, 2), (1 << 24, 4096, 3),
-                                                (0, 500, 4), (1 << 22, 0, 5), (0, 64, 6)])
+                                                (0, 500, 4), (1 << 22, 0, 5), (0, 64, 6), (0, 300, 0),
+                                                (1 << 24, 0, 0), (1 << 20, 64, 1)])
 def test_batched_rounds_small_queues_and_strategies(H, hubs, cap, chunk, strategy):
     """Hub-heavy R-MAT, tiny frontier caps (many yields and backtracks per query),
-    small segments and every lane-merge strategy: equal to single runs."""
+    small segments and every strategy (lane merges; 0 and 1 run binary-search
+    tiles): equal to single runs."""
     g, G = hubs
     names = ["triangle", "4-cycle", "diamond", "house", "5-cycle", "tailed-triangle", "4-clique"]
     if cap >= (1 << 24):
@@ -98,6 +100,40 @@ def test_batched_rounds_tuned_table_and_no_hash(H, hubs):
         assert q["count"] == single["count"] and q["hash_sum"] == 0
 
 
+def _table(H, search_j, strat):
+    """A tune table: Ext sizes in search_j take `strat` (0 or 1), the others the
+    block-cached long lane merge, in every bucket."""
+    nb = H.TUNE_BUCKETS
+    return H.TuneTable.from_dict({
+        "strategy": [[strat if j in search_j else 6 for _ in range(nb)] for j in range(H.KMAX + 1)],
+        "chunk_rows": [0] * (H.KMAX + 1), "ms": [[0.0] * nb for _ in range(H.KMAX + 1)],
+        "items": [[1] * nb for _ in range(H.KMAX + 1)]})
+
+
+@pytest.mark.parametrize("search_j,strat", [((1, 3), 0), ((2,), 1), ((1, 2, 3, 4), 0), ((), 0)])
+def test_batched_rounds_search_and_merge_launches(H, hubs, search_j, strat):
+    """A table that sends some Ext sizes to binary-search or wave-staged strategies
+    and the others to lane merges: each query level runs its kind of tile inside
+    the level's one extend launch (binary search for both search strategies),
+    both kinds share the rounds, and every result equals the query's single run."""
+    g, G = hubs
+    names = ["triangle", "4-cycle", "diamond", "house", "5-cycle", "4-clique", "tailed-triangle", "5-clique"]
+    plans = [H.plan(G, *P.NAMED[n]) for n in names]
+    print("batched rounds search j=%s strategy=%d" % (search_j, strat), flush=True)
+    t = _table(H, search_j, strat)
+    for cap in (0, 1 << 24):
+        outs = H.count_batch(G, plans, engine=H.ENGINE_GRAPH, tune=t, cap=cap)
+        for n, pl, r in zip(names, plans, outs):
+            k = P.NAMED[n][0]
+            single = H.count(G, pl)
+            assert cmp_key(r, k) == cmp_key(single, k), (n, cap)
+            assert r["level_counts"][:k] == single["level_counts"][:k], (n, cap)
+            assert r["level_work"][:k] == single["level_work"][:k], (n, cap)
+    nh = H.count_batch(G, plans, engine=H.ENGINE_GRAPH, tune=t, hash=False)
+    for n, pl, r in zip(names, plans, nh):
+        assert r["count"] == H.count(G, pl)["count"] and r["hash_sum"] == 0, n
+
+
 def test_batched_rounds_workspace_reuse_and_replays(H, graph):
     """A caller workspace reused across calls of different batches gives the same
     results as fresh allocations, with eager work and synchronisations between."""
@@ -133,7 +169,7 @@ def test_batched_rounds_edge_cases_and_errors(H):
     r = H.count_batch(G7, pl, engine=H.ENGINE_GRAPH)
     assert r[0]["count"] == 36  # C(9, 7)
     assert r[1]["count"] == 84 * 60  # C(9, 6) * 6! / 12
-    with pytest.raises(H.HugeError):
-        H.count_batch(G7, pl, engine=H.ENGINE_GRAPH, strategy=0)
+    r0 = H.count_batch(G7, pl, engine=H.ENGINE_GRAPH, strategy=0)
+    assert [cmp_key(x, 0) for x in r0] == [cmp_key(x, 0) for x in r]
     with pytest.raises(H.HugeError):
         H.count_batch(G7, pl, engine=H.ENGINE_GRAPH, work_limit=10)
