@@ -162,7 +162,8 @@ __device__ __forceinline__ void wave_sync() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-constexpr int kStage = 512;  // staged list entries per wave
+constexpr int kStage = 512;     // staged list entries per wave
+constexpr int kRowStage = 1024; // row offsets of a binary-search tile staged in LDS
 
 struct WaveSeg {
     int head, tail;  // first and last lane of this lane's row segment
@@ -233,7 +234,8 @@ __device__ __forceinline__ bool wave_member(const GraphDev &g, bool need_any, in
 }
 
 // The binary-search strategy's items of one lane: the kIPT work items
-// w = tile0 + j * kT + threadIdx.x.  Their searches run in lockstep -- the
+// w = tile0 + j * kT + threadIdx.x (every thread of the workgroup calls it: it
+// stages the tile's row offsets in LDS).  Their searches run in lockstep -- the
 // row of each item in the tile's offsets, then for every Ext list the
 // membership of each candidate by a branch-free binary search (Khuong and
 // Morin's form: halve the range on one comparison per round, test the one
@@ -246,20 +248,29 @@ __device__ __forceinline__ void bsearch_items(const ExtArgs &a, const DevStep &s
                                               int64_t rlo, int64_t rhi, bool (&ok)[kIPT], int32_t (&v)[kIPT],
                                               int64_t (&r)[kIPT], int32_t (&f)[kIPT][W]) {
     const GraphDev &g = a.g;
+    // the tile's row offsets off[rlo .. rhi + 1], staged in LDS with coalesced
+    // loads when they fit, so the row searches below run on LDS
+    __shared__ int64_t s_off[kRowStage + 1];
+    const int64_t nr = rhi - rlo + 1;
+    const bool staged = nr <= kRowStage;
+    if (staged)
+        for (int64_t i = threadIdx.x; i <= nr; i += kT) s_off[i] = a.off[rlo + i];
+    __syncthreads();
+    const int64_t *off = staged ? s_off : a.off + rlo;  // off[i] is the offset of row rlo + i
     int64_t w[kIPT], lo[kIPT], hi[kIPT];
 #pragma unroll
     for (int j = 0; j < kIPT; ++j) {
         w[j] = tile0 + j * kT + threadIdx.x;
         ok[j] = w[j] < tile1;
-        lo[j] = rlo;
-        hi[j] = ok[j] ? rhi : rlo;
+        lo[j] = 0;
+        hi[j] = ok[j] ? nr - 1 : 0;
     }
-    // rows: the last r in [rlo, rhi] with off[r] <= w (every probe inside the tile's rows)
+    // rows: the last i in [0, nr) with off[i] <= w (every probe inside the tile's rows)
     for (;;) {
         bool more = false;
         int64_t x[kIPT];
 #pragma unroll
-        for (int j = 0; j < kIPT; ++j) x[j] = a.off[lo[j] < hi[j] ? (lo[j] + hi[j] + 1) >> 1 : lo[j]];
+        for (int j = 0; j < kIPT; ++j) x[j] = off[lo[j] < hi[j] ? (lo[j] + hi[j] + 1) >> 1 : lo[j]];
 #pragma unroll
         for (int j = 0; j < kIPT; ++j) {
             if (lo[j] < hi[j]) {
@@ -273,10 +284,10 @@ __device__ __forceinline__ void bsearch_items(const ExtArgs &a, const DevStep &s
     int pp[kIPT];
 #pragma unroll
     for (int j = 0; j < kIPT; ++j) {
-        r[j] = lo[j];
+        r[j] = rlo + lo[j];
         const uint64_t pi = a.pinfo[r[j]];
         pp[j] = (int)(pi >> 56);
-        v[j] = g.col[(int64_t)(pi & kPbMask) + (ok[j] ? w[j] - a.off[r[j]] : 0)];
+        v[j] = g.col[(int64_t)(pi & kPbMask) + (ok[j] ? w[j] - off[lo[j]] : 0)];
         load_row<W>(a.rows, g, row_at(a, r[j]), f[j]);
     }
 #pragma unroll
