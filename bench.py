@@ -450,8 +450,8 @@ def bench_variants(args, huge, torch):
     for name in V["oracle_motifs"]:
         k, e = P.NAMED[name]
         r = oracle.enumerate_query(g.row_ptr, g.col, k, e, threads=threads)
-        key = oracle._iso_key(k, [tuple(x) for x in e])
-        hit = [m for m in motifs[k] if oracle._iso_key(k, [tuple(x) for x in m["edges"]]) == key]
+        key = oracle.iso_key(k, e)
+        hit = [m for m in motifs[k] if oracle.iso_key(k, m["edges"]) == key]
         if len(hit) != 1 or (hit[0]["noninduced"], hit[0]["hash_sum"], hit[0]["hash_xor"]) != \
                 (r["count"], r["hash_sum"], r["hash_xor"]):
             raise SystemExit("motif %s disagrees with the oracle" % name)

@@ -301,6 +301,11 @@ def _iso_key(k, edges):
     return best
 
 
+def iso_key(k, edges):
+    """The isomorphism class key of a small graph on vertices 0..k-1 (see _iso_key)."""
+    return _iso_key(k, [tuple(x) for x in edges])
+
+
 def _connected(k, edges):
     adj = {v: set() for v in range(k)}
     for a, b in edges:
