@@ -149,6 +149,13 @@ def load_library(path: str = LIB_PATH):
         if not os.path.exists(path):
             raise RuntimeError("libhuge.so is not built (run __graft_entry__.build() or "
                                "python paper_2103_14294_amd/build.py); there is no fallback path")
+        # One HIP runtime per process: the library shares streams and device memory with
+        # torch, so torch's runtime is loaded first and the library binds to it (the two
+        # runtimes have one soname; whichever loads first serves both).
+        try:
+            _torch()
+        except ImportError:
+            pass
         lib = ctypes.CDLL(path)
         vp, i32, i64, u32 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32
         st = ctypes.c_int

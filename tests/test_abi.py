@@ -121,3 +121,17 @@ def test_ctypes_mirrors_match_the_header_layout(H, tmp_path):
         assert got[(cname, "size")] == ctypes.sizeof(py), cname
         for fname, _ in py._fields_:
             assert got[(cname, fname)] == getattr(py, fname).offset, (cname, fname)
+
+
+def test_library_binds_to_torchs_hip_runtime():
+    """Loading the library first loads torch, so that the process holds one HIP
+    runtime (torch's) whose streams and memory the library shares."""
+    import subprocess
+    import sys
+
+    code = ("import sys, paper_2103_14294_amd as H; H.load_library(); "
+            "print('torch' in sys.modules)")
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    out = subprocess.run([sys.executable, "-c", code], cwd=root, capture_output=True, text=True, timeout=300)
+    assert out.returncode == 0, out.stderr
+    assert out.stdout.strip().endswith("True")
